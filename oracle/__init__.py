@@ -1,0 +1,214 @@
+"""CPU oracle for finite-element assembly -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The GPU library (paper_1805_03949_amd) never imports it;
+the two share no code apart from the seeded input generator (meshgen).
+
+Contents:
+  fea_oracle.c   plain FP64 C: shape functions, Gauss rules, element
+                 matrices (Poisson, linear elasticity, neo-Hookean tangent),
+                 sparsity pattern / element-to-nonzero map / inverse map,
+                 greedy colouring, Algorithm 1 assembly with |term| sums
+  dense.py       a second, independent formulation (dense Voigt B^T D B) for
+                 tiny meshes, used to cross-check fea_oracle.c
+  mlp.py         FP64 NumPy forward/backward/Adam for the cost model
+  sched.py       load-balance metric and list-scheduling simulation
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fea_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+POISSON, ELASTIC = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.or_shape.argtypes = [ctypes.c_int, P, P, P]
+        L.or_rule.argtypes = [ctypes.c_int, P, P]
+        L.or_element.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_double,
+                                 ctypes.c_double, P, P, P, P, P, P]
+        L.or_element_fint.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_double, P, P]
+        L.or_graph_rows.argtypes = [i64, i64, P, P, P, P, P]
+        L.or_graph_rows.restype = i64
+        L.or_graph_fill.argtypes = [i64, i64, P, P, P, P, P, P, P, P]
+        L.or_colour_greedy.argtypes = [i64, i64, P, P, P]
+        L.or_assemble.argtypes = [i64, i64, P, P, P, P, P, P, ctypes.c_int, P, P, P, P, P,
+                                  P, P, P, P, P, P, P]
+        L.or_assemble.restype = i64
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+NODES = (4, 5, 6, 8)
+
+
+def shape(etype, xi):
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    N = np.zeros(8)
+    dN = np.zeros((8, 3))
+    nn = lib().or_shape(etype, _p(xi), _p(N), _p(dN))
+    return N[:nn].copy(), dN[:nn].copy()
+
+
+def rule(etype):
+    pts = np.zeros((8, 3))
+    w = np.zeros(8)
+    nq = lib().or_rule(etype, _p(pts), _p(w))
+    return pts[:nq].copy(), w[:nq].copy()
+
+
+def element(etype, X, model=ELASTIC, young=1.0, nu=0.3, f=None, u=None, nh=False,
+            with_terms=False):
+    """Element matrix Ke[(nn*B),(nn*B)] (dof = a*B + i) and vector fe[nn*B]."""
+    nn = NODES[etype]
+    B = 1 if model == POISSON else 3
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(nn, 3)
+    U = np.zeros((nn, 3)) if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(nn, 3)
+    if f is None:
+        f = np.ones(1) if B == 1 else np.array([0.0, 0.0, -1.0])
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    Ke = np.zeros(nn * nn * B * B)
+    fe = np.zeros(nn * B)
+    Tk = np.zeros_like(Ke)
+    Tf = np.zeros_like(fe)
+    rc = lib().or_element(etype, model, int(bool(nh)), _p(X), young, nu, _p(U), _p(f), _p(Ke),
+                          _p(fe), _p(Tk), _p(Tf))
+    if rc != 0:
+        raise ValueError(f"element rejected (code {rc}): detJ <= 0")
+    # block order (a, b, i, j) -> dense (a*B+i, b*B+j)
+    K = Ke.reshape(nn, nn, B, B).transpose(0, 2, 1, 3).reshape(nn * B, nn * B)
+    if with_terms:
+        T = Tk.reshape(nn, nn, B, B).transpose(0, 2, 1, 3).reshape(nn * B, nn * B)
+        return K, fe, T, Tf
+    return K, fe
+
+
+def element_fint(etype, X, young, nu, u):
+    nn = NODES[etype]
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(nn, 3)
+    U = np.ascontiguousarray(u, dtype=np.float64).reshape(nn, 3)
+    out = np.zeros(nn * 3)
+    rc = lib().or_element_fint(etype, _p(X), young, nu, _p(U), _p(out))
+    if rc != 0:
+        raise ValueError("element rejected")
+    return out
+
+
+class Graph:
+    """Block sparsity pattern + element-to-nonzero map + inverse map."""
+
+    def __init__(self, row_ptr, col, map_ptr, e2nnz, inv_ptr, inv):
+        self.row_ptr, self.col, self.map_ptr = row_ptr, col, map_ptr
+        self.e2nnz, self.inv_ptr, self.inv = e2nnz, inv_ptr, inv
+
+    @property
+    def nnz(self):
+        return int(self.col.shape[0])
+
+
+class MeshError(ValueError):
+    def __init__(self, elem):
+        super().__init__(f"invalid element {elem}")
+        self.elem = elem
+
+
+def graph(n_nodes, types, conn_ptr, conn):
+    types = np.ascontiguousarray(types, dtype=np.uint8)
+    conn_ptr = np.ascontiguousarray(conn_ptr, dtype=np.int64)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    E = types.shape[0]
+    row_ptr = np.zeros(n_nodes + 1, dtype=np.int64)
+    map_ptr = np.zeros(E + 1, dtype=np.int64)
+    rc = lib().or_graph_rows(n_nodes, E, _p(types), _p(conn_ptr), _p(conn), _p(row_ptr),
+                             _p(map_ptr))
+    if rc != 0:
+        raise MeshError(-rc - 1)
+    nnz = int(row_ptr[-1])
+    ml = int(map_ptr[-1])
+    col = np.zeros(nnz, dtype=np.int32)
+    e2nnz = np.zeros(ml, dtype=np.int32)
+    inv_ptr = np.zeros(nnz + 1, dtype=np.int64)
+    inv = np.zeros(ml, dtype=np.int32)
+    rc = lib().or_graph_fill(n_nodes, E, _p(conn_ptr), _p(conn), _p(row_ptr), _p(map_ptr),
+                             _p(col), _p(e2nnz), _p(inv_ptr), _p(inv))
+    if rc != 0:
+        raise RuntimeError(f"or_graph_fill failed ({rc})")
+    return Graph(row_ptr, col, map_ptr, e2nnz, inv_ptr, inv)
+
+
+def mesh_graph(mesh):
+    return graph(mesh.n_nodes, mesh.types, mesh.conn_ptr, mesh.conn)
+
+
+def colour_greedy(n_nodes, conn_ptr, conn):
+    E = conn_ptr.shape[0] - 1
+    colour = np.zeros(E, dtype=np.int16)
+    nc = lib().or_colour_greedy(n_nodes, E, _p(np.ascontiguousarray(conn_ptr, dtype=np.int64)),
+                                _p(np.ascontiguousarray(conn, dtype=np.int32)), _p(colour))
+    return colour, nc
+
+
+def assemble(mesh, g, model=ELASTIC, with_terms=False, use_nh=True):
+    """Algorithm 1 assembly of the whole mesh. Returns (vals, rhs[, tvals, trhs])."""
+    B = 1 if model == POISSON else 3
+    nnz = g.nnz
+    vals = np.zeros(nnz * B * B)
+    rhs = np.zeros(mesh.n_nodes * B)
+    tv = np.zeros_like(vals) if with_terms else None
+    tr = np.zeros_like(rhs) if with_terms else None
+    if mesh.source.shape[1] < B:
+        raise ValueError("elasticity needs a 3-component source per element")
+    src = np.ascontiguousarray(mesh.source[:, :B], dtype=np.float64)
+    nh = np.ascontiguousarray(mesh.nh_flag, dtype=np.uint8) if use_nh else None
+    rc = lib().or_assemble(mesh.n_nodes, mesh.n_elems, _p(mesh.types), _p(mesh.conn_ptr),
+                           _p(mesh.conn), _p(mesh.x), _p(mesh.y), _p(mesh.z), model,
+                           _p(mesh.young), _p(mesh.nu), _p(nh), _p(mesh.u), _p(src),
+                           _p(g.row_ptr), _p(g.map_ptr), _p(g.e2nnz), _p(vals), _p(rhs),
+                           _p(tv), _p(tr))
+    if rc != 0:
+        raise MeshError(-rc - 1)
+    if with_terms:
+        return vals, rhs, tv, tr
+    return vals, rhs
+
+
+def to_dense(g, vals, B, n_nodes):
+    """Dense matrix (dof = node*B + i) from block CSR values (tiny meshes only)."""
+    A = np.zeros((n_nodes * B, n_nodes * B))
+    V = vals.reshape(-1, B, B)
+    for r in range(n_nodes):
+        for k in range(g.row_ptr[r], g.row_ptr[r + 1]):
+            c = g.col[k]
+            A[r * B:(r + 1) * B, c * B:(c + 1) * B] = V[k]
+    return A

@@ -1,0 +1,35 @@
+"""Load-balance metric and list scheduling -- TEST ONLY.
+
+Load balance follows the paper's definition (Section 4.1): useful time over
+total time, sum_i t_i / (n * max_i t_i), for n workers with busy times t_i.
+A dynamic work queue hands the next item to whichever worker frees first;
+`list_schedule` simulates that for given item costs and queue order, which is
+what ordering the queue by predicted cost (largest first) tries to improve.
+"""
+from __future__ import annotations
+
+import heapq
+
+import numpy as np
+
+
+def load_balance(times):
+    t = np.asarray(times, dtype=np.float64)
+    return float(t.sum() / (t.size * t.max()))
+
+
+def list_schedule(costs, n_workers):
+    """Busy time per worker when items are taken in the given order."""
+    heap = [(0.0, w) for w in range(n_workers)]
+    busy = np.zeros(n_workers)
+    for c in costs:
+        t, w = heapq.heappop(heap)
+        busy[w] += c
+        heapq.heappush(heap, (t + c, w))
+    return busy
+
+
+def lpt_order(pred):
+    """Indices by descending prediction; ties keep ascending index."""
+    pred = np.asarray(pred)
+    return np.lexsort((np.arange(pred.size), -pred))

@@ -1,0 +1,499 @@
+"""Pins for the CPU oracle: it is checked against what the mathematics fixes
+(closed forms, invariants, brute force, an independent dense formulation),
+never against itself or the GPU library."""
+import itertools
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+import oracle
+from oracle import dense
+
+TET4, PYR5, PEN6, HEX8 = 0, 1, 2, 3
+
+REF_NODES = {
+    TET4: np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float),
+    HEX8: np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
+                    [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], float),
+    PEN6: np.array([[0, 0, -1], [1, 0, -1], [0, 1, -1], [0, 0, 1], [1, 0, 1], [0, 1, 1]], float),
+    PYR5: np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1], [0, 0, 1]], float),
+}
+REF_VOLUME = {TET4: 1 / 6, HEX8: 8.0, PEN6: 1.0, PYR5: 8.0}
+
+
+def random_ref_point(t, rng):
+    if t == TET4:
+        p = rng.dirichlet(np.ones(4))
+        return p[1:]
+    if t == PEN6:
+        p = rng.dirichlet(np.ones(3))
+        return np.array([p[1], p[2], rng.uniform(-1, 1)])
+    return rng.uniform(-1, 1, 3)
+
+
+# ---------------------------------------------------------------- reference elements
+
+@pytest.mark.parametrize("t", [TET4, PYR5, PEN6, HEX8])
+def test_partition_of_unity_and_kronecker(t):
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        N, dN = oracle.shape(t, random_ref_point(t, rng))
+        assert abs(N.sum() - 1) < 1e-14
+        assert np.abs(dN.sum(axis=0)).max() < 1e-14
+    for b, xb in enumerate(REF_NODES[t]):
+        N, _ = oracle.shape(t, xb)
+        np.testing.assert_allclose(N, np.eye(len(N))[b], atol=1e-15)
+
+
+@pytest.mark.parametrize("t", [TET4, PYR5, PEN6, HEX8])
+def test_shape_gradients_central_difference(t):
+    rng = np.random.default_rng(1)
+    h = 1e-6
+    for _ in range(10):
+        xi = random_ref_point(t, rng) * 0.9
+        _, dN = oracle.shape(t, xi)
+        for j in range(3):
+            e = np.zeros(3)
+            e[j] = h
+            fd = (oracle.shape(t, xi + e)[0] - oracle.shape(t, xi - e)[0]) / (2 * h)
+            np.testing.assert_allclose(dN[:, j], fd, atol=1e-9)
+
+
+@pytest.mark.parametrize("t", [TET4, PYR5, PEN6, HEX8])
+def test_rule_weights_and_exactness(t):
+    pts, w = oracle.rule(t)
+    assert len(w) == {TET4: 1, PYR5: 8, PEN6: 6, HEX8: 8}[t]
+    assert abs(w.sum() - REF_VOLUME[t]) < 1e-14
+    if t in (HEX8, PYR5):
+        # 2-point Gauss per axis is exact for x^2 y^2 z^2 over [-1,1]^3: (2/3)^3
+        assert abs((w * (pts ** 2).prod(axis=1)).sum() - (2 / 3) ** 3) < 1e-14
+    if t == PEN6:
+        # integral of r^2 over the triangle (1/12) times integral of t^2 (2/3)
+        assert abs((w * pts[:, 0] ** 2 * pts[:, 2] ** 2).sum() - (1 / 12) * (2 / 3)) < 1e-14
+        assert abs((w * pts[:, 0] * pts[:, 1]).sum() - (1 / 24) * 2) < 1e-14
+    if t == TET4:
+        # a linear function is integrated exactly: int r over the unit tet = 1/24
+        assert abs((w * pts[:, 0]).sum() - 1 / 24) < 1e-15
+
+
+# ---------------------------------------------------------------- closed forms
+
+def _box_hex(hx, hy, hz, x0=(0.3, -0.2, 0.1)):
+    s = REF_NODES[HEX8]
+    return np.array(x0) + (s + 1) / 2 * np.array([hx, hy, hz])
+
+
+def _k1(h):
+    return np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
+
+
+def _m1(h):
+    return h * np.array([[1 / 3, 1 / 6], [1 / 6, 1 / 3]])
+
+
+C1D = np.array([[-0.5, -0.5], [0.5, 0.5]])   # int phi'_a phi_b on an interval
+
+
+def test_hex8_poisson_box_closed_form():
+    hx, hy, hz = 0.7, 1.3, 0.4
+    K, fe = oracle.element(HEX8, _box_hex(hx, hy, hz), model=oracle.POISSON)
+    bits = ((REF_NODES[HEX8] + 1) / 2).astype(int)
+    h = (hx, hy, hz)
+    Kx = np.zeros((8, 8))
+    for a in range(8):
+        for b in range(8):
+            v = 0.0
+            for d in range(3):
+                term = 1.0
+                for e in range(3):
+                    M = _k1(h[e]) if e == d else _m1(h[e])
+                    term *= M[bits[a, e], bits[b, e]]
+                v += term
+            Kx[a, b] = v
+    np.testing.assert_allclose(K, Kx, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(fe, np.full(8, hx * hy * hz / 8), atol=1e-15)
+
+
+def test_hex8_poisson_unit_cube_values():
+    K, _ = oracle.element(HEX8, _box_hex(1, 1, 1), model=oracle.POISSON)
+    assert abs(K[0, 0] - 1 / 3) < 1e-15
+    assert abs(K[0, 1]) < 1e-15            # edge neighbour
+    assert abs(K[0, 2] + 1 / 12) < 1e-15   # face diagonal
+    assert abs(K[0, 6] + 1 / 12) < 1e-15   # body diagonal
+
+
+def test_hex8_elasticity_box_closed_form():
+    hx, hy, hz = 0.5, 0.8, 1.1
+    young, nu = 2.0, 0.27
+    lam = young * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = young / (2 * (1 + nu))
+    K, _ = oracle.element(HEX8, _box_hex(hx, hy, hz), young=young, nu=nu)
+    bits = ((REF_NODES[HEX8] + 1) / 2).astype(int)
+    h = (hx, hy, hz)
+
+    def integ(a, b, i, j):
+        """int dN_a/dx_i dN_b/dx_j over the box, by tensor products."""
+        v = 1.0
+        for d in range(3):
+            A, B = bits[a, d], bits[b, d]
+            if d == i and d == j:
+                v *= _k1(h[d])[A, B]
+            elif d == i:
+                v *= C1D[A, B]
+            elif d == j:
+                v *= C1D[B, A]
+            else:
+                v *= _m1(h[d])[A, B]
+        return v
+
+    Kx = np.zeros((24, 24))
+    for a in range(8):
+        for b in range(8):
+            dot = sum(integ(a, b, k, k) for k in range(3))
+            for i in range(3):
+                for j in range(3):
+                    Kx[3 * a + i, 3 * b + j] = (lam * integ(a, b, i, j) + mu * integ(a, b, j, i)
+                                                + (mu * dot if i == j else 0.0))
+    np.testing.assert_allclose(K, Kx, rtol=0, atol=1e-14)
+
+
+def _barycentric_gradients(X):
+    """Gradients of the P1 barycentric functions of a tetrahedron (linear solve)."""
+    M = np.hstack([np.ones((4, 1)), X])
+    Minv = np.linalg.inv(M)
+    return Minv[1:, :].T, abs(np.linalg.det(M)) / 6.0
+
+
+def test_tet4_closed_forms():
+    rng = np.random.default_rng(3)
+    Xr = REF_NODES[TET4]
+    K, fe = oracle.element(TET4, Xr, model=oracle.POISSON)
+    Kx = np.array([[3, -1, -1, -1], [-1, 1, 0, 0], [-1, 0, 1, 0], [-1, 0, 0, 1]]) / 6
+    np.testing.assert_allclose(K, Kx, atol=1e-15)
+    np.testing.assert_allclose(fe, np.full(4, 1 / 24), atol=1e-16)
+    for _ in range(5):
+        X = Xr + rng.uniform(-0.15, 0.15, (4, 3))
+        Gb, V = _barycentric_gradients(X)
+        K, fe = oracle.element(TET4, X, model=oracle.POISSON)
+        np.testing.assert_allclose(K, V * Gb @ Gb.T, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(fe, np.full(4, V / 4), rtol=1e-13)
+        # elasticity: V * B^T D B with a hand-built Voigt B
+        B = dense.voigt_B(Gb)
+        D = dense.voigt_D(1.0, 0.3)
+        K, fe = oracle.element(TET4, X, young=1.0, nu=0.3)
+        np.testing.assert_allclose(K, V * B.T @ D @ B, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(fe.reshape(4, 3), np.tile([0, 0, -V / 4], (4, 1)), atol=1e-15)
+
+
+def test_pen6_right_prism_closed_form():
+    Lz = 0.6
+    tri = np.array([[0.1, 0.2], [0.9, 0.3], [0.4, 1.0]])
+    X = np.array([[tri[k, 0], tri[k, 1], z] for z in (0.0, Lz) for k in range(3)])
+    K, fe = oracle.element(PEN6, X, model=oracle.POISSON)
+    M = np.hstack([np.ones((3, 1)), tri])
+    A = abs(np.linalg.det(M)) / 2
+    G = np.linalg.inv(M)[1:, :].T
+    k_tri = A * G @ G.T
+    m_tri = A / 12 * np.array([[2, 1, 1], [1, 2, 1], [1, 1, 2]])
+    Kx = np.kron(_m1(Lz), k_tri) + np.kron(_k1(Lz), m_tri)
+    np.testing.assert_allclose(K, Kx, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(fe, np.full(6, A * Lz / 6), atol=1e-15)
+
+
+def test_pyr5_square_pyramid_rhs_and_volume():
+    side, height = 0.8, 0.5
+    X = np.array([[0, 0, 0], [side, 0, 0], [side, side, 0], [0, side, 0],
+                  [side / 2, side / 2, height]])
+    _, fe = oracle.element(PYR5, X, model=oracle.POISSON)
+    V = side * side * height / 3
+    np.testing.assert_allclose(fe[4], V / 4, rtol=1e-14)
+    np.testing.assert_allclose(fe[:4], np.full(4, 3 * V / 16), rtol=1e-14)
+    assert abs(fe.sum() - V) < 1e-15
+
+
+# ---------------------------------------------------------------- meshes / graph
+
+def small_meshes():
+    out = {}
+    out["hex_jitter"] = mg.tiny_mesh(np.full((3, 3, 3), HEX8), jitter=0.2, seed=5)
+    out["hex_jitter"].source[:, 0] = 1.0     # Poisson source f = 1 in column 0
+    out["bands"] = mg.hybrid_bands(4, seed=6)
+    ct = np.random.default_rng(7).integers(0, 4, (3, 3, 3))
+    out["random_mix_jitter"] = mg.tiny_mesh(ct, jitter=0.25, seed=8)
+    return out
+
+
+def brute_force_pattern(mesh):
+    rows = [set() for _ in range(mesh.n_nodes)]
+    for e in range(mesh.n_elems):
+        nodes = mesh.conn[mesh.conn_ptr[e]:mesh.conn_ptr[e + 1]]
+        for a in nodes:
+            for b in nodes:
+                rows[a].add(int(b))
+    return rows
+
+
+@pytest.mark.parametrize("name", ["hex_jitter", "bands", "random_mix_jitter"])
+def test_graph_brute_force(name):
+    m = small_meshes()[name]
+    g = oracle.mesh_graph(m)
+    rows = brute_force_pattern(m)
+    for i in range(m.n_nodes):
+        cols = g.col[g.row_ptr[i]:g.row_ptr[i + 1]]
+        assert list(cols) == sorted(rows[i])
+        assert i in cols
+    # e2nnz points at the right (row, col), and the inverse map is its inverse
+    rowof = np.repeat(np.arange(m.n_nodes), np.diff(g.row_ptr))
+    for e in range(m.n_elems):
+        nodes = m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]]
+        nn = len(nodes)
+        for a, b in itertools.product(range(nn), range(nn)):
+            k = g.e2nnz[g.map_ptr[e] + a * nn + b]
+            assert rowof[k] == nodes[a] and g.col[k] == nodes[b]
+    slot_elem = np.repeat(np.arange(m.n_elems), np.diff(g.map_ptr))
+    for k in range(g.nnz):
+        sl = g.inv[g.inv_ptr[k]:g.inv_ptr[k + 1]]
+        assert np.all(g.e2nnz[sl] == k)
+        assert np.all(np.diff(slot_elem[sl]) > 0)
+    assert g.inv_ptr[-1] == m.map_len()
+    assert np.array_equal(np.sort(g.inv), np.arange(m.map_len()))
+
+
+def test_hex_grid_nnz_closed_form():
+    for n in (2, 5):
+        m = mg.tiny_mesh(np.full((n, n, n), HEX8), dofs=1)
+        g = oracle.mesh_graph(m)
+        assert g.nnz == (3 * (n + 1) - 2) ** 3
+
+
+def test_invalid_connectivity_is_reported():
+    m = small_meshes()["bands"]
+    bad = m.conn.copy()
+    e = 17
+    bad[m.conn_ptr[e] + 1] = bad[m.conn_ptr[e]]          # repeated node
+    with pytest.raises(oracle.MeshError) as ei:
+        oracle.graph(m.n_nodes, m.types, m.conn_ptr, bad)
+    assert ei.value.elem == e
+    bad = m.conn.copy()
+    bad[m.conn_ptr[40]] = m.n_nodes                       # out of range
+    with pytest.raises(oracle.MeshError) as ei:
+        oracle.graph(m.n_nodes, m.types, m.conn_ptr, bad)
+    assert ei.value.elem == 40
+    t = m.types.copy()
+    t[3] = 9                                              # unknown type
+    with pytest.raises(oracle.MeshError) as ei:
+        oracle.graph(m.n_nodes, t, m.conn_ptr, m.conn)
+    assert ei.value.elem == 3
+
+
+def test_inverted_element_is_reported():
+    m = mg.tiny_mesh(np.full((2, 2, 2), TET4))
+    g = oracle.mesh_graph(m)
+    e = 5
+    c = m.conn.copy()
+    c[m.conn_ptr[e] + 1], c[m.conn_ptr[e] + 2] = c[m.conn_ptr[e] + 2], c[m.conn_ptr[e] + 1]
+    m.conn = c
+    with pytest.raises(oracle.MeshError) as ei:
+        oracle.assemble(m, oracle.mesh_graph(m))
+    assert ei.value.elem == e
+    del g
+
+
+def test_greedy_colouring_valid_and_first_fit():
+    m = small_meshes()["random_mix_jitter"]
+    col, nc = oracle.colour_greedy(m.n_nodes, m.conn_ptr, m.conn)
+    assert nc == col.max() + 1
+    elems_of = [[] for _ in range(m.n_nodes)]
+    for e in range(m.n_elems):
+        for v in m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]]:
+            elems_of[v].append(e)
+    for e in range(m.n_elems):
+        nb = {o for v in m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]] for o in elems_of[v] if o != e}
+        assert all(col[o] != col[e] for o in nb)
+        earlier = {int(col[o]) for o in nb if o < e}
+        assert col[e] == min(set(range(len(earlier) + 1)) - earlier)
+
+
+# ---------------------------------------------------------------- invariants
+
+def _dense(m, model):
+    g = oracle.mesh_graph(m)
+    vals, rhs = oracle.assemble(m, g, model=model)
+    B = 1 if model == oracle.POISSON else 3
+    return oracle.to_dense(g, vals, B, m.n_nodes), rhs, g
+
+
+@pytest.mark.parametrize("name", ["hex_jitter", "bands", "random_mix_jitter"])
+def test_cross_oracle_dense_voigt(name):
+    m = small_meshes()[name]
+    for model in (oracle.POISSON, oracle.ELASTIC):
+        A, b, _ = _dense(m, model)
+        Ad, bd = dense.assemble_dense(m, poisson=(model == oracle.POISSON))
+        scale = np.abs(Ad).max()
+        assert np.abs(A - Ad).max() <= 1e-13 * scale
+        assert np.abs(b - bd).max() <= 1e-13 * np.abs(bd).max()
+
+
+def test_volume_and_rhs_sum():
+    m = small_meshes()["hex_jitter"]       # conforming jittered hexes: volume 1
+    A, b, _ = _dense(m, oracle.POISSON)
+    assert abs(b.sum() - 1.0) < 1e-13
+    m = small_meshes()["bands"]            # unjittered hybrid: volume 1
+    A, b, _ = _dense(m, oracle.ELASTIC)
+    np.testing.assert_allclose(b.reshape(-1, 3).sum(axis=0), [0, 0, -1.0], atol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["hex_jitter", "bands", "random_mix_jitter"])
+def test_poisson_row_sums_and_symmetry(name):
+    m = small_meshes()[name]
+    A, _, _ = _dense(m, oracle.POISSON)
+    scale = np.abs(A).max()
+    assert np.abs(A.sum(axis=1)).max() < 1e-14 * 64 * scale
+    assert np.abs(A - A.T).max() < 1e-15 * 8 * scale
+
+
+@pytest.mark.parametrize("name", ["hex_jitter", "bands", "random_mix_jitter"])
+def test_elasticity_rigid_modes_and_symmetry(name):
+    m = small_meshes()[name]
+    A, _, _ = _dense(m, oracle.ELASTIC)
+    X = np.stack([m.x, m.y, m.z], axis=1)
+    modes = []
+    for i in range(3):
+        t = np.zeros_like(X)
+        t[:, i] = 1.0
+        modes.append(t.ravel())
+    for w in np.eye(3):
+        modes.append(np.cross(w, X).ravel())
+    scale = np.abs(A).max()
+    for r in modes:
+        assert np.abs(A @ r).max() < 1e-13 * scale * np.abs(r).max()
+    assert np.abs(A - A.T).max() < 1e-14 * scale
+    # and nothing else: exactly six zero eigenvalues
+    ev = np.linalg.eigvalsh(0.5 * (A + A.T))
+    assert np.sum(np.abs(ev) < 1e-10 * scale) == 6
+
+
+@pytest.mark.parametrize("ctype", [HEX8, TET4, PYR5, PEN6])
+def test_patch_test_linear_field(ctype):
+    m = mg.tiny_mesh(np.full((3, 3, 3), ctype), jitter=0.2, seed=11)
+    m.nu[:] = 0.3
+    X = np.stack([m.x, m.y, m.z], axis=1)
+    interior = ~m.boundary
+    G = np.array([[0.3, -0.1, 0.2], [0.05, 0.4, -0.2], [0.1, 0.0, -0.3]])
+    u = X @ G.T + np.array([0.1, 0.2, 0.3])
+    A, _, _ = _dense(m, oracle.ELASTIC)
+    r = (A @ u.ravel()).reshape(-1, 3)
+    assert np.abs(r[interior]).max() < 1e-13 * np.abs(A).max()
+    Ap, _, _ = _dense(m, oracle.POISSON)
+    rp = Ap @ (X @ np.array([0.7, -0.3, 0.2]))
+    assert np.abs(rp[interior]).max() < 1e-13 * np.abs(Ap).max()
+
+
+def test_patch_test_conforming_prism_tet_interface():
+    ct = np.zeros((4, 4, 4), dtype=np.uint8)
+    ct[:2] = PEN6
+    ct[2:] = TET4
+    m = mg.tiny_mesh(ct, jitter=0.15, seed=12)
+    m.nu[:] = 0.25
+    X = np.stack([m.x, m.y, m.z], axis=1)
+    A, _, _ = _dense(m, oracle.ELASTIC)
+    u = X @ np.array([[0.2, 0.1, 0], [0, -0.3, 0.1], [0.1, 0.2, 0.3]]).T
+    r = (A @ u.ravel()).reshape(-1, 3)
+    assert np.abs(r[~m.boundary]).max() < 1e-13 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("t", [TET4, PYR5, PEN6, HEX8])
+def test_covariance(t):
+    rng = np.random.default_rng(20 + t)
+    X = REF_NODES[t] * 0.3 + rng.uniform(-0.03, 0.03, REF_NODES[t].shape)
+    K, fe = oracle.element(t, X, young=1.3, nu=0.31)
+    Kt, fet = oracle.element(t, X + np.array([5.0, -2.0, 1.0]), young=1.3, nu=0.31)
+    np.testing.assert_allclose(Kt, K, atol=1e-12 * np.abs(K).max())
+    q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    R = q * np.sign(np.linalg.det(q))
+    Kr, _ = oracle.element(t, X @ R.T, young=1.3, nu=0.31)
+    nn = len(X)
+    Rb = np.kron(np.eye(nn), R)
+    np.testing.assert_allclose(Kr, Rb @ K @ Rb.T, atol=1e-13 * np.abs(K).max())
+    s = 2.5
+    Kp, fp = oracle.element(t, X, model=oracle.POISSON)
+    Ks, fs = oracle.element(t, X * s, model=oracle.POISSON)
+    np.testing.assert_allclose(Ks, s * Kp, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(fs, s ** 3 * fp, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- neo-Hookean
+
+@pytest.mark.parametrize("t", [TET4, PYR5, PEN6, HEX8])
+def test_neo_hookean_reduces_to_linear_at_identity(t):
+    rng = np.random.default_rng(30 + t)
+    X = REF_NODES[t] * 0.2 + rng.uniform(-0.02, 0.02, REF_NODES[t].shape)
+    Kl, _ = oracle.element(t, X, young=1.0, nu=0.3)
+    Kn, _ = oracle.element(t, X, young=1.0, nu=0.3, nh=True, u=np.zeros_like(X))
+    np.testing.assert_allclose(Kn, Kl, atol=1e-15 * 10 * np.abs(Kl).max())
+
+
+@pytest.mark.parametrize("t", [TET4, PYR5, PEN6, HEX8])
+def test_neo_hookean_tangent_is_derivative_of_internal_force(t):
+    rng = np.random.default_rng(40 + t)
+    X = REF_NODES[t] * 0.2 + rng.uniform(-0.02, 0.02, REF_NODES[t].shape)
+    u = rng.uniform(-0.02, 0.02, X.shape)
+    young, nu = 1.0, 0.32
+    K, _ = oracle.element(t, X, young=young, nu=nu, nh=True, u=u)
+    nn = len(X)
+    h = 1e-7
+    fd = np.zeros((3 * nn, 3 * nn))
+    for c in range(3 * nn):
+        du = np.zeros(3 * nn)
+        du[c] = h
+        fp = oracle.element_fint(t, X, young, nu, (u.ravel() + du).reshape(nn, 3))
+        fm = oracle.element_fint(t, X, young, nu, (u.ravel() - du).reshape(nn, 3))
+        fd[:, c] = (fp - fm) / (2 * h)
+    assert np.abs(K - fd).max() <= 1e-6 * np.abs(K).max()
+    assert np.abs(K - K.T).max() <= 1e-13 * np.abs(K).max()
+    for i in range(3):
+        tr = np.zeros((nn, 3))
+        tr[:, i] = 1.0
+        assert np.abs(K @ tr.ravel()).max() <= 1e-13 * np.abs(K).max()
+
+
+def test_neo_hookean_internal_force_zero_at_rest():
+    X = REF_NODES[HEX8] * 0.2
+    f = oracle.element_fint(HEX8, X, 1.0, 0.3, np.zeros((8, 3)))
+    assert np.abs(f).max() < 1e-16
+
+
+# ---------------------------------------------------------------- FP32 bound companion
+
+def test_term_sums_bound_values():
+    m = small_meshes()["random_mix_jitter"]
+    g = oracle.mesh_graph(m)
+    v, r, tv, tr = oracle.assemble(m, g, with_terms=True)
+    assert np.all(tv >= np.abs(v) * (1 - 1e-12))
+    assert np.all(tr >= np.abs(r) * (1 - 1e-12))
+    # Poisson diagonal entries are sums of non-negative terms: T == value
+    vp, _, tvp, _ = oracle.assemble(m, g, model=oracle.POISSON, with_terms=True)
+    diag = [np.searchsorted(g.col[g.row_ptr[i]:g.row_ptr[i + 1]], i) + g.row_ptr[i]
+            for i in range(m.n_nodes)]
+    np.testing.assert_allclose(tvp[diag], vp[diag], rtol=1e-14)
+
+
+# ---------------------------------------------------------------- paper fixture
+
+def test_table2_load_balance_golden():
+    """Element-count load balance (average/maximum, Section 4.1) from Table 2."""
+    from oracle import sched
+    rows = np.loadtxt(__file__.replace("test_oracle.py", "golden/table2_chunks.txt"))
+    for row in rows:
+        chunk = row[0]
+        for p, (mx, mn, avg) in zip((256, 512, 1024), row[1:].reshape(3, 3)):
+            # the average chunk count times chunk size times partitions is the mesh size
+            if chunk == 100:
+                assert abs(avg * chunk * p - 17.7e6) / 17.7e6 < 0.01
+            assert mn <= avg <= mx
+    r100 = rows[0][1:].reshape(3, 3)
+    # non-weighted LB = average / maximum
+    lbs = [avg / mx for mx, _, avg in r100]
+    np.testing.assert_allclose(lbs, [0.345, 0.252, 0.247], atol=1e-3)
+    assert abs(sched.load_balance([1.0, 2.0, 3.0]) - 6.0 / 9.0) < 1e-15
