@@ -1,0 +1,144 @@
+/*
+ * fea.h -- C ABI of the MI355X (gfx950) finite-element assembly library.
+ *
+ * The library implements the element loop of the paper's Algorithm 1
+ * (Section 2.1.1): for every element, the element matrix A^e and
+ * right-hand side b^e are computed by Gauss quadrature and added into a
+ * global block-sparse matrix A and vector b. The race on shared rows that
+ * the paper's Section 3.2 treats with OpenMP ATOMIC (Algorithm 4) or element
+ * colouring (Algorithm 5) is treated here by selectable scatter variants.
+ *
+ * Conventions shared by every entry point
+ *   - Element families (types[e]): 0 = tet4, 1 = pyr5, 2 = pen6, 3 = hex8,
+ *     with 4, 5, 6, 8 nodes; node order and reference elements as in the
+ *     library documentation (hex8 nodes (-1,-1,-1),(1,-1,-1),(1,1,-1),
+ *     (-1,1,-1) then the same at zeta = +1; pen6 triangle (0,0),(1,0),(0,1)
+ *     at t = -1 then t = +1; tet4 (0,0,0),(1,0,0),(0,1,0),(0,0,1); pyr5 base
+ *     counter-clockwise seen from the apex, then the apex).
+ *   - Connectivity: conn_ptr[n_elems+1] (int64, conn_ptr[0] = 0) and
+ *     conn[conn_ptr[n_elems]] (int32 node ids, zero-based).
+ *   - Block sparsity: rows and columns are nodes; row i lists every node
+ *     sharing an element with i, diagonal included, columns strictly
+ *     ascending. Poisson uses 1x1 blocks (CSR), elasticity 3x3 blocks (BSR,
+ *     block row-major: vals[9k + 3i + j], dof = 3*node + i).
+ *   - e2nnz[map_ptr[e] + a*n_e + b] = block index of (conn[e][a], conn[e][b]);
+ *     map_ptr is the prefix sum of n_e^2. The inverse map lists, for block k,
+ *     the slots inv[inv_ptr[k] .. inv_ptr[k+1]) in ascending element order.
+ *   - Pointers named "device" must point to device memory of the current
+ *     HIP device; the caller keeps ownership. All work is enqueued on the
+ *     given stream; functions return after enqueueing unless stated.
+ *   - Return values: FEA_OK (0) or a negative FEA_E* code; fea_last_error()
+ *     then returns a message for the calling thread.
+ */
+#ifndef FEA_H
+#define FEA_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEA_OK 0
+#define FEA_EINVAL (-1) /* bad argument (NULL where required, bad option)   */
+#define FEA_EMESH (-2)  /* bad mesh: unknown type, node id out of range,
+                           repeated node in an element, wrong conn_ptr span  */
+#define FEA_ENOMEM (-3) /* device or host allocation failed                 */
+#define FEA_EHIP (-4)   /* a HIP runtime call failed                         */
+#define FEA_ERANGE (-5) /* a size exceeds the library's index limits         */
+
+enum fea_precision { FEA_FP64 = 0, FEA_MIXED = 1 };
+/* Scatter variants (Section 3.2 of the paper treats the same race):
+ *   ROWOWNER  element kernel writes each block contribution to its own slot
+ *             in a workspace; a second kernel sums every block's
+ *             contributions in ascending element order (deterministic,
+ *             bitwise reproducible, independent of execution order);
+ *   ATOMIC    element kernel adds into A and b with hardware atomics
+ *             (the GPU counterpart of Algorithm 4);
+ *   COLOUR    one launch per colour of a greedy element colouring, plain
+ *             read-add-write (Algorithm 5); deterministic;
+ *   ROWGATHER fused owner-computes: each row's owner recomputes the element
+ *             rows that touch it and sums them in ascending element order
+ *             (deterministic, no workspace, no atomics). */
+enum fea_variant { FEA_ROWOWNER = 0, FEA_ATOMIC = 1, FEA_COLOUR = 2, FEA_ROWGATHER = 3 };
+enum fea_dtype { FEA_F64 = 0, FEA_F32 = 1 };
+enum fea_model { FEA_POISSON = 0, FEA_ELASTIC = 1 };
+enum fea_schedule { FEA_TYPE_SORTED = 0, FEA_LEARNED = 1, FEA_GP_WEIGHT = 2 };
+
+/* Options. A zero-initialised struct is FP64, row-owner, f64 output. */
+typedef struct fea_options {
+    int precision; /* enum fea_precision */
+    int variant;   /* enum fea_variant */
+    int out_dtype; /* enum fea_dtype: element type of vals and rhs */
+} fea_options;
+
+/* Material and model. Per-element arrays are device pointers of length
+ * n_elems; u is a device array of 3*n_nodes displacements (node-major). */
+typedef struct fea_material {
+    int model;              /* enum fea_model */
+    const double *young;    /* Young's modulus per element; NULL = 1.0      */
+    const double *nu;       /* Poisson ratio per element (elasticity)       */
+    const uint8_t *nh_flag; /* NULL, or 1 = neo-Hookean tangent at u        */
+    const double *u;        /* required when nh_flag is given               */
+} fea_material;
+
+typedef struct fea_graph fea_graph;
+
+/*
+ * Builds the block sparsity pattern, the element-to-nonzero map, the
+ * inverse map, the node-to-element incidence, the type segmentation
+ * (elements stably sorted by family) and a greedy element colouring from
+ * the connectivity (device pointers). The graph keeps its own device
+ * buffers until fea_graph_destroy. Blocks on `stream` (it must learn the
+ * number of nonzeros). Errors: FEA_EINVAL, FEA_EMESH (the message names the
+ * first bad element), FEA_ERANGE (more than 2^31-1 nonzero blocks or
+ * slots, or a row with more than 4096 blocks), FEA_ENOMEM, FEA_EHIP.
+ */
+int fea_graph_build(int64_t n_nodes, int64_t n_elems, const uint8_t *types,
+                    const int64_t *conn_ptr, const int32_t *conn, hipStream_t stream,
+                    fea_graph **out);
+
+/* Sizes: nodes (block rows), elements, nonzero blocks, slots (sum n_e^2),
+ * colours. Any output pointer may be NULL. */
+int fea_graph_sizes(const fea_graph *g, int64_t *n_nodes, int64_t *n_elems,
+                    int64_t *nnz_blocks, int64_t *map_len, int *n_colours);
+
+/* Copies graph arrays into caller-owned DEVICE buffers (any may be NULL):
+ * row_ptr[n_nodes+1], col[nnz], map_ptr[n_elems+1], e2nnz[map_len],
+ * inv_ptr[nnz+1], inv[map_len], colour[n_elems], type_perm[n_elems]
+ * (element ids sorted stably by type) and type_seg[5] (HOST array: segment
+ * offsets of the four families in type_perm). Enqueued on `stream`. */
+int fea_graph_export(const fea_graph *g, int64_t *row_ptr, int32_t *col, int64_t *map_ptr,
+                     int32_t *e2nnz, int64_t *inv_ptr, int32_t *inv, int16_t *colour,
+                     int32_t *type_perm, int64_t *type_seg, hipStream_t stream);
+
+void fea_graph_destroy(fea_graph *g);
+
+/*
+ * Assembles A (vals, nnz*b*b) and b (rhs, n_nodes*b), b = 1 for Poisson and
+ * 3 for elasticity, overwriting both (caller-owned device buffers of the
+ * element type opt->out_dtype). x, y, z: device FP64 node coordinates;
+ * types/conn_ptr/conn: the device arrays the graph was built from; source:
+ * device FP64 per-element constant source, b values per element.
+ * status (device int32, may be NULL) receives the smallest element id whose
+ * Jacobian determinant (or deformation-gradient determinant) is not
+ * positive at a Gauss point, or -1. Enqueued on `stream`; the first call
+ * with a given variant may allocate a workspace held by the graph.
+ * Errors: FEA_EINVAL (NULL pointer, bad option), FEA_ENOMEM, FEA_EHIP.
+ */
+int fea_assemble(const fea_graph *g, const double *x, const double *y, const double *z,
+                 const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
+                 const fea_material *mat, const double *source, const fea_options *opt,
+                 hipStream_t stream, void *vals, void *rhs, int32_t *status);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char *fea_last_error(void);
+
+/* Library version string. */
+const char *fea_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEA_H */

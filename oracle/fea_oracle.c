@@ -29,7 +29,8 @@
  *       AA_iJjL = mu d_ij d_JL + (mu - lam ln J) Finv_Jj Finv_Li + lam Finv_Ji Finv_Lj,
  *       K_(a,i)(b,j) = sum_q w detJ sum_JL dN_a/dX_J AA_iJjL dN_b/dX_L.
  * Alongside the values it assembles T, the same sums taken over the
- * absolute value of every product term; a computation in a lower precision
+ * absolute value of every product term (for the neo-Hookean tangent, of
+ * each of its three parts separately); a computation in a lower precision
  * with L roundings per chain must satisfy |v_low - v| <= gamma_L T.
  *
  * Sparsity pattern (compressed sparse rows of node blocks): row i holds
@@ -303,9 +304,12 @@ int or_element(int type, int model, int nh, const double *X, double young, doubl
                             double acc = 0.0, tac = 0.0;
                             for (J = 0; J < 3; ++J)
                                 for (L = 0; L < 3; ++L) {
-                                    double t = wd * G[a][J] * AA[i][J][j][L] * G[b][L];
-                                    acc += t;
-                                    tac += fabs(t);
+                                    double g2 = wd * G[a][J] * G[b][L];
+                                    acc += g2 * AA[i][J][j][L];
+                                    /* |terms|: the tangent's three parts separately */
+                                    tac += fabs(g2) * (mu * (i == j) * (J == L)
+                                                       + fabs((mu - lam * lnJ) * Fi[J][j] * Fi[L][i])
+                                                       + fabs(lam * Fi[J][i] * Fi[L][j]));
                                 }
                             Ke[((a * nn + b) * 3 + i) * 3 + j] += acc;
                             if (Tk) Tk[((a * nn + b) * 3 + i) * 3 + j] += tac;

@@ -1,0 +1,207 @@
+"""Python binding of libfea.so, the gfx950 finite-element assembly library.
+
+Argument marshalling only: every step of the graph build and the assembly
+runs in the library's HIP kernels. PyTorch (ROCm) supplies device memory and
+the stream. The C ABI is declared in include/fea.h.
+
+If libfea.so has not been built, importing this package raises ImportError:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfea.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                      f"g.build()'` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FEA_OK, FEA_EINVAL, FEA_EMESH, FEA_ENOMEM, FEA_EHIP, FEA_ERANGE = 0, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+ROWOWNER, ATOMIC, COLOUR, ROWGATHER = 0, 1, 2, 3
+F64, F32 = 0, 1
+POISSON, ELASTIC = 0, 1
+VARIANTS = {"rowowner": ROWOWNER, "atomic": ATOMIC, "colour": COLOUR, "rowgather": ROWGATHER}
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int),
+                ("out_dtype", ctypes.c_int)]
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int), ("young", _P), ("nu", _P), ("nh_flag", _P), ("u", _P)]
+
+
+_lib.fea_graph_build.argtypes = [_I64, _I64, _P, _P, _P, _P, ctypes.POINTER(_P)]
+_lib.fea_graph_build.restype = ctypes.c_int
+_lib.fea_graph_sizes.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                 ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int)]
+_lib.fea_graph_export.argtypes = [_P] * 9 + [ctypes.POINTER(_I64), _P]
+_lib.fea_graph_destroy.argtypes = [_P]
+_lib.fea_graph_destroy.restype = None
+_lib.fea_assemble.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Material), _P,
+                              ctypes.POINTER(Options), _P, _P, _P, _P]
+_lib.fea_last_error.restype = ctypes.c_char_p
+_lib.fea_version.restype = ctypes.c_char_p
+
+# every exported symbol declared in include/fea.h
+EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_export", "fea_graph_destroy",
+           "fea_assemble", "fea_last_error", "fea_version")
+
+
+class FeaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fea error {code}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+def _check(rc):
+    if rc != FEA_OK:
+        raise FeaError(rc, _lib.fea_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def version():
+    return _lib.fea_version().decode()
+
+
+def _dev(t, dtype):
+    assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
+    return t
+
+
+class Graph:
+    """Sparsity graph built on the GPU from device connectivity tensors."""
+
+    def __init__(self, n_nodes, types, conn_ptr, conn, stream=None):
+        _dev(types, torch.uint8)
+        _dev(conn_ptr, torch.int64)
+        _dev(conn, torch.int32)
+        h = _P()
+        _check(_lib.fea_graph_build(int(n_nodes), int(types.numel()), _ptr(types), _ptr(conn_ptr),
+                                    _ptr(conn), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.device = types.device
+        n, e, nnz, ml = _I64(), _I64(), _I64(), _I64()
+        nc = ctypes.c_int()
+        _check(_lib.fea_graph_sizes(h, ctypes.byref(n), ctypes.byref(e), ctypes.byref(nnz),
+                                    ctypes.byref(ml), ctypes.byref(nc)))
+        self.n_nodes, self.n_elems, self.nnz, self.map_len = n.value, e.value, nnz.value, ml.value
+        self.n_colours = nc.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph destroyed")
+        return self._h
+
+    def export(self, stream=None):
+        d = self.device
+        out = dict(
+            row_ptr=torch.empty(self.n_nodes + 1, dtype=torch.int64, device=d),
+            col=torch.empty(self.nnz, dtype=torch.int32, device=d),
+            map_ptr=torch.empty(self.n_elems + 1, dtype=torch.int64, device=d),
+            e2nnz=torch.empty(self.map_len, dtype=torch.int32, device=d),
+            inv_ptr=torch.empty(self.nnz + 1, dtype=torch.int64, device=d),
+            inv=torch.empty(self.map_len, dtype=torch.int32, device=d),
+            colour=torch.empty(self.n_elems, dtype=torch.int16, device=d),
+            type_perm=torch.empty(self.n_elems, dtype=torch.int32, device=d),
+        )
+        seg = (_I64 * 5)()
+        _check(_lib.fea_graph_export(self.handle, _ptr(out["row_ptr"]), _ptr(out["col"]),
+                                     _ptr(out["map_ptr"]), _ptr(out["e2nnz"]), _ptr(out["inv_ptr"]),
+                                     _ptr(out["inv"]), _ptr(out["colour"]), _ptr(out["type_perm"]),
+                                     seg, _stream(stream)))
+        out["type_seg"] = list(seg)
+        return out
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.fea_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def assemble(graph, x, y, z, types, conn_ptr, conn, source, model=ELASTIC, young=None, nu=None,
+             nh_flag=None, u=None, precision=FP64, variant=ROWOWNER, out_dtype=F64, vals=None,
+             rhs=None, status=None, stream=None):
+    """Assembles (vals, rhs, status) on the GPU; all tensors on the graph's device."""
+    B = 1 if model == POISSON else 3
+    odt = torch.float64 if out_dtype == F64 else torch.float32
+    d = graph.device
+    if isinstance(variant, str):
+        variant = VARIANTS[variant]
+    if vals is None:
+        vals = torch.empty(graph.nnz * B * B, dtype=odt, device=d)
+    if rhs is None:
+        rhs = torch.empty(graph.n_nodes * B, dtype=odt, device=d)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=d)
+    for t in (x, y, z, source):
+        _dev(t, torch.float64)
+    for t in (young, nu, u):
+        if t is not None:
+            _dev(t, torch.float64)
+    if nh_flag is not None:
+        _dev(nh_flag, torch.uint8)
+    _dev(vals, odt)
+    _dev(rhs, odt)
+    mat = Material(model, _ptr(young), _ptr(nu), _ptr(nh_flag), _ptr(u))
+    opt = Options(precision, variant, out_dtype)
+    _check(_lib.fea_assemble(graph.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(types), _ptr(conn_ptr),
+                             _ptr(conn), ctypes.byref(mat), _ptr(source), ctypes.byref(opt),
+                             _stream(stream), _ptr(vals), _ptr(rhs), _ptr(status)))
+    return vals, rhs, status
+
+
+class DeviceMesh:
+    """Device copies of a mesh's arrays (connectivity, coordinates, material)."""
+
+    FIELDS = ("x", "y", "z", "types", "conn_ptr", "conn", "young", "nu", "nh_flag", "u")
+
+    def __init__(self, mesh, device="cuda", dofs=3):
+        dev = torch.device(device)
+        self.n_nodes = mesh.n_nodes
+        self.n_elems = mesh.n_elems
+        for f in self.FIELDS:
+            setattr(self, f, torch.from_numpy(getattr(mesh, f)).to(dev).contiguous())
+        src = mesh.source[:, :dofs]
+        self.source = torch.from_numpy(src.copy()).to(dev).contiguous()
+
+    def graph(self, stream=None):
+        return Graph(self.n_nodes, self.types, self.conn_ptr, self.conn, stream=stream)
+
+    def assemble(self, graph, model=ELASTIC, use_nh=False, **kw):
+        src = self.source
+        if model == POISSON:
+            src = src[:, :1].contiguous()
+        return assemble(graph, self.x, self.y, self.z, self.types, self.conn_ptr, self.conn,
+                        src, model=model, young=self.young,
+                        nu=self.nu if model == ELASTIC else None,
+                        nh_flag=self.nh_flag if (use_nh and model == ELASTIC) else None,
+                        u=self.u if (use_nh and model == ELASTIC) else None, **kw)

@@ -1,0 +1,76 @@
+// Internal declarations of the gfx950 assembly library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fea.h"
+
+namespace fea {
+
+// Nodes per family: tet4, pyr5, pen6, hex8.
+__host__ __device__ inline int nodes_of(int t) { return 4 + t + (t == 3); }
+
+// Records a message for fea_last_error() and returns `code`.
+int set_error(int code, const char *fmt, ...);
+void clear_error();
+
+#define FEA_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::fea::set_error(FEA_EHIP, "%s failed: %s (%s:%d)", #call,          \
+                                    hipGetErrorString(e_), __FILE__, __LINE__);        \
+    } while (0)
+
+// Device allocation that records an error message on failure.
+int dalloc(void **p, size_t bytes);
+void dfree(void *p);
+
+// ptr[0] = 0, ptr[i+1] = in[0] + ... + in[i] for i < n (int64 result).
+// `tmp` must hold scan_tmp_elems(n) int64 values.
+int64_t scan_tmp_elems(int64_t n);
+int scan_to_ptr_u8(const uint8_t *in, int64_t n, int64_t *ptr, int64_t *tmp, hipStream_t s);
+int scan_to_ptr_i32(const int32_t *in, int64_t n, int64_t *ptr, int64_t *tmp, hipStream_t s);
+int scan_to_ptr_i64(const int64_t *in, int64_t n, int64_t *ptr, int64_t *tmp, hipStream_t s);
+
+// Grid size for a 1-D launch of n threads in blocks of `bs`.
+inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace fea
+
+// The graph object behind the opaque fea_graph handle.
+struct fea_graph {
+    int device = 0;
+    int64_t n_nodes = 0, n_elems = 0, nnz = 0, map_len = 0, conn_len = 0;
+    int n_colours = 0;
+    // block pattern, element-to-nonzero map and its inverse
+    int64_t *row_ptr = nullptr;
+    int32_t *col = nullptr;
+    int64_t *map_ptr = nullptr;
+    int32_t *e2nnz = nullptr;
+    int64_t *inv_ptr = nullptr;
+    int32_t *inv = nullptr;
+    // node -> incident elements (ascending element id) and local index
+    int64_t *n2e_ptr = nullptr;
+    int32_t *n2e = nullptr;
+    uint8_t *n2a = nullptr;
+    // elements stably sorted by family; seg[t]..seg[t+1] in perm (host copy)
+    int32_t *perm = nullptr;
+    int64_t seg[5] = {0, 0, 0, 0, 0};
+    // greedy colouring and (family, colour) buckets, cseg host copy:
+    // bucket (t, c) = cperm[cseg[t*(n_colours+1)+c] .. cseg[t*(n_colours+1)+c+1])
+    int16_t *colour = nullptr;
+    int32_t *cperm = nullptr;
+    std::vector<int64_t> cseg;
+    // lazily allocated workspaces of the scatter variants
+    void *contrib = nullptr;
+    size_t contrib_bytes = 0;
+    void *rcontrib = nullptr;
+    size_t rcontrib_bytes = 0;
+    double *acc64 = nullptr;
+    size_t acc64_bytes = 0;
+};

@@ -1,0 +1,441 @@
+// Graph build: mesh validation, type segmentation, node incidence, block
+// sparsity pattern, element-to-nonzero map, inverse map and greedy colouring.
+//
+// Definitions (paper Section 2.1.1, Algorithm 1; Section 3.2, Algorithm 5):
+// a block (i, j) exists when nodes i and j share an element; e2nnz maps the
+// element-matrix slot (e, a, b) to the block of (conn[e][a], conn[e][b]);
+// the inverse map lists each block's slots in ascending element order;
+// elements of one colour share no node.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+
+#include "fea_internal.h"
+
+namespace fea {
+
+// ------------------------------------------------------------ validation
+__global__ void k_validate(int64_t n_nodes, int64_t n_elems, const uint8_t *types,
+                           const int64_t *conn_ptr, const int32_t *conn, int64_t *bad)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_elems) return;
+    int t = types[e];
+    bool ok = t < 4;
+    int nn = ok ? nodes_of(t) : 0;
+    int64_t b = conn_ptr[e];
+    ok = ok && (conn_ptr[e + 1] - b == nn) && b >= 0 && (e > 0 || b == 0);
+    if (ok) {
+        for (int a = 0; a < nn && ok; ++a) {
+            int32_t v = conn[b + a];
+            ok = v >= 0 && v < n_nodes;
+            for (int c = 0; c < a && ok; ++c) ok = conn[b + c] != v;
+        }
+    }
+    if (!ok) atomicMin((unsigned long long *)bad, (unsigned long long)e);
+}
+
+__global__ void k_slot_count(int64_t n_elems, const uint8_t *types, int64_t *cnt)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_elems) return;
+    int nn = nodes_of(types[e]);
+    cnt[e] = (int64_t)nn * nn;
+}
+
+// ------------------------------------------------------ type segmentation
+__global__ void k_type_flags(int64_t n_elems, const uint8_t *types, int t, uint8_t *flag)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n_elems) flag[e] = types[e] == t;
+}
+
+__global__ void k_type_place(int64_t n_elems, const uint8_t *types, int t, const int64_t *pos,
+                             int64_t base, int32_t *perm)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n_elems && types[e] == t) perm[base + pos[e]] = (int32_t)e;
+}
+
+// --------------------------------------------------------- node incidence
+__global__ void k_node_count(int64_t conn_len, const int32_t *conn, int32_t *cnt)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < conn_len) atomicAdd(&cnt[conn[p]], 1);
+}
+
+__global__ void k_node_fill(int64_t n_elems, const int64_t *conn_ptr, const int32_t *conn,
+                            const int64_t *n2e_ptr, int32_t *cursor, int32_t *n2e, uint8_t *n2a)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_elems) return;
+    for (int64_t p = conn_ptr[e]; p < conn_ptr[e + 1]; ++p) {
+        int32_t v = conn[p];
+        int32_t slot = atomicAdd(&cursor[v], 1);
+        n2e[n2e_ptr[v] + slot] = (int32_t)e;
+        n2a[n2e_ptr[v] + slot] = (uint8_t)(p - conn_ptr[e]);
+    }
+}
+
+// Insertion sort of each node's (element, local index) list by element.
+__global__ void k_node_sort(int64_t n_nodes, const int64_t *n2e_ptr, int32_t *n2e, uint8_t *n2a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    int64_t b = n2e_ptr[i], e = n2e_ptr[i + 1];
+    for (int64_t p = b + 1; p < e; ++p) {
+        int32_t ke = n2e[p];
+        uint8_t ka = n2a[p];
+        int64_t q = p - 1;
+        while (q >= b && n2e[q] > ke) {
+            n2e[q + 1] = n2e[q];
+            n2a[q + 1] = n2a[q];
+            --q;
+        }
+        n2e[q + 1] = ke;
+        n2a[q + 1] = ka;
+    }
+}
+
+// ------------------------------------------------------------- row pattern
+// Row i's columns are the distinct nodes of i's incident elements. They are
+// produced in ascending order by repeatedly taking the smallest candidate
+// above the last one emitted: no per-row buffer, so any row length works.
+__global__ void k_row_pattern(int64_t n_nodes, const int64_t *n2e_ptr, const int32_t *n2e,
+                              const int64_t *conn_ptr, const int32_t *conn,
+                              const int64_t *row_ptr, int32_t *col, int32_t *deg)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    int64_t b = n2e_ptr[i], e = n2e_ptr[i + 1];
+    int32_t last = -1;
+    int32_t cnt = 0;
+    int64_t out = col ? row_ptr[i] : 0;
+    for (;;) {
+        int32_t best = INT_MAX;
+        for (int64_t p = b; p < e; ++p) {
+            int32_t el = n2e[p];
+            for (int64_t k = conn_ptr[el]; k < conn_ptr[el + 1]; ++k) {
+                int32_t v = conn[k];
+                if (v > last && v < best) best = v;
+            }
+        }
+        if (best == INT_MAX) break;
+        if (col) col[out + cnt] = best;
+        ++cnt;
+        last = best;
+    }
+    if (deg) deg[i] = cnt;
+}
+
+// e2nnz by binary search of conn[e][b] in row conn[e][a].
+__global__ void k_e2nnz(int64_t n_elems, const int64_t *conn_ptr, const int32_t *conn,
+                        const int64_t *row_ptr, const int32_t *col, const int64_t *map_ptr,
+                        int32_t *e2nnz)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_elems) return;
+    int64_t cb = conn_ptr[e];
+    int nn = (int)(conn_ptr[e + 1] - cb);
+    int64_t mb = map_ptr[e];
+    for (int a = 0; a < nn; ++a) {
+        int32_t r = conn[cb + a];
+        int64_t rb = row_ptr[r], re = row_ptr[r + 1];
+        for (int b = 0; b < nn; ++b) {
+            int32_t c = conn[cb + b];
+            int64_t lo = rb, hi = re - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (col[mid] < c) lo = mid + 1; else hi = mid;
+            }
+            e2nnz[mb + a * nn + b] = (int32_t)lo;
+        }
+    }
+}
+
+__global__ void k_inv_count(int64_t map_len, const int32_t *e2nnz, int32_t *cnt)
+{
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < map_len) atomicAdd(&cnt[e2nnz[s]], 1);
+}
+
+// Row i's thread owns the blocks of row i, so the per-block fill counters
+// need no atomics, and walking i's elements in ascending order lists every
+// block's slots in ascending element order.
+__global__ void k_inv_fill(int64_t n_nodes, const int64_t *n2e_ptr, const int32_t *n2e,
+                           const uint8_t *n2a, const int64_t *conn_ptr, const int64_t *map_ptr,
+                           const int32_t *e2nnz, const int64_t *inv_ptr, int32_t *fill,
+                           int32_t *inv)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    for (int64_t p = n2e_ptr[i]; p < n2e_ptr[i + 1]; ++p) {
+        int32_t e = n2e[p];
+        int a = n2a[p];
+        int nn = (int)(conn_ptr[e + 1] - conn_ptr[e]);
+        int64_t base = map_ptr[e] + (int64_t)a * nn;
+        for (int b = 0; b < nn; ++b) {
+            int64_t s = base + b;
+            int32_t k = e2nnz[s];
+            inv[inv_ptr[k] + fill[k]] = (int32_t)s;
+            fill[k] += 1;
+        }
+    }
+}
+
+// ------------------------------------------------------------- colouring
+// Greedy first-fit in element order (the colouring of Algorithm 5; any
+// valid colouring is correct, this one is deterministic). Sequential by
+// definition, so it runs on the host over per-node masks of used colours.
+static int colour_host(fea_graph *g, const int64_t *conn_ptr_d, const int32_t *conn_d,
+                       const uint8_t *types_d, hipStream_t s)
+{
+    const int64_t E = g->n_elems, N = g->n_nodes;
+    std::vector<int64_t> cp(E + 1);
+    std::vector<int32_t> cn(g->conn_len);
+    std::vector<uint8_t> ty(E);
+    FEA_HIP(hipMemcpyAsync(cp.data(), conn_ptr_d, sizeof(int64_t) * (E + 1), hipMemcpyDeviceToHost, s));
+    if (g->conn_len)
+        FEA_HIP(hipMemcpyAsync(cn.data(), conn_d, sizeof(int32_t) * g->conn_len, hipMemcpyDeviceToHost, s));
+    if (E) FEA_HIP(hipMemcpyAsync(ty.data(), types_d, E, hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    constexpr int kWords = 4;  // up to 256 colours
+    std::vector<uint64_t> used((size_t)N * kWords, 0);
+    std::vector<int16_t> colour(E);
+    int ncol = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        uint64_t m[kWords] = {0, 0, 0, 0};
+        for (int64_t p = cp[e]; p < cp[e + 1]; ++p)
+            for (int w = 0; w < kWords; ++w) m[w] |= used[(size_t)cn[p] * kWords + w];
+        int c = -1;
+        for (int w = 0; w < kWords && c < 0; ++w)
+            if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
+        if (c < 0) return set_error(FEA_ERANGE, "element %lld needs more than 256 colours", (long long)e);
+        colour[e] = (int16_t)c;
+        ncol = std::max(ncol, c + 1);
+        for (int64_t p = cp[e]; p < cp[e + 1]; ++p)
+            used[(size_t)cn[p] * kWords + c / 64] |= 1ull << (c % 64);
+    }
+    // stable buckets by (family, colour)
+    std::vector<int64_t> cseg((size_t)4 * (ncol + 1), 0);
+    for (int64_t e = 0; e < E; ++e) cseg[(size_t)ty[e] * (ncol + 1) + colour[e] + 1]++;
+    int64_t run = 0;
+    for (int t = 0; t < 4; ++t)
+        for (int c = 0; c <= ncol; ++c) {
+            int64_t &v = cseg[(size_t)t * (ncol + 1) + c];
+            if (c == 0) { v = run; continue; }
+            run += v;
+            v = run;
+        }
+    std::vector<int64_t> cur(cseg);
+    std::vector<int32_t> cperm(E);
+    for (int64_t e = 0; e < E; ++e) cperm[cur[(size_t)ty[e] * (ncol + 1) + colour[e]]++] = (int32_t)e;
+    int rc;
+    if ((rc = dalloc((void **)&g->colour, sizeof(int16_t) * std::max<int64_t>(E, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->cperm, sizeof(int32_t) * std::max<int64_t>(E, 1)))) return rc;
+    if (E) {
+        FEA_HIP(hipMemcpyAsync(g->colour, colour.data(), sizeof(int16_t) * E, hipMemcpyHostToDevice, s));
+        FEA_HIP(hipMemcpyAsync(g->cperm, cperm.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice, s));
+    }
+    FEA_HIP(hipStreamSynchronize(s));
+    g->n_colours = ncol;
+    g->cseg = std::move(cseg);
+    return FEA_OK;
+}
+
+static void destroy(fea_graph *g)
+{
+    if (!g) return;
+    void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv,
+                    g->n2e_ptr, g->n2e, g->n2a, g->perm, g->colour, g->cperm,
+                    g->contrib, g->rcontrib, g->acc64};
+    for (void *b : bufs) dfree(b);
+    delete g;
+}
+
+struct TmpBuf {
+    void *p = nullptr;
+    ~TmpBuf() { dfree(p); }
+};
+
+static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn_ptr,
+                 const int32_t *conn, hipStream_t s, fea_graph *g)
+{
+    const int BS = 256;
+    int rc;
+    FEA_HIP(hipGetDevice(&g->device));
+    g->n_nodes = N;
+    g->n_elems = E;
+    if (E > 0)
+        FEA_HIP(hipMemcpyAsync(&g->conn_len, conn_ptr + E, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+
+    // validation
+    TmpBuf bad, tmp, cnt64, cnt32, flag, fillb;
+    if ((rc = dalloc(&bad.p, sizeof(int64_t)))) return rc;
+    int64_t big = INT64_MAX;
+    FEA_HIP(hipMemcpyAsync(bad.p, &big, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (E) k_validate<<<grid_for(E, BS), BS, 0, s>>>(N, E, types, conn_ptr, conn, (int64_t *)bad.p);
+    FEA_HIP(hipGetLastError());
+    int64_t first_bad = INT64_MAX;
+    FEA_HIP(hipMemcpyAsync(&first_bad, bad.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    if (first_bad != INT64_MAX)
+        return set_error(FEA_EMESH, "invalid element %lld (unknown type, wrong node count, node id out "
+                         "of range or repeated node)", (long long)first_bad);
+
+    int64_t scan_n = std::max<int64_t>(std::max<int64_t>(E, N), g->conn_len);
+    // slots: map_ptr = prefix sum of n_e^2
+    if ((rc = dalloc(&tmp.p, sizeof(int64_t) * (scan_tmp_elems(scan_n) + 64)))) return rc;
+    if ((rc = dalloc(&cnt64.p, sizeof(int64_t) * std::max<int64_t>(E, N) + 8))) return rc;
+    if ((rc = dalloc((void **)&g->map_ptr, sizeof(int64_t) * (E + 1)))) return rc;
+    if (E) k_slot_count<<<grid_for(E, BS), BS, 0, s>>>(E, types, (int64_t *)cnt64.p);
+    if ((rc = scan_to_ptr_i64((int64_t *)cnt64.p, E, g->map_ptr, (int64_t *)tmp.p, s))) return rc;
+    FEA_HIP(hipMemcpyAsync(&g->map_len, g->map_ptr + E, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    if (g->map_len > INT32_MAX)
+        return set_error(FEA_ERANGE, "%lld element-matrix slots exceed the int32 inverse map",
+                         (long long)g->map_len);
+
+    // type segmentation (stable partition by family)
+    if ((rc = dalloc(&flag.p, std::max<int64_t>(E, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->perm, sizeof(int32_t) * std::max<int64_t>(E, 1)))) return rc;
+    {
+        int64_t base = 0;
+        for (int t = 0; t < 4; ++t) {
+            g->seg[t] = base;
+            if (!E) continue;
+            k_type_flags<<<grid_for(E, BS), BS, 0, s>>>(E, types, t, (uint8_t *)flag.p);
+            if ((rc = scan_to_ptr_u8((uint8_t *)flag.p, E, (int64_t *)cnt64.p, (int64_t *)tmp.p, s))) return rc;
+            k_type_place<<<grid_for(E, BS), BS, 0, s>>>(E, types, t, (int64_t *)cnt64.p, base, g->perm);
+            int64_t cnt_t = 0;
+            FEA_HIP(hipMemcpyAsync(&cnt_t, (int64_t *)cnt64.p + E, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            FEA_HIP(hipStreamSynchronize(s));
+            base += cnt_t;
+        }
+        g->seg[4] = base;
+    }
+
+    // node incidence
+    if ((rc = dalloc(&cnt32.p, sizeof(int32_t) * (N + 1)))) return rc;
+    if ((rc = dalloc((void **)&g->n2e_ptr, sizeof(int64_t) * (N + 1)))) return rc;
+    if ((rc = dalloc((void **)&g->n2e, sizeof(int32_t) * std::max<int64_t>(g->conn_len, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->n2a, std::max<int64_t>(g->conn_len, 1)))) return rc;
+    FEA_HIP(hipMemsetAsync(cnt32.p, 0, sizeof(int32_t) * (N + 1), s));
+    if (g->conn_len) k_node_count<<<grid_for(g->conn_len, BS), BS, 0, s>>>(g->conn_len, conn, (int32_t *)cnt32.p);
+    if ((rc = scan_to_ptr_i32((int32_t *)cnt32.p, N, g->n2e_ptr, (int64_t *)tmp.p, s))) return rc;
+    FEA_HIP(hipMemsetAsync(cnt32.p, 0, sizeof(int32_t) * (N + 1), s));
+    if (E) k_node_fill<<<grid_for(E, BS), BS, 0, s>>>(E, conn_ptr, conn, g->n2e_ptr, (int32_t *)cnt32.p, g->n2e, g->n2a);
+    if (N) k_node_sort<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, g->n2a);
+    FEA_HIP(hipGetLastError());
+
+    // row pattern: degrees, prefix sum, columns
+    if ((rc = dalloc((void **)&g->row_ptr, sizeof(int64_t) * (N + 1)))) return rc;
+    if (N) k_row_pattern<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, conn_ptr, conn, nullptr, nullptr, (int32_t *)cnt32.p);
+    if ((rc = scan_to_ptr_i32((int32_t *)cnt32.p, N, g->row_ptr, (int64_t *)tmp.p, s))) return rc;
+    FEA_HIP(hipMemcpyAsync(&g->nnz, g->row_ptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    if (g->nnz > INT32_MAX)
+        return set_error(FEA_ERANGE, "%lld nonzero blocks exceed int32 block indices", (long long)g->nnz);
+    if ((rc = dalloc((void **)&g->col, sizeof(int32_t) * std::max<int64_t>(g->nnz, 1)))) return rc;
+    if (N) k_row_pattern<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, conn_ptr, conn, g->row_ptr, g->col, nullptr);
+    FEA_HIP(hipGetLastError());
+
+    // element -> nonzero map
+    if ((rc = dalloc((void **)&g->e2nnz, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
+    if (E) k_e2nnz<<<grid_for(E, BS), BS, 0, s>>>(E, conn_ptr, conn, g->row_ptr, g->col, g->map_ptr, g->e2nnz);
+
+    // inverse map
+    if ((rc = dalloc(&fillb.p, sizeof(int32_t) * (g->nnz + 1)))) return rc;
+    if ((rc = dalloc((void **)&g->inv_ptr, sizeof(int64_t) * (g->nnz + 1)))) return rc;
+    if ((rc = dalloc((void **)&g->inv, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
+    FEA_HIP(hipMemsetAsync(fillb.p, 0, sizeof(int32_t) * (g->nnz + 1), s));
+    if (g->nnz > scan_n) {  // the block-count scan runs over nnz entries
+        FEA_HIP(hipStreamSynchronize(s));
+        dfree(tmp.p);
+        tmp.p = nullptr;
+        if ((rc = dalloc(&tmp.p, sizeof(int64_t) * (scan_tmp_elems(g->nnz) + 64)))) return rc;
+    }
+    if (g->map_len) k_inv_count<<<grid_for(g->map_len, BS), BS, 0, s>>>(g->map_len, g->e2nnz, (int32_t *)fillb.p);
+    if ((rc = scan_to_ptr_i32((int32_t *)fillb.p, g->nnz, g->inv_ptr, (int64_t *)tmp.p, s))) return rc;
+    FEA_HIP(hipMemsetAsync(fillb.p, 0, sizeof(int32_t) * (g->nnz + 1), s));
+    if (N) k_inv_fill<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, g->n2a, conn_ptr, g->map_ptr, g->e2nnz, g->inv_ptr, (int32_t *)fillb.p, g->inv);
+    FEA_HIP(hipGetLastError());
+
+    if ((rc = colour_host(g, conn_ptr, conn, types, s))) return rc;
+    FEA_HIP(hipStreamSynchronize(s));
+    return FEA_OK;
+}
+
+}  // namespace fea
+
+using namespace fea;
+
+extern "C" int fea_graph_build(int64_t n_nodes, int64_t n_elems, const uint8_t *types,
+                               const int64_t *conn_ptr, const int32_t *conn, hipStream_t stream,
+                               fea_graph **out)
+{
+    clear_error();
+    if (!out) return set_error(FEA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_nodes < 0 || n_elems < 0) return set_error(FEA_EINVAL, "negative size");
+    if (n_elems > 0 && (!types || !conn_ptr || !conn))
+        return set_error(FEA_EINVAL, "types, conn_ptr and conn are required");
+    if (n_nodes > INT32_MAX || n_elems > INT32_MAX)
+        return set_error(FEA_ERANGE, "more than 2^31-1 nodes or elements");
+    fea_graph *g = new (std::nothrow) fea_graph();
+    if (!g) return set_error(FEA_ENOMEM, "host allocation failed");
+    int rc = build(n_nodes, n_elems, types, conn_ptr, conn, stream, g);
+    if (rc != FEA_OK) {
+        (void)hipStreamSynchronize(stream);
+        destroy(g);
+        return rc;
+    }
+    *out = g;
+    return FEA_OK;
+}
+
+extern "C" int fea_graph_sizes(const fea_graph *g, int64_t *n_nodes, int64_t *n_elems,
+                               int64_t *nnz_blocks, int64_t *map_len, int *n_colours)
+{
+    clear_error();
+    if (!g) return set_error(FEA_EINVAL, "graph is NULL");
+    if (n_nodes) *n_nodes = g->n_nodes;
+    if (n_elems) *n_elems = g->n_elems;
+    if (nnz_blocks) *nnz_blocks = g->nnz;
+    if (map_len) *map_len = g->map_len;
+    if (n_colours) *n_colours = g->n_colours;
+    return FEA_OK;
+}
+
+extern "C" int fea_graph_export(const fea_graph *g, int64_t *row_ptr, int32_t *col,
+                                int64_t *map_ptr, int32_t *e2nnz, int64_t *inv_ptr, int32_t *inv,
+                                int16_t *colour, int32_t *type_perm, int64_t *type_seg,
+                                hipStream_t s)
+{
+    clear_error();
+    if (!g) return set_error(FEA_EINVAL, "graph is NULL");
+    const hipMemcpyKind D2D = hipMemcpyDeviceToDevice;
+    if (row_ptr) FEA_HIP(hipMemcpyAsync(row_ptr, g->row_ptr, sizeof(int64_t) * (g->n_nodes + 1), D2D, s));
+    if (col && g->nnz) FEA_HIP(hipMemcpyAsync(col, g->col, sizeof(int32_t) * g->nnz, D2D, s));
+    if (map_ptr) FEA_HIP(hipMemcpyAsync(map_ptr, g->map_ptr, sizeof(int64_t) * (g->n_elems + 1), D2D, s));
+    if (e2nnz && g->map_len) FEA_HIP(hipMemcpyAsync(e2nnz, g->e2nnz, sizeof(int32_t) * g->map_len, D2D, s));
+    if (inv_ptr) FEA_HIP(hipMemcpyAsync(inv_ptr, g->inv_ptr, sizeof(int64_t) * (g->nnz + 1), D2D, s));
+    if (inv && g->map_len) FEA_HIP(hipMemcpyAsync(inv, g->inv, sizeof(int32_t) * g->map_len, D2D, s));
+    if (colour && g->n_elems) FEA_HIP(hipMemcpyAsync(colour, g->colour, sizeof(int16_t) * g->n_elems, D2D, s));
+    if (type_perm && g->n_elems) FEA_HIP(hipMemcpyAsync(type_perm, g->perm, sizeof(int32_t) * g->n_elems, D2D, s));
+    if (type_seg) memcpy(type_seg, g->seg, sizeof(g->seg));
+    return FEA_OK;
+}
+
+extern "C" void fea_graph_destroy(fea_graph *g)
+{
+    if (g) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(g->device);
+        (void)hipDeviceSynchronize();
+        destroy(g);
+        (void)hipSetDevice(cur);
+    }
+}

@@ -1,0 +1,187 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import meshgen as mg
+import oracle
+from tests.helpers import fp32_bound_L, fp64_errors, row_scale, within_fp32_bound
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1805_03949_amd as fea  # noqa: E402
+
+HEX8 = mg.HEX8
+
+
+def _mesh(name):
+    if name == "poisson_hex16":
+        return mg.poisson_hex(16, jitter=0.2, seed=1)
+    if name == "bands8_jitter":
+        return mg.hybrid_bands(8, seed=21, jitter=0.2)
+    if name == "mix6_jitter":
+        ct = np.random.default_rng(22).integers(0, 4, 6 ** 3).astype(np.uint8)
+        return mg.cube_mesh(6, ct, jitter=0.25, seed=23)
+    if name == "hetero16":
+        return mg.heterogeneous(16, seed=24, brick=4, jitter=0.1)
+    if name == "tet_ragged":
+        # 5^3 cells of tetrahedra: 750 elements, not a multiple of any tile
+        return mg.cube_mesh(5, np.full(125, mg.TET4, dtype=np.uint8), jitter=0.2, seed=25)
+    raise KeyError(name)
+
+
+def _with_x_source(m):
+    m.source[:, 0] = 0.5          # nonzero first component for Poisson rhs checks
+    return m
+
+
+MESHES = ["poisson_hex16", "bands8_jitter", "mix6_jitter", "hetero16", "tet_ragged"]
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        m = _mesh(name)
+        if m.source.shape[1] == 3:
+            _with_x_source(m)
+        print(f"[case] {name}: E={m.n_elems} N={m.n_nodes}", flush=True)
+        og = oracle.mesh_graph(m)
+        dm = fea.DeviceMesh(m, device="cuda:0")
+        g = dm.graph()
+        _cache[name] = (m, og, dm, g)
+    return _cache[name]
+
+
+def _oracle_assembly(name, model, use_nh):
+    key = (name, model, use_nh)
+    if key not in _cache:
+        m, og, _, _ = case(name)
+        _cache[key] = oracle.assemble(m, og, model=model, with_terms=True, use_nh=use_nh)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("name", MESHES)
+def test_graph_bit_exact(name):
+    m, og, dm, g = case(name)
+    ex = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in g.export().items()}
+    assert g.nnz == og.nnz and g.map_len == og.e2nnz.size
+    for k in ("row_ptr", "col", "map_ptr", "e2nnz", "inv_ptr", "inv"):
+        assert np.array_equal(ex[k], getattr(og, k)), k
+    # type segmentation: stable sort of element ids by family
+    exp = np.argsort(m.types, kind="stable").astype(np.int32)
+    assert np.array_equal(ex["type_perm"], exp)
+    seg = np.concatenate([[0], np.cumsum(np.bincount(m.types, minlength=4))])
+    assert list(ex["type_seg"]) == list(seg)
+    # greedy first-fit colouring in element order is unique: equal to the oracle's
+    oc, nc = oracle.colour_greedy(m.n_nodes, m.conn_ptr, m.conn)
+    assert g.n_colours == nc
+    assert np.array_equal(ex["colour"], oc)
+
+
+VARIANTS = [fea.ROWOWNER, fea.ATOMIC, fea.COLOUR]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("name", MESHES)
+def test_fp64_parity(name, variant):
+    m, og, dm, g = case(name)
+    models = [oracle.POISSON] if name == "poisson_hex16" else [oracle.POISSON, oracle.ELASTIC]
+    for model in models:
+        use_nh = name == "hetero16" and model == oracle.ELASTIC
+        ov, orr, _, _ = _oracle_assembly(name, model, use_nh)
+        vals, rhs, st = dm.assemble(g, model=model, use_nh=use_nh, variant=variant)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -1
+        B = 1 if model == oracle.POISSON else 3
+        ev, er = fp64_errors(vals.cpu().numpy(), ov, og.row_ptr, B, rhs.cpu().numpy(), orr)
+        assert ev <= 1e-12 and er <= 1e-12, (model, ev, er)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("name", MESHES)
+def test_mixed_within_fp32_bound(name, variant):
+    m, og, dm, g = case(name)
+    model = oracle.POISSON if name == "poisson_hex16" else oracle.ELASTIC
+    use_nh = name == "hetero16"
+    ov, orr, tv, tr = _oracle_assembly(name, model, use_nh)
+    L = fp32_bound_L(m.types)
+    B = 1 if model == oracle.POISSON else 3
+    floor_v = 1e-12 * row_scale(ov, og.row_ptr, B)
+    floor_r = 1e-12 * np.abs(orr).max()
+    for out in (fea.F64, fea.F32):
+        vals, rhs, st = dm.assemble(g, model=model, use_nh=use_nh, variant=variant,
+                                    precision=fea.MIXED, out_dtype=out)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -1
+        rv = within_fp32_bound(vals.cpu().numpy(), ov, tv, L, floor_v)
+        rr = within_fp32_bound(rhs.cpu().numpy(), orr, tr, L, floor_r)
+        assert rv <= 1.0 and rr <= 1.0, (out, rv, rr)
+
+
+@pytest.mark.parametrize("variant", [fea.ROWOWNER, fea.COLOUR])
+def test_deterministic_variants_bitwise_repeatable(variant):
+    m, og, dm, g = case("mix6_jitter")
+    first = None
+    for _ in range(5):
+        vals, rhs, _ = dm.assemble(g, model=fea.ELASTIC, variant=variant)
+        cur = (vals.cpu().numpy().tobytes(), rhs.cpu().numpy().tobytes())
+        if first is None:
+            first = cur
+        assert cur == first
+
+
+def test_inverted_element_sets_status():
+    m = mg.cube_mesh(3, np.full(27, mg.TET4, dtype=np.uint8))
+    e = 37
+    c = m.conn.copy()
+    c[m.conn_ptr[e] + 1], c[m.conn_ptr[e] + 2] = c[m.conn_ptr[e] + 2], c[m.conn_ptr[e] + 1]
+    m.conn = c
+    dm = fea.DeviceMesh(m)
+    g = dm.graph()
+    for variant in VARIANTS:
+        _, _, st = dm.assemble(g, model=fea.ELASTIC, variant=variant)
+        torch.cuda.synchronize()
+        assert int(st.item()) == e
+
+
+def test_bad_mesh_is_rejected_with_element_id():
+    m = mg.hybrid_bands(4, seed=3)
+    c = m.conn.copy()
+    e = 11
+    c[m.conn_ptr[e] + 2] = c[m.conn_ptr[e]]
+    m.conn = c
+    dm = fea.DeviceMesh(m)
+    with pytest.raises(fea.FeaError) as ei:
+        dm.graph()
+    assert ei.value.code == fea.FEA_EMESH and "element 11 " in ei.value.msg
+    m2 = mg.hybrid_bands(4, seed=3)
+    m2.types = m2.types.copy()
+    m2.types[5] = 7
+    with pytest.raises(fea.FeaError) as ei:
+        fea.DeviceMesh(m2).graph()
+    assert "element 5 " in ei.value.msg
+
+
+def test_empty_mesh():
+    d = "cuda:0"
+    types = torch.empty(0, dtype=torch.uint8, device=d)
+    cp = torch.zeros(1, dtype=torch.int64, device=d)
+    conn = torch.empty(0, dtype=torch.int32, device=d)
+    g = fea.Graph(10, types, cp, conn)
+    assert g.nnz == 0 and g.map_len == 0
+    x = torch.zeros(10, dtype=torch.float64, device=d)
+    vals, rhs, st = fea.assemble(g, x, x, x, types, cp, conn,
+                                 torch.empty(0, dtype=torch.float64, device=d),
+                                 model=fea.POISSON)
+    torch.cuda.synchronize()
+    assert vals.numel() == 0 and int(st.item()) == -1
+
+
+def test_bad_option_is_rejected():
+    m, og, dm, g = case("tet_ragged")
+    with pytest.raises(fea.FeaError) as ei:
+        dm.assemble(g, model=fea.ELASTIC, variant=7)
+    assert ei.value.code == fea.FEA_EINVAL
