@@ -1,0 +1,211 @@
+"""Benchmark: finite-element assembly on one MI355X.
+
+A step is one fea_assemble call over the whole workload (element quadrature
+for every element plus the race-free scatter into the 3x3 block matrix and
+the right-hand side), with the mesh, graph and outputs resident in HBM.
+The graph build is timed once and reported separately.
+
+Workload (default): linear elasticity on a 96^3-cell hybrid mesh, four
+z-bands of 24 cell layers (hex8 / pen6 / tet4 / pyr5), E = 1, nu per element
+U[0.2, 0.35], body force (0, 0, -1); 3,317,760 elements, 1,133,857 nodes.
+
+Prints one JSON line. Usage:
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--variant rowowner]
+                  [--precision fp64|mixed] [--no-cpu] [--no-variants]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "elements assembled/s + scatter HBM GB/s (% peak); learned+mixed vs plain FP64"
+
+
+def scatter_bytes(g, B, s_c, s_v, conn_len, n_nodes):
+    """Algorithmic bytes of the row-owner second phase: every contribution,
+    its inverse-map entry and each block's range read once, every output
+    value written once; the right-hand side likewise through the node
+    incidence (element id, local index and that element's conn offset)."""
+    return (g.map_len * (B * B * s_c + 4) + (g.nnz + 1) * 8 + g.nnz * B * B * s_v
+            + conn_len * (B * s_c + 4 + 1 + 8) + (n_nodes + 1) * 8 + n_nodes * B * s_v)
+
+
+def element_bytes(g, B, s_c, conn_len, n_nodes, n_elems, variant):
+    """Algorithmic bytes of the element phase: node coordinates once, the
+    connectivity and per-element data once, and its outputs once (the slot
+    contributions for row-owner)."""
+    inputs = n_nodes * 24 + conn_len * 4 + n_elems * (8 + 4 + 8 + 16 + 8 * B)
+    if variant == "rowowner":
+        return inputs + g.map_len * B * B * s_c + conn_len * B * s_c
+    return inputs + g.map_len * 4 + g.nnz * B * B * 8 * 2 + n_nodes * B * 8 * 2
+
+
+def traffic_from_profile(kernel_key):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    names this kernel and matches the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1805_03949_amd", "csrc", "assemble.hip"), "rb").read()
+    digest = hashlib.sha256(src).hexdigest()[:16]
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("source_sha256_16") != digest:
+        return None
+    v = rec.get(f"{kernel_key}_bytes")
+    return float(v) if v else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cells", type=int, default=96)
+    ap.add_argument("--variant", default="rowowner")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(assembly shards across GPUs without communication; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import meshgen as mg
+    import paper_1805_03949_amd as fea
+
+    t0 = time.time()
+    mesh = mg.hybrid_bands(args.cells, seed=2)
+    print(f"[bench] mesh {mesh.n_elems} elements in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    dm = fea.DeviceMesh(mesh, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = dm.graph()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3
+
+    prec = fea.FP64 if args.precision == "fp64" else fea.MIXED
+    outd = fea.F64 if prec == fea.FP64 else fea.F32
+    var = fea.VARIANTS[args.variant]
+    B = 3
+    s_c = 8 if prec == fea.FP64 else 4
+    s_v = 8 if outd == fea.F64 else 4
+    conn_len = int(mesh.conn_ptr[-1])
+
+    vals, rhs, st = dm.assemble(g, variant=var, precision=prec, out_dtype=outd)
+
+    def step(timing=False):
+        dm.assemble(g, variant=var, precision=prec, out_dtype=outd, vals=vals, rhs=rhs, status=st,
+                    timing=timing)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert int(st.item()) == -1, "an element was rejected"
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    print(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # phase durations from HIP events recorded by the library on its stream
+    phases = []
+    for _ in range(max(5, min(args.steps, 20))):
+        step(timing=True)
+        phases.append(g.last_timing())
+    ph = np.median(np.array(phases), axis=0)
+    elem_ms, second_ms = float(ph[0]), float(ph[1])
+    eb = element_bytes(g, B, s_c, conn_len, mesh.n_nodes, mesh.n_elems, args.variant)
+    if args.variant == "rowowner" and second_ms >= elem_ms:
+        kernel, k_ms, k_bytes = "rowowner_reduce", second_ms, scatter_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes)
+    else:
+        kernel, k_ms, k_bytes = f"{args.variant}_element", elem_ms, eb
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9
+    sb = scatter_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes)
+    traffic = traffic_from_profile(kernel)
+
+    variants = {}
+    if not args.no_variants:
+        for vname in ("rowowner", "atomic", "colour"):
+            for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
+                vv, rr, ss = dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o)
+                dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o, vals=vv, rhs=rr, status=ss)
+                ts = []
+                for _ in range(5):
+                    dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o, vals=vv, rhs=rr,
+                                status=ss, timing=True)
+                    ts.append(g.last_timing())
+                med = np.median(np.array(ts), axis=0)
+                variants[f"{vname}_{pname}"] = {"total_ms": round(float(med[2]), 4),
+                                                "element_ms": round(float(med[0]), 4),
+                                                "second_phase_ms": round(float(med[1]), 4)}
+                del vv, rr, ss
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        og = oracle.mesh_graph(mesh)
+        t0 = time.perf_counter()
+        oracle.assemble(mesh, og, model=oracle.ELASTIC)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(mesh.n_elems / cpu_s, 1), "unit": "elements/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"the whole workload ({mesh.n_elems} elements), FP64 C oracle, sequential "
+                         f"Algorithm 1 order, graph build excluded; {cpu_s:.1f} s"}
+
+    value = mesh.n_elems / (ms_per_step * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == fea.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"hybrid{args.cells}-elasticity (hex8/pen6/tet4/pyr5 z-bands, 3x3 BSR)",
+                   "elements": mesh.n_elems, "nodes": mesh.n_nodes, "nnz_blocks": g.nnz,
+                   "variant": args.variant, "precision": args.precision,
+                   "out_dtype": "f64" if outd == fea.F64 else "f32"},
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4)},
+        "scatter": {"effective_GBps": round(sb / (second_ms * 1e-3) / 1e9, 1) if args.variant == "rowowner" else None,
+                    "frac_of_peak": round(sb / (second_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if args.variant == "rowowner" else None,
+                    "algorithmic_bytes": int(sb)},
+        "phases_ms": {"element": round(elem_ms, 4), "second_phase": round(second_ms, 4),
+                      "total": round(float(ph[2]), 4)},
+        "graph_build_ms": round(graph_ms, 2),
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

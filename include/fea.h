@@ -71,6 +71,8 @@ typedef struct fea_options {
     int precision; /* enum fea_precision */
     int variant;   /* enum fea_variant */
     int out_dtype; /* enum fea_dtype: element type of vals and rhs */
+    int timing;    /* nonzero: record HIP events around the phases of this
+                      call on its stream (read with fea_last_timing) */
 } fea_options;
 
 /* Material and model. Per-element arrays are device pointers of length
@@ -93,7 +95,7 @@ typedef struct fea_graph fea_graph;
  * buffers until fea_graph_destroy. Blocks on `stream` (it must learn the
  * number of nonzeros). Errors: FEA_EINVAL, FEA_EMESH (the message names the
  * first bad element), FEA_ERANGE (more than 2^31-1 nonzero blocks or
- * slots, or a row with more than 4096 blocks), FEA_ENOMEM, FEA_EHIP.
+ * slots), FEA_ENOMEM, FEA_EHIP. Nodes in no element get empty rows.
  */
 int fea_graph_build(int64_t n_nodes, int64_t n_elems, const uint8_t *types,
                     const int64_t *conn_ptr, const int32_t *conn, hipStream_t stream,
@@ -131,6 +133,14 @@ int fea_assemble(const fea_graph *g, const double *x, const double *y, const dou
                  const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
                  const fea_material *mat, const double *source, const fea_options *opt,
                  hipStream_t stream, void *vals, void *rhs, int32_t *status);
+
+/* Phase durations of the graph's last fea_assemble call made with
+ * opt->timing set, in milliseconds, measured with HIP events on that call's
+ * stream: ms[0] element kernels (with the fused scatter for ATOMIC and
+ * COLOUR), ms[1] second phase (row-owner reduction; FP32 conversion for
+ * ATOMIC/COLOUR with FP32 output), ms[2] the whole call including
+ * zero-fill. Waits for the events. FEA_EINVAL if no timed call was made. */
+int fea_last_timing(const fea_graph *g, float *ms);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char *fea_last_error(void);

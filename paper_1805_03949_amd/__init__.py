@@ -36,7 +36,7 @@ _I64 = ctypes.c_int64
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int),
-                ("out_dtype", ctypes.c_int)]
+                ("out_dtype", ctypes.c_int), ("timing", ctypes.c_int)]
 
 
 class Material(ctypes.Structure):
@@ -52,12 +52,13 @@ _lib.fea_graph_destroy.argtypes = [_P]
 _lib.fea_graph_destroy.restype = None
 _lib.fea_assemble.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Material), _P,
                               ctypes.POINTER(Options), _P, _P, _P, _P]
+_lib.fea_last_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.fea_last_error.restype = ctypes.c_char_p
 _lib.fea_version.restype = ctypes.c_char_p
 
 # every exported symbol declared in include/fea.h
 EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_export", "fea_graph_destroy",
-           "fea_assemble", "fea_last_error", "fea_version")
+           "fea_assemble", "fea_last_timing", "fea_last_error", "fea_version")
 
 
 class FeaError(RuntimeError):
@@ -135,6 +136,12 @@ class Graph:
         out["type_seg"] = list(seg)
         return out
 
+    def last_timing(self):
+        """(element ms, second-phase ms, total ms) of the last timed assemble."""
+        ms = (ctypes.c_float * 3)()
+        _check(_lib.fea_last_timing(self.handle, ms))
+        return tuple(float(v) for v in ms)
+
     def destroy(self):
         if getattr(self, "_h", None) is not None:
             _lib.fea_graph_destroy(self._h)
@@ -149,7 +156,7 @@ class Graph:
 
 def assemble(graph, x, y, z, types, conn_ptr, conn, source, model=ELASTIC, young=None, nu=None,
              nh_flag=None, u=None, precision=FP64, variant=ROWOWNER, out_dtype=F64, vals=None,
-             rhs=None, status=None, stream=None):
+             rhs=None, status=None, stream=None, timing=False):
     """Assembles (vals, rhs, status) on the GPU; all tensors on the graph's device."""
     B = 1 if model == POISSON else 3
     odt = torch.float64 if out_dtype == F64 else torch.float32
@@ -172,7 +179,7 @@ def assemble(graph, x, y, z, types, conn_ptr, conn, source, model=ELASTIC, young
     _dev(vals, odt)
     _dev(rhs, odt)
     mat = Material(model, _ptr(young), _ptr(nu), _ptr(nh_flag), _ptr(u))
-    opt = Options(precision, variant, out_dtype)
+    opt = Options(precision, variant, out_dtype, int(bool(timing)))
     _check(_lib.fea_assemble(graph.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(types), _ptr(conn_ptr),
                              _ptr(conn), ctypes.byref(mat), _ptr(source), ctypes.byref(opt),
                              _stream(stream), _ptr(vals), _ptr(rhs), _ptr(status)))

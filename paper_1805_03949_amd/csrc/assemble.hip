@@ -156,6 +156,8 @@ struct ElemArgs {
     int64_t n;             // number of ids
     const int64_t *map_ptr;
     const int32_t *e2nnz;
+    const int32_t *e2pos;  // row-owner: destination position of every slot
+    const int32_t *rpos;   // row-owner: destination position of every conn entry
     const double *young, *nu;
     const uint8_t *nh_flag;
     const double *u;
@@ -191,31 +193,62 @@ __device__ inline void inv3(const double J[3][3], double d, double Ji[3][3])
     Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
 }
 
+// The hardware hands workgroup b to XCD b % 8. Renumbering tiles so that
+// each XCD receives one contiguous range keeps neighbouring elements (which
+// share nodes, coordinates and destination cache lines) in the same L2.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nblk)
+{
+    const int64_t q = nblk >> 3, rem = nblk & 7, x = b & 7, r = b >> 3;
+    return x * q + (x < rem ? x : rem) + r;
+}
+
 template <int T, int MODEL, int VAR, typename CT>
 __global__ void __launch_bounds__(256) k_element(ElemArgs A)
 {
     constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
     constexpr int EPB = 256 / P;
-    constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
+    constexpr bool ELAS = MODEL != FEA_POISSON;
+    constexpr int B = ELAS ? 3 : 1;
     constexpr int BB = B * B;
-    constexpr int EU = MODEL == FEA_POISSON ? 1 : EPB;
+    constexpr int EU = ELAS ? EPB : 1;
+    constexpr bool RO = VAR == V_ROWOWNER;
 
     __shared__ double sX[EPB][NN][3];
     __shared__ double sU[EU][NN][3];
-    __shared__ CT sG[EPB][NQ][NN][3];
-    __shared__ CT sH[EU][NQ][NN][3];
-    __shared__ CT sC[EPB][NQ][4];  // wd, wd*lam, wd*mu, wd*c2
+    __shared__ CT sG[EPB][NQ][NN][3];   // physical gradients
+    __shared__ CT sH[EU][NQ][NN][3];    // neo-Hookean: gradients pushed through F^-T
+    __shared__ CT sC[EPB][NQ][4];       // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
+    __shared__ double sLM[EU][2];       // lam, mu
     __shared__ int32_t sE[EPB];
     __shared__ int sNH[EPB];
+    __shared__ int64_t sM[EPB];         // first slot of each element
+    __shared__ int64_t sCP[EPB];        // first conn position of each element
+    __shared__ double sDN[NQ][NN][3];   // reference gradients of this family
+    __shared__ double sNr[NQ][NN];      // reference shape functions
 
     const int tid = threadIdx.x;
-    const int64_t first = (int64_t)blockIdx.x * EPB;
+    const int64_t first = xcd_tile(blockIdx.x, gridDim.x) * EPB;
+
+    for (int i = tid; i < NQ * NN; i += 256) {
+        const int q = i / NN, a = i % NN;
+        sNr[q][a] = c_ref.N[T][q][a];
+        sDN[q][a][0] = c_ref.dN[T][q][a][0];
+        sDN[q][a][1] = c_ref.dN[T][q][a][1];
+        sDN[q][a][2] = c_ref.dN[T][q][a][2];
+    }
 
     if (tid < EPB) {
         int64_t i = first + tid;
         int32_t e = i < A.n ? A.elems[i] : -1;
         sE[tid] = e;
-        sNH[tid] = (MODEL != FEA_POISSON && e >= 0 && A.nh_flag) ? (int)A.nh_flag[e] : 0;
+        sM[tid] = e >= 0 ? A.map_ptr[e] : 0;
+        sCP[tid] = e >= 0 ? A.conn_ptr[e] : 0;
+        sNH[tid] = (ELAS && e >= 0 && A.nh_flag) ? (int)A.nh_flag[e] : 0;
+        if constexpr (ELAS) {
+            double E = (e >= 0 && A.young) ? A.young[e] : 1.0, nu = e >= 0 ? A.nu[e] : 0.25;
+            sLM[tid][0] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+            sLM[tid][1] = E / (2.0 * (1.0 + nu));
+        }
     }
     __syncthreads();
 
@@ -223,11 +256,11 @@ __global__ void __launch_bounds__(256) k_element(ElemArgs A)
         int el = tid / NN, a = tid % NN;
         int32_t e = sE[el];
         if (e >= 0) {
-            int32_t v = A.conn[A.conn_ptr[e] + a];
+            int32_t v = A.conn[sCP[el] + a];
             sX[el][a][0] = A.x[v];
             sX[el][a][1] = A.y[v];
             sX[el][a][2] = A.z[v];
-            if constexpr (MODEL != FEA_POISSON) {
+            if constexpr (ELAS) {
                 bool nh = sNH[el] != 0;
                 for (int k = 0; k < 3; ++k) sU[el][a][k] = nh ? A.u[3 * (int64_t)v + k] : 0.0;
             }
@@ -235,6 +268,7 @@ __global__ void __launch_bounds__(256) k_element(ElemArgs A)
     }
     __syncthreads();
 
+    // geometry: one thread per (element, Gauss point), in FP64
     if (tid < EPB * NQ) {
         int el = tid / NQ, q = tid % NQ;
         int32_t e = sE[el];
@@ -245,7 +279,7 @@ __global__ void __launch_bounds__(256) k_element(ElemArgs A)
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) J[i][j] += sX[el][a][i] * c_ref.dN[T][q][a][j];
+                    for (int j = 0; j < 3; ++j) J[i][j] += sX[el][a][i] * sDN[q][a][j];
             double d = det3(J);
             if (!(d > 0.0)) atomicMin(A.status, e);
             double Ji[3][3];
@@ -255,19 +289,14 @@ __global__ void __launch_bounds__(256) k_element(ElemArgs A)
             for (int a = 0; a < NN; ++a)
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    G[a][i] = Ji[0][i] * c_ref.dN[T][q][a][0] + Ji[1][i] * c_ref.dN[T][q][a][1] +
-                              Ji[2][i] * c_ref.dN[T][q][a][2];
+                    G[a][i] = Ji[0][i] * sDN[q][a][0] + Ji[1][i] * sDN[q][a][1] + Ji[2][i] * sDN[q][a][2];
                     sG[el][q][a][i] = (CT)G[a][i];
                 }
             double wd = c_ref.w[T][q] * d;
-            if constexpr (MODEL == FEA_POISSON) {
-                sC[el][q][0] = (CT)wd;
-            } else {
-                double E = A.young ? A.young[e] : 1.0, nu = A.nu[e];
-                double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-                double mu = E / (2.0 * (1.0 + nu));
-                double c2 = mu;
+            sC[el][q][0] = (CT)wd;
+            if constexpr (ELAS) {
                 if (sNH[el]) {
+                    const double lam = sLM[el][0], mu = sLM[el][1];
                     double F[3][3];
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
@@ -282,75 +311,113 @@ __global__ void __launch_bounds__(256) k_element(ElemArgs A)
                     if (!(jf > 0.0)) atomicMin(A.status, e);
                     double Fi[3][3];
                     inv3(F, jf, Fi);
-                    c2 = mu - lam * log(jf);
 #pragma unroll
                     for (int a = 0; a < NN; ++a)
 #pragma unroll
                         for (int j = 0; j < 3; ++j)
                             sH[el][q][a][j] =
                                 (CT)(G[a][0] * Fi[0][j] + G[a][1] * Fi[1][j] + G[a][2] * Fi[2][j]);
-                } else {
-#pragma unroll
-                    for (int a = 0; a < NN; ++a)
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) sH[el][q][a][j] = (CT)G[a][j];
+                    sC[el][q][1] = (CT)(wd * lam);
+                    sC[el][q][2] = (CT)(wd * (mu - lam * log(jf)));
+                    sC[el][q][3] = (CT)(wd * mu);
                 }
-                sC[el][q][0] = (CT)wd;
-                sC[el][q][1] = (CT)(wd * lam);
-                sC[el][q][2] = (CT)(wd * mu);
-                sC[el][q][3] = (CT)(wd * c2);
             }
         }
     }
     __syncthreads();
 
+    // element matrix: one thread per (element, block a-b)
     if (tid < EPB * P) {
         int el = tid / P, p = tid % P, a = p / NN, b = p % NN;
         int32_t e = sE[el];
         if (e >= 0) {
-            CT acc[BB];
+            // destination of this block, fetched before the contraction
+            const int64_t dest = RO ? (int64_t)A.e2pos[sM[el] + p] : (int64_t)A.e2nnz[sM[el] + p];
+            CT K[BB];
+            if constexpr (!ELAS) {
+                CT acc = 0;
 #pragma unroll
-            for (int c = 0; c < BB; ++c) acc[c] = 0;
+                for (int q = 0; q < NQ; ++q) {
+                    CT dot = sG[el][q][a][0] * sG[el][q][b][0] + sG[el][q][a][1] * sG[el][q][b][1] +
+                             sG[el][q][a][2] * sG[el][q][b][2];
+                    acc += sC[el][q][0] * dot;
+                }
+                K[0] = acc;
+            } else if (!sNH[el]) {
+                // linear: K = lam S + mu S^T + mu tr(S) I, S = sum_q wd G_a (x) G_b
+                CT S[9];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                CT ga0 = sG[el][q][a][0], ga1 = sG[el][q][a][1], ga2 = sG[el][q][a][2];
-                CT gb0 = sG[el][q][b][0], gb1 = sG[el][q][b][1], gb2 = sG[el][q][b][2];
-                CT dot = ga0 * gb0 + ga1 * gb1 + ga2 * gb2;
-                if constexpr (MODEL == FEA_POISSON) {
-                    acc[0] += sC[el][q][0] * dot;
-                } else {
-                    CT c1 = sC[el][q][1], c0 = sC[el][q][2], c2 = sC[el][q][3];
+                for (int c = 0; c < 9; ++c) S[c] = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    CT w = sC[el][q][0];
+                    CT ga[3] = {w * sG[el][q][a][0], w * sG[el][q][a][1], w * sG[el][q][a][2]};
+                    CT gb[3] = {sG[el][q][b][0], sG[el][q][b][1], sG[el][q][b][2]};
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) S[i * 3 + j] += ga[i] * gb[j];
+                }
+                const CT lam = (CT)sLM[el][0], mu = (CT)sLM[el][1];
+                const CT tr = S[0] + S[4] + S[8];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        CT v = lam * S[i * 3 + j] + mu * S[j * 3 + i];
+                        if (i == j) v += mu * tr;
+                        K[i * 3 + j] = v;
+                    }
+            } else {
+                // neo-Hookean: K_ij = sum_q c1 h_a,i h_b,j + c2 h_a,j h_b,i + c0 d_ij G_a.G_b
+                CT T1[9], T2[9], dsum = 0;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) T1[c] = T2[c] = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    CT c1 = sC[el][q][1], c2 = sC[el][q][2], c0 = sC[el][q][3];
                     CT ha[3] = {sH[el][q][a][0], sH[el][q][a][1], sH[el][q][a][2]};
                     CT hb[3] = {sH[el][q][b][0], sH[el][q][b][1], sH[el][q][b][2]};
+                    CT dot = sG[el][q][a][0] * sG[el][q][b][0] + sG[el][q][a][1] * sG[el][q][b][1] +
+                             sG[el][q][a][2] * sG[el][q][b][2];
+                    dsum += c0 * dot;
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
 #pragma unroll
                         for (int j = 0; j < 3; ++j) {
-                            CT v = c1 * (ha[i] * hb[j]) + c2 * (ha[j] * hb[i]);
-                            if (i == j) v += c0 * dot;
-                            acc[i * 3 + j] += v;
+                            CT hh = ha[i] * hb[j];
+                            T1[i * 3 + j] += c1 * hh;
+                            T2[i * 3 + j] += c2 * hh;
                         }
                 }
-            }
-            int64_t slot = A.map_ptr[e] + p;
-            if constexpr (VAR == V_ROWOWNER) {
-                CT *dst = (CT *)A.contrib + slot * BB;
 #pragma unroll
-                for (int c = 0; c < BB; ++c) dst[c] = acc[c];
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        CT v = T1[i * 3 + j] + T2[j * 3 + i];
+                        if (i == j) v += dsum;
+                        K[i * 3 + j] = v;
+                    }
+            }
+            if constexpr (RO) {
+                // row-owner: the workspace is sorted by destination block
+                CT *dst = (CT *)A.contrib + dest * BB;
+#pragma unroll
+                for (int c = 0; c < BB; ++c) dst[c] = K[c];
             } else {
-                int64_t k = A.e2nnz[slot];
-                double *dst = A.vals + k * BB;
+                double *dst = A.vals + dest * BB;
 #pragma unroll
                 for (int c = 0; c < BB; ++c) {
                     if constexpr (VAR == V_ATOMIC)
-                        unsafeAtomicAdd(dst + c, (double)acc[c]);
+                        unsafeAtomicAdd(dst + c, (double)K[c]);
                     else
-                        dst[c] += (double)acc[c];
+                        dst[c] += (double)K[c];
                 }
             }
         }
     }
 
+    // right-hand side: one thread per (element, node)
     if (tid < EPB * NN) {
         int el = tid / NN, a = tid % NN;
         int32_t e = sE[el];
@@ -360,17 +427,16 @@ __global__ void __launch_bounds__(256) k_element(ElemArgs A)
             for (int i = 0; i < B; ++i) f[i] = 0;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                CT wn = sC[el][q][0] * (CT)c_ref.N[T][q][a];
+                CT wn = sC[el][q][0] * (CT)sNr[q][a];
 #pragma unroll
                 for (int i = 0; i < B; ++i) f[i] += wn * (CT)A.source[(int64_t)e * B + i];
             }
-            int64_t cpos = A.conn_ptr[e] + a;
-            if constexpr (VAR == V_ROWOWNER) {
-                CT *dst = (CT *)A.rcontrib + cpos * B;
+            if constexpr (RO) {
+                CT *dst = (CT *)A.rcontrib + (int64_t)A.rpos[sCP[el] + a] * B;
 #pragma unroll
                 for (int i = 0; i < B; ++i) dst[i] = f[i];
             } else {
-                int64_t v = A.conn[cpos];
+                int64_t v = A.conn[sCP[el] + a];
                 double *dst = A.rhs + v * B;
 #pragma unroll
                 for (int i = 0; i < B; ++i) {
@@ -382,38 +448,36 @@ __global__ void __launch_bounds__(256) k_element(ElemArgs A)
             }
         }
     }
+
 }
 
-// Row-owner second phase: block k's value is the sum of its slots'
-// contributions in ascending element order (the order of Algorithm 1).
-template <int BB, typename CT, typename OT>
-__global__ void __launch_bounds__(256) k_reduce_vals(int64_t nnz, const int64_t *inv_ptr,
-                                                     const int32_t *inv, const CT *contrib,
-                                                     OT *vals)
+// Row-owner second phase. The workspace holds every block's contributions
+// contiguously, in ascending element order (the order of Algorithm 1), so
+// block k's value is a plain sum over its segment: a streaming pass with
+// the result independent of how the element phase was scheduled.
+template <int W, typename CT, typename OT>
+__global__ void __launch_bounds__(256) k_reduce_seg(int64_t nseg, const int64_t *seg_ptr,
+                                                    const CT *data, OT *out)
 {
     int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= nnz * BB) return;
-    int64_t k = t / BB;
-    int c = (int)(t - k * BB);
+    if (t >= nseg * W) return;
+    int64_t k = t / W;
+    int c = (int)(t - k * W);
     double s = 0.0;
-    for (int64_t p = inv_ptr[k]; p < inv_ptr[k + 1]; ++p) s += (double)contrib[(int64_t)inv[p] * BB + c];
-    vals[t] = (OT)s;
-}
-
-template <int B, typename CT, typename OT>
-__global__ void __launch_bounds__(256) k_reduce_rhs(int64_t n_nodes, const int64_t *n2e_ptr,
-                                                    const int32_t *n2e, const uint8_t *n2a,
-                                                    const int64_t *conn_ptr, const CT *rcontrib,
-                                                    OT *rhs)
-{
-    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_nodes * B) return;
-    int64_t i = t / B;
-    int c = (int)(t - i * B);
-    double s = 0.0;
-    for (int64_t p = n2e_ptr[i]; p < n2e_ptr[i + 1]; ++p)
-        s += (double)rcontrib[(conn_ptr[n2e[p]] + n2a[p]) * B + c];
-    rhs[t] = (OT)s;
+    const int64_t e = seg_ptr[k + 1];
+    const CT *d = data + c;
+    // four loads in flight per step; the additions stay in ascending order
+    for (int64_t j = seg_ptr[k]; j < e; j += 4) {
+        CT v0 = d[j * W];
+        CT v1 = j + 1 < e ? d[(j + 1) * W] : (CT)0;
+        CT v2 = j + 2 < e ? d[(j + 2) * W] : (CT)0;
+        CT v3 = j + 3 < e ? d[(j + 3) * W] : (CT)0;
+        s += (double)v0;
+        if (j + 1 < e) s += (double)v1;
+        if (j + 2 < e) s += (double)v2;
+        if (j + 3 < e) s += (double)v3;
+    }
+    out[t] = (OT)s;
 }
 
 __global__ void k_fill_f64(double *p, int64_t n, double v)
@@ -472,6 +536,11 @@ static int ensure_ws(void **p, size_t *have, size_t need)
     return FEA_OK;
 }
 
+static inline void mark(fea_graph *g, int i, const fea_options *o, hipStream_t s)
+{
+    if (o->timing) (void)hipEventRecord(g->ev[i], s);
+}
+
 template <int MODEL, typename CT>
 static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, void *vals, void *rhs)
 {
@@ -485,18 +554,21 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         if ((rc = ensure_ws(&g->rcontrib, &g->rcontrib_bytes, sizeof(CT) * (size_t)g->conn_len * B))) return rc;
         a.contrib = g->contrib;
         a.rcontrib = g->rcontrib;
+        mark(g, 0, o, s);
         for (int t = 0; t < 4; ++t) {
             a.elems = g->perm + g->seg[t];
             a.n = g->seg[t + 1] - g->seg[t];
             launch_type<MODEL, V_ROWOWNER, CT>(t, a, s);
         }
+        mark(g, 1, o, s);
         if (f32) {
-            if (nv) k_reduce_vals<BB, CT, float><<<grid_for(nv, 256), 256, 0, s>>>(g->nnz, g->inv_ptr, g->inv, (const CT *)g->contrib, (float *)vals);
-            if (nr) k_reduce_rhs<B, CT, float><<<grid_for(nr, 256), 256, 0, s>>>(g->n_nodes, g->n2e_ptr, g->n2e, g->n2a, a.conn_ptr, (const CT *)g->rcontrib, (float *)rhs);
+            if (nv) k_reduce_seg<BB, CT, float><<<grid_for(nv, 256), 256, 0, s>>>(g->nnz, g->inv_ptr, (const CT *)g->contrib, (float *)vals);
+            if (nr) k_reduce_seg<B, CT, float><<<grid_for(nr, 256), 256, 0, s>>>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs);
         } else {
-            if (nv) k_reduce_vals<BB, CT, double><<<grid_for(nv, 256), 256, 0, s>>>(g->nnz, g->inv_ptr, g->inv, (const CT *)g->contrib, (double *)vals);
-            if (nr) k_reduce_rhs<B, CT, double><<<grid_for(nr, 256), 256, 0, s>>>(g->n_nodes, g->n2e_ptr, g->n2e, g->n2a, a.conn_ptr, (const CT *)g->rcontrib, (double *)rhs);
+            if (nv) k_reduce_seg<BB, CT, double><<<grid_for(nv, 256), 256, 0, s>>>(g->nnz, g->inv_ptr, (const CT *)g->contrib, (double *)vals);
+            if (nr) k_reduce_seg<B, CT, double><<<grid_for(nr, 256), 256, 0, s>>>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs);
         }
+        mark(g, 2, o, s);
         FEA_HIP(hipGetLastError());
         return FEA_OK;
     }
@@ -511,6 +583,7 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         tv = (double *)vals;
         tr = (double *)rhs;
     }
+    mark(g, 0, o, s);
     if (nv) k_fill_f64<<<grid_for(nv, 256), 256, 0, s>>>(tv, nv, 0.0);
     if (nr) k_fill_f64<<<grid_for(nr, 256), 256, 0, s>>>(tr, nr, 0.0);
     a.vals = tv;
@@ -531,10 +604,12 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
                 launch_type<MODEL, V_COLOUR, CT>(t, a, s);
             }
     }
+    mark(g, 1, o, s);
     if (f32) {
         if (nv) k_to_f32<<<grid_for(nv, 256), 256, 0, s>>>(tv, (float *)vals, nv);
         if (nr) k_to_f32<<<grid_for(nr, 256), 256, 0, s>>>(tr, (float *)rhs, nr);
     }
+    mark(g, 2, o, s);
     FEA_HIP(hipGetLastError());
     return FEA_OK;
 }
@@ -550,7 +625,7 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
 {
     clear_error();
     fea_graph *g = const_cast<fea_graph *>(gc);
-    fea_options dflt = {0, 0, 0};
+    fea_options dflt = {0, 0, 0, 0};
     const fea_options *o = opt ? opt : &dflt;
     if (!g || !mat) return set_error(FEA_EINVAL, "graph and material are required");
     if (o->precision < 0 || o->precision > 1 || o->variant < 0 || o->variant > 2 ||
@@ -572,6 +647,11 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     if (dev != g->device) return set_error(FEA_EINVAL, "graph lives on device %d, current is %d", g->device, dev);
     int rc = ensure_tables();
     if (rc) return rc;
+    if (o->timing) {
+        for (hipEvent_t &e : g->ev)
+            if (!e) FEA_HIP(hipEventCreate(&e));
+    }
+    g->timed = false;
 
     int32_t *st = status;
     if (!st) {
@@ -587,6 +667,8 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     a.conn = conn;
     a.map_ptr = g->map_ptr;
     a.e2nnz = g->e2nnz;
+    a.e2pos = g->e2pos;
+    a.rpos = g->rpos;
     a.young = mat->young;
     a.nu = mat->nu;
     a.nh_flag = mat->model == FEA_ELASTIC ? mat->nh_flag : nullptr;
@@ -611,5 +693,18 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     }
     k_status_final<<<1, 1, 0, stream>>>(st);
     FEA_HIP(hipGetLastError());
+    g->timed = o->timing && g->n_elems > 0;
+    return FEA_OK;
+}
+
+extern "C" int fea_last_timing(const fea_graph *g, float *ms)
+{
+    clear_error();
+    if (!g || !ms) return set_error(FEA_EINVAL, "graph and ms are required");
+    if (!g->timed) return set_error(FEA_EINVAL, "no timed fea_assemble call on this graph");
+    FEA_HIP(hipEventSynchronize(g->ev[2]));
+    FEA_HIP(hipEventElapsedTime(&ms[0], g->ev[0], g->ev[1]));
+    FEA_HIP(hipEventElapsedTime(&ms[1], g->ev[1], g->ev[2]));
+    FEA_HIP(hipEventElapsedTime(&ms[2], g->ev[0], g->ev[2]));
     return FEA_OK;
 }

@@ -54,6 +54,11 @@ struct fea_graph {
     int32_t *e2nnz = nullptr;
     int64_t *inv_ptr = nullptr;
     int32_t *inv = nullptr;
+    // destination positions of the row-owner workspace, which is kept sorted
+    // by destination: slot s goes to e2pos[s] (e2pos[inv[j]] = j), and the
+    // right-hand-side entry of conn position c to rpos[c] (its incidence index)
+    int32_t *e2pos = nullptr;
+    int32_t *rpos = nullptr;
     // node -> incident elements (ascending element id) and local index
     int64_t *n2e_ptr = nullptr;
     int32_t *n2e = nullptr;
@@ -73,4 +78,7 @@ struct fea_graph {
     size_t rcontrib_bytes = 0;
     double *acc64 = nullptr;
     size_t acc64_bytes = 0;
+    // phase events of the last timed fea_assemble (begin, elements done, end)
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool timed = false;
 };

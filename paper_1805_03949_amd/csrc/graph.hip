@@ -183,6 +183,23 @@ __global__ void k_inv_fill(int64_t n_nodes, const int64_t *n2e_ptr, const int32_
     }
 }
 
+// Inverse permutation of the inverse map, and the incidence index of every
+// conn position: the places where the element kernel of the row-owner
+// variant stores its contributions, so that they lie sorted by destination.
+__global__ void k_e2pos(int64_t map_len, const int32_t *inv, int32_t *e2pos)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < map_len) e2pos[inv[j]] = (int32_t)j;
+}
+
+__global__ void k_rpos(int64_t n_nodes, const int64_t *n2e_ptr, const int32_t *n2e,
+                       const uint8_t *n2a, const int64_t *conn_ptr, int32_t *rpos)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    for (int64_t p = n2e_ptr[i]; p < n2e_ptr[i + 1]; ++p) rpos[conn_ptr[n2e[p]] + n2a[p]] = (int32_t)p;
+}
+
 // ------------------------------------------------------------- colouring
 // Greedy first-fit in element order (the colouring of Algorithm 5; any
 // valid colouring is correct, this one is deterministic). Sequential by
@@ -246,10 +263,12 @@ static int colour_host(fea_graph *g, const int64_t *conn_ptr_d, const int32_t *c
 static void destroy(fea_graph *g)
 {
     if (!g) return;
-    void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv,
+    void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv, g->e2pos, g->rpos,
                     g->n2e_ptr, g->n2e, g->n2a, g->perm, g->colour, g->cperm,
                     g->contrib, g->rcontrib, g->acc64};
     for (void *b : bufs) dfree(b);
+    for (hipEvent_t e : g->ev)
+        if (e) (void)hipEventDestroy(e);
     delete g;
 }
 
@@ -293,9 +312,9 @@ static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn
     if ((rc = scan_to_ptr_i64((int64_t *)cnt64.p, E, g->map_ptr, (int64_t *)tmp.p, s))) return rc;
     FEA_HIP(hipMemcpyAsync(&g->map_len, g->map_ptr + E, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     FEA_HIP(hipStreamSynchronize(s));
-    if (g->map_len > INT32_MAX)
-        return set_error(FEA_ERANGE, "%lld element-matrix slots exceed the int32 inverse map",
-                         (long long)g->map_len);
+    if (g->map_len > INT32_MAX || g->conn_len > INT32_MAX)
+        return set_error(FEA_ERANGE, "%lld element-matrix slots / %lld incidences exceed int32 maps",
+                         (long long)g->map_len, (long long)g->conn_len);
 
     // type segmentation (stable partition by family)
     if ((rc = dalloc(&flag.p, std::max<int64_t>(E, 1)))) return rc;
@@ -360,6 +379,13 @@ static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn
     if ((rc = scan_to_ptr_i32((int32_t *)fillb.p, g->nnz, g->inv_ptr, (int64_t *)tmp.p, s))) return rc;
     FEA_HIP(hipMemsetAsync(fillb.p, 0, sizeof(int32_t) * (g->nnz + 1), s));
     if (N) k_inv_fill<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, g->n2a, conn_ptr, g->map_ptr, g->e2nnz, g->inv_ptr, (int32_t *)fillb.p, g->inv);
+    FEA_HIP(hipGetLastError());
+
+    // destination positions for the row-owner workspace
+    if ((rc = dalloc((void **)&g->e2pos, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->rpos, sizeof(int32_t) * std::max<int64_t>(g->conn_len, 1)))) return rc;
+    if (g->map_len) k_e2pos<<<grid_for(g->map_len, BS), BS, 0, s>>>(g->map_len, g->inv, g->e2pos);
+    if (N) k_rpos<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, g->n2a, conn_ptr, g->rpos);
     FEA_HIP(hipGetLastError());
 
     if ((rc = colour_host(g, conn_ptr, conn, types, s))) return rc;
