@@ -28,13 +28,19 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "elements assembled/s + scatter HBM GB/s (% peak); learned+mixed vs plain FP64"
 
 
+def reduce_bytes(g, B, s_c, s_v):
+    """Algorithmic bytes of one launch of the row-owner block-value kernel:
+    every slot contribution read once (the workspace is sorted by
+    destination, so no map is read), each block's segment bound read once
+    (int64), every block value written once."""
+    return g.map_len * B * B * s_c + (g.nnz + 1) * 8 + g.nnz * B * B * s_v
+
+
 def scatter_bytes(g, B, s_c, s_v, conn_len, n_nodes):
-    """Algorithmic bytes of the row-owner second phase: every contribution,
-    its inverse-map entry and each block's range read once, every output
-    value written once; the right-hand side likewise through the node
-    incidence (element id, local index and that element's conn offset)."""
-    return (g.map_len * (B * B * s_c + 4) + (g.nnz + 1) * 8 + g.nnz * B * B * s_v
-            + conn_len * (B * s_c + 4 + 1 + 8) + (n_nodes + 1) * 8 + n_nodes * B * s_v)
+    """Algorithmic bytes of the whole scatter (matrix and right-hand side):
+    reduce_bytes plus the right-hand-side contributions, node segment
+    bounds and values."""
+    return reduce_bytes(g, B, s_c, s_v) + conn_len * B * s_c + (n_nodes + 1) * 8 + n_nodes * B * s_v
 
 
 def element_bytes(g, B, s_c, conn_len, n_nodes, n_elems, variant):
@@ -77,7 +83,18 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 8}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(assembly shards across GPUs without communication; see the design notes).",
@@ -136,10 +153,10 @@ def main():
     ph = np.median(np.array(phases), axis=0)
     elem_ms, second_ms = float(ph[0]), float(ph[1])
     eb = element_bytes(g, B, s_c, conn_len, mesh.n_nodes, mesh.n_elems, args.variant)
-    if args.variant == "rowowner" and second_ms >= elem_ms:
-        kernel, k_ms, k_bytes = "rowowner_reduce", second_ms, scatter_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes)
+    if args.variant == "rowowner":
+        kernel, k_ms, k_bytes = "k_reduce_seg<9>", second_ms, reduce_bytes(g, B, s_c, s_v)
     else:
-        kernel, k_ms, k_bytes = f"{args.variant}_element", elem_ms, eb
+        kernel, k_ms, k_bytes = f"{args.variant} element phase", elem_ms, eb
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     sb = scatter_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes)
     traffic = traffic_from_profile(kernel)
@@ -158,7 +175,8 @@ def main():
                 med = np.median(np.array(ts), axis=0)
                 variants[f"{vname}_{pname}"] = {"total_ms": round(float(med[2]), 4),
                                                 "element_ms": round(float(med[0]), 4),
-                                                "second_phase_ms": round(float(med[1]), 4)}
+                                                "block_value_kernel_ms": round(float(med[1]), 4),
+                                                "elements_per_s": round(mesh.n_elems / (float(med[2]) * 1e-3), 1)}
                 del vv, rr, ss
         torch.cuda.synchronize()
 
@@ -195,10 +213,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4)},
-        "scatter": {"effective_GBps": round(sb / (second_ms * 1e-3) / 1e9, 1) if args.variant == "rowowner" else None,
-                    "frac_of_peak": round(sb / (second_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if args.variant == "rowowner" else None,
-                    "algorithmic_bytes": int(sb)},
-        "phases_ms": {"element": round(elem_ms, 4), "second_phase": round(second_ms, 4),
+        "scatter": {"effective_GBps": round(sb / ((float(ph[2]) - elem_ms) * 1e-3) / 1e9, 1) if args.variant == "rowowner" else None,
+                    "frac_of_peak": round(sb / ((float(ph[2]) - elem_ms) * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if args.variant == "rowowner" else None,
+                    "algorithmic_bytes": int(sb), "note": "matrix and right-hand side, second phase"},
+        "element_phase": {"algorithmic_bytes": int(eb), "ms": round(elem_ms, 4),
+                          "effective_GBps": round(eb / (elem_ms * 1e-3) / 1e9, 1)},
+        "phases_ms": {"element": round(elem_ms, 4), "block_value_kernel": round(second_ms, 4),
                       "total": round(float(ph[2]), 4)},
         "graph_build_ms": round(graph_ms, 2),
         "variants": variants,

@@ -137,9 +137,11 @@ int fea_assemble(const fea_graph *g, const double *x, const double *y, const dou
 /* Phase durations of the graph's last fea_assemble call made with
  * opt->timing set, in milliseconds, measured with HIP events on that call's
  * stream: ms[0] element kernels (with the fused scatter for ATOMIC and
- * COLOUR), ms[1] second phase (row-owner reduction; FP32 conversion for
- * ATOMIC/COLOUR with FP32 output), ms[2] the whole call including
- * zero-fill. Waits for the events. FEA_EINVAL if no timed call was made. */
+ * COLOUR), ms[1] the one kernel that forms the matrix values after them
+ * (row-owner: the segmented reduction of the block values; ATOMIC/COLOUR
+ * with FP32 output: the conversion; otherwise empty), ms[2] the whole call
+ * including zero-fill and the right-hand side. Waits for the events.
+ * FEA_EINVAL if no timed call was made. */
 int fea_last_timing(const fea_graph *g, float *ms);
 
 /* Message for the last error on the calling thread ("" if none). */

@@ -563,12 +563,14 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         mark(g, 1, o, s);
         if (f32) {
             if (nv) k_reduce_seg<BB, CT, float><<<grid_for(nv, 256), 256, 0, s>>>(g->nnz, g->inv_ptr, (const CT *)g->contrib, (float *)vals);
+            mark(g, 2, o, s);
             if (nr) k_reduce_seg<B, CT, float><<<grid_for(nr, 256), 256, 0, s>>>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs);
         } else {
             if (nv) k_reduce_seg<BB, CT, double><<<grid_for(nv, 256), 256, 0, s>>>(g->nnz, g->inv_ptr, (const CT *)g->contrib, (double *)vals);
+            mark(g, 2, o, s);
             if (nr) k_reduce_seg<B, CT, double><<<grid_for(nr, 256), 256, 0, s>>>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs);
         }
-        mark(g, 2, o, s);
+        mark(g, 3, o, s);
         FEA_HIP(hipGetLastError());
         return FEA_OK;
     }
@@ -605,11 +607,10 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
             }
     }
     mark(g, 1, o, s);
-    if (f32) {
-        if (nv) k_to_f32<<<grid_for(nv, 256), 256, 0, s>>>(tv, (float *)vals, nv);
-        if (nr) k_to_f32<<<grid_for(nr, 256), 256, 0, s>>>(tr, (float *)rhs, nr);
-    }
+    if (f32 && nv) k_to_f32<<<grid_for(nv, 256), 256, 0, s>>>(tv, (float *)vals, nv);
     mark(g, 2, o, s);
+    if (f32 && nr) k_to_f32<<<grid_for(nr, 256), 256, 0, s>>>(tr, (float *)rhs, nr);
+    mark(g, 3, o, s);
     FEA_HIP(hipGetLastError());
     return FEA_OK;
 }
@@ -702,9 +703,9 @@ extern "C" int fea_last_timing(const fea_graph *g, float *ms)
     clear_error();
     if (!g || !ms) return set_error(FEA_EINVAL, "graph and ms are required");
     if (!g->timed) return set_error(FEA_EINVAL, "no timed fea_assemble call on this graph");
-    FEA_HIP(hipEventSynchronize(g->ev[2]));
+    FEA_HIP(hipEventSynchronize(g->ev[3]));
     FEA_HIP(hipEventElapsedTime(&ms[0], g->ev[0], g->ev[1]));
     FEA_HIP(hipEventElapsedTime(&ms[1], g->ev[1], g->ev[2]));
-    FEA_HIP(hipEventElapsedTime(&ms[2], g->ev[0], g->ev[2]));
+    FEA_HIP(hipEventElapsedTime(&ms[2], g->ev[0], g->ev[3]));
     return FEA_OK;
 }

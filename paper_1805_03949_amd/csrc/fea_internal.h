@@ -78,7 +78,8 @@ struct fea_graph {
     size_t rcontrib_bytes = 0;
     double *acc64 = nullptr;
     size_t acc64_bytes = 0;
-    // phase events of the last timed fea_assemble (begin, elements done, end)
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    // events of the last timed fea_assemble: begin, element kernels done,
+    // block-value scatter kernel done, end
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
 };
