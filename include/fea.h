@@ -144,6 +144,97 @@ int fea_assemble(const fea_graph *g, const double *x, const double *y, const dou
  * FEA_EINVAL if no timed call was made. */
 int fea_last_timing(const fea_graph *g, float *ms);
 
+/* ------------------------------------------------------------------ *
+ * Batched assembly: many independent meshes in one persistent launch. *
+ * ------------------------------------------------------------------ */
+
+/* One mesh of a batch. All pointers are device pointers owned by the
+ * caller and must stay valid while the batch is used; fields as in
+ * fea_assemble (source: b values per element; nh_flag/u may be NULL). */
+typedef struct fea_mesh_desc {
+    int64_t n_nodes, n_elems;
+    const uint8_t *types;
+    const int64_t *conn_ptr;
+    const int32_t *conn;
+    const double *x, *y, *z;
+    const double *young, *nu;
+    const uint8_t *nh_flag;
+    const double *u;
+    const double *source;
+} fea_mesh_desc;
+
+typedef struct fea_batch fea_batch;
+
+/*
+ * Builds a graph per mesh and the work items of one persistent launch. A
+ * work item is `count` consecutive elements of one family of one mesh, in
+ * that mesh's type-sorted element order; tile[f] (elements per item for
+ * family f = tet4, pyr5, pen6, hex8; NULL = defaults) sets the item sizes.
+ * The paper's dynamic schedule with a chunk size (Section 5.1, chunk study)
+ * is the analogue: items are chunks handed out by a device work queue.
+ * The queue order starts type-sorted (family, mesh, first element).
+ * Outputs of all meshes are concatenated: mesh m's values start at
+ * vals_off[m] and its right-hand side at rhs_off[m] (fea_batch_offsets).
+ * model: enum fea_model, common to all meshes. Blocks on `stream`.
+ * Errors as fea_graph_build (the message names the mesh), FEA_EINVAL.
+ */
+int fea_batch_build(int n_meshes, const fea_mesh_desc *meshes, int model, const int32_t *tile,
+                    hipStream_t stream, fea_batch **out);
+
+/* Totals: value and right-hand-side lengths (scalars), work items, elements. */
+int fea_batch_sizes(const fea_batch *b, int64_t *vals_len, int64_t *rhs_len, int64_t *n_items,
+                    int64_t *n_elems);
+
+/* HOST arrays of n_meshes+1 scalar offsets into vals and rhs. */
+int fea_batch_offsets(const fea_batch *b, int64_t *vals_off, int64_t *rhs_off);
+
+/* HOST array of n_items x 4 int32: mesh, family, first element, count. */
+int fea_batch_items(const fea_batch *b, int32_t *items);
+
+/* Replaces the work items with new per-family tile sizes (resets the
+ * queue order to type-sorted and drops a captured graph). */
+int fea_batch_set_tiles(fea_batch *b, const int32_t *tile);
+
+/* Sets the queue order: HOST permutation of 0..n_items-1, item order[j] is
+ * dequeued j-th. Drops a captured graph. FEA_EINVAL if not a permutation. */
+int fea_batch_set_order(fea_batch *b, const int32_t *order);
+
+/*
+ * One batched assembly on `stream`: reset the queue head, one persistent
+ * kernel (row-owner slot contributions, FP64 or mixed per opt->precision),
+ * then the block-value and right-hand-side reductions over all meshes.
+ * vals/rhs: device buffers of the lengths from fea_batch_sizes, element
+ * type opt->out_dtype, overwritten. status: device int32[n_meshes] (may be
+ * NULL), per mesh the smallest rejected element id or -1. opt->variant must
+ * be FEA_ROWOWNER. With opt->timing, fea_batch_last_ms reads the
+ * persistent kernel's duration.
+ */
+int fea_batch_assemble(fea_batch *b, const fea_options *opt, hipStream_t stream, void *vals,
+                       void *rhs, int32_t *status);
+
+/* Captures the sequence of fea_batch_assemble into a HIP graph (stream
+ * capture on `stream`, which must not be the legacy default stream) and
+ * keeps the executable graph in the batch; fea_batch_replay launches it
+ * `n` times on `stream`. The captured graph contains kernels only. */
+int fea_batch_capture(fea_batch *b, const fea_options *opt, hipStream_t stream, void *vals,
+                      void *rhs, int32_t *status);
+int fea_batch_replay(fea_batch *b, int n, hipStream_t stream);
+
+/* Per-item records of the last persistent launch, copied into DEVICE
+ * buffers of n_items entries (any may be NULL): shader-clock cycles from
+ * the item's dequeue to its completion, the workgroup that ran it and the
+ * compute unit (hardware id). */
+int fea_batch_cycles(const fea_batch *b, uint64_t *cycles, int32_t *worker, int32_t *cu,
+                     hipStream_t stream);
+
+/* Duration in ms of the persistent kernel of the last timed assemble. */
+int fea_batch_last_ms(const fea_batch *b, float *ms);
+
+/* Number of persistent workgroups (workers) the batch launches. */
+int fea_batch_workers(const fea_batch *b, int *workers);
+
+void fea_batch_destroy(fea_batch *b);
+
 /* Message for the last error on the calling thread ("" if none). */
 const char *fea_last_error(void);
 

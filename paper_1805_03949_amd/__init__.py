@@ -56,9 +56,38 @@ _lib.fea_last_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.fea_last_error.restype = ctypes.c_char_p
 _lib.fea_version.restype = ctypes.c_char_p
 
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_nodes", _I64), ("n_elems", _I64), ("types", _P), ("conn_ptr", _P), ("conn", _P),
+                ("x", _P), ("y", _P), ("z", _P), ("young", _P), ("nu", _P), ("nh_flag", _P),
+                ("u", _P), ("source", _P)]
+
+
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_I64P = ctypes.POINTER(_I64)
+_lib.fea_batch_build.argtypes = [ctypes.c_int, ctypes.POINTER(MeshDesc), ctypes.c_int, _I32P, _P,
+                                 ctypes.POINTER(_P)]
+_lib.fea_batch_sizes.argtypes = [_P, _I64P, _I64P, _I64P, _I64P]
+_lib.fea_batch_offsets.argtypes = [_P, _I64P, _I64P]
+_lib.fea_batch_items.argtypes = [_P, _I32P]
+_lib.fea_batch_set_tiles.argtypes = [_P, _I32P]
+_lib.fea_batch_set_order.argtypes = [_P, _I32P]
+_lib.fea_batch_assemble.argtypes = [_P, ctypes.POINTER(Options), _P, _P, _P, _P]
+_lib.fea_batch_capture.argtypes = [_P, ctypes.POINTER(Options), _P, _P, _P, _P]
+_lib.fea_batch_replay.argtypes = [_P, ctypes.c_int, _P]
+_lib.fea_batch_cycles.argtypes = [_P, _P, _P, _P, _P]
+_lib.fea_batch_last_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
+_lib.fea_batch_workers.argtypes = [_P, ctypes.POINTER(ctypes.c_int)]
+_lib.fea_batch_destroy.argtypes = [_P]
+_lib.fea_batch_destroy.restype = None
+
 # every exported symbol declared in include/fea.h
 EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_export", "fea_graph_destroy",
-           "fea_assemble", "fea_last_timing", "fea_last_error", "fea_version")
+           "fea_assemble", "fea_last_timing", "fea_last_error", "fea_version",
+           "fea_batch_build", "fea_batch_sizes", "fea_batch_offsets", "fea_batch_items",
+           "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_assemble", "fea_batch_capture",
+           "fea_batch_replay", "fea_batch_cycles", "fea_batch_last_ms", "fea_batch_workers",
+           "fea_batch_destroy")
 
 
 class FeaError(RuntimeError):
@@ -212,3 +241,112 @@ class DeviceMesh:
                         nu=self.nu if model == ELASTIC else None,
                         nh_flag=self.nh_flag if (use_nh and model == ELASTIC) else None,
                         u=self.u if (use_nh and model == ELASTIC) else None, **kw)
+
+
+def _np_i32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_I32P)
+
+
+class Batch:
+    """Many meshes assembled by one persistent launch fed from a device queue."""
+
+    def __init__(self, meshes, model=ELASTIC, tile=None, use_nh=False, stream=None):
+        import numpy as np
+        self.meshes = list(meshes)
+        self.model = model
+        self.device = self.meshes[0].x.device if self.meshes else torch.device("cuda")
+        self._keep = []
+        descs = (MeshDesc * max(1, len(self.meshes)))()
+        for i, dm in enumerate(self.meshes):
+            src = dm.source if model == ELASTIC else dm.source[:, :1].contiguous()
+            self._keep.append(src)
+            nh = dm.nh_flag if (use_nh and model == ELASTIC) else None
+            descs[i] = MeshDesc(dm.n_nodes, dm.n_elems, _ptr(dm.types), _ptr(dm.conn_ptr), _ptr(dm.conn),
+                                _ptr(dm.x), _ptr(dm.y), _ptr(dm.z), _ptr(dm.young),
+                                _ptr(dm.nu) if model == ELASTIC else None, _ptr(nh),
+                                _ptr(dm.u) if nh is not None else None, _ptr(src))
+        h = _P()
+        tp = None
+        if tile is not None:
+            self._tile, tp = _np_i32(tile)
+        _check(_lib.fea_batch_build(len(self.meshes), descs, model, tp, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._refresh()
+
+    def _refresh(self):
+        import numpy as np
+        v, r, ni, ne = _I64(), _I64(), _I64(), _I64()
+        _check(_lib.fea_batch_sizes(self._h, ctypes.byref(v), ctypes.byref(r), ctypes.byref(ni),
+                                    ctypes.byref(ne)))
+        self.vals_len, self.rhs_len, self.n_items, self.n_elems = v.value, r.value, ni.value, ne.value
+        n = len(self.meshes)
+        vo = (_I64 * (n + 1))()
+        ro = (_I64 * (n + 1))()
+        _check(_lib.fea_batch_offsets(self._h, vo, ro))
+        self.vals_off = np.array(list(vo), dtype=np.int64)
+        self.rhs_off = np.array(list(ro), dtype=np.int64)
+        items = np.zeros(max(1, self.n_items) * 4, dtype=np.int32)
+        _check(_lib.fea_batch_items(self._h, items.ctypes.data_as(_I32P)))
+        self.items = items[: self.n_items * 4].reshape(-1, 4)
+
+    def set_tiles(self, tile):
+        self._tile, tp = _np_i32(tile)
+        _check(_lib.fea_batch_set_tiles(self._h, tp))
+        self._refresh()
+
+    def set_order(self, order):
+        arr, p = _np_i32(order)
+        _check(_lib.fea_batch_set_order(self._h, p))
+
+    def outputs(self, out_dtype=F64):
+        odt = torch.float64 if out_dtype == F64 else torch.float32
+        return (torch.empty(self.vals_len, dtype=odt, device=self.device),
+                torch.empty(self.rhs_len, dtype=odt, device=self.device),
+                torch.empty(max(1, len(self.meshes)), dtype=torch.int32, device=self.device))
+
+    def assemble(self, precision=FP64, out_dtype=F64, vals=None, rhs=None, status=None, stream=None,
+                 timing=False):
+        if vals is None:
+            vals, rhs, status = self.outputs(out_dtype)
+        opt = Options(precision, ROWOWNER, out_dtype, int(bool(timing)))
+        _check(_lib.fea_batch_assemble(self._h, ctypes.byref(opt), _stream(stream), _ptr(vals), _ptr(rhs),
+                                       _ptr(status)))
+        return vals, rhs, status
+
+    def capture(self, vals, rhs, status, precision=FP64, out_dtype=F64, stream=None):
+        opt = Options(precision, ROWOWNER, out_dtype, 0)
+        _check(_lib.fea_batch_capture(self._h, ctypes.byref(opt), _stream(stream), _ptr(vals), _ptr(rhs),
+                                      _ptr(status)))
+
+    def replay(self, n=1, stream=None):
+        _check(_lib.fea_batch_replay(self._h, int(n), _stream(stream)))
+
+    def cycles(self, stream=None):
+        c = torch.empty(self.n_items, dtype=torch.int64, device=self.device)
+        w = torch.empty(self.n_items, dtype=torch.int32, device=self.device)
+        u = torch.empty(self.n_items, dtype=torch.int32, device=self.device)
+        _check(_lib.fea_batch_cycles(self._h, _ptr(c), _ptr(w), _ptr(u), _stream(stream)))
+        return c, w, u
+
+    def last_ms(self):
+        ms = ctypes.c_float()
+        _check(_lib.fea_batch_last_ms(self._h, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def workers(self):
+        w = ctypes.c_int()
+        _check(_lib.fea_batch_workers(self._h, ctypes.byref(w)))
+        return int(w.value)
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.fea_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

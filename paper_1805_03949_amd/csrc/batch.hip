@@ -1,0 +1,597 @@
+// Batched assembly of many independent meshes in one persistent launch.
+//
+// The paper distributes the element loop over threads with a dynamic
+// schedule and a chunk size (Section 3.2, Algorithms 4 and 5; chunk study
+// in Section 5.1) and over ranks with weighted partitions (Section 4.1).
+// Here the chunks are work items -- `count` consecutive elements of one
+// family of one mesh -- handed out by a device queue (an atomic head over an
+// order array) to persistent workgroups. Each workgroup records the shader
+// clock around every item it runs; those cycle counts are the measured
+// per-item cost (Section 4.1, measured load balance) that the cost model
+// learns from. Results are deterministic: each block is summed by the
+// row-owner reduction in ascending element order, whatever the queue order.
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "elem.h"
+
+namespace fea {
+
+// Per-mesh view used by the persistent kernel.
+struct BatchMesh {
+    ElemArgs a;      // pointers of the mesh and its graph (elems = perm)
+    int64_t seg[5];  // family segments in perm
+    int64_t coff;    // first slot of this mesh in the slot workspace
+    int64_t roff;    // first incidence of this mesh in the rhs workspace
+};
+
+template <int MODEL, typename CT>
+union BatchSmem {
+    ElemSmem<0, MODEL, V_ROWOWNER, CT> s0;
+    ElemSmem<1, MODEL, V_ROWOWNER, CT> s1;
+    ElemSmem<2, MODEL, V_ROWOWNER, CT> s2;
+    ElemSmem<3, MODEL, V_ROWOWNER, CT> s3;
+};
+
+template <int T, int MODEL, typename CT>
+__device__ inline void run_item(ElemArgs &A, int32_t count, ElemSmem<T, MODEL, V_ROWOWNER, CT> &S)
+{
+    constexpr int EPB = ElemSmem<T, MODEL, V_ROWOWNER, CT>::EPB;
+#pragma nounroll
+    for (int32_t sub = 0; sub < count; sub += EPB) elem_tile<T, MODEL, V_ROWOWNER, CT>(A, sub, S, opaque_tid());
+}
+
+// Persistent kernel: every workgroup dequeues items until the queue is
+// empty (each workgroup reaches the exit test after every item). The
+// register budget is capped at three waves per SIMD: the four element
+// families inlined into one loop would otherwise take the whole register
+// file (one wave per SIMD).
+template <int MODEL, typename CT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_batch(const BatchMesh *meshes, const int4 *items,
+                                               const int32_t *order, int32_t n_items,
+                                               int32_t *head, CT *contrib, CT *rcontrib,
+                                               int32_t *status, uint64_t *cycles,
+                                               int32_t *worker, int32_t *cu)
+{
+    constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
+    __shared__ BatchSmem<MODEL, CT> U;
+    __shared__ int32_t s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t q = atomicAdd(head, 1);
+            s_item = q < n_items ? order[q] : -1;
+        }
+        __syncthreads();
+        // the item is the same for the whole workgroup: keep it (and the
+        // mesh view it selects) in scalar registers
+        const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it < 0) break;
+        const uint64_t t0 = clock64();
+        const int4 wv = items[it];
+        const int4 w = make_int4(__builtin_amdgcn_readfirstlane(wv.x), __builtin_amdgcn_readfirstlane(wv.y),
+                                 __builtin_amdgcn_readfirstlane(wv.z), __builtin_amdgcn_readfirstlane(wv.w));
+        const BatchMesh &M = meshes[w.x];
+        ElemArgs A = M.a;
+        A.contrib = contrib + M.coff * B * B;
+        A.rcontrib = rcontrib + M.roff * B;
+        A.elems = M.a.elems + M.seg[w.y] + w.z;
+        A.n = w.w;
+        A.status = status + w.x;
+        switch (w.y) {
+        case 0: run_item<0, MODEL, CT>(A, w.w, U.s0); break;
+        case 1: run_item<1, MODEL, CT>(A, w.w, U.s1); break;
+        case 2: run_item<2, MODEL, CT>(A, w.w, U.s2); break;
+        default: run_item<3, MODEL, CT>(A, w.w, U.s3); break;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            cycles[it] = clock64() - t0;
+            worker[it] = blockIdx.x;
+            cu[it] = (int32_t)__smid();
+        }
+    }
+}
+
+template <int W, typename CT, typename OT>
+__global__ void __launch_bounds__(256) k_breduce(int64_t nseg, const int64_t *seg_ptr,
+                                                 const CT *data, OT *out)
+{
+    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nseg * W) return;
+    int64_t k = t / W;
+    int c = (int)(t - k * W);
+    double s = 0.0;
+    const int64_t e = seg_ptr[k + 1];
+    const CT *d = data + c;
+    for (int64_t j = seg_ptr[k]; j < e; j += 4) {
+        CT v0 = d[j * W];
+        CT v1 = j + 1 < e ? d[(j + 1) * W] : (CT)0;
+        CT v2 = j + 2 < e ? d[(j + 2) * W] : (CT)0;
+        CT v3 = j + 3 < e ? d[(j + 3) * W] : (CT)0;
+        s += (double)v0;
+        if (j + 1 < e) s += (double)v1;
+        if (j + 2 < e) s += (double)v2;
+        if (j + 3 < e) s += (double)v3;
+    }
+    out[t] = (OT)s;
+}
+
+// Concatenated segment bounds: out[i] = in[i] + off for i in [0, n].
+__global__ void k_offset_ptr(const int64_t *in, int64_t n, int64_t off, int64_t *out)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i <= n) out[i] = in[i] + off;
+}
+
+__global__ void k_batch_begin(int32_t *head, int32_t *status, int n_meshes)
+{
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) *head = 0;
+    if (i < n_meshes) status[i] = INT_MAX;
+}
+
+__global__ void k_batch_end(int32_t *status, int n_meshes, int32_t *out)
+{
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n_meshes) {
+        int32_t v = status[i] == INT_MAX ? -1 : status[i];
+        if (out) out[i] = v;
+    }
+}
+
+}  // namespace fea
+
+using namespace fea;
+
+struct fea_batch {
+    int device = 0;
+    int model = FEA_ELASTIC;
+    int n_meshes = 0;
+    std::vector<fea_mesh_desc> desc;
+    std::vector<fea_graph *> graphs;
+    std::vector<int64_t> vals_off, rhs_off, slot_off, inc_off;  // scalars / slots / incidences
+    int64_t n_elems = 0, total_blocks = 0, total_slots = 0, total_inc = 0;
+    int32_t tile[4] = {64, 40, 28, 16};
+    std::vector<int32_t> items;  // 4 per item
+    std::vector<int32_t> order;
+    // device
+    BatchMesh *d_meshes = nullptr;
+    int4 *d_items = nullptr;
+    int32_t *d_order = nullptr;
+    int32_t *d_head = nullptr;
+    int32_t *d_status = nullptr;
+    int64_t *d_vseg = nullptr, *d_rseg = nullptr;
+    uint64_t *d_cycles = nullptr;
+    int32_t *d_worker = nullptr, *d_cu = nullptr;
+    size_t items_cap = 0;
+    void *contrib = nullptr;
+    size_t contrib_bytes = 0;
+    void *rcontrib = nullptr;
+    size_t rcontrib_bytes = 0;
+    int workers = 0;
+    int workers_for = -1;  // (model, precision) the worker count was computed for
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool timed = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void drop_graph(fea_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+void destroy_batch(fea_batch *b)
+{
+    if (!b) return;
+    drop_graph(b);
+    for (fea_graph *g : b->graphs)
+        if (g) fea_graph_destroy(g);
+    void *bufs[] = {b->d_meshes, b->d_items, b->d_order, b->d_head, b->d_status, b->d_vseg,
+                    b->d_rseg, b->d_cycles, b->d_worker, b->d_cu, b->contrib, b->rcontrib};
+    for (void *p : bufs) dfree(p);
+    for (hipEvent_t e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete b;
+}
+
+int build_items(fea_batch *b)
+{
+    b->items.clear();
+    for (int t = 0; t < 4; ++t)
+        for (int m = 0; m < b->n_meshes; ++m) {
+            const fea_graph *g = b->graphs[m];
+            const int64_t n = g->seg[t + 1] - g->seg[t];
+            for (int64_t s = 0; s < n; s += b->tile[t]) {
+                b->items.push_back(m);
+                b->items.push_back(t);
+                b->items.push_back((int32_t)s);
+                b->items.push_back((int32_t)std::min<int64_t>(b->tile[t], n - s));
+            }
+        }
+    const size_t ni = b->items.size() / 4;
+    b->order.resize(ni);
+    for (size_t i = 0; i < ni; ++i) b->order[i] = (int32_t)i;
+    if (ni > b->items_cap) {
+        void *bufs[] = {b->d_items, b->d_order, b->d_cycles, b->d_worker, b->d_cu};
+        for (void *p : bufs) dfree(p);
+        b->d_items = nullptr;
+        b->d_order = nullptr;
+        b->d_cycles = nullptr;
+        b->d_worker = b->d_cu = nullptr;
+        int rc;
+        if ((rc = dalloc((void **)&b->d_items, sizeof(int4) * ni))) return rc;
+        if ((rc = dalloc((void **)&b->d_order, sizeof(int32_t) * ni))) return rc;
+        if ((rc = dalloc((void **)&b->d_cycles, sizeof(uint64_t) * ni))) return rc;
+        if ((rc = dalloc((void **)&b->d_worker, sizeof(int32_t) * ni))) return rc;
+        if ((rc = dalloc((void **)&b->d_cu, sizeof(int32_t) * ni))) return rc;
+        b->items_cap = ni;
+    }
+    if (ni) {
+        FEA_HIP(hipMemcpy(b->d_items, b->items.data(), sizeof(int4) * ni, hipMemcpyHostToDevice));
+        FEA_HIP(hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice));
+    }
+    drop_graph(b);
+    return FEA_OK;
+}
+
+template <int MODEL, typename CT>
+int worker_count(fea_batch *b)
+{
+    const int key = MODEL * 2 + (sizeof(CT) == 4);
+    if (b->workers_for == key) return FEA_OK;
+    int cus = 0, per = 0;
+    FEA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<MODEL, CT>, 256, 0));
+    b->workers = std::max(1, cus * std::max(1, per));
+    b->workers_for = key;
+    return FEA_OK;
+}
+
+template <int MODEL, typename CT, typename OT>
+int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void *rhs,
+                 int32_t *status)
+{
+    constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
+    constexpr int BB = B * B;
+    int rc;
+    if ((rc = worker_count<MODEL, CT>(b))) return rc;
+    const size_t need_c = sizeof(CT) * (size_t)b->total_slots * BB;
+    const size_t need_r = sizeof(CT) * (size_t)b->total_inc * B;
+    if (b->contrib_bytes < need_c) {
+        dfree(b->contrib);
+        b->contrib = nullptr;
+        b->contrib_bytes = 0;
+        if ((rc = dalloc(&b->contrib, need_c))) return rc;
+        b->contrib_bytes = need_c;
+    }
+    if (b->rcontrib_bytes < need_r) {
+        dfree(b->rcontrib);
+        b->rcontrib = nullptr;
+        b->rcontrib_bytes = 0;
+        if ((rc = dalloc(&b->rcontrib, need_r))) return rc;
+        b->rcontrib_bytes = need_r;
+    }
+    const int32_t ni = (int32_t)(b->items.size() / 4);
+    k_batch_begin<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_head, b->d_status, b->n_meshes);
+    if (o->timing) FEA_HIP(hipEventRecord(b->ev[0], s));
+    if (ni)
+        k_batch<MODEL, CT><<<b->workers, 256, 0, s>>>(b->d_meshes, b->d_items, b->d_order, ni, b->d_head,
+                                                      (CT *)b->contrib, (CT *)b->rcontrib, b->d_status,
+                                                      b->d_cycles, b->d_worker, b->d_cu);
+    if (o->timing) FEA_HIP(hipEventRecord(b->ev[1], s));
+    const int64_t nv = b->total_blocks * BB, nr = b->rhs_off.back();
+    if (nv) k_breduce<BB, CT, OT><<<grid_for(nv, 256), 256, 0, s>>>(b->total_blocks, b->d_vseg, (const CT *)b->contrib, (OT *)vals);
+    if (nr) k_breduce<B, CT, OT><<<grid_for(nr, 256), 256, 0, s>>>(nr / B, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs);
+    k_batch_end<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_status, b->n_meshes, status);
+    FEA_HIP(hipGetLastError());
+    return FEA_OK;
+}
+
+int dispatch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void *rhs, int32_t *status)
+{
+    const bool f32 = o->out_dtype == FEA_F32;
+    if (b->model == FEA_POISSON) {
+        if (o->precision == FEA_FP64)
+            return f32 ? launch_batch<FEA_POISSON, double, float>(b, o, s, vals, rhs, status)
+                       : launch_batch<FEA_POISSON, double, double>(b, o, s, vals, rhs, status);
+        return f32 ? launch_batch<FEA_POISSON, float, float>(b, o, s, vals, rhs, status)
+                   : launch_batch<FEA_POISSON, float, double>(b, o, s, vals, rhs, status);
+    }
+    if (o->precision == FEA_FP64)
+        return f32 ? launch_batch<FEA_ELASTIC, double, float>(b, o, s, vals, rhs, status)
+                   : launch_batch<FEA_ELASTIC, double, double>(b, o, s, vals, rhs, status);
+    return f32 ? launch_batch<FEA_ELASTIC, float, float>(b, o, s, vals, rhs, status)
+               : launch_batch<FEA_ELASTIC, float, double>(b, o, s, vals, rhs, status);
+}
+
+int check_opts(const fea_batch *b, const fea_options *o)
+{
+    if (!b || !o) return set_error(FEA_EINVAL, "batch and options are required");
+    if (o->variant != FEA_ROWOWNER) return set_error(FEA_EINVAL, "batched assembly is row-owner only");
+    if (o->precision < 0 || o->precision > 1 || o->out_dtype < 0 || o->out_dtype > 1)
+        return set_error(FEA_EINVAL, "bad option");
+    int dev = 0;
+    FEA_HIP(hipGetDevice(&dev));
+    if (dev != b->device) return set_error(FEA_EINVAL, "batch lives on device %d, current is %d", b->device, dev);
+    return FEA_OK;
+}
+
+int check_tiles(const int32_t *tile)
+{
+    for (int t = 0; t < 4; ++t)
+        if (tile[t] < 1 || tile[t] > (1 << 20)) return set_error(FEA_EINVAL, "tile[%d] = %d out of range", t, tile[t]);
+    return FEA_OK;
+}
+
+int build(int n, const fea_mesh_desc *md, int model, const int32_t *tile, hipStream_t s, fea_batch *b)
+{
+    int rc;
+    FEA_HIP(hipGetDevice(&b->device));
+    b->model = model;
+    b->n_meshes = n;
+    b->desc.assign(md, md + n);
+    b->graphs.assign(n, nullptr);
+    if (tile) {
+        if ((rc = check_tiles(tile))) return rc;
+        std::copy(tile, tile + 4, b->tile);
+    }
+    const int B = model == FEA_POISSON ? 1 : 3;
+    b->vals_off.assign(1, 0);
+    b->rhs_off.assign(1, 0);
+    b->slot_off.assign(1, 0);
+    b->inc_off.assign(1, 0);
+    for (int m = 0; m < n; ++m) {
+        const fea_mesh_desc &d = md[m];
+        if (d.n_elems > 0 && (!d.x || !d.y || !d.z || !d.source || (model == FEA_ELASTIC && !d.nu) ||
+                              (d.nh_flag && !d.u)))
+            return set_error(FEA_EINVAL, "mesh %d: NULL array argument", m);
+        rc = fea_graph_build(d.n_nodes, d.n_elems, d.types, d.conn_ptr, d.conn, s, &b->graphs[m]);
+        if (rc) {
+            std::string msg = fea_last_error();
+            return set_error(rc, "mesh %d: %s", m, msg.c_str());
+        }
+        const fea_graph *g = b->graphs[m];
+        b->vals_off.push_back(b->vals_off.back() + g->nnz * B * B);
+        b->rhs_off.push_back(b->rhs_off.back() + g->n_nodes * B);
+        b->slot_off.push_back(b->slot_off.back() + g->map_len);
+        b->inc_off.push_back(b->inc_off.back() + g->conn_len);
+        b->n_elems += g->n_elems;
+        b->total_blocks += g->nnz;
+    }
+    b->total_slots = b->slot_off.back();
+    b->total_inc = b->inc_off.back();
+    if (b->total_slots > INT64_MAX / 16) return set_error(FEA_ERANGE, "batch too large");
+
+    // per-mesh kernel views and the concatenated segment bounds
+    std::vector<BatchMesh> bm(n);
+    for (int m = 0; m < n; ++m) {
+        const fea_mesh_desc &d = md[m];
+        const fea_graph *g = b->graphs[m];
+        ElemArgs a = {};
+        a.x = d.x; a.y = d.y; a.z = d.z;
+        a.conn_ptr = d.conn_ptr;
+        a.conn = d.conn;
+        a.elems = g->perm;
+        a.map_ptr = g->map_ptr;
+        a.e2nnz = g->e2nnz;
+        a.e2pos = g->e2pos;
+        a.rpos = g->rpos;
+        a.young = d.young;
+        a.nu = d.nu;
+        a.nh_flag = model == FEA_ELASTIC ? d.nh_flag : nullptr;
+        a.u = d.u;
+        a.source = d.source;
+        bm[m].a = a;
+        std::copy(g->seg, g->seg + 5, bm[m].seg);
+        bm[m].coff = b->slot_off[m];
+        bm[m].roff = b->inc_off[m];
+    }
+    if ((rc = dalloc((void **)&b->d_meshes, sizeof(BatchMesh) * std::max(n, 1)))) return rc;
+    if (n) FEA_HIP(hipMemcpy(b->d_meshes, bm.data(), sizeof(BatchMesh) * n, hipMemcpyHostToDevice));
+    if ((rc = dalloc((void **)&b->d_head, sizeof(int32_t)))) return rc;
+    if ((rc = dalloc((void **)&b->d_status, sizeof(int32_t) * std::max(n, 1)))) return rc;
+    if ((rc = dalloc((void **)&b->d_vseg, sizeof(int64_t) * (b->total_blocks + 1)))) return rc;
+    if ((rc = dalloc((void **)&b->d_rseg, sizeof(int64_t) * (b->rhs_off.back() / B + 1)))) return rc;
+    int64_t zero = 0;
+    FEA_HIP(hipMemcpy(b->d_vseg, &zero, sizeof(int64_t), hipMemcpyHostToDevice));
+    FEA_HIP(hipMemcpy(b->d_rseg, &zero, sizeof(int64_t), hipMemcpyHostToDevice));
+    int64_t kb = 0, nb = 0;
+    for (int m = 0; m < n; ++m) {
+        const fea_graph *g = b->graphs[m];
+        if (g->nnz) k_offset_ptr<<<grid_for(g->nnz + 1, 256), 256, 0, s>>>(g->inv_ptr, g->nnz, b->slot_off[m], b->d_vseg + kb);
+        if (g->n_nodes) k_offset_ptr<<<grid_for(g->n_nodes + 1, 256), 256, 0, s>>>(g->n2e_ptr, g->n_nodes, b->inc_off[m], b->d_rseg + nb);
+        kb += g->nnz;
+        nb += g->n_nodes;
+    }
+    FEA_HIP(hipGetLastError());
+    FEA_HIP(hipStreamSynchronize(s));
+    for (hipEvent_t &e : b->ev) FEA_HIP(hipEventCreate(&e));
+    return build_items(b);
+}
+
+}  // namespace
+
+extern "C" int fea_batch_build(int n_meshes, const fea_mesh_desc *meshes, int model, const int32_t *tile,
+                               hipStream_t stream, fea_batch **out)
+{
+    clear_error();
+    if (!out) return set_error(FEA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_meshes < 0 || (n_meshes > 0 && !meshes)) return set_error(FEA_EINVAL, "bad mesh list");
+    if (model != FEA_POISSON && model != FEA_ELASTIC) return set_error(FEA_EINVAL, "unknown model %d", model);
+    fea_batch *b = new (std::nothrow) fea_batch();
+    if (!b) return set_error(FEA_ENOMEM, "host allocation failed");
+    int rc = ensure_tables();
+    if (!rc) rc = build(n_meshes, meshes, model, tile, stream, b);
+    if (rc) {
+        std::string msg = fea_last_error();
+        (void)hipStreamSynchronize(stream);
+        destroy_batch(b);
+        return set_error(rc, "%s", msg.c_str());
+    }
+    *out = b;
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_sizes(const fea_batch *b, int64_t *vals_len, int64_t *rhs_len, int64_t *n_items,
+                               int64_t *n_elems)
+{
+    clear_error();
+    if (!b) return set_error(FEA_EINVAL, "batch is NULL");
+    if (vals_len) *vals_len = b->vals_off.back();
+    if (rhs_len) *rhs_len = b->rhs_off.back();
+    if (n_items) *n_items = (int64_t)(b->items.size() / 4);
+    if (n_elems) *n_elems = b->n_elems;
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_offsets(const fea_batch *b, int64_t *vals_off, int64_t *rhs_off)
+{
+    clear_error();
+    if (!b) return set_error(FEA_EINVAL, "batch is NULL");
+    if (vals_off) std::copy(b->vals_off.begin(), b->vals_off.end(), vals_off);
+    if (rhs_off) std::copy(b->rhs_off.begin(), b->rhs_off.end(), rhs_off);
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_items(const fea_batch *b, int32_t *items)
+{
+    clear_error();
+    if (!b || !items) return set_error(FEA_EINVAL, "batch and items are required");
+    std::copy(b->items.begin(), b->items.end(), items);
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_set_tiles(fea_batch *b, const int32_t *tile)
+{
+    clear_error();
+    if (!b || !tile) return set_error(FEA_EINVAL, "batch and tile are required");
+    int rc = check_tiles(tile);
+    if (rc) return rc;
+    std::copy(tile, tile + 4, b->tile);
+    return build_items(b);
+}
+
+extern "C" int fea_batch_set_order(fea_batch *b, const int32_t *order)
+{
+    clear_error();
+    if (!b || !order) return set_error(FEA_EINVAL, "batch and order are required");
+    const size_t ni = b->items.size() / 4;
+    std::vector<char> seen(ni, 0);
+    for (size_t j = 0; j < ni; ++j) {
+        if (order[j] < 0 || (size_t)order[j] >= ni || seen[order[j]])
+            return set_error(FEA_EINVAL, "order is not a permutation of the %zu items", ni);
+        seen[order[j]] = 1;
+    }
+    b->order.assign(order, order + ni);
+    if (ni) FEA_HIP(hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice));
+    drop_graph(b);
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_assemble(fea_batch *b, const fea_options *opt, hipStream_t stream, void *vals,
+                                  void *rhs, int32_t *status)
+{
+    clear_error();
+    int rc = check_opts(b, opt);
+    if (rc) return rc;
+    if ((b->vals_off.back() && !vals) || (b->rhs_off.back() && !rhs))
+        return set_error(FEA_EINVAL, "NULL output argument");
+    if ((rc = ensure_tables())) return rc;
+    b->timed = false;
+    if ((rc = dispatch(b, opt, stream, vals, rhs, status))) return rc;
+    b->timed = opt->timing != 0;
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_capture(fea_batch *b, const fea_options *opt, hipStream_t stream, void *vals,
+                                 void *rhs, int32_t *status)
+{
+    clear_error();
+    int rc = check_opts(b, opt);
+    if (rc) return rc;
+    if ((b->vals_off.back() && !vals) || (b->rhs_off.back() && !rhs))
+        return set_error(FEA_EINVAL, "NULL output argument");
+    if ((rc = ensure_tables())) return rc;
+    fea_options o = *opt;
+    o.timing = 0;
+    // size the workspaces and the worker count outside the capture
+    if ((rc = dispatch(b, &o, stream, vals, rhs, status))) return rc;
+    FEA_HIP(hipStreamSynchronize(stream));
+    drop_graph(b);
+    FEA_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    rc = dispatch(b, &o, stream, vals, rhs, status);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return set_error(FEA_EHIP, "stream capture failed: %s", hipGetErrorString(e));
+    b->graph = graph;
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(b);
+        return set_error(FEA_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_replay(fea_batch *b, int n, hipStream_t stream)
+{
+    clear_error();
+    if (!b || !b->exec) return set_error(FEA_EINVAL, "no captured graph");
+    for (int i = 0; i < n; ++i) FEA_HIP(hipGraphLaunch(b->exec, stream));
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_cycles(const fea_batch *b, uint64_t *cycles, int32_t *worker, int32_t *cu,
+                                hipStream_t s)
+{
+    clear_error();
+    if (!b) return set_error(FEA_EINVAL, "batch is NULL");
+    const size_t ni = b->items.size() / 4;
+    if (!ni) return FEA_OK;
+    if (cycles) FEA_HIP(hipMemcpyAsync(cycles, b->d_cycles, sizeof(uint64_t) * ni, hipMemcpyDeviceToDevice, s));
+    if (worker) FEA_HIP(hipMemcpyAsync(worker, b->d_worker, sizeof(int32_t) * ni, hipMemcpyDeviceToDevice, s));
+    if (cu) FEA_HIP(hipMemcpyAsync(cu, b->d_cu, sizeof(int32_t) * ni, hipMemcpyDeviceToDevice, s));
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_last_ms(const fea_batch *b, float *ms)
+{
+    clear_error();
+    if (!b || !ms) return set_error(FEA_EINVAL, "batch and ms are required");
+    if (!b->timed) return set_error(FEA_EINVAL, "no timed batched assembly");
+    FEA_HIP(hipEventSynchronize(b->ev[1]));
+    FEA_HIP(hipEventElapsedTime(ms, b->ev[0], b->ev[1]));
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_workers(const fea_batch *b, int *workers)
+{
+    clear_error();
+    if (!b || !workers) return set_error(FEA_EINVAL, "batch and workers are required");
+    *workers = b->workers;
+    return FEA_OK;
+}
+
+extern "C" void fea_batch_destroy(fea_batch *b)
+{
+    if (b) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(b->device);
+        (void)hipDeviceSynchronize();
+        destroy_batch(b);
+        (void)hipSetDevice(cur);
+    }
+}

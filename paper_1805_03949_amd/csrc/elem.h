@@ -1,0 +1,494 @@
+// Element quadrature device code shared by the one-launch-per-family
+// kernels and the persistent batched kernel.
+//
+//
+// Element arithmetic (isoparametric, Gauss quadrature):
+//   J = sum_a x_a (x) dN_a/dxi, G_a = J^-T dN_a/dxi, wd = w_q detJ
+//   Poisson     K_ab    += wd G_a.G_b,            f_a   += wd N_a f
+//   elasticity  K_ab,ij += wd [lam h_a,i h_b,j + c2 h_a,j h_b,i
+//                              + mu delta_ij G_a.G_b],  f_a,i += wd N_a f_i
+// with h = G and c2 = mu for linear elasticity, and for the compressible
+// neo-Hookean tangent (Section 2.2, A = Jacobian of the first Piola-Kirchhoff
+// stress) F = I + sum_a u_a (x) G_a, h_a = F^-T-applied gradient
+// (h_a,j = sum_J G_a,J Finv_Jj) and c2 = mu - lam ln det F. That factored
+// form is algebraically identical to contracting the 81-entry tangent
+// AA_iJjL = mu d_ij d_JL + (mu - lam lnJ) Finv_Jj Finv_Li + lam Finv_Ji Finv_Lj.
+//
+// Work layout: one 256-thread workgroup holds EPB = 256 / n^2 elements of
+// one family; geometry runs one thread per (element, Gauss point) and
+// writes gradients to LDS; the element matrix runs one thread per
+// (element, block a-b), each accumulating its b x b block over the Gauss
+// points; the right-hand side one thread per (element, node).
+#pragma once
+#include <climits>
+#include <cstring>
+#include <mutex>
+
+#include "fea_internal.h"
+
+namespace fea {
+
+struct RefTables {
+    double N[4][8][8];      // [family][gauss point][node]
+    double dN[4][8][8][3];  // [family][gauss point][node][reference direction]
+    double w[4][8];
+};
+
+// one copy per translation unit, uploaded by that unit's ensure_tables()
+static __constant__ RefTables c_ref;
+
+template <int T>
+struct Fam {
+    static constexpr int NN = 4 + T + (T == 3);
+    static constexpr int NQ = T == 0 ? 1 : (T == 2 ? 6 : 8);
+};
+
+// Reference shape functions and Gauss rules (host side, uploaded once per
+// device). hex8 / pyr5: 2x2x2 Gauss, xi fastest; pen6: 3-point triangle
+// rule (weights 1/6) x 2-point Gauss in t, triangle point fastest; tet4:
+// one point at the centroid, weight 1/6. The pyramid is the hexahedron with
+// its top face collapsed into the apex.
+static void shape_host(int t, const double p[3], double N[8], double dN[8][3])
+{
+    static const int sg[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                 {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+    if (t == 3 || t == 1) {
+        double h[8], dh[8][3];
+        for (int a = 0; a < 8; ++a) {
+            double fx = 0.5 * (1 + sg[a][0] * p[0]), fy = 0.5 * (1 + sg[a][1] * p[1]),
+                   fz = 0.5 * (1 + sg[a][2] * p[2]);
+            h[a] = fx * fy * fz;
+            dh[a][0] = 0.5 * sg[a][0] * fy * fz;
+            dh[a][1] = 0.5 * sg[a][1] * fx * fz;
+            dh[a][2] = 0.5 * sg[a][2] * fx * fy;
+        }
+        int nb = t == 3 ? 8 : 4;
+        for (int a = 0; a < nb; ++a) {
+            N[a] = h[a];
+            for (int j = 0; j < 3; ++j) dN[a][j] = dh[a][j];
+        }
+        if (t == 1) {
+            N[4] = h[4] + h[5] + h[6] + h[7];
+            for (int j = 0; j < 3; ++j) dN[4][j] = dh[4][j] + dh[5][j] + dh[6][j] + dh[7][j];
+        }
+    } else if (t == 2) {
+        double L[3] = {1 - p[0] - p[1], p[0], p[1]};
+        double dL[3][2] = {{-1, -1}, {1, 0}, {0, 1}};
+        for (int a = 0; a < 6; ++a) {
+            int k = a % 3;
+            double s = a < 3 ? -1.0 : 1.0;
+            double g = 0.5 * (1 + s * p[2]);
+            N[a] = L[k] * g;
+            dN[a][0] = dL[k][0] * g;
+            dN[a][1] = dL[k][1] * g;
+            dN[a][2] = 0.5 * s * L[k];
+        }
+    } else {
+        N[0] = 1 - p[0] - p[1] - p[2];
+        N[1] = p[0];
+        N[2] = p[1];
+        N[3] = p[2];
+        for (int a = 0; a < 4; ++a)
+            for (int j = 0; j < 3; ++j) dN[a][j] = (a == 0) ? -1.0 : (a - 1 == j ? 1.0 : 0.0);
+    }
+}
+
+static void build_tables(RefTables *R)
+{
+    memset(R, 0, sizeof(*R));
+    const double g = 0.57735026918962576451;  // 1/sqrt(3)
+    for (int t = 0; t < 4; ++t) {
+        double pts[8][3], w[8];
+        int nq = 0;
+        if (t == 0) {
+            pts[0][0] = pts[0][1] = pts[0][2] = 0.25;
+            w[0] = 1.0 / 6.0;
+            nq = 1;
+        } else if (t == 2) {
+            const double tr[3][2] = {{1.0 / 6, 1.0 / 6}, {2.0 / 3, 1.0 / 6}, {1.0 / 6, 2.0 / 3}};
+            for (int k = 0; k < 2; ++k)
+                for (int i = 0; i < 3; ++i, ++nq) {
+                    pts[nq][0] = tr[i][0];
+                    pts[nq][1] = tr[i][1];
+                    pts[nq][2] = k ? g : -g;
+                    w[nq] = 1.0 / 6.0;
+                }
+        } else {
+            for (int k = 0; k < 2; ++k)
+                for (int j = 0; j < 2; ++j)
+                    for (int i = 0; i < 2; ++i, ++nq) {
+                        pts[nq][0] = i ? g : -g;
+                        pts[nq][1] = j ? g : -g;
+                        pts[nq][2] = k ? g : -g;
+                        w[nq] = 1.0;
+                    }
+        }
+        for (int q = 0; q < nq; ++q) {
+            double N[8] = {0}, dN[8][3] = {{0}};
+            shape_host(t, pts[q], N, dN);
+            R->w[t][q] = w[q];
+            for (int a = 0; a < 8; ++a) {
+                R->N[t][q][a] = N[a];
+                for (int j = 0; j < 3; ++j) R->dN[t][q][a][j] = dN[a][j];
+            }
+        }
+    }
+}
+
+static int ensure_tables()
+{
+    static std::mutex mtx;
+    static bool done[64] = {false};
+    int dev = 0;
+    FEA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(FEA_EINVAL, "device index %d unsupported", dev);
+    std::lock_guard<std::mutex> lock(mtx);
+    if (done[dev]) return FEA_OK;
+    RefTables R;
+    build_tables(&R);
+    FEA_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_ref), &R, sizeof(R), 0, hipMemcpyHostToDevice));
+    done[dev] = true;
+    return FEA_OK;
+}
+
+struct ElemArgs {
+    const double *x, *y, *z;
+    const int64_t *conn_ptr;
+    const int32_t *conn;
+    const int32_t *elems;  // element ids handled by this launch
+    int64_t n;             // number of ids
+    const int64_t *map_ptr;
+    const int32_t *e2nnz;
+    const int32_t *e2pos;  // row-owner: destination position of every slot
+    const int32_t *rpos;   // row-owner: destination position of every conn entry
+    const double *young, *nu;
+    const uint8_t *nh_flag;
+    const double *u;
+    const double *source;
+    double *vals;    // FP64 target of ATOMIC / COLOUR
+    double *rhs;
+    void *contrib;   // ROWOWNER slot workspace (compute type)
+    void *rcontrib;  // ROWOWNER right-hand-side workspace
+    int32_t *status;
+};
+
+enum { V_ROWOWNER = 0, V_ATOMIC = 1, V_COLOUR = 2 };
+
+__device__ inline double det3(const double J[3][3])
+{
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// inverse through the adjugate
+__device__ inline void inv3(const double J[3][3], double d, double Ji[3][3])
+{
+    double r = 1.0 / d;
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * r;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * r;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * r;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+}
+
+// The hardware hands workgroup b to XCD b % 8. Renumbering tiles so that
+// each XCD receives one contiguous range keeps neighbouring elements (which
+// share nodes, coordinates and destination cache lines) in the same L2.
+// The thread index as a value the compiler cannot treat as loop-invariant:
+// inside a persistent loop this keeps per-thread index arithmetic from being
+// hoisted out of the loop and held in registers across iterations.
+__device__ inline int opaque_tid()
+{
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    return t;
+}
+
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nblk)
+{
+    const int64_t q = nblk >> 3, rem = nblk & 7, x = b & 7, r = b >> 3;
+    return x * q + (x < rem ? x : rem) + r;
+}
+
+template <int T, int MODEL, int VAR, typename CT>
+struct ElemSmem {
+    static constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
+    static constexpr int EPB = 256 / P;
+    static constexpr bool ELAS = MODEL != FEA_POISSON;
+    static constexpr int B = ELAS ? 3 : 1;
+    static constexpr int BB = B * B;
+    static constexpr int EU = ELAS ? EPB : 1;
+    static constexpr bool RO = VAR == V_ROWOWNER;
+
+    double sX[EPB][NN][3];
+    double sU[EU][NN][3];
+    CT sG[EPB][NQ][NN][3];   // physical gradients
+    CT sH[EU][NQ][NN][3];    // neo-Hookean: gradients pushed through F^-T
+    CT sC[EPB][NQ][4];       // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
+    double sLM[EU][2];       // lam, mu
+    int32_t sE[EPB];
+    int sNH[EPB];
+    int64_t sM[EPB];         // first slot of each element
+    int64_t sCP[EPB];        // first conn position of each element
+    double sDN[NQ][NN][3];   // reference gradients of this family
+    double sNr[NQ][NN];      // reference shape functions
+
+};
+
+// Processes the EPB elements A.elems[first .. first + EPB) (ids beyond A.n
+// are skipped) with the calling workgroup's 256 threads and LDS S.
+template <int T, int MODEL, int VAR, typename CT>
+__device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, VAR, CT> &S,
+                          const int tid = threadIdx.x)
+{
+    constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
+    constexpr int EPB = 256 / P;
+    constexpr bool ELAS = MODEL != FEA_POISSON;
+    constexpr int B = ELAS ? 3 : 1;
+    constexpr int BB = B * B;
+    constexpr int EU = ELAS ? EPB : 1;
+    constexpr bool RO = VAR == V_ROWOWNER;
+
+    auto &sX = S.sX;
+    auto &sU = S.sU;
+    auto &sG = S.sG;
+    auto &sH = S.sH;
+    auto &sC = S.sC;
+    auto &sLM = S.sLM;
+    auto &sE = S.sE;
+    auto &sNH = S.sNH;
+    auto &sM = S.sM;
+    auto &sCP = S.sCP;
+    auto &sDN = S.sDN;
+    auto &sNr = S.sNr;
+    __syncthreads();  // the previous tile's readers of S are done
+
+    for (int i = tid; i < NQ * NN; i += 256) {
+        const int q = i / NN, a = i % NN;
+        sNr[q][a] = c_ref.N[T][q][a];
+        sDN[q][a][0] = c_ref.dN[T][q][a][0];
+        sDN[q][a][1] = c_ref.dN[T][q][a][1];
+        sDN[q][a][2] = c_ref.dN[T][q][a][2];
+    }
+
+    if (tid < EPB) {
+        int64_t i = first + tid;
+        int32_t e = i < A.n ? A.elems[i] : -1;
+        sE[tid] = e;
+        sM[tid] = e >= 0 ? A.map_ptr[e] : 0;
+        sCP[tid] = e >= 0 ? A.conn_ptr[e] : 0;
+        sNH[tid] = (ELAS && e >= 0 && A.nh_flag) ? (int)A.nh_flag[e] : 0;
+        if constexpr (ELAS) {
+            double E = (e >= 0 && A.young) ? A.young[e] : 1.0, nu = e >= 0 ? A.nu[e] : 0.25;
+            sLM[tid][0] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+            sLM[tid][1] = E / (2.0 * (1.0 + nu));
+        }
+    }
+    __syncthreads();
+
+    if (tid < EPB * NN) {
+        int el = tid / NN, a = tid % NN;
+        int32_t e = sE[el];
+        if (e >= 0) {
+            int32_t v = A.conn[sCP[el] + a];
+            sX[el][a][0] = A.x[v];
+            sX[el][a][1] = A.y[v];
+            sX[el][a][2] = A.z[v];
+            if constexpr (ELAS) {
+                bool nh = sNH[el] != 0;
+                for (int k = 0; k < 3; ++k) sU[el][a][k] = nh ? A.u[3 * (int64_t)v + k] : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+
+    // geometry: one thread per (element, Gauss point), in FP64
+    if (tid < EPB * NQ) {
+        int el = tid / NQ, q = tid % NQ;
+        int32_t e = sE[el];
+        if (e >= 0) {
+            double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+            for (int a = 0; a < NN; ++a)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) J[i][j] += sX[el][a][i] * sDN[q][a][j];
+            double d = det3(J);
+            if (!(d > 0.0)) atomicMin(A.status, e);
+            double Ji[3][3];
+            inv3(J, d, Ji);
+            double G[NN][3];
+#pragma unroll
+            for (int a = 0; a < NN; ++a)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    G[a][i] = Ji[0][i] * sDN[q][a][0] + Ji[1][i] * sDN[q][a][1] + Ji[2][i] * sDN[q][a][2];
+                    sG[el][q][a][i] = (CT)G[a][i];
+                }
+            double wd = c_ref.w[T][q] * d;
+            sC[el][q][0] = (CT)wd;
+            if constexpr (ELAS) {
+                if (sNH[el]) {
+                    const double lam = sLM[el][0], mu = sLM[el][1];
+                    double F[3][3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+                            for (int a = 0; a < NN; ++a) acc += sU[el][a][i] * G[a][j];
+                            F[i][j] = acc;
+                        }
+                    double jf = det3(F);
+                    if (!(jf > 0.0)) atomicMin(A.status, e);
+                    double Fi[3][3];
+                    inv3(F, jf, Fi);
+#pragma unroll
+                    for (int a = 0; a < NN; ++a)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j)
+                            sH[el][q][a][j] =
+                                (CT)(G[a][0] * Fi[0][j] + G[a][1] * Fi[1][j] + G[a][2] * Fi[2][j]);
+                    sC[el][q][1] = (CT)(wd * lam);
+                    sC[el][q][2] = (CT)(wd * (mu - lam * log(jf)));
+                    sC[el][q][3] = (CT)(wd * mu);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // element matrix: one thread per (element, block a-b)
+    if (tid < EPB * P) {
+        int el = tid / P, p = tid % P, a = p / NN, b = p % NN;
+        int32_t e = sE[el];
+        if (e >= 0) {
+            // destination of this block, fetched before the contraction
+            const int64_t dest = RO ? (int64_t)A.e2pos[sM[el] + p] : (int64_t)A.e2nnz[sM[el] + p];
+            CT K[BB];
+            if constexpr (!ELAS) {
+                CT acc = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    CT dot = sG[el][q][a][0] * sG[el][q][b][0] + sG[el][q][a][1] * sG[el][q][b][1] +
+                             sG[el][q][a][2] * sG[el][q][b][2];
+                    acc += sC[el][q][0] * dot;
+                }
+                K[0] = acc;
+            } else if (!sNH[el]) {
+                // linear: K = lam S + mu S^T + mu tr(S) I, S = sum_q wd G_a (x) G_b
+                CT S[9];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) S[c] = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    CT w = sC[el][q][0];
+                    CT ga[3] = {w * sG[el][q][a][0], w * sG[el][q][a][1], w * sG[el][q][a][2]};
+                    CT gb[3] = {sG[el][q][b][0], sG[el][q][b][1], sG[el][q][b][2]};
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) S[i * 3 + j] += ga[i] * gb[j];
+                }
+                const CT lam = (CT)sLM[el][0], mu = (CT)sLM[el][1];
+                const CT tr = S[0] + S[4] + S[8];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        CT v = lam * S[i * 3 + j] + mu * S[j * 3 + i];
+                        if (i == j) v += mu * tr;
+                        K[i * 3 + j] = v;
+                    }
+            } else {
+                // neo-Hookean: K_ij = sum_q c1 h_a,i h_b,j + c2 h_a,j h_b,i + c0 d_ij G_a.G_b
+                CT T1[9], T2[9], dsum = 0;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) T1[c] = T2[c] = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    CT c1 = sC[el][q][1], c2 = sC[el][q][2], c0 = sC[el][q][3];
+                    CT ha[3] = {sH[el][q][a][0], sH[el][q][a][1], sH[el][q][a][2]};
+                    CT hb[3] = {sH[el][q][b][0], sH[el][q][b][1], sH[el][q][b][2]};
+                    CT dot = sG[el][q][a][0] * sG[el][q][b][0] + sG[el][q][a][1] * sG[el][q][b][1] +
+                             sG[el][q][a][2] * sG[el][q][b][2];
+                    dsum += c0 * dot;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            CT hh = ha[i] * hb[j];
+                            T1[i * 3 + j] += c1 * hh;
+                            T2[i * 3 + j] += c2 * hh;
+                        }
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        CT v = T1[i * 3 + j] + T2[j * 3 + i];
+                        if (i == j) v += dsum;
+                        K[i * 3 + j] = v;
+                    }
+            }
+            if constexpr (RO) {
+                // row-owner: the workspace is sorted by destination block
+                CT *dst = (CT *)A.contrib + dest * BB;
+#pragma unroll
+                for (int c = 0; c < BB; ++c) dst[c] = K[c];
+            } else {
+                double *dst = A.vals + dest * BB;
+#pragma unroll
+                for (int c = 0; c < BB; ++c) {
+                    if constexpr (VAR == V_ATOMIC)
+                        unsafeAtomicAdd(dst + c, (double)K[c]);
+                    else
+                        dst[c] += (double)K[c];
+                }
+            }
+        }
+    }
+
+    // right-hand side: one thread per (element, node)
+    if (tid < EPB * NN) {
+        int el = tid / NN, a = tid % NN;
+        int32_t e = sE[el];
+        if (e >= 0) {
+            CT f[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) f[i] = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                CT wn = sC[el][q][0] * (CT)sNr[q][a];
+#pragma unroll
+                for (int i = 0; i < B; ++i) f[i] += wn * (CT)A.source[(int64_t)e * B + i];
+            }
+            if constexpr (RO) {
+                CT *dst = (CT *)A.rcontrib + (int64_t)A.rpos[sCP[el] + a] * B;
+#pragma unroll
+                for (int i = 0; i < B; ++i) dst[i] = f[i];
+            } else {
+                int64_t v = A.conn[sCP[el] + a];
+                double *dst = A.rhs + v * B;
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    if constexpr (VAR == V_ATOMIC)
+                        unsafeAtomicAdd(dst + i, (double)f[i]);
+                    else
+                        dst[i] += (double)f[i];
+                }
+            }
+        }
+    }
+
+}
+
+
+}  // namespace fea
