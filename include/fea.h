@@ -235,6 +235,98 @@ int fea_batch_workers(const fea_batch *b, int *workers);
 
 void fea_batch_destroy(fea_batch *b);
 
+/*
+ * Tile autotuner: chooses the elements per work item of each family by
+ * timing the batch's persistent kernel (the GPU counterpart of the paper's
+ * chunk-size study, Section 5.1). Coordinate descent: for each family in
+ * turn the candidates EPB*{1,2,4,8,16,32} are tried with the other tiles
+ * fixed (EPB = elements one workgroup pass holds: 16 tet4, 10 pyr5, 7 pen6,
+ * 4 hex8), two sweeps, each candidate timed as the median of `reps`
+ * launches. The best tiles are applied to the batch, returned in tile_out
+ * (HOST int32[4]) and, if table_path is not NULL, stored in that text file
+ * under the key (gfx950, model, precision). Allocates temporary outputs.
+ */
+int fea_batch_autotune(fea_batch *b, const fea_options *opt, int reps, const char *table_path,
+                       hipStream_t stream, int32_t *tile_out);
+
+/* Reads the tiles stored for (gfx950, model, precision) from a table file
+ * written by fea_batch_autotune. FEA_EINVAL if the file has no such entry. */
+int fea_tile_table_load(const char *table_path, int model, int precision, int32_t *tile_out);
+
+/*
+ * Queue order of a batch (enum fea_schedule):
+ *   FEA_TYPE_SORTED  items by (family, mesh, first element): the static
+ *                    fallback;
+ *   FEA_GP_WEIGHT    largest first by (Gauss points x elements), the paper's
+ *                    a-priori element weight (Section 4.1);
+ *   FEA_LEARNED      largest first by pred[item] (device float[n_items],
+ *                    e.g. fea_cost_predict output), ties by item index.
+ * Drops a captured graph. Waits on `stream` to read pred.
+ */
+int fea_batch_order(fea_batch *b, int schedule, const float *pred, hipStream_t stream);
+
+/*
+ * Cost-model features of every work item (device float[n_items x 12]),
+ * per item: family one-hot (4), fraction of neo-Hookean elements,
+ * log2(element count), log2 of the node-id span per element node
+ * (a locality proxy), mean Poisson ratio, log of the mean and of the
+ * largest element distortion max_q detJ / min_q detJ, log10 of the mean
+ * element volume, and `fp64_geometry` (1 when the geometry runs in FP64).
+ */
+int fea_batch_features(const fea_batch *b, int fp64_geometry, float *feats, hipStream_t stream);
+
+/* ------------------------------------------------------------------ *
+ * Learned cost model: a 12 -> 64 -> 64 -> 1 ReLU perceptron (FP32)      *
+ * predicting log(cycles) of a work item. The paper finds that element   *
+ * cost cannot be known a priori and that Gauss-point weights balance    *
+ * poorly (abstract; Section 4.1); this model learns the weight from the *
+ * cycle counts the batched assembly records.                           *
+ * Parameters: W1[64][12], b1[64], W2[64][64], b2[64], W3[64], b3 (5,057). *
+ * Inputs are standardised with a per-feature mean and scale.           *
+ * ------------------------------------------------------------------ */
+typedef struct fea_cost fea_cost;
+
+#define FEA_COST_FEATURES 12
+#define FEA_COST_PARAMS 5057
+
+/* He-normal weights (seeded, counter-based generator), zero biases,
+ * mean 0 / scale 1, Adam state zero. */
+int fea_cost_create(uint64_t seed, fea_cost **out);
+void fea_cost_destroy(fea_cost *c);
+
+/* HOST copies of the parameters (float[5057]) and of the input
+ * standardisation (float[12] each). */
+int fea_cost_get_params(const fea_cost *c, float *params);
+int fea_cost_set_params(fea_cost *c, const float *params);
+int fea_cost_set_norm(fea_cost *c, const float *mean, const float *scale);
+
+/* Sets the standardisation from device features (float[n x 12]): mean and
+ * population standard deviation per feature (scale 1 where it is 0). */
+int fea_cost_fit_norm(fea_cost *c, const float *feats, int64_t n, hipStream_t stream);
+
+/* pred[i] = model(feats[i]) for i < n (device arrays). */
+int fea_cost_predict(const fea_cost *c, const float *feats, int64_t n, float *pred,
+                     hipStream_t stream);
+
+/* Mean squared error against target (device float[n]) and its gradient
+ * (device float[5057], parameter order), reduced in a fixed order. */
+int fea_cost_grad(const fea_cost *c, const float *feats, const float *target, int64_t n,
+                  float *grad, float *loss, hipStream_t stream);
+
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, step
+ * size lr); loss_hist (device float[steps], may be NULL) receives the loss
+ * before each step. */
+int fea_cost_train(fea_cost *c, const float *feats, const float *target, int64_t n, int steps,
+                   float lr, float *loss_hist, hipStream_t stream);
+
+/* target[i] = log(cycles[i]) (device arrays). */
+int fea_cost_log_cycles(const uint64_t *cycles, int64_t n, float *target, hipStream_t stream);
+
+/* Binary checkpoint: magic, version, "gfx950", standardisation, parameters,
+ * Adam moments and step count. */
+int fea_cost_save(const fea_cost *c, const char *path);
+int fea_cost_load(fea_cost *c, const char *path);
+
 /* Message for the last error on the calling thread ("" if none). */
 const char *fea_last_error(void);
 

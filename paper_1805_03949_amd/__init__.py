@@ -80,6 +80,27 @@ _lib.fea_batch_last_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.fea_batch_workers.argtypes = [_P, ctypes.POINTER(ctypes.c_int)]
 _lib.fea_batch_destroy.argtypes = [_P]
 _lib.fea_batch_destroy.restype = None
+_lib.fea_batch_autotune.argtypes = [_P, ctypes.POINTER(Options), ctypes.c_int, ctypes.c_char_p, _P, _I32P]
+_lib.fea_tile_table_load.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, _I32P]
+_lib.fea_batch_order.argtypes = [_P, ctypes.c_int, _P, _P]
+_lib.fea_batch_features.argtypes = [_P, ctypes.c_int, _P, _P]
+_lib.fea_cost_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(_P)]
+_lib.fea_cost_destroy.argtypes = [_P]
+_lib.fea_cost_destroy.restype = None
+_F32P = ctypes.POINTER(ctypes.c_float)
+_lib.fea_cost_get_params.argtypes = [_P, _F32P]
+_lib.fea_cost_set_params.argtypes = [_P, _F32P]
+_lib.fea_cost_set_norm.argtypes = [_P, _F32P, _F32P]
+_lib.fea_cost_fit_norm.argtypes = [_P, _P, _I64, _P]
+_lib.fea_cost_predict.argtypes = [_P, _P, _I64, _P, _P]
+_lib.fea_cost_grad.argtypes = [_P, _P, _P, _I64, _P, _P, _P]
+_lib.fea_cost_train.argtypes = [_P, _P, _P, _I64, ctypes.c_int, ctypes.c_float, _P, _P]
+_lib.fea_cost_log_cycles.argtypes = [_P, _I64, _P, _P]
+_lib.fea_cost_save.argtypes = [_P, ctypes.c_char_p]
+_lib.fea_cost_load.argtypes = [_P, ctypes.c_char_p]
+
+TYPE_SORTED, LEARNED, GP_WEIGHT = 0, 1, 2
+N_FEATURES, N_PARAMS = 12, 5057
 
 # every exported symbol declared in include/fea.h
 EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_export", "fea_graph_destroy",
@@ -87,7 +108,10 @@ EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_export", "fea_graph_
            "fea_batch_build", "fea_batch_sizes", "fea_batch_offsets", "fea_batch_items",
            "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_assemble", "fea_batch_capture",
            "fea_batch_replay", "fea_batch_cycles", "fea_batch_last_ms", "fea_batch_workers",
-           "fea_batch_destroy")
+           "fea_batch_destroy", "fea_batch_autotune", "fea_tile_table_load", "fea_batch_order",
+           "fea_batch_features", "fea_cost_create", "fea_cost_destroy", "fea_cost_get_params",
+           "fea_cost_set_params", "fea_cost_set_norm", "fea_cost_fit_norm", "fea_cost_predict",
+           "fea_cost_grad", "fea_cost_train", "fea_cost_log_cycles", "fea_cost_save", "fea_cost_load")
 
 
 class FeaError(RuntimeError):
@@ -335,6 +359,24 @@ class Batch:
         _check(_lib.fea_batch_last_ms(self._h, ctypes.byref(ms)))
         return float(ms.value)
 
+    def autotune(self, precision=FP64, out_dtype=F64, reps=5, table_path=None, stream=None):
+        import numpy as np
+        opt = Options(precision, ROWOWNER, out_dtype, 0)
+        tile = np.zeros(4, dtype=np.int32)
+        path = table_path.encode() if table_path else None
+        _check(_lib.fea_batch_autotune(self._h, ctypes.byref(opt), int(reps), path, _stream(stream),
+                                       tile.ctypes.data_as(_I32P)))
+        self._refresh()
+        return tile
+
+    def order(self, schedule, pred=None, stream=None):
+        _check(_lib.fea_batch_order(self._h, int(schedule), _ptr(pred), _stream(stream)))
+
+    def features(self, fp64_geometry=True, stream=None):
+        f = torch.empty((self.n_items, N_FEATURES), dtype=torch.float32, device=self.device)
+        _check(_lib.fea_batch_features(self._h, int(bool(fp64_geometry)), _ptr(f), _stream(stream)))
+        return f
+
     def workers(self):
         w = ctypes.c_int()
         _check(_lib.fea_batch_workers(self._h, ctypes.byref(w)))
@@ -343,6 +385,86 @@ class Batch:
     def destroy(self):
         if getattr(self, "_h", None) is not None:
             _lib.fea_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def tile_table_load(path, model, precision):
+    import numpy as np
+    tile = np.zeros(4, dtype=np.int32)
+    _check(_lib.fea_tile_table_load(path.encode(), int(model), int(precision), tile.ctypes.data_as(_I32P)))
+    return tile
+
+
+class CostModel:
+    """12 -> 64 -> 64 -> 1 ReLU perceptron predicting log(cycles) of a work item."""
+
+    def __init__(self, seed=0, device="cuda"):
+        h = _P()
+        _check(_lib.fea_cost_create(int(seed), ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device(device)
+
+    def params(self):
+        import numpy as np
+        p = np.zeros(N_PARAMS, dtype=np.float32)
+        _check(_lib.fea_cost_get_params(self._h, p.ctypes.data_as(_F32P)))
+        return p
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(_lib.fea_cost_set_params(self._h, p.ctypes.data_as(_F32P)))
+
+    def set_norm(self, mean, scale):
+        import numpy as np
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        sc = np.ascontiguousarray(scale, dtype=np.float32)
+        _check(_lib.fea_cost_set_norm(self._h, m.ctypes.data_as(_F32P), sc.ctypes.data_as(_F32P)))
+
+    def fit_norm(self, feats, stream=None):
+        _dev(feats, torch.float32)
+        _check(_lib.fea_cost_fit_norm(self._h, _ptr(feats), feats.shape[0], _stream(stream)))
+
+    def predict(self, feats, stream=None):
+        _dev(feats, torch.float32)
+        out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+        _check(_lib.fea_cost_predict(self._h, _ptr(feats), feats.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def grad(self, feats, target, stream=None):
+        g = torch.empty(N_PARAMS, dtype=torch.float32, device=feats.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        _check(_lib.fea_cost_grad(self._h, _ptr(feats), _ptr(target), feats.shape[0], _ptr(g), _ptr(loss),
+                                  _stream(stream)))
+        return g, loss
+
+    def train(self, feats, target, steps=500, lr=1e-3, stream=None):
+        hist = torch.empty(max(1, steps), dtype=torch.float32, device=feats.device)
+        _check(_lib.fea_cost_train(self._h, _ptr(feats), _ptr(target), feats.shape[0], int(steps),
+                                   float(lr), _ptr(hist), _stream(stream)))
+        return hist[:steps]
+
+    @staticmethod
+    def log_cycles(cycles, stream=None):
+        out = torch.empty(cycles.shape[0], dtype=torch.float32, device=cycles.device)
+        _check(_lib.fea_cost_log_cycles(_ptr(cycles), cycles.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def save(self, path):
+        _check(_lib.fea_cost_save(self._h, path.encode()))
+
+    def load(self, path):
+        _check(_lib.fea_cost_load(self._h, path.encode()))
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.fea_cost_destroy(self._h)
             self._h = None
 
     def __del__(self):

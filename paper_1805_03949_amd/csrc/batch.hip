@@ -12,6 +12,9 @@
 // row-owner reduction in ascending element order, whatever the queue order.
 #include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "elem.h"
@@ -138,6 +141,91 @@ __global__ void k_batch_end(int32_t *status, int n_meshes, int32_t *out)
     if (i < n_meshes) {
         int32_t v = status[i] == INT_MAX ? -1 : status[i];
         if (out) out[i] = v;
+    }
+}
+
+
+// Work-item features for the cost model: one workgroup per item.
+__device__ inline void block_reduce3(float &a, float &b, float &c, int op_max_b, float *sh)
+{
+    // sums a and c, and b by max (op_max_b) or sum; fixed tree order
+    const int t = threadIdx.x;
+    sh[t] = a;
+    sh[256 + t] = b;
+    sh[512 + t] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+            sh[t] += sh[t + off];
+            sh[256 + t] = op_max_b ? fmaxf(sh[256 + t], sh[256 + t + off]) : sh[256 + t] + sh[256 + t + off];
+            sh[512 + t] += sh[512 + t + off];
+        }
+        __syncthreads();
+    }
+    a = sh[0];
+    b = sh[256];
+    c = sh[512];
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_features(const BatchMesh *meshes, const int4 *items,
+                                                  int fp64, float *feats)
+{
+    __shared__ float sh[768];
+    const int4 w = items[blockIdx.x];
+    const BatchMesh &M = meshes[w.x];
+    const int t = w.y, nn = nodes_of(t);
+    const int nq = t == 0 ? 1 : (t == 2 ? 6 : 8);
+    float nh = 0.f, nu = 0.f, dsum = 0.f, dmax = 0.f, vol = 0.f;
+    float nmin = 3.0e38f, nmax = -1.f;
+    for (int j = threadIdx.x; j < w.w; j += 256) {
+        const int32_t e = M.a.elems[M.seg[t] + w.z + j];
+        if (M.a.nh_flag) nh += M.a.nh_flag[e] ? 1.f : 0.f;
+        if (M.a.nu) nu += (float)M.a.nu[e];
+        double X[8][3];
+        const int64_t c0 = M.a.conn_ptr[e];
+        for (int a = 0; a < nn; ++a) {
+            const int32_t v = M.a.conn[c0 + a];
+            X[a][0] = M.a.x[v];
+            X[a][1] = M.a.y[v];
+            X[a][2] = M.a.z[v];
+            nmin = fminf(nmin, (float)v);
+            nmax = fmaxf(nmax, (float)v);
+        }
+        double dlo = 1e300, dhi = 0.0, ve = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int a = 0; a < nn; ++a)
+                for (int i = 0; i < 3; ++i)
+                    for (int k = 0; k < 3; ++k) J[i][k] += X[a][i] * c_ref.dN[t][q][a][k];
+            const double d = det3(J);
+            dlo = fmin(dlo, d);
+            dhi = fmax(dhi, d);
+            ve += c_ref.w[t][q] * d;
+        }
+        const float de = dlo > 0.0 ? (float)(dhi / dlo) : 1.0e6f;
+        dsum += de;
+        dmax = fmaxf(dmax, de);
+        vol += (float)ve;
+    }
+    block_reduce3(nh, dmax, nu, 1, sh);
+    block_reduce3(dsum, nmax, vol, 1, sh);
+    // min of node ids through the max of their negation
+    float neg = -nmin, zero0 = 0.f, zero1 = 0.f;
+    block_reduce3(zero0, neg, zero1, 1, sh);
+    nmin = -neg;
+    if (threadIdx.x == 0) {
+        const float cnt = (float)w.w;
+        float *f = feats + (int64_t)blockIdx.x * 12;
+        for (int k = 0; k < 4; ++k) f[k] = (k == t) ? 1.f : 0.f;
+        f[4] = nh / cnt;
+        f[5] = log2f(cnt);
+        f[6] = log2f((nmax - nmin + 1.f) / (cnt * nn));
+        f[7] = nu / cnt;
+        f[8] = logf(dsum / cnt);
+        f[9] = logf(dmax);
+        f[10] = log10f(fmaxf(vol / cnt, 1e-30f));
+        f[11] = fp64 ? 1.f : 0.f;
     }
 }
 
@@ -418,6 +506,176 @@ int build(int n, const fea_mesh_desc *md, int model, const int32_t *tile, hipStr
 }
 
 }  // namespace
+
+
+namespace {
+
+const int kEPB[4] = {16, 10, 7, 4};
+const int kNQ[4] = {1, 8, 6, 8};
+
+int upload_order(fea_batch *b)
+{
+    const size_t ni = b->items.size() / 4;
+    if (ni) FEA_HIP(hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice));
+    drop_graph(b);
+    return FEA_OK;
+}
+
+// median duration (ms) of the persistent kernel over `reps` launches
+int time_batch(fea_batch *b, const fea_options *o, int reps, hipStream_t s, void *vals, void *rhs, float *ms)
+{
+    fea_options t = *o;
+    t.timing = 1;
+    std::vector<float> v;
+    int rc;
+    if ((rc = dispatch(b, &t, s, vals, rhs, nullptr))) return rc;  // warm-up
+    for (int r = 0; r < reps; ++r) {
+        if ((rc = dispatch(b, &t, s, vals, rhs, nullptr))) return rc;
+        FEA_HIP(hipEventSynchronize(b->ev[1]));
+        float x = 0.f;
+        FEA_HIP(hipEventElapsedTime(&x, b->ev[0], b->ev[1]));
+        v.push_back(x);
+    }
+    std::sort(v.begin(), v.end());
+    *ms = v[v.size() / 2];
+    return FEA_OK;
+}
+
+std::string table_key(int model, int precision)
+{
+    char k[96];
+    snprintf(k, sizeof(k), "gfx950 model=%d precision=%d", model, precision);
+    return k;
+}
+
+}  // namespace
+
+extern "C" int fea_batch_autotune(fea_batch *b, const fea_options *opt, int reps, const char *table_path,
+                                  hipStream_t stream, int32_t *tile_out)
+{
+    clear_error();
+    int rc = check_opts(b, opt);
+    if (rc) return rc;
+    if (reps < 1) return set_error(FEA_EINVAL, "reps must be positive");
+    if ((rc = ensure_tables())) return rc;
+    const size_t esz = opt->out_dtype == FEA_F32 ? 4 : 8;
+    void *vals = nullptr, *rhs = nullptr;
+    if ((rc = dalloc(&vals, esz * std::max<int64_t>(b->vals_off.back(), 1)))) return rc;
+    if ((rc = dalloc(&rhs, esz * std::max<int64_t>(b->rhs_off.back(), 1)))) {
+        dfree(vals);
+        return rc;
+    }
+    int32_t best[4];
+    std::copy(b->tile, b->tile + 4, best);
+    float best_ms = 0.f;
+    rc = time_batch(b, opt, reps, stream, vals, rhs, &best_ms);
+    const int mult[6] = {1, 2, 4, 8, 16, 32};
+    for (int sweep = 0; sweep < 2 && !rc; ++sweep)
+        for (int t = 0; t < 4 && !rc; ++t) {
+            bool present = false;
+            for (fea_graph *g : b->graphs) present |= g->seg[t + 1] > g->seg[t];
+            if (!present) continue;
+            for (int m : mult) {
+                int32_t cand[4];
+                std::copy(best, best + 4, cand);
+                cand[t] = kEPB[t] * m;
+                if (cand[t] == best[t]) continue;
+                std::copy(cand, cand + 4, b->tile);
+                if ((rc = build_items(b))) break;
+                float ms = 0.f;
+                if ((rc = time_batch(b, opt, reps, stream, vals, rhs, &ms))) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    std::copy(cand, cand + 4, best);
+                }
+            }
+        }
+    dfree(vals);
+    dfree(rhs);
+    if (rc) return rc;
+    std::copy(best, best + 4, b->tile);
+    if ((rc = build_items(b))) return rc;
+    if (tile_out) std::copy(best, best + 4, tile_out);
+    if (table_path) {
+        std::vector<std::string> lines;
+        const std::string key = table_key(b->model, opt->precision);
+        if (FILE *f = fopen(table_path, "r")) {
+            char buf[512];
+            while (fgets(buf, sizeof(buf), f)) {
+                std::string l(buf);
+                if (l.compare(0, key.size(), key) != 0) lines.push_back(l);
+            }
+            fclose(f);
+        }
+        char entry[256];
+        snprintf(entry, sizeof(entry), "%s tiles=%d,%d,%d,%d ms=%.4f\n", key.c_str(), best[0], best[1],
+                 best[2], best[3], best_ms);
+        lines.push_back(entry);
+        FILE *f = fopen(table_path, "w");
+        if (!f) return set_error(FEA_EINVAL, "cannot write %s", table_path);
+        for (const std::string &l : lines) fputs(l.c_str(), f);
+        fclose(f);
+    }
+    return FEA_OK;
+}
+
+extern "C" int fea_tile_table_load(const char *table_path, int model, int precision, int32_t *tile_out)
+{
+    clear_error();
+    if (!table_path || !tile_out) return set_error(FEA_EINVAL, "path and tile_out are required");
+    FILE *f = fopen(table_path, "r");
+    if (!f) return set_error(FEA_EINVAL, "cannot read %s", table_path);
+    const std::string key = table_key(model, precision);
+    char buf[512];
+    int found = 0;
+    while (fgets(buf, sizeof(buf), f)) {
+        if (strncmp(buf, key.c_str(), key.size()) != 0) continue;
+        const char *p = strstr(buf, "tiles=");
+        if (p && sscanf(p, "tiles=%d,%d,%d,%d", &tile_out[0], &tile_out[1], &tile_out[2], &tile_out[3]) == 4)
+            found = 1;
+    }
+    fclose(f);
+    if (!found) return set_error(FEA_EINVAL, "no entry for %s in %s", key.c_str(), table_path);
+    return check_tiles(tile_out);
+}
+
+extern "C" int fea_batch_order(fea_batch *b, int schedule, const float *pred, hipStream_t stream)
+{
+    clear_error();
+    if (!b) return set_error(FEA_EINVAL, "batch is NULL");
+    const size_t ni = b->items.size() / 4;
+    std::vector<double> w(ni, 0.0);
+    if (schedule == FEA_TYPE_SORTED) {
+        for (size_t i = 0; i < ni; ++i) b->order[i] = (int32_t)i;
+        return upload_order(b);
+    } else if (schedule == FEA_GP_WEIGHT) {
+        for (size_t i = 0; i < ni; ++i) w[i] = (double)b->items[4 * i + 3] * kNQ[b->items[4 * i + 1]];
+    } else if (schedule == FEA_LEARNED) {
+        if (!pred && ni) return set_error(FEA_EINVAL, "pred is required for the learned schedule");
+        std::vector<float> p(ni);
+        if (ni) FEA_HIP(hipMemcpyAsync(p.data(), pred, sizeof(float) * ni, hipMemcpyDeviceToHost, stream));
+        FEA_HIP(hipStreamSynchronize(stream));
+        for (size_t i = 0; i < ni; ++i) w[i] = p[i];
+    } else {
+        return set_error(FEA_EINVAL, "unknown schedule %d", schedule);
+    }
+    // longest processing time first; ties keep the item order
+    for (size_t i = 0; i < ni; ++i) b->order[i] = (int32_t)i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t x, int32_t y) { return w[x] > w[y]; });
+    return upload_order(b);
+}
+
+extern "C" int fea_batch_features(const fea_batch *b, int fp64_geometry, float *feats, hipStream_t stream)
+{
+    clear_error();
+    if (!b || !feats) return set_error(FEA_EINVAL, "batch and feats are required");
+    int rc = ensure_tables();
+    if (rc) return rc;
+    const int32_t ni = (int32_t)(b->items.size() / 4);
+    if (ni) k_features<<<ni, 256, 0, stream>>>(b->d_meshes, b->d_items, fp64_geometry ? 1 : 0, feats);
+    FEA_HIP(hipGetLastError());
+    return FEA_OK;
+}
 
 extern "C" int fea_batch_build(int n_meshes, const fea_mesh_desc *meshes, int model, const int32_t *tile,
                                hipStream_t stream, fea_batch **out)
