@@ -73,6 +73,138 @@ def traffic_from_profile(kernel_key):
     return float(v) if v else None
 
 
+def _median_ms(fn, reps):
+    import numpy as np
+    vals = [fn() for _ in range(reps)]
+    return float(np.median(vals))
+
+
+def batched_workload(fea, mg, torch):
+    """64 independent meshes (8^3..48^3 cells, random family mix, jitter
+    0.25 h) in one persistent launch, mixed precision, tiles autotuned,
+    replayed 100 times from a HIP graph."""
+    import tempfile
+    meshes = mg.batched(64)
+    dms = [fea.DeviceMesh(m) for m in meshes]
+    b = fea.Batch(dms, model=fea.ELASTIC)
+    n_items_default = b.n_items
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        vals, rhs, status = b.outputs(fea.F32)
+        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs, status=status, timing=True)
+        side.synchronize()
+        default_ms = _median_ms(lambda: (b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs,
+                                                    status=status, timing=True), b.last_ms())[1], 5)
+        with tempfile.TemporaryDirectory() as d:
+            tile = b.autotune(precision=fea.MIXED, out_dtype=fea.F32, reps=3, table_path=f"{d}/tiles.txt")
+        tuned_ms = _median_ms(lambda: (b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs,
+                                                  status=status, timing=True), b.last_ms())[1], 5)
+        b.capture(vals, rhs, status, precision=fea.MIXED, out_dtype=fea.F32)
+        b.replay(3)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(side)
+        b.replay(100)
+        e1.record(side)
+        side.synchronize()
+        ms = e0.elapsed_time(e1) / 100
+        ok = bool((status.cpu() == -1).all())
+    return {"workload": "batched64-elasticity (64 meshes, 8^3..48^3 cells, jitter 0.25h)",
+            "elements": int(b.n_elems), "items": int(b.n_items), "items_default_tiles": int(n_items_default),
+            "precision": "mixed", "tiles": [int(t) for t in tile],
+            "persistent_kernel_ms_default_tiles": round(default_ms, 4),
+            "persistent_kernel_ms_tuned_tiles": round(tuned_ms, 4),
+            "ms_per_replay": round(ms, 4), "elements_per_s": round(b.n_elems / (ms * 1e-3), 1),
+            "replays": 100, "workers": b.workers(), "status_ok": ok}
+
+
+def heterogeneous_workload(fea, mg, torch, np, cells=128):
+    """Hybrid split mesh (40/30/20/10 hex/tet/pen/pyr layers) where 30% of
+    8^3-cell bricks use the neo-Hookean tangent: the cost model is trained
+    on the recorded cycles and orders the queue; compared with the
+    type-sorted order and the Gauss-point-weight order, and the learned
+    mixed-precision form with the plain FP64 form."""
+    mesh = mg.heterogeneous(cells, seed=4)
+    dm = fea.DeviceMesh(mesh)
+    b = fea.Batch([dm], model=fea.ELASTIC, use_nh=True)
+
+    def run(precision, reps=9):
+        outd = fea.F64 if precision == fea.FP64 else fea.F32
+        vals, rhs, st = b.outputs(outd)
+        b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st)
+        kern, tot = [], []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(reps):
+            e0.record()
+            b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st, timing=True)
+            e1.record()
+            torch.cuda.synchronize()
+            kern.append(b.last_ms())
+            tot.append(e0.elapsed_time(e1))
+        c, w, _ = b.cycles()
+        c = c.cpu().numpy().astype(np.float64)
+        w = w.cpu().numpy()
+        busy = np.bincount(w, weights=c, minlength=b.workers())
+        busy = busy[busy > 0]
+        return {"kernel_ms": round(float(np.median(kern)), 4), "total_ms": round(float(np.median(tot)), 4),
+                "load_balance": round(float(busy.sum() / (busy.size * busy.max())), 4)}, vals, st
+
+    out = {"workload": f"hetero{cells}-elasticity (30% neo-Hookean bricks, 40/30/20/10 hex/tet/pen/pyr)",
+           "elements": int(mesh.n_elems), "items": int(b.n_items), "workers": 0}
+    fp64_ts, v64, st64 = run(fea.FP64)
+    out["fp64_type_sorted"] = fp64_ts
+    mix_ts, vmx, stm = run(fea.MIXED)
+    out["mixed_type_sorted"] = mix_ts
+    # training data: the cycles of the mixed type-sorted runs
+    c, _, _ = b.cycles()
+    target = fea.CostModel.log_cycles(c)
+    feats = b.features(fp64_geometry=False)
+    cm = fea.CostModel(seed=7)
+    cm.fit_norm(feats)
+    t0 = time.perf_counter()
+    hist = cm.train(feats, target, steps=600, lr=3e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    pred = cm.predict(feats)
+    t = target.cpu().numpy().astype(np.float64)
+    p = pred.cpu().numpy().astype(np.float64)
+    gp = np.log(b.items[:, 3] * np.array([1, 8, 6, 8])[b.items[:, 1]])
+
+    def r2(x, y):
+        x = x - x.mean()
+        y = y - y.mean()
+        return float((x @ y) ** 2 / ((x @ x) * (y @ y)))
+
+    out["cost_model"] = {"train_steps": 600, "train_s": round(train_s, 3),
+                         "loss_first": round(float(hist[0].item()), 5), "loss_last": round(float(hist[-1].item()), 5),
+                         "r2_learned_vs_measured": round(r2(p, t), 4),
+                         "r2_gauss_point_weight_vs_measured": round(r2(gp, t), 4)}
+    # dynamic queue, largest predicted cost first
+    b.order(fea.GP_WEIGHT)
+    out["mixed_queue_gp_weight_lpt"], _, _ = run(fea.MIXED)
+    b.order(fea.LEARNED, pred)
+    out["mixed_queue_learned_lpt"], _, _ = run(fea.MIXED)
+    # static partitions of the type-sorted items, one range per workgroup
+    b.partition(fea.TYPE_SORTED)
+    out["mixed_static_by_elements"], _, _ = run(fea.MIXED)
+    b.partition(fea.GP_WEIGHT)
+    out["mixed_static_by_gauss_points"], _, _ = run(fea.MIXED)
+    b.partition(fea.LEARNED, pred)
+    out["mixed_static_learned"], vl, stl = run(fea.MIXED)
+    b.partition(fea.LEARNED, pred)
+    out["fp64_static_learned"], _, _ = run(fea.FP64)
+    b.order(fea.TYPE_SORTED)
+    out["workers"] = b.workers()
+    best_learned = min(out["mixed_queue_learned_lpt"]["total_ms"], out["mixed_static_learned"]["total_ms"])
+    out["speedup_learned_mixed_vs_fp64_type_sorted"] = round(fp64_ts["total_ms"] / best_learned, 4)
+    out["speedup_learned_static_vs_gauss_point_static"] = round(
+        out["mixed_static_by_gauss_points"]["total_ms"] / out["mixed_static_learned"]["total_ms"], 4)
+    out["speedup_learned_vs_type_sorted_queue_mixed"] = round(mix_ts["total_ms"] / best_learned, 4)
+    d = (vl.double() - v64).norm() / v64.norm()
+    out["mixed_vs_fp64_rel_frobenius"] = float(d.item())
+    out["status_ok"] = bool((st64.cpu() == -1).all()) and bool((stl.cpu() == -1).all())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +215,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and heterogeneous-cost workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -180,8 +314,20 @@ def main():
                 del vv, rr, ss
         torch.cuda.synchronize()
 
+    extras = {}
+    if not args.no_extras:
+        del vals, rhs
+        torch.cuda.empty_cache()
+        print("[bench] batched workload", file=sys.stderr, flush=True)
+        extras["batched"] = batched_workload(fea, mg, torch)
+        torch.cuda.empty_cache()
+        print("[bench] heterogeneous workload", file=sys.stderr, flush=True)
+        extras["heterogeneous"] = heterogeneous_workload(fea, mg, torch, np)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         import oracle
         og = oracle.mesh_graph(mesh)
         t0 = time.perf_counter()
@@ -222,6 +368,7 @@ def main():
                       "total": round(float(ph[2]), 4)},
         "graph_build_ms": round(graph_ms, 2),
         "variants": variants,
+        **extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

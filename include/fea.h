@@ -266,6 +266,19 @@ int fea_tile_table_load(const char *table_path, int model, int precision, int32_
 int fea_batch_order(fea_batch *b, int schedule, const float *pred, hipStream_t stream);
 
 /*
+ * Static partition instead of the dynamic queue: the items, in type-sorted
+ * order (neighbouring elements stay together), are split into one
+ * contiguous range per persistent workgroup with nearly equal total weight,
+ * and every workgroup runs its own range without touching the queue head.
+ * The counterpart of the paper's weighted partitions (Section 4.1):
+ * weights = FEA_TYPE_SORTED: element count (non-weighted); FEA_GP_WEIGHT:
+ * Gauss points x elements; FEA_LEARNED: exp(pred[item]) with pred a
+ * predicted log-cost (device float[n_items]). fea_batch_order returns to
+ * the dynamic queue. Drops a captured graph.
+ */
+int fea_batch_partition(fea_batch *b, int weights, const float *pred, hipStream_t stream);
+
+/*
  * Cost-model features of every work item (device float[n_items x 12]),
  * per item: family one-hot (4), fraction of neo-Hookean elements,
  * log2(element count), log2 of the node-id span per element node

@@ -188,15 +188,17 @@ def _base_coords(n, n_nodes, cell_types):
     return x, y, z, bnd
 
 
-def corner_tet_volumes(x, y, z, types, conn_ptr, conn):
-    """Minimum signed corner-tetrahedron volume per element (6x volume)."""
-    E = types.shape[0]
-    out = np.full(E, np.inf)
+def corner_tet_volumes(x, y, z, types, conn_ptr, conn, subset=None):
+    """Minimum signed corner-tetrahedron volume per element (6x volume),
+    for all elements or for the element ids in `subset` (in that order)."""
+    ids = np.arange(types.shape[0]) if subset is None else np.asarray(subset)
+    out = np.full(ids.shape[0], np.inf)
+    st = types[ids]
     for t in range(4):
-        eids = np.nonzero(types == t)[0]
-        if eids.size == 0:
+        sel = np.nonzero(st == t)[0]
+        if sel.size == 0:
             continue
-        base = conn_ptr[eids]
+        base = conn_ptr[ids[sel]]
         for (v, p, q, r) in _CORNER_TETS[t]:
             a = conn[base + v]
             b = conn[base + p]
@@ -206,7 +208,7 @@ def corner_tet_volumes(x, y, z, types, conn_ptr, conn):
             vx, vy, vz = x[c] - x[a], y[c] - y[a], z[c] - z[a]
             wx, wy, wz = x[d] - x[a], y[d] - y[a], z[d] - z[a]
             tri = ux * (vy * wz - vz * wy) - uy * (vx * wz - vz * wx) + uz * (vx * wy - vy * wx)
-            out[eids] = np.minimum(out[eids], tri)
+            out[sel] = np.minimum(out[sel], tri)
     return out
 
 
@@ -234,19 +236,28 @@ def cube_mesh(n, cell_types, jitter=0.0, seed=0, dofs=3, nu_range=(0.2, 0.35),
         x[interior] += d[:, 0]
         y[interior] += d[:, 1]
         z[interior] += d[:, 2]
+        q = corner_tet_volumes(x, y, z, types, conn_ptr, conn)
+        bad = np.nonzero(q <= quality * h ** 3)[0]
+        elem_of_pos = np.repeat(np.arange(types.shape[0]), np.diff(conn_ptr))
         for _ in range(200):
-            q = corner_tet_volumes(x, y, z, types, conn_ptr, conn)
-            bad = np.nonzero(q <= quality * h ** 3)[0]
             if bad.size == 0:
                 break
-            nodes = np.unique(np.concatenate(
-                [conn[conn_ptr[e]:conn_ptr[e + 1]] for e in bad[:200000]]))
+            starts = conn_ptr[bad]
+            lens = conn_ptr[bad + 1] - starts
+            pos = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + \
+                np.arange(int(lens.sum()))
+            nodes = np.unique(conn[pos])
             nodes = nodes[~bnd[nodes]]
             redraws += int(nodes.size)
             d = rng.uniform(-jitter * h, jitter * h, size=(nodes.size, 3))
             x[nodes] = x0[nodes] + d[:, 0]
             y[nodes] = y0[nodes] + d[:, 1]
             z[nodes] = z0[nodes] + d[:, 2]
+            moved = np.zeros(x.shape[0], dtype=bool)
+            moved[nodes] = True
+            touched = np.unique(elem_of_pos[moved[conn]])
+            qt = corner_tet_volumes(x, y, z, types, conn_ptr, conn, subset=touched)
+            bad = touched[qt <= quality * h ** 3]
         else:
             raise RuntimeError("jitter redraw did not converge")
     E = types.shape[0]

@@ -83,6 +83,7 @@ _lib.fea_batch_destroy.restype = None
 _lib.fea_batch_autotune.argtypes = [_P, ctypes.POINTER(Options), ctypes.c_int, ctypes.c_char_p, _P, _I32P]
 _lib.fea_tile_table_load.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, _I32P]
 _lib.fea_batch_order.argtypes = [_P, ctypes.c_int, _P, _P]
+_lib.fea_batch_partition.argtypes = [_P, ctypes.c_int, _P, _P]
 _lib.fea_batch_features.argtypes = [_P, ctypes.c_int, _P, _P]
 _lib.fea_cost_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(_P)]
 _lib.fea_cost_destroy.argtypes = [_P]
@@ -109,6 +110,7 @@ EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_export", "fea_graph_
            "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_assemble", "fea_batch_capture",
            "fea_batch_replay", "fea_batch_cycles", "fea_batch_last_ms", "fea_batch_workers",
            "fea_batch_destroy", "fea_batch_autotune", "fea_tile_table_load", "fea_batch_order",
+           "fea_batch_partition",
            "fea_batch_features", "fea_cost_create", "fea_cost_destroy", "fea_cost_get_params",
            "fea_cost_set_params", "fea_cost_set_norm", "fea_cost_fit_norm", "fea_cost_predict",
            "fea_cost_grad", "fea_cost_train", "fea_cost_log_cycles", "fea_cost_save", "fea_cost_load")
@@ -371,6 +373,9 @@ class Batch:
 
     def order(self, schedule, pred=None, stream=None):
         _check(_lib.fea_batch_order(self._h, int(schedule), _ptr(pred), _stream(stream)))
+
+    def partition(self, weights, pred=None, stream=None):
+        _check(_lib.fea_batch_partition(self._h, int(weights), _ptr(pred), _stream(stream)))
 
     def features(self, fp64_geometry=True, stream=None):
         f = torch.empty((self.n_items, N_FEATURES), dtype=torch.float32, device=self.device)

@@ -12,6 +12,7 @@
 // row-owner reduction in ascending element order, whatever the queue order.
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -53,19 +54,23 @@ __device__ inline void run_item(ElemArgs &A, int32_t count, ElemSmem<T, MODEL, V
 template <int MODEL, typename CT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_batch(const BatchMesh *meshes, const int4 *items,
                                                const int32_t *order, int32_t n_items,
-                                               int32_t *head, CT *contrib, CT *rcontrib,
-                                               int32_t *status, uint64_t *cycles,
+                                               int32_t *head, const int32_t *part, CT *contrib,
+                                               CT *rcontrib, int32_t *status, uint64_t *cycles,
                                                int32_t *worker, int32_t *cu)
 {
     constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
     __shared__ BatchSmem<MODEL, CT> U;
     __shared__ int32_t s_item;
+    // static partition: this workgroup runs order[part[w] .. part[w+1])
+    int32_t next = part ? part[blockIdx.x] : 0;
+    const int32_t last = part ? part[blockIdx.x + 1] : 0;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) {
-            int32_t q = atomicAdd(head, 1);
-            s_item = q < n_items ? order[q] : -1;
+            int32_t q = part ? next : atomicAdd(head, 1);
+            s_item = q < (part ? last : n_items) ? order[q] : -1;
         }
+        ++next;
         __syncthreads();
         // the item is the same for the whole workgroup: keep it (and the
         // mesh view it selects) in scalar registers
@@ -260,6 +265,11 @@ struct fea_batch {
     size_t rcontrib_bytes = 0;
     int workers = 0;
     int workers_for = -1;  // (model, precision) the worker count was computed for
+    // static partition of the order over the workers (used when part_for
+    // equals the current worker count; -1 = dynamic queue)
+    std::vector<double> part_w;  // item weights of the requested partition
+    int32_t *d_part = nullptr;
+    int part_for = -1;
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool timed = false;
     hipGraph_t graph = nullptr;
@@ -283,7 +293,8 @@ void destroy_batch(fea_batch *b)
     for (fea_graph *g : b->graphs)
         if (g) fea_graph_destroy(g);
     void *bufs[] = {b->d_meshes, b->d_items, b->d_order, b->d_head, b->d_status, b->d_vseg,
-                    b->d_rseg, b->d_cycles, b->d_worker, b->d_cu, b->contrib, b->rcontrib};
+                    b->d_rseg, b->d_cycles, b->d_worker, b->d_cu, b->contrib, b->rcontrib,
+                    b->d_part};
     for (void *p : bufs) dfree(p);
     for (hipEvent_t e : b->ev)
         if (e) (void)hipEventDestroy(e);
@@ -307,6 +318,8 @@ int build_items(fea_batch *b)
     const size_t ni = b->items.size() / 4;
     b->order.resize(ni);
     for (size_t i = 0; i < ni; ++i) b->order[i] = (int32_t)i;
+    b->part_for = -1;
+    b->part_w.clear();
     if (ni > b->items_cap) {
         void *bufs[] = {b->d_items, b->d_order, b->d_cycles, b->d_worker, b->d_cu};
         for (void *p : bufs) dfree(p);
@@ -330,6 +343,33 @@ int build_items(fea_batch *b)
     return FEA_OK;
 }
 
+// Splits the current order into `workers` contiguous ranges of nearly equal
+// total weight (cut where the running sum crosses k * total / workers).
+int make_partition(fea_batch *b)
+{
+    const int W = b->workers;
+    const size_t ni = b->order.size();
+    std::vector<int32_t> part(W + 1, 0);
+    double total = 0.0;
+    for (size_t j = 0; j < ni; ++j) total += b->part_w[b->order[j]];
+    double run = 0.0;
+    int k = 1;
+    for (size_t j = 0; j < ni && k < W; ++j) {
+        const double wj = b->part_w[b->order[j]];
+        while (k < W && run + 0.5 * wj >= total * k / W) part[k++] = (int32_t)j;
+        run += wj;
+    }
+    while (k <= W) part[k++] = (int32_t)ni;
+    dfree(b->d_part);
+    b->d_part = nullptr;
+    int rc = dalloc((void **)&b->d_part, sizeof(int32_t) * (W + 1));
+    if (rc) return rc;
+    FEA_HIP(hipMemcpy(b->d_part, part.data(), sizeof(int32_t) * (W + 1), hipMemcpyHostToDevice));
+    b->part_for = W;
+    drop_graph(b);
+    return FEA_OK;
+}
+
 template <int MODEL, typename CT>
 int worker_count(fea_batch *b)
 {
@@ -340,6 +380,7 @@ int worker_count(fea_batch *b)
     FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<MODEL, CT>, 256, 0));
     b->workers = std::max(1, cus * std::max(1, per));
     b->workers_for = key;
+    if (!b->part_w.empty()) return make_partition(b);
     return FEA_OK;
 }
 
@@ -372,6 +413,7 @@ int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, 
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[0], s));
     if (ni)
         k_batch<MODEL, CT><<<b->workers, 256, 0, s>>>(b->d_meshes, b->d_items, b->d_order, ni, b->d_head,
+                                                      b->part_for == b->workers ? b->d_part : nullptr,
                                                       (CT *)b->contrib, (CT *)b->rcontrib, b->d_status,
                                                       b->d_cycles, b->d_worker, b->d_cu);
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[1], s));
@@ -645,6 +687,8 @@ extern "C" int fea_batch_order(fea_batch *b, int schedule, const float *pred, hi
     if (!b) return set_error(FEA_EINVAL, "batch is NULL");
     const size_t ni = b->items.size() / 4;
     std::vector<double> w(ni, 0.0);
+    b->part_for = -1;
+    b->part_w.clear();
     if (schedule == FEA_TYPE_SORTED) {
         for (size_t i = 0; i < ni; ++i) b->order[i] = (int32_t)i;
         return upload_order(b);
@@ -663,6 +707,36 @@ extern "C" int fea_batch_order(fea_batch *b, int schedule, const float *pred, hi
     for (size_t i = 0; i < ni; ++i) b->order[i] = (int32_t)i;
     std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t x, int32_t y) { return w[x] > w[y]; });
     return upload_order(b);
+}
+
+
+extern "C" int fea_batch_partition(fea_batch *b, int weights, const float *pred, hipStream_t stream)
+{
+    clear_error();
+    if (!b) return set_error(FEA_EINVAL, "batch is NULL");
+    const size_t ni = b->items.size() / 4;
+    std::vector<double> w(ni, 0.0);
+    if (weights == FEA_TYPE_SORTED) {
+        for (size_t i = 0; i < ni; ++i) w[i] = (double)b->items[4 * i + 3];
+    } else if (weights == FEA_GP_WEIGHT) {
+        for (size_t i = 0; i < ni; ++i) w[i] = (double)b->items[4 * i + 3] * kNQ[b->items[4 * i + 1]];
+    } else if (weights == FEA_LEARNED) {
+        if (!pred && ni) return set_error(FEA_EINVAL, "pred is required for learned weights");
+        std::vector<float> p(ni);
+        if (ni) FEA_HIP(hipMemcpyAsync(p.data(), pred, sizeof(float) * ni, hipMemcpyDeviceToHost, stream));
+        FEA_HIP(hipStreamSynchronize(stream));
+        for (size_t i = 0; i < ni; ++i) w[i] = exp((double)p[i]);
+    } else {
+        return set_error(FEA_EINVAL, "unknown weights %d", weights);
+    }
+    // items keep the type-sorted order (neighbouring elements stay together)
+    for (size_t i = 0; i < ni; ++i) b->order[i] = (int32_t)i;
+    int rc = upload_order(b);
+    if (rc) return rc;
+    b->part_w = std::move(w);
+    b->part_for = -1;
+    if (b->workers_for >= 0) return make_partition(b);
+    return FEA_OK;  // computed at the first launch, once the worker count is known
 }
 
 extern "C" int fea_batch_features(const fea_batch *b, int fp64_geometry, float *feats, hipStream_t stream)

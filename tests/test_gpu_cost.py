@@ -166,3 +166,29 @@ def test_schedules_order_items_and_keep_results():
     assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
     with pytest.raises(fea.FeaError):
         b.order(fea.LEARNED, None)
+
+
+def test_static_partitions_keep_results_and_ranges():
+    mesh = mg.heterogeneous(16, seed=42, brick=4)
+    dm = fea.DeviceMesh(mesh)
+    b = fea.Batch([dm], model=fea.ELASTIC, use_nh=True)
+    v0, r0, _ = b.assemble()
+    ref = (v0.cpu().numpy().tobytes(), r0.cpu().numpy().tobytes())
+    c, _, _ = b.cycles()
+    target = fea.CostModel.log_cycles(c)
+    cm = fea.CostModel(seed=3)
+    feats = b.features()
+    cm.fit_norm(feats)
+    cm.train(feats, target, steps=100, lr=3e-3)
+    pred = cm.predict(feats)
+    for weights in (fea.TYPE_SORTED, fea.GP_WEIGHT, fea.LEARNED):
+        b.partition(weights, pred if weights == fea.LEARNED else None)
+        v, r, st = b.assemble()
+        assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
+        _, w, _ = b.cycles()
+        w = w.cpu().numpy()
+        # every workgroup ran one contiguous range of the type-sorted items
+        assert np.all(np.diff(w) >= 0)
+    b.order(fea.TYPE_SORTED)
+    v, r, _ = b.assemble()
+    assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
