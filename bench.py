@@ -117,6 +117,71 @@ def batched_workload(fea, mg, torch):
             "replays": 100, "workers": b.workers(), "status_ok": ok}
 
 
+def copy_bandwidth(torch):
+    """Device-to-device copy of 2 GiB (read + write), GB/s: the practical
+    streaming ceiling next to the 8 TB/s nominal peak."""
+    a = torch.empty(1 << 28, dtype=torch.float64, device="cuda:0")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    return round(2 * a.numel() * 8 / (ms * 1e-3) / 1e9, 1)
+
+
+def large_workload(fea, mg, torch, np, cells=256):
+    """53.9M-element hybrid mesh (40/30/20/10 hex/tet/pen/pyr layers) through
+    the persistent path: plain FP64 against mixed precision with the learned
+    schedule."""
+    mesh = mg.hybrid_split(cells, seed=5)
+    dm = fea.DeviceMesh(mesh)
+    b = fea.Batch([dm], model=fea.ELASTIC)
+    out = {"workload": f"hybrid{cells}-elasticity (40/30/20/10 hex/tet/pen/pyr layers)",
+           "elements": int(mesh.n_elems), "nodes": int(mesh.n_nodes), "nnz_blocks": int(b.vals_len // 9),
+           "items": int(b.n_items)}
+
+    def run(precision, reps=5):
+        outd = fea.F64 if precision == fea.FP64 else fea.F32
+        vals, rhs, st = b.outputs(outd)
+        b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tot = []
+        for _ in range(reps):
+            e0.record()
+            b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st)
+            e1.record()
+            torch.cuda.synchronize()
+            tot.append(e0.elapsed_time(e1))
+        ok = bool((st.cpu() == -1).all())
+        del vals, rhs
+        return {"total_ms": round(float(np.median(tot)), 3),
+                "elements_per_s": round(mesh.n_elems / (float(np.median(tot)) * 1e-3), 1), "status_ok": ok}
+
+    out["fp64_type_sorted"] = run(fea.FP64)
+    out["mixed_type_sorted"] = run(fea.MIXED)
+    c, _, _ = b.cycles()
+    target = fea.CostModel.log_cycles(c)
+    feats = b.features(fp64_geometry=False)
+    cm = fea.CostModel(seed=7)
+    cm.fit_norm(feats)
+    cm.train(feats, target, steps=600, lr=3e-3)
+    pred = cm.predict(feats)
+    b.partition(fea.LEARNED, pred)
+    out["mixed_static_learned"] = run(fea.MIXED)
+    b.order(fea.LEARNED, pred)
+    out["mixed_queue_learned"] = run(fea.MIXED)
+    best = min(out["mixed_static_learned"]["total_ms"], out["mixed_queue_learned"]["total_ms"])
+    out["speedup_learned_mixed_vs_fp64"] = round(out["fp64_type_sorted"]["total_ms"] / best, 4)
+    b.destroy()
+    return out
+
+
 def heterogeneous_workload(fea, mg, torch, np, cells=128):
     """Hybrid split mesh (40/30/20/10 hex/tet/pen/pyr layers) where 30% of
     8^3-cell bricks use the neo-Hookean tangent: the cost model is trained
@@ -215,6 +280,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 workload")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and heterogeneous-cost workloads")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -294,6 +360,7 @@ def main():
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     sb = scatter_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes)
     traffic = traffic_from_profile(kernel)
+    copy_gbps = copy_bandwidth(torch)
 
     variants = {}
     if not args.no_variants:
@@ -324,6 +391,10 @@ def main():
         print("[bench] heterogeneous workload", file=sys.stderr, flush=True)
         extras["heterogeneous"] = heterogeneous_workload(fea, mg, torch, np)
         torch.cuda.empty_cache()
+        if not args.no_large:
+            print("[bench] large workload", file=sys.stderr, flush=True)
+            extras["large"] = large_workload(fea, mg, torch, np)
+            torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu:
@@ -358,7 +429,8 @@ def main():
                    "out_dtype": "f64" if outd == fea.F64 else "f32"},
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4)},
+                     "traffic": traffic, "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4),
+                     "copy_GBps": copy_gbps, "frac_of_copy": round(achieved / copy_gbps, 4)},
         "scatter": {"effective_GBps": round(sb / ((float(ph[2]) - elem_ms) * 1e-3) / 1e9, 1) if args.variant == "rowowner" else None,
                     "frac_of_peak": round(sb / ((float(ph[2]) - elem_ms) * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if args.variant == "rowowner" else None,
                     "algorithmic_bytes": int(sb), "note": "matrix and right-hand side, second phase"},

@@ -124,6 +124,9 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         for (int t = 0; t < 4; ++t) {
             a.elems = g->perm + g->seg[t];
             a.n = g->seg[t + 1] - g->seg[t];
+            a.pnodes = g->pnodes + g->node_base[t];
+            a.prdest = g->prdest + g->node_base[t];
+            a.pdest = g->pdest + g->slot_base[t];
             launch_type<MODEL, V_ROWOWNER, CT>(t, a, s);
         }
         mark(g, 1, o, s);
@@ -234,8 +237,6 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     a.conn = conn;
     a.map_ptr = g->map_ptr;
     a.e2nnz = g->e2nnz;
-    a.e2pos = g->e2pos;
-    a.rpos = g->rpos;
     a.young = mat->young;
     a.nu = mat->nu;
     a.nh_flag = mat->model == FEA_ELASTIC ? mat->nh_flag : nullptr;

@@ -26,6 +26,7 @@ namespace fea {
 struct BatchMesh {
     ElemArgs a;      // pointers of the mesh and its graph (elems = perm)
     int64_t seg[5];  // family segments in perm
+    int64_t node_base[5], slot_base[5];  // family starts in pnodes/prdest and pdest
     int64_t coff;    // first slot of this mesh in the slot workspace
     int64_t roff;    // first incidence of this mesh in the rhs workspace
 };
@@ -86,6 +87,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
         A.rcontrib = rcontrib + M.roff * B;
         A.elems = M.a.elems + M.seg[w.y] + w.z;
         A.n = w.w;
+        {
+            const int64_t nn = nodes_of(w.y);
+            A.pnodes = M.a.pnodes + M.node_base[w.y] + (int64_t)w.z * nn;
+            A.prdest = M.a.prdest + M.node_base[w.y] + (int64_t)w.z * nn;
+            A.pdest = M.a.pdest + M.slot_base[w.y] + (int64_t)w.z * nn * nn;
+        }
         A.status = status + w.x;
         switch (w.y) {
         case 0: run_item<0, MODEL, CT>(A, w.w, U.s0); break;
@@ -512,8 +519,9 @@ int build(int n, const fea_mesh_desc *md, int model, const int32_t *tile, hipStr
         a.elems = g->perm;
         a.map_ptr = g->map_ptr;
         a.e2nnz = g->e2nnz;
-        a.e2pos = g->e2pos;
-        a.rpos = g->rpos;
+        a.pnodes = g->pnodes;
+        a.pdest = g->pdest;
+        a.prdest = g->prdest;
         a.young = d.young;
         a.nu = d.nu;
         a.nh_flag = model == FEA_ELASTIC ? d.nh_flag : nullptr;
@@ -521,6 +529,8 @@ int build(int n, const fea_mesh_desc *md, int model, const int32_t *tile, hipStr
         a.source = d.source;
         bm[m].a = a;
         std::copy(g->seg, g->seg + 5, bm[m].seg);
+        std::copy(g->node_base, g->node_base + 5, bm[m].node_base);
+        std::copy(g->slot_base, g->slot_base + 5, bm[m].slot_base);
         bm[m].coff = b->slot_off[m];
         bm[m].roff = b->inc_off[m];
     }

@@ -54,11 +54,16 @@ struct fea_graph {
     int32_t *e2nnz = nullptr;
     int64_t *inv_ptr = nullptr;
     int32_t *inv = nullptr;
-    // destination positions of the row-owner workspace, which is kept sorted
-    // by destination: slot s goes to e2pos[s] (e2pos[inv[j]] = j), and the
-    // right-hand-side entry of conn position c to rpos[c] (its incidence index)
-    int32_t *e2pos = nullptr;
-    int32_t *rpos = nullptr;
+    // Row-owner layout, in type-sorted element order (position p = index in
+    // perm): node ids pnodes, destination of every slot pdest (its index in
+    // the inverse map, so the workspace lies sorted by destination block) and
+    // of every right-hand-side entry prdest (its incidence index). Family t
+    // starts at node_base[t] (pnodes, prdest) and slot_base[t] (pdest).
+    int32_t *pnodes = nullptr;
+    int32_t *pdest = nullptr;
+    int32_t *prdest = nullptr;
+    int64_t node_base[5] = {0, 0, 0, 0, 0};
+    int64_t slot_base[5] = {0, 0, 0, 0, 0};
     // node -> incident elements (ascending element id) and local index
     int64_t *n2e_ptr = nullptr;
     int32_t *n2e = nullptr;

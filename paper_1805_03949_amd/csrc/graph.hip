@@ -200,6 +200,32 @@ __global__ void k_rpos(int64_t n_nodes, const int64_t *n2e_ptr, const int32_t *n
     for (int64_t p = n2e_ptr[i]; p < n2e_ptr[i + 1]; ++p) rpos[conn_ptr[n2e[p]] + n2a[p]] = (int32_t)p;
 }
 
+// Row-owner layout in type-sorted order, one thread per position.
+struct Bases {
+    int64_t seg[5], node[5], slot[5];
+};
+
+__global__ void k_position_maps(int64_t n_elems, Bases bs, const int32_t *perm, const int64_t *conn_ptr,
+                                const int32_t *conn, const int64_t *map_ptr, const int32_t *e2pos,
+                                const int32_t *rpos, int32_t *pnodes, int32_t *pdest, int32_t *prdest)
+{
+    int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= n_elems) return;
+    int t = 0;
+    while (t < 3 && pos >= bs.seg[t + 1]) ++t;
+    const int n = nodes_of(t);
+    const int64_t i = pos - bs.seg[t];
+    const int32_t e = perm[pos];
+    const int64_t c0 = conn_ptr[e], m0 = map_ptr[e];
+    int32_t *pn = pnodes + bs.node[t] + i * n, *pr = prdest + bs.node[t] + i * n;
+    int32_t *pd = pdest + bs.slot[t] + i * n * n;
+    for (int a = 0; a < n; ++a) {
+        pn[a] = conn[c0 + a];
+        pr[a] = rpos[c0 + a];
+    }
+    for (int p = 0; p < n * n; ++p) pd[p] = e2pos[m0 + p];
+}
+
 // ------------------------------------------------------------- colouring
 // Greedy first-fit in element order (the colouring of Algorithm 5; any
 // valid colouring is correct, this one is deterministic). Sequential by
@@ -263,7 +289,7 @@ static int colour_host(fea_graph *g, const int64_t *conn_ptr_d, const int32_t *c
 static void destroy(fea_graph *g)
 {
     if (!g) return;
-    void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv, g->e2pos, g->rpos,
+    void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv, g->pnodes, g->pdest, g->prdest,
                     g->n2e_ptr, g->n2e, g->n2a, g->perm, g->colour, g->cperm,
                     g->contrib, g->rcontrib, g->acc64};
     for (void *b : bufs) dfree(b);
@@ -381,12 +407,31 @@ static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn
     if (N) k_inv_fill<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, g->n2a, conn_ptr, g->map_ptr, g->e2nnz, g->inv_ptr, (int32_t *)fillb.p, g->inv);
     FEA_HIP(hipGetLastError());
 
-    // destination positions for the row-owner workspace
-    if ((rc = dalloc((void **)&g->e2pos, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
-    if ((rc = dalloc((void **)&g->rpos, sizeof(int32_t) * std::max<int64_t>(g->conn_len, 1)))) return rc;
-    if (g->map_len) k_e2pos<<<grid_for(g->map_len, BS), BS, 0, s>>>(g->map_len, g->inv, g->e2pos);
-    if (N) k_rpos<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, g->n2a, conn_ptr, g->rpos);
-    FEA_HIP(hipGetLastError());
+    // destination positions for the row-owner workspace, laid out in
+    // type-sorted order
+    {
+        TmpBuf e2pos, rpos;
+        if ((rc = dalloc(&e2pos.p, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
+        if ((rc = dalloc(&rpos.p, sizeof(int32_t) * std::max<int64_t>(g->conn_len, 1)))) return rc;
+        if (g->map_len) k_e2pos<<<grid_for(g->map_len, BS), BS, 0, s>>>(g->map_len, g->inv, (int32_t *)e2pos.p);
+        if (N) k_rpos<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, g->n2a, conn_ptr, (int32_t *)rpos.p);
+        Bases bs;
+        for (int t = 0; t <= 4; ++t) bs.seg[t] = g->seg[t];
+        bs.node[0] = bs.slot[0] = 0;
+        for (int t = 0; t < 4; ++t) {
+            const int64_t cnt = g->seg[t + 1] - g->seg[t], n = nodes_of(t);
+            bs.node[t + 1] = bs.node[t] + cnt * n;
+            bs.slot[t + 1] = bs.slot[t] + cnt * n * n;
+        }
+        memcpy(g->node_base, bs.node, sizeof(bs.node));
+        memcpy(g->slot_base, bs.slot, sizeof(bs.slot));
+        if ((rc = dalloc((void **)&g->pnodes, sizeof(int32_t) * std::max<int64_t>(g->conn_len, 1)))) return rc;
+        if ((rc = dalloc((void **)&g->prdest, sizeof(int32_t) * std::max<int64_t>(g->conn_len, 1)))) return rc;
+        if ((rc = dalloc((void **)&g->pdest, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
+        if (E) k_position_maps<<<grid_for(E, BS), BS, 0, s>>>(E, bs, g->perm, conn_ptr, conn, g->map_ptr, (int32_t *)e2pos.p, (int32_t *)rpos.p, g->pnodes, g->pdest, g->prdest);
+        FEA_HIP(hipGetLastError());
+        FEA_HIP(hipStreamSynchronize(s));
+    }
 
     if ((rc = colour_host(g, conn_ptr, conn, types, s))) return rc;
     FEA_HIP(hipStreamSynchronize(s));

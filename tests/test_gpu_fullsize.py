@@ -1,0 +1,101 @@
+"""Parity at the benchmark sizes, in the launch configurations bench.py times,
+on sampled rows that the oracle computes element by element."""
+import numpy as np
+import pytest
+
+import meshgen as mg
+from tests.helpers import fp32_bound_L
+from tests.sampled import check_rows, oracle_rows
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1805_03949_amd as fea  # noqa: E402
+
+
+def sample_nodes(mesh, k, seed):
+    rng = np.random.default_rng(seed)
+    nodes = set(rng.choice(mesh.n_nodes, k, replace=False).tolist())
+    nodes.update([0, mesh.n_nodes - 1])
+    # rows on family interfaces (z-band boundaries) and pyramid centre nodes
+    n = mesh.n_cells
+    m = n + 1
+    for kz in range(1, n):
+        nodes.add(int(kz * m * m + (m // 2) * m + m // 3))
+    return sorted(nodes)
+
+
+def test_hybrid96_rowowner_fp64_and_mixed_sampled_rows():
+    mesh = mg.hybrid_bands(96, seed=2)
+    print(f"[case] hybrid96: {mesh.n_elems} elements", flush=True)
+    dm = fea.DeviceMesh(mesh)
+    g = dm.graph()
+    ex = g.export()
+    row_ptr = ex["row_ptr"].cpu().numpy()
+    col = ex["col"].cpu().numpy()
+    nodes = sample_nodes(mesh, 300, 1)
+    rows = oracle_rows(mesh, nodes)
+    v, r, st = dm.assemble(g, variant=fea.ROWOWNER)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -1
+    assert check_rows(mesh, rows, row_ptr, col, v, r, 3) <= 1e-12
+    v, r, st = dm.assemble(g, variant=fea.ROWOWNER, precision=fea.MIXED, out_dtype=fea.F32)
+    torch.cuda.synchronize()
+    L = fp32_bound_L(mesh.types)
+    assert check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L) <= 1.0
+    for variant in (fea.ATOMIC, fea.COLOUR):
+        v, r, _ = dm.assemble(g, variant=variant)
+        torch.cuda.synchronize()
+        assert check_rows(mesh, rows, row_ptr, col, v, r, 3) <= 1e-12
+
+
+def _batch_rows_check(mesh, b, precisions, seed, k=200):
+    nodes = sample_nodes(mesh, k, seed)
+    rows = oracle_rows(mesh, nodes)
+    # the batch's graph arrays of mesh 0 come from a one-mesh graph export
+    dm = b.meshes[0]
+    gr = dm.graph()
+    ex = gr.export()
+    row_ptr = ex["row_ptr"].cpu().numpy()
+    col = ex["col"].cpu().numpy()
+    gr.destroy()
+    for prec in precisions:
+        outd = fea.F64 if prec == fea.FP64 else fea.F32
+        v, r, st = b.assemble(precision=prec, out_dtype=outd)
+        torch.cuda.synchronize()
+        assert int(st[0].item()) == -1
+        L = None if prec == fea.FP64 else fp32_bound_L(mesh.types)
+        worst = check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L)
+        assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (prec, worst)
+        del v, r
+
+
+def test_hetero128_batched_sampled_rows_with_neo_hookean():
+    mesh = mg.heterogeneous(128, seed=4)
+    print(f"[case] hetero128: {mesh.n_elems} elements", flush=True)
+    dm = fea.DeviceMesh(mesh)
+    b = fea.Batch([dm], model=fea.ELASTIC, use_nh=True)
+    # rows inside the neo-Hookean bricks as well as outside
+    _batch_rows_check(mesh, b, (fea.FP64, fea.MIXED), seed=2)
+    nh_nodes = mesh.conn[mesh.conn_ptr[np.nonzero(mesh.nh_flag)[0][:50]]]
+    rows = oracle_rows(mesh, sorted(set(nh_nodes.tolist())))
+    gr = dm.graph()
+    ex = gr.export()
+    v, r, _ = b.assemble()
+    torch.cuda.synchronize()
+    assert check_rows(mesh, rows, ex["row_ptr"].cpu().numpy(), ex["col"].cpu().numpy(),
+                      v, r, 3) <= 1e-12
+
+
+def test_hybrid256_batched_sampled_rows():
+    """53.9M elements, 391M nonzero blocks: FP64 and mixed, one mesh through
+    the persistent batched path."""
+    mesh = mg.hybrid_split(256, seed=5)
+    print(f"[case] hybrid256: {mesh.n_elems} elements", flush=True)
+    dm = fea.DeviceMesh(mesh)
+    b = fea.Batch([dm], model=fea.ELASTIC)
+    print(f"[case] hybrid256 graph built: {b.vals_len // 9} blocks", flush=True)
+    _batch_rows_check(mesh, b, (fea.MIXED, fea.FP64), seed=3, k=150)
