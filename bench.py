@@ -219,9 +219,17 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
     out["fp64_type_sorted"] = fp64_ts
     mix_ts, vmx, stm = run(fea.MIXED)
     out["mixed_type_sorted"] = mix_ts
-    # training data: the cycles of the mixed type-sorted runs
-    c, _, _ = b.cycles()
-    target = fea.CostModel.log_cycles(c)
+    # training data: log-cycles of every item, averaged over five
+    # type-sorted mixed runs (single runs are noisy: concurrent workgroups
+    # share the caches and memory channels)
+    vals, rhs, st = b.outputs(fea.F32)
+    logs = []
+    for _ in range(5):
+        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs, status=st)
+        c, _, _ = b.cycles()
+        logs.append(fea.CostModel.log_cycles(c))
+    target = torch.stack(logs).mean(dim=0).contiguous()
+    del vals, rhs, st
     feats = b.features(fp64_geometry=False)
     cm = fea.CostModel(seed=7)
     cm.fit_norm(feats)
