@@ -248,9 +248,12 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
         if (mat->model == FEA_POISSON)
             rc = o->precision == FEA_FP64 ? run<FEA_POISSON, double>(g, a, o, stream, vals, rhs)
                                           : run<FEA_POISSON, float>(g, a, o, stream, vals, rhs);
-        else
+        else if (!a.nh_flag)
             rc = o->precision == FEA_FP64 ? run<FEA_ELASTIC, double>(g, a, o, stream, vals, rhs)
                                           : run<FEA_ELASTIC, float>(g, a, o, stream, vals, rhs);
+        else
+            rc = o->precision == FEA_FP64 ? run<M_ELASTIC_NH, double>(g, a, o, stream, vals, rhs)
+                                          : run<M_ELASTIC_NH, float>(g, a, o, stream, vals, rhs);
         if (rc) return rc;
     } else {
         const int B = mat->model == FEA_POISSON ? 1 : 3;

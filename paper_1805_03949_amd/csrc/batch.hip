@@ -248,6 +248,7 @@ using namespace fea;
 struct fea_batch {
     int device = 0;
     int model = FEA_ELASTIC;
+    bool has_nh = false;  // some mesh gives neo-Hookean flags
     int n_meshes = 0;
     std::vector<fea_mesh_desc> desc;
     std::vector<fea_graph *> graphs;
@@ -380,7 +381,7 @@ int make_partition(fea_batch *b)
 template <int MODEL, typename CT>
 int worker_count(fea_batch *b)
 {
-    const int key = MODEL * 2 + (sizeof(CT) == 4);
+    const int key = MODEL * 2 + (sizeof(CT) == 4);  // MODEL 0..2
     if (b->workers_for == key) return FEA_OK;
     int cus = 0, per = 0;
     FEA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
@@ -441,6 +442,13 @@ int dispatch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void
                        : launch_batch<FEA_POISSON, double, double>(b, o, s, vals, rhs, status);
         return f32 ? launch_batch<FEA_POISSON, float, float>(b, o, s, vals, rhs, status)
                    : launch_batch<FEA_POISSON, float, double>(b, o, s, vals, rhs, status);
+    }
+    if (b->has_nh) {
+        if (o->precision == FEA_FP64)
+            return f32 ? launch_batch<M_ELASTIC_NH, double, float>(b, o, s, vals, rhs, status)
+                       : launch_batch<M_ELASTIC_NH, double, double>(b, o, s, vals, rhs, status);
+        return f32 ? launch_batch<M_ELASTIC_NH, float, float>(b, o, s, vals, rhs, status)
+                   : launch_batch<M_ELASTIC_NH, float, double>(b, o, s, vals, rhs, status);
     }
     if (o->precision == FEA_FP64)
         return f32 ? launch_batch<FEA_ELASTIC, double, float>(b, o, s, vals, rhs, status)
@@ -525,6 +533,7 @@ int build(int n, const fea_mesh_desc *md, int model, const int32_t *tile, hipStr
         a.young = d.young;
         a.nu = d.nu;
         a.nh_flag = model == FEA_ELASTIC ? d.nh_flag : nullptr;
+        if (a.nh_flag) b->has_nh = true;
         a.u = d.u;
         a.source = d.source;
         bm[m].a = a;

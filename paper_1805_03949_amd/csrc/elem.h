@@ -178,6 +178,11 @@ struct ElemArgs {
 
 enum { V_ROWOWNER = 0, V_ATOMIC = 1, V_COLOUR = 2 };
 
+// Kernel model codes: FEA_POISSON, FEA_ELASTIC (linear elements only) and
+// M_ELASTIC_NH (some elements use the neo-Hookean tangent; only these
+// kernels carry the displacement and pushed-gradient LDS arrays).
+constexpr int M_ELASTIC_NH = 2;
+
 
 __device__ inline double det3(const double J[3][3])
 {
@@ -225,9 +230,10 @@ struct ElemSmem {
     static constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
     static constexpr int EPB = 256 / P;
     static constexpr bool ELAS = MODEL != FEA_POISSON;
+    static constexpr bool NHK = MODEL == M_ELASTIC_NH;
     static constexpr int B = ELAS ? 3 : 1;
     static constexpr int BB = B * B;
-    static constexpr int EU = ELAS ? EPB : 1;
+    static constexpr int EU = NHK ? EPB : 1;
     static constexpr bool RO = VAR == V_ROWOWNER;
 
     double sX[EPB][NN][3];
@@ -235,7 +241,7 @@ struct ElemSmem {
     CT sG[EPB][NQ][NN][3];   // physical gradients
     CT sH[EU][NQ][NN][3];    // neo-Hookean: gradients pushed through F^-T
     CT sC[EPB][NQ][4];       // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
-    double sLM[EU][2];       // lam, mu
+    double sLM[ELAS ? EPB : 1][2];  // lam, mu of every element (elasticity)
     int32_t sE[EPB];
     int sNH[EPB];
     int64_t sM[EPB];         // first slot of each element
@@ -243,7 +249,7 @@ struct ElemSmem {
     // Row-owner stores staged in LDS so that BB consecutive threads write one
     // block's BB contiguous values. Measured per family on MI355X: a gain
     // everywhere except FP64 pyramids, where the extra LDS halves occupancy.
-    static constexpr bool STAGE = RO && (sizeof(CT) == 4 || T != 1);
+    static constexpr bool STAGE = RO && (sizeof(CT) == 4 || T != 1 || !NHK);
     CT sK[STAGE ? EPB * P * BB : 1];
     int32_t sD[STAGE ? EPB * P : 1];
     double sDN[NQ][NN][3];   // reference gradients of this family
@@ -260,9 +266,10 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
     constexpr int EPB = 256 / P;
     constexpr bool ELAS = MODEL != FEA_POISSON;
+    constexpr bool NHK = MODEL == M_ELASTIC_NH;
     constexpr int B = ELAS ? 3 : 1;
     constexpr int BB = B * B;
-    constexpr int EU = ELAS ? EPB : 1;
+    constexpr int EU = NHK ? EPB : 1;
     constexpr bool RO = VAR == V_ROWOWNER;
 
     auto &sX = S.sX;
@@ -316,9 +323,8 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                 sX[el][a][0] = A.x[v];
                 sX[el][a][1] = A.y[v];
                 sX[el][a][2] = A.z[v];
-                if constexpr (ELAS) {
-                    const bool nh = A.nh_flag != nullptr;
-                    for (int c = 0; c < 3; ++c) sU[el][a][c] = nh ? A.u[3 * (int64_t)v + c] : 0.0;
+                if constexpr (NHK) {
+                    for (int c = 0; c < 3; ++c) sU[el][a][c] = A.u[3 * (int64_t)v + c];
                 }
             }
         }
@@ -333,7 +339,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                 sX[el][a][0] = A.x[v];
                 sX[el][a][1] = A.y[v];
                 sX[el][a][2] = A.z[v];
-                if constexpr (ELAS) {
+                if constexpr (NHK) {
                     bool nh = sNH[el] != 0;
                     for (int c = 0; c < 3; ++c) sU[el][a][c] = nh ? A.u[3 * (int64_t)v + c] : 0.0;
                 }
@@ -368,7 +374,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                 }
             double wd = c_ref.w[T][q] * d;
             sC[el][q][0] = (CT)wd;
-            if constexpr (ELAS) {
+            if constexpr (NHK) {
                 if (sNH[el]) {
                     const double lam = sLM[el][0], mu = sLM[el][1];
                     double F[3][3];
@@ -417,7 +423,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                     acc += sC[el][q][0] * dot;
                 }
                 K[0] = acc;
-            } else if (!sNH[el]) {
+            } else if (!NHK || !sNH[el]) {
                 // linear: K = lam S + mu S^T + mu tr(S) I, S = sum_q wd G_a (x) G_b
                 CT S[9];
 #pragma unroll
@@ -442,7 +448,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                         if (i == j) v += mu * tr;
                         K[i * 3 + j] = v;
                     }
-            } else {
+            } else if constexpr (NHK) {
                 // neo-Hookean: K_ij = sum_q c1 h_a,i h_b,j + c2 h_a,j h_b,i + c0 d_ij G_a.G_b
                 CT T1[9], T2[9], dsum = 0;
 #pragma unroll
