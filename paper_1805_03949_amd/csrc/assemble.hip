@@ -198,7 +198,7 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     fea_options dflt = {0, 0, 0, 0};
     const fea_options *o = opt ? opt : &dflt;
     if (!g || !mat) return set_error(FEA_EINVAL, "graph and material are required");
-    if (o->precision < 0 || o->precision > 1 || o->variant < 0 || o->variant > 2 ||
+    if (o->precision < 0 || o->precision > 1 || o->variant < 0 || o->variant > 3 ||
         o->out_dtype < 0 || o->out_dtype > 1)
         return set_error(FEA_EINVAL, "bad option (precision %d, variant %d, out_dtype %d)",
                          o->precision, o->variant, o->out_dtype);
@@ -244,7 +244,14 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     a.source = source;
     a.status = st;
 
-    if (g->n_elems > 0) {
+    if (g->n_elems > 0 && o->variant == FEA_ROWGATHER) {
+        if (a.nh_flag)
+            return set_error(FEA_EINVAL, "FEA_ROWGATHER assembles Poisson and linear elasticity only");
+        GatherInput in = {x, y, z, types, conn_ptr, conn, mat->young, mat->nu, source, st};
+        if ((rc = gather_assemble(g, in, mat->model, o->precision, o->out_dtype == FEA_F32, o->timing != 0,
+                                  stream, vals, rhs)))
+            return rc;
+    } else if (g->n_elems > 0) {
         if (mat->model == FEA_POISSON)
             rc = o->precision == FEA_FP64 ? run<FEA_POISSON, double>(g, a, o, stream, vals, rhs)
                                           : run<FEA_POISSON, float>(g, a, o, stream, vals, rhs);

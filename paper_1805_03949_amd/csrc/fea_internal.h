@@ -40,6 +40,16 @@ int scan_to_ptr_i64(const int64_t *in, int64_t n, int64_t *ptr, int64_t *tmp, hi
 // Grid size for a 1-D launch of n threads in blocks of `bs`.
 inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+struct GatherInput {
+    const double *x, *y, *z;
+    const uint8_t *types;
+    const int64_t *conn_ptr;
+    const int32_t *conn;
+    const double *young, *nu;
+    const double *source;
+    int32_t *status;
+};
+
 }  // namespace fea
 
 // The graph object behind the opaque fea_graph handle.
@@ -76,6 +86,20 @@ struct fea_graph {
     int16_t *colour = nullptr;
     int32_t *cperm = nullptr;
     std::vector<int64_t> cseg;
+    // Row-gather layout (built by the first FEA_ROWGATHER assembly). Tiles
+    // of consecutive rows, listed by class (rows of pure tet4, pyr5, pen6,
+    // hex8, then rows touching several families), class c at gtile_off[c] ..
+    // gtile_off[c+1]; each tile record holds r0, rows, first pair, pairs,
+    // first block, blocks, first inverse-map entry, entries (8 x int32). The
+    // (row, element) pairs of a tile are its rows' incidence entries; lane l
+    // of a tile is node l of the concatenated node lists of its pairs, whose
+    // node ids are gnodes[j0 + l]; gdesc[j] is the tile lane of inverse-map
+    // entry j's contribution.
+    int32_t *gtile = nullptr;
+    int64_t gtile_off[6] = {0, 0, 0, 0, 0, 0};
+    int32_t *gnodes = nullptr;
+    uint8_t *gdesc = nullptr;
+    bool gready = false;
     // lazily allocated workspaces of the scatter variants
     void *contrib = nullptr;
     size_t contrib_bytes = 0;
@@ -88,3 +112,11 @@ struct fea_graph {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
 };
+
+namespace fea {
+// Fused owner-computes assembly (FEA_ROWGATHER), in gather.hip. Builds the
+// row tiles on first use (blocks on the stream). model: FEA_POISSON or
+// FEA_ELASTIC (linear); precision: enum fea_precision.
+int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precision, bool out_f32,
+                    bool timing, hipStream_t s, void *vals, void *rhs);
+}  // namespace fea

@@ -291,7 +291,7 @@ static void destroy(fea_graph *g)
     if (!g) return;
     void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv, g->pnodes, g->pdest, g->prdest,
                     g->n2e_ptr, g->n2e, g->n2a, g->perm, g->colour, g->cperm,
-                    g->contrib, g->rcontrib, g->acc64};
+                    g->contrib, g->rcontrib, g->acc64, g->gtile, g->gnodes, g->gdesc};
     for (void *b : bufs) dfree(b);
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);

@@ -81,7 +81,12 @@ def test_graph_bit_exact(name):
     assert np.array_equal(ex["colour"], oc)
 
 
-VARIANTS = [fea.ROWOWNER, fea.ATOMIC, fea.COLOUR]
+VARIANTS = [fea.ROWOWNER, fea.ATOMIC, fea.COLOUR, fea.ROWGATHER]
+
+
+def _nh(name, model, variant):
+    # the row-gather variant assembles Poisson and linear elasticity only
+    return name == "hetero16" and model == oracle.ELASTIC and variant != fea.ROWGATHER
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -90,7 +95,7 @@ def test_fp64_parity(name, variant):
     m, og, dm, g = case(name)
     models = [oracle.POISSON] if name == "poisson_hex16" else [oracle.POISSON, oracle.ELASTIC]
     for model in models:
-        use_nh = name == "hetero16" and model == oracle.ELASTIC
+        use_nh = _nh(name, model, variant)
         ov, orr, _, _ = _oracle_assembly(name, model, use_nh)
         vals, rhs, st = dm.assemble(g, model=model, use_nh=use_nh, variant=variant)
         torch.cuda.synchronize()
@@ -105,7 +110,7 @@ def test_fp64_parity(name, variant):
 def test_mixed_within_fp32_bound(name, variant):
     m, og, dm, g = case(name)
     model = oracle.POISSON if name == "poisson_hex16" else oracle.ELASTIC
-    use_nh = name == "hetero16"
+    use_nh = _nh(name, model, variant)
     ov, orr, tv, tr = _oracle_assembly(name, model, use_nh)
     L = fp32_bound_L(m.types)
     B = 1 if model == oracle.POISSON else 3
@@ -121,7 +126,7 @@ def test_mixed_within_fp32_bound(name, variant):
         assert rv <= 1.0 and rr <= 1.0, (out, rv, rr)
 
 
-@pytest.mark.parametrize("variant", [fea.ROWOWNER, fea.COLOUR])
+@pytest.mark.parametrize("variant", [fea.ROWOWNER, fea.COLOUR, fea.ROWGATHER])
 def test_deterministic_variants_bitwise_repeatable(variant):
     m, og, dm, g = case("mix6_jitter")
     first = None
@@ -184,4 +189,86 @@ def test_bad_option_is_rejected():
     m, og, dm, g = case("tet_ragged")
     with pytest.raises(fea.FeaError) as ei:
         dm.assemble(g, model=fea.ELASTIC, variant=7)
+    assert ei.value.code == fea.FEA_EINVAL
+
+
+@pytest.mark.parametrize("name", ["bands8_jitter", "mix6_jitter", "tet_ragged"])
+def test_rowgather_matches_rowowner(name):
+    """Both sum every block's contributions in ascending element order from
+    the same per-element expressions; they may differ only by rounding."""
+    m, og, dm, g = case(name)
+    for prec, out in ((fea.FP64, fea.F64), (fea.MIXED, fea.F32)):
+        a = dm.assemble(g, model=fea.ELASTIC, variant=fea.ROWOWNER, precision=prec, out_dtype=out)
+        b = dm.assemble(g, model=fea.ELASTIC, variant=fea.ROWGATHER, precision=prec, out_dtype=out)
+        torch.cuda.synchronize()
+        for x, y in ((a[0], b[0]), (a[1], b[1])):
+            x = x.cpu().numpy().astype(np.float64)
+            y = y.cpu().numpy().astype(np.float64)
+            tol = 1e-14 if prec == fea.FP64 else 1e-6
+            assert np.abs(x - y).max() <= tol * np.abs(x).max(), (prec, np.abs(x - y).max())
+
+
+def test_rowgather_isolated_nodes_get_zero_rows():
+    m = mg.hybrid_bands(4, seed=31, jitter=0.2)
+    extra = 7
+    n = m.n_nodes + extra
+    d = "cuda:0"
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(d)
+    pad = lambda a, v: np.concatenate([a, np.full(extra, v)])
+    x, y, z = (dev(pad(c, 0.5)) for c in (m.x, m.y, m.z))
+    types, cp, conn = dev(m.types), dev(m.conn_ptr), dev(m.conn)
+    g = fea.Graph(n, types, cp, conn)
+    src = dev(m.source)
+    kw = dict(model=fea.ELASTIC, young=dev(m.young), nu=dev(m.nu))
+    v0, r0, _ = fea.assemble(g, x, y, z, types, cp, conn, src, variant=fea.ROWOWNER, **kw)
+    v1, r1, s1 = fea.assemble(g, x, y, z, types, cp, conn, src, variant=fea.ROWGATHER, **kw)
+    torch.cuda.synchronize()
+    assert int(s1.item()) == -1
+    r1 = r1.cpu().numpy()
+    assert np.all(r1[3 * m.n_nodes:] == 0.0)
+    assert np.abs(r1 - r0.cpu().numpy()).max() <= 1e-14 * np.abs(r1).max()
+    assert np.abs(v1.cpu().numpy() - v0.cpu().numpy()).max() <= 1e-14 * np.abs(v0.cpu().numpy()).max()
+
+
+def test_rowgather_rejects_node_in_too_many_elements():
+    """A node shared by 70 tetrahedra exceeds the 64 (row, element) pairs a
+    row-gather tile holds: the call fails with FEA_ERANGE naming the node,
+    and the row-owner variant still assembles the mesh."""
+    k = 70
+    ang = 2 * np.pi * np.arange(k) / k
+    pts = [(0.0, 0.0, 0.0)]
+    conn = []
+    for i in range(k):
+        c, s = np.cos(ang[i]), np.sin(ang[i])
+        base = len(pts)
+        pts += [(c, s, 0.0), (c + 0.1 * -s, s + 0.1 * c, 0.0), (c, s, 1.0)]
+        conn += [0, base, base + 1, base + 2]
+    pts = np.array(pts)
+    conn = np.array(conn, dtype=np.int32)
+    # orient every tetrahedron positively
+    for e in range(k):
+        a, b, c_, d_ = pts[conn[4 * e:4 * e + 4]]
+        if np.linalg.det(np.stack([b - a, c_ - a, d_ - a])) < 0:
+            conn[4 * e + 1], conn[4 * e + 2] = conn[4 * e + 2], conn[4 * e + 1]
+    d = "cuda:0"
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(d)
+    types = dev(np.zeros(k, dtype=np.uint8))
+    cp = dev(np.arange(0, 4 * k + 1, 4, dtype=np.int64))
+    cn = dev(conn)
+    g = fea.Graph(len(pts), types, cp, cn)
+    x, y, z = (dev(pts[:, i].copy()) for i in range(3))
+    src = dev(np.zeros((k, 3)))
+    nu = dev(np.full(k, 0.3))
+    _, _, st = fea.assemble(g, x, y, z, types, cp, cn, src, model=fea.ELASTIC, nu=nu)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -1
+    with pytest.raises(fea.FeaError) as ei:
+        fea.assemble(g, x, y, z, types, cp, cn, src, model=fea.ELASTIC, nu=nu, variant=fea.ROWGATHER)
+    assert ei.value.code == fea.FEA_ERANGE and "node 0 " in ei.value.msg
+
+
+def test_rowgather_rejects_neo_hookean():
+    m, og, dm, g = case("hetero16")
+    with pytest.raises(fea.FeaError) as ei:
+        dm.assemble(g, model=fea.ELASTIC, use_nh=True, variant=fea.ROWGATHER)
     assert ei.value.code == fea.FEA_EINVAL

@@ -46,10 +46,14 @@ def test_hybrid96_rowowner_fp64_and_mixed_sampled_rows():
     torch.cuda.synchronize()
     L = fp32_bound_L(mesh.types)
     assert check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L) <= 1.0
-    for variant in (fea.ATOMIC, fea.COLOUR):
-        v, r, _ = dm.assemble(g, variant=variant)
+    for variant in (fea.ATOMIC, fea.COLOUR, fea.ROWGATHER):
+        v, r, st = dm.assemble(g, variant=variant)
         torch.cuda.synchronize()
+        assert int(st.item()) == -1
         assert check_rows(mesh, rows, row_ptr, col, v, r, 3) <= 1e-12
+    v, r, _ = dm.assemble(g, variant=fea.ROWGATHER, precision=fea.MIXED, out_dtype=fea.F32)
+    torch.cuda.synchronize()
+    assert check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L) <= 1.0
 
 
 def _batch_rows_check(mesh, b, precisions, seed, k=200):
