@@ -10,7 +10,7 @@ z-bands of 24 cell layers (hex8 / pen6 / tet4 / pyr5), E = 1, nu per element
 U[0.2, 0.35], body force (0, 0, -1); 3,317,760 elements, 1,133,857 nodes.
 
 Prints one JSON line. Usage:
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--variant rowowner]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--variant rowgather]
                   [--precision fp64|mixed] [--no-cpu] [--no-variants]
 """
 from __future__ import annotations
@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector
 METRIC = "elements assembled/s + scatter HBM GB/s (% peak); learned+mixed vs plain FP64"
 
 
@@ -43,31 +44,66 @@ def scatter_bytes(g, B, s_c, s_v, conn_len, n_nodes):
     return reduce_bytes(g, B, s_c, s_v) + conn_len * B * s_c + (n_nodes + 1) * 8 + n_nodes * B * s_v
 
 
-def element_bytes(g, B, s_c, conn_len, n_nodes, n_elems, variant):
+def element_bytes(g, B, s_c, s_v, conn_len, n_nodes, n_elems, variant):
     """Algorithmic bytes of the element phase: node coordinates once, the
     connectivity and per-element data once, and its outputs once (the slot
-    contributions for row-owner)."""
+    contributions for row-owner; for row-gather the final values, plus the
+    pair-ordered node lists, lane bytes and segment bounds it reads)."""
     inputs = n_nodes * 24 + conn_len * 4 + n_elems * (8 + 4 + 8 + 16 + 8 * B)
     if variant == "rowowner":
         return inputs + g.map_len * B * B * s_c + conn_len * B * s_c
+    if variant == "rowgather":
+        maps = g.map_len * (4 + 1) + conn_len * 5 + (g.nnz + 1) * 8 + (n_nodes + 1) * 8
+        return inputs + maps + g.nnz * B * B * s_v + n_nodes * B * s_v
     return inputs + g.map_len * 4 + g.nnz * B * B * 8 * 2 + n_nodes * B * 8 * 2
 
 
-def traffic_from_profile(kernel_key):
+GATHER_FAMILIES = ("tet4", "pyr5", "pen6", "hex8", "interface")
+NODES = (4, 5, 6, 8)
+GAUSS = (1, 8, 6, 8)
+
+
+def gather_pair_flops(t, B=3):
+    """FP64 (or mixed) floating-point operations the row-gather kernel
+    executes for one (row, element) pair of family t, recomputation
+    included: per Gauss point the Jacobian (18 n), its determinant (14) and
+    inverse (37), the row node's weighted gradient (19) and the pair's
+    right-hand-side term (7); per element node b and Gauss point the
+    gradient of b (15) and the 3x3 outer-product update (18), then the
+    block from S (33); per element node one 9-value addition into the
+    block sums."""
+    n, q = NODES[t], GAUSS[t]
+    return q * (18 * n + 70 + 7) + n * (q * 33 + 33) + n * B * B
+
+
+def gather_class_flops(mesh, np):
+    """Executed flops of each row-tile class kernel (pure tet4, pyr5, pen6,
+    hex8 rows, interface rows) for one assembly."""
+    et = mesh.types[np.repeat(np.arange(mesh.n_elems), np.diff(mesh.conn_ptr))]
+    mask = np.zeros(mesh.n_nodes, dtype=np.int64)
+    np.bitwise_or.at(mask, mesh.conn, (1 << et.astype(np.int64)))
+    single = (mask & (mask - 1)) == 0
+    cls = np.where(single, np.log2(np.maximum(mask, 1)).astype(np.int64), 4)
+    pair_cls = cls[mesh.conn]
+    pf = np.array([gather_pair_flops(t) for t in range(4)], dtype=np.float64)[et]
+    return [float(pf[pair_cls == c].sum()) for c in range(5)]
+
+
+def traffic_from_profile(kernel_key, source):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    names this kernel and matches the current kernel source."""
+    names this kernel and matches the current source file of the kernel."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
     import hashlib
-    src = open(os.path.join(ROOT, "paper_1805_03949_amd", "csrc", "assemble.hip"), "rb").read()
+    src = open(os.path.join(ROOT, "paper_1805_03949_amd", "csrc", source), "rb").read()
     digest = hashlib.sha256(src).hexdigest()[:16]
     rec = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("source_sha256_16") != digest:
+    if rec.get(f"source_sha256_16[{source}]") != digest:
         return None
     v = rec.get(f"{kernel_key}_bytes")
     return float(v) if v else None
@@ -284,7 +320,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cells", type=int, default=96)
-    ap.add_argument("--variant", default="rowowner")
+    ap.add_argument("--variant", default="rowgather")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -354,25 +390,51 @@ def main():
     print(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
 
     # phase durations from HIP events recorded by the library on its stream
-    phases = []
+    phases, classes = [], []
     for _ in range(max(5, min(args.steps, 20))):
         step(timing=True)
         phases.append(g.last_timing())
+        if args.variant == "rowgather":
+            classes.append(g.last_class_timing())
     ph = np.median(np.array(phases), axis=0)
     elem_ms, second_ms = float(ph[0]), float(ph[1])
-    eb = element_bytes(g, B, s_c, conn_len, mesh.n_nodes, mesh.n_elems, args.variant)
-    if args.variant == "rowowner":
+    eb = element_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes, mesh.n_elems, args.variant)
+    sb = scatter_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes)
+    copy_gbps = copy_bandwidth(torch)
+    class_ms = None
+    if args.variant == "rowgather":
+        # dominant kernel: the row-tile class kernel that takes longest; its
+        # bound is FP64 (vector ALU) arithmetic, not HBM
+        cm = np.median(np.array(classes), axis=0)
+        class_ms = {n: round(float(v), 4) for n, v in zip(GATHER_FAMILIES, cm)}
+        flops = gather_class_flops(mesh, np)
+        c = int(np.argmax(cm))
+        kernel, k_ms, k_work = f"k_gather<{GATHER_FAMILIES[c]}>", float(cm[c]), flops[c]
+        achieved = k_work / (k_ms * 1e-3) / 1e12
+        peak = PEAK_FP64_TFLOPS
+        roofline = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 2), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                    "traffic": traffic_from_profile(kernel, "gather.hip"),
+                    "algorithmic_flops": int(k_work), "kernel_ms": round(k_ms, 4),
+                    "note": "flops as executed: geometry recomputed once per (row, element) pair"}
+    elif args.variant == "rowowner":
         kernel, k_ms, k_bytes = "k_reduce_seg<9>", second_ms, reduce_bytes(g, B, s_c, s_v)
+        achieved = k_bytes / (k_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                    "traffic": traffic_from_profile(kernel, "assemble.hip"),
+                    "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4),
+                    "copy_GBps": copy_gbps, "frac_of_copy": round(achieved / copy_gbps, 4)}
     else:
         kernel, k_ms, k_bytes = f"{args.variant} element phase", elem_ms, eb
-    achieved = k_bytes / (k_ms * 1e-3) / 1e9
-    sb = scatter_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes)
-    traffic = traffic_from_profile(kernel)
-    copy_gbps = copy_bandwidth(torch)
+        achieved = k_bytes / (k_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                    "traffic": None, "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4)}
 
     variants = {}
     if not args.no_variants:
-        for vname in ("rowowner", "atomic", "colour"):
+        for vname in ("rowgather", "rowowner", "atomic", "colour"):
             for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
                 vv, rr, ss = dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o)
                 dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o, vals=vv, rhs=rr, status=ss)
@@ -388,6 +450,14 @@ def main():
                                                 "elements_per_s": round(mesh.n_elems / (float(med[2]) * 1e-3), 1)}
                 del vv, rr, ss
         torch.cuda.synchronize()
+        ro = variants["rowowner_fp64"]
+        rb = reduce_bytes(g, B, 8, 8)
+        ra = rb / (ro["block_value_kernel_ms"] * 1e-3) / 1e9
+        variants["rowowner_fp64"]["roofline"] = {
+            "bound": "hbm", "kernel": "k_reduce_seg<9>", "achieved": round(ra, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(ra / PEAK_HBM_GBS, 4),
+            "traffic": traffic_from_profile("k_reduce_seg<9>", "assemble.hip"),
+            "algorithmic_bytes": int(rb), "copy_GBps": copy_gbps, "frac_of_copy": round(ra / copy_gbps, 4)}
 
     extras = {}
     if not args.no_extras:
@@ -435,13 +505,11 @@ def main():
                    "elements": mesh.n_elems, "nodes": mesh.n_nodes, "nnz_blocks": g.nnz,
                    "variant": args.variant, "precision": args.precision,
                    "out_dtype": "f64" if outd == fea.F64 else "f32"},
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4),
-                     "copy_GBps": copy_gbps, "frac_of_copy": round(achieved / copy_gbps, 4)},
+        "roofline": roofline,
         "scatter": {"effective_GBps": round(sb / ((float(ph[2]) - elem_ms) * 1e-3) / 1e9, 1) if args.variant == "rowowner" else None,
                     "frac_of_peak": round(sb / ((float(ph[2]) - elem_ms) * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if args.variant == "rowowner" else None,
-                    "algorithmic_bytes": int(sb), "note": "matrix and right-hand side, second phase"},
+                    "algorithmic_bytes": int(sb), "note": "matrix and right-hand side, second phase of the row-owner form"},
+        "gather_class_ms": class_ms,
         "element_phase": {"algorithmic_bytes": int(eb), "ms": round(elem_ms, 4),
                           "effective_GBps": round(eb / (elem_ms * 1e-3) / 1e9, 1)},
         "phases_ms": {"element": round(elem_ms, 4), "block_value_kernel": round(second_ms, 4),

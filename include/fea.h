@@ -127,7 +127,12 @@ void fea_graph_destroy(fea_graph *g);
  * Jacobian determinant (or deformation-gradient determinant) is not
  * positive at a Gauss point, or -1. Enqueued on `stream`; the first call
  * with a given variant may allocate a workspace held by the graph.
- * Errors: FEA_EINVAL (NULL pointer, bad option), FEA_ENOMEM, FEA_EHIP.
+ * FEA_ROWGATHER: Poisson and linear elasticity (nh_flag must be NULL); its
+ * first call on a graph builds the row tiles and blocks on `stream`; a
+ * node may lie in at most 64 elements (and its elements may hold at most
+ * 256 nodes and 384 Gauss points in total), else FEA_ERANGE naming the node.
+ * Errors: FEA_EINVAL (NULL pointer, bad option), FEA_ERANGE, FEA_ENOMEM,
+ * FEA_EHIP.
  */
 int fea_assemble(const fea_graph *g, const double *x, const double *y, const double *z,
                  const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
@@ -137,12 +142,19 @@ int fea_assemble(const fea_graph *g, const double *x, const double *y, const dou
 /* Phase durations of the graph's last fea_assemble call made with
  * opt->timing set, in milliseconds, measured with HIP events on that call's
  * stream: ms[0] element kernels (with the fused scatter for ATOMIC and
- * COLOUR), ms[1] the one kernel that forms the matrix values after them
- * (row-owner: the segmented reduction of the block values; ATOMIC/COLOUR
- * with FP32 output: the conversion; otherwise empty), ms[2] the whole call
- * including zero-fill and the right-hand side. Waits for the events.
- * FEA_EINVAL if no timed call was made. */
+ * COLOUR, and all of ROWGATHER), ms[1] the one kernel that forms the matrix
+ * values after them (row-owner: the segmented reduction of the block
+ * values; ATOMIC/COLOUR with FP32 output: the conversion; otherwise empty),
+ * ms[2] the whole call including zero-fill and the right-hand side. Waits
+ * for the events. FEA_EINVAL if no timed call was made. */
 int fea_last_timing(const fea_graph *g, float *ms);
+
+/* Durations (ms, HIP events on the call's stream) of the five kernels of
+ * the graph's last timed FEA_ROWGATHER assembly, one per row-tile class:
+ * ms[0..3] rows whose elements are all tet4, pyr5, pen6, hex8, ms[4] rows
+ * on family interfaces (0 for a class with no rows). Waits for the events.
+ * FEA_EINVAL if the last timed assembly was not FEA_ROWGATHER. */
+int fea_last_class_timing(const fea_graph *g, float *ms);
 
 /* ------------------------------------------------------------------ *
  * Batched assembly: many independent meshes in one persistent launch. *

@@ -53,6 +53,7 @@ _lib.fea_graph_destroy.restype = None
 _lib.fea_assemble.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Material), _P,
                               ctypes.POINTER(Options), _P, _P, _P, _P]
 _lib.fea_last_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
+_lib.fea_last_class_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.fea_last_error.restype = ctypes.c_char_p
 _lib.fea_version.restype = ctypes.c_char_p
 
@@ -105,7 +106,7 @@ N_FEATURES, N_PARAMS = 12, 5057
 
 # every exported symbol declared in include/fea.h
 EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_export", "fea_graph_destroy",
-           "fea_assemble", "fea_last_timing", "fea_last_error", "fea_version",
+           "fea_assemble", "fea_last_timing", "fea_last_class_timing", "fea_last_error", "fea_version",
            "fea_batch_build", "fea_batch_sizes", "fea_batch_offsets", "fea_batch_items",
            "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_assemble", "fea_batch_capture",
            "fea_batch_replay", "fea_batch_cycles", "fea_batch_last_ms", "fea_batch_workers",
@@ -195,6 +196,13 @@ class Graph:
         """(element ms, second-phase ms, total ms) of the last timed assemble."""
         ms = (ctypes.c_float * 3)()
         _check(_lib.fea_last_timing(self.handle, ms))
+        return tuple(float(v) for v in ms)
+
+    def last_class_timing(self):
+        """Per-class kernel ms (tet4, pyr5, pen6, hex8, interface rows) of the
+        last timed row-gather assemble."""
+        ms = (ctypes.c_float * 5)()
+        _check(_lib.fea_last_class_timing(self.handle, ms))
         return tuple(float(v) for v in ms)
 
     def destroy(self):

@@ -222,6 +222,7 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
             if (!e) FEA_HIP(hipEventCreate(&e));
     }
     g->timed = false;
+    g->gtimed = false;
 
     int32_t *st = status;
     if (!st) {

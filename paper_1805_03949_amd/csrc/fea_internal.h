@@ -100,6 +100,10 @@ struct fea_graph {
     int32_t *gnodes = nullptr;
     uint8_t *gdesc = nullptr;
     bool gready = false;
+    // events around the five class kernels of the last timed row-gather
+    // assembly (gev[c] before class c, gev[5] after the last)
+    hipEvent_t gev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool gtimed = false;
     // lazily allocated workspaces of the scatter variants
     void *contrib = nullptr;
     size_t contrib_bytes = 0;

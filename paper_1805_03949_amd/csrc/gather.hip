@@ -714,10 +714,11 @@ static int launch_class(GatherArgs A, int64_t n, hipStream_t s)
 }
 
 template <int MODEL, typename CT>
-static int launch_classes(fea_graph *g, GatherArgs A, hipStream_t s)
+static int launch_classes(fea_graph *g, GatherArgs A, hipStream_t s, bool timing)
 {
     int rc = FEA_OK;
     for (int c = 0; c < 5 && !rc; ++c) {
+        if (timing) FEA_HIP(hipEventRecord(g->gev[c], s));
         const int64_t n = g->gtile_off[c + 1] - g->gtile_off[c];
         if (n <= 0) continue;
         A.tiles = g->gtile + 8 * g->gtile_off[c];
@@ -729,6 +730,7 @@ static int launch_classes(fea_graph *g, GatherArgs A, hipStream_t s)
         default: rc = launch_class<G_MIXED, MODEL, CT>(A, n, s); break;
         }
     }
+    if (!rc && timing) FEA_HIP(hipEventRecord(g->gev[5], s));
     return rc;
 }
 
@@ -756,14 +758,20 @@ int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precisio
     A.vals = vals;
     A.rhs = rhs;
     A.out_f32 = out_f32 ? 1 : 0;
-    if (timing) FEA_HIP(hipEventRecord(g->ev[0], s));
+    g->gtimed = false;
+    if (timing) {
+        for (hipEvent_t &e : g->gev)
+            if (!e) FEA_HIP(hipEventCreate(&e));
+        FEA_HIP(hipEventRecord(g->ev[0], s));
+    }
     if (model == FEA_POISSON)
-        rc = precision == FEA_FP64 ? launch_classes<FEA_POISSON, double>(g, A, s)
-                                   : launch_classes<FEA_POISSON, float>(g, A, s);
+        rc = precision == FEA_FP64 ? launch_classes<FEA_POISSON, double>(g, A, s, timing)
+                                   : launch_classes<FEA_POISSON, float>(g, A, s, timing);
     else
-        rc = precision == FEA_FP64 ? launch_classes<FEA_ELASTIC, double>(g, A, s)
-                                   : launch_classes<FEA_ELASTIC, float>(g, A, s);
+        rc = precision == FEA_FP64 ? launch_classes<FEA_ELASTIC, double>(g, A, s, timing)
+                                   : launch_classes<FEA_ELASTIC, float>(g, A, s, timing);
     if (rc) return rc;
+    g->gtimed = timing;
     FEA_HIP(hipGetLastError());
     if (timing) {
         // one fused kernel per class: no separate block-value phase
@@ -775,3 +783,15 @@ int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precisio
 }
 
 }  // namespace fea
+
+using namespace fea;
+
+extern "C" int fea_last_class_timing(const fea_graph *g, float *ms)
+{
+    clear_error();
+    if (!g || !ms) return set_error(FEA_EINVAL, "graph and ms are required");
+    if (!g->gtimed) return set_error(FEA_EINVAL, "no timed FEA_ROWGATHER assembly on this graph");
+    FEA_HIP(hipEventSynchronize(g->gev[5]));
+    for (int c = 0; c < 5; ++c) FEA_HIP(hipEventElapsedTime(&ms[c], g->gev[c], g->gev[c + 1]));
+    return FEA_OK;
+}

@@ -295,6 +295,8 @@ static void destroy(fea_graph *g)
     for (void *b : bufs) dfree(b);
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : g->gev)
+        if (e) (void)hipEventDestroy(e);
     delete g;
 }
 
