@@ -491,7 +491,26 @@ k_gather(GatherArgs A, int64_t ntiles)
             double s[B];
 #pragma unroll
             for (int c = 0; c < B; ++c) s[c] = 0.0;
-            for (int j = S.sIP[k]; j < S.sIP[k + 1]; ++j) {
+            int j = S.sIP[k];
+            const int je = S.sIP[k + 1];
+            // four contributions' loads in flight; additions in ascending order
+            for (; j + 4 <= je; j += 4) {
+                const CT *s0 = S.sL[S.sD[j]].k + i * B, *s1 = S.sL[S.sD[j + 1]].k + i * B;
+                const CT *s2 = S.sL[S.sD[j + 2]].k + i * B, *s3 = S.sL[S.sD[j + 3]].k + i * B;
+                CT v[4][B];
+#pragma unroll
+                for (int c = 0; c < B; ++c) {
+                    v[0][c] = s0[c];
+                    v[1][c] = s1[c];
+                    v[2][c] = s2[c];
+                    v[3][c] = s3[c];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < B; ++c) s[c] += (double)v[u][c];
+            }
+            for (; j < je; ++j) {
                 const CT *src = S.sL[S.sD[j]].k + i * B;
 #pragma unroll
                 for (int c = 0; c < B; ++c) s[c] += (double)src[c];
