@@ -173,8 +173,8 @@ def copy_bandwidth(torch):
 
 def large_workload(fea, mg, torch, np, cells=256):
     """53.9M-element hybrid mesh (40/30/20/10 hex/tet/pen/pyr layers) through
-    the persistent path: plain FP64 against mixed precision with the learned
-    schedule."""
+    the persistent path (plain FP64 against mixed precision with the learned
+    schedule), then through the fused row-gather form."""
     mesh = mg.hybrid_split(cells, seed=5)
     dm = fea.DeviceMesh(mesh)
     b = fea.Batch([dm], model=fea.ELASTIC)
@@ -215,6 +215,23 @@ def large_workload(fea, mg, torch, np, cells=256):
     best = min(out["mixed_static_learned"]["total_ms"], out["mixed_queue_learned"]["total_ms"])
     out["speedup_learned_mixed_vs_fp64"] = round(out["fp64_type_sorted"]["total_ms"] / best, 4)
     b.destroy()
+    torch.cuda.empty_cache()
+
+    # the same mesh through the fused row-gather form (no workspace)
+    g = dm.graph()
+    for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
+        vals, rhs, st = dm.assemble(g, variant=fea.ROWGATHER, precision=p, out_dtype=o)
+        tot = []
+        for _ in range(5):
+            dm.assemble(g, variant=fea.ROWGATHER, precision=p, out_dtype=o, vals=vals, rhs=rhs, status=st,
+                        timing=True)
+            tot.append(g.last_timing()[2])
+        ok = int(st.item()) == -1
+        out[f"rowgather_{pname}"] = {"total_ms": round(float(np.median(tot)), 3),
+                                    "elements_per_s": round(mesh.n_elems / (float(np.median(tot)) * 1e-3), 1),
+                                    "status_ok": ok}
+        del vals, rhs, st
+    g.destroy()
     return out
 
 

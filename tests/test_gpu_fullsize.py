@@ -103,3 +103,23 @@ def test_hybrid256_batched_sampled_rows():
     b = fea.Batch([dm], model=fea.ELASTIC)
     print(f"[case] hybrid256 graph built: {b.vals_len // 9} blocks", flush=True)
     _batch_rows_check(mesh, b, (fea.MIXED, fea.FP64), seed=3, k=150)
+    b.destroy()
+    del b
+    torch.cuda.empty_cache()
+    # the same mesh through the row-gather form, on other sampled rows
+    nodes = sample_nodes(mesh, 150, 4)
+    rows = oracle_rows(mesh, nodes)
+    g = dm.graph()
+    ex = g.export()
+    row_ptr, col = ex["row_ptr"].cpu().numpy(), ex["col"].cpu().numpy()
+    del ex
+    for prec in (fea.FP64, fea.MIXED):
+        outd = fea.F64 if prec == fea.FP64 else fea.F32
+        print(f"[case] hybrid256 row-gather precision {prec}", flush=True)
+        v, r, st = dm.assemble(g, variant=fea.ROWGATHER, precision=prec, out_dtype=outd)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -1
+        L = None if prec == fea.FP64 else fp32_bound_L(mesh.types)
+        worst = check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L)
+        assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (prec, worst)
+        del v, r
