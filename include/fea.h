@@ -127,8 +127,8 @@ void fea_graph_destroy(fea_graph *g);
  * Jacobian determinant (or deformation-gradient determinant) is not
  * positive at a Gauss point, or -1. Enqueued on `stream`; the first call
  * with a given variant may allocate a workspace held by the graph.
- * FEA_ROWGATHER: Poisson and linear elasticity (nh_flag must be NULL); its
- * first call on a graph builds the row tiles and blocks on `stream`; a
+ * FEA_ROWGATHER: the first call on a graph builds the row tiles and blocks
+ * on `stream`; a
  * node may lie in at most 64 elements (and its elements may hold at most
  * 256 nodes and 384 Gauss points in total), else FEA_ERANGE naming the node.
  * Errors: FEA_EINVAL (NULL pointer, bad option), FEA_ERANGE, FEA_ENOMEM,

@@ -246,9 +246,7 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     a.status = st;
 
     if (g->n_elems > 0 && o->variant == FEA_ROWGATHER) {
-        if (a.nh_flag)
-            return set_error(FEA_EINVAL, "FEA_ROWGATHER assembles Poisson and linear elasticity only");
-        GatherInput in = {x, y, z, types, conn_ptr, conn, mat->young, mat->nu, source, st};
+        GatherInput in = {x, y, z, types, conn_ptr, conn, mat->young, mat->nu, source, st, a.nh_flag, mat->u};
         if ((rc = gather_assemble(g, in, mat->model, o->precision, o->out_dtype == FEA_F32, o->timing != 0,
                                   stream, vals, rhs)))
             return rc;

@@ -48,6 +48,8 @@ struct GatherInput {
     const double *young, *nu;
     const double *source;
     int32_t *status;
+    const uint8_t *nh_flag;  // NULL, or neo-Hookean tangent where set
+    const double *u;
 };
 
 }  // namespace fea
@@ -120,7 +122,8 @@ struct fea_graph {
 namespace fea {
 // Fused owner-computes assembly (FEA_ROWGATHER), in gather.hip. Builds the
 // row tiles on first use (blocks on the stream). model: FEA_POISSON or
-// FEA_ELASTIC (linear); precision: enum fea_precision.
+// FEA_ELASTIC (with in.nh_flag: the neo-Hookean tangent where flagged);
+// precision: enum fea_precision.
 int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precision, bool out_f32,
                     bool timing, hipStream_t s, void *vals, void *rhs);
 }  // namespace fea

@@ -54,25 +54,34 @@ struct GatherSmem {
     // One-family tiles take their Gauss points in NCH chunks of QC: the
     // geometry records of one chunk at a time live in LDS (the strips keep
     // their partial sums in registers), which halves the records' LDS.
-    static constexpr int NCH = (!MIX && NQ >= 6) ? 2 : 1;
+    static constexpr bool NHK = MODEL == M_ELASTIC_NH;
+    static constexpr int NCH = MIX ? 1 : (NQ < 6 ? 1 : (NHK ? NQ / 2 : 2));
     static constexpr int QC = NQ / NCH;
+    static_assert(NQ % NCH == 0 && NCH <= 4, "whole chunks");
     // Records of pair p start at p * GS: an odd stride (5 for 4 points)
     // keeps the records that one wave's lanes read at the same point in
     // distinct LDS banks (a stride of 4 or 8 maps every fourth pair to one).
-    static constexpr int GS = (QC == 4 || QC == 8) ? QC + 1 : QC;
+    static constexpr int GS = (QC == 2 || QC == 4 || QC == 8) ? QC + 1 : QC;
     static constexpr int GMAX = MIX ? G_GMAX_MIXED : PMAX * GS;
     static constexpr int NT = MIX ? 4 : 1;
     static constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
     static constexpr int BB = B * B;
+    // accumulators of a strip lane: S, or T1, T2 and the gradient dot sum
+    static constexpr int ACC = NHK ? 19 : BB;
 
     double sJi[GMAX][9];      // inverse Jacobian at each (pair, Gauss point)
     CT sGa[GMAX][3];          // physical gradient of the row node there
-                              // (elasticity: times the weight, wd G_a)
+                              // (linear elasticity: times the weight, wd G_a)
     CT sWd[GMAX];             // weight times det J
-    // one slot per lane: the node's coordinates until the geometry is done,
-    // then the lane's block
+    // neo-Hookean pairs: F^-1, the row node's gradient pushed through it
+    // (h_a,j = sum_J G_a,J Finv_Jj) and wd lam, wd (mu - lam ln det F), wd mu
+    double sFi[NHK ? GMAX : 1][9];
+    CT sHa[NHK ? GMAX : 1][3];
+    CT sCc[NHK ? GMAX : 1][3];
+    // one slot per lane: the node's coordinates (and displacement) until the
+    // geometry is done, then the lane's block
     union LaneSlot {
-        double x[3];
+        double x[NHK ? 6 : 3];
         CT k[BB];
     };
     static constexpr int LMAX = MIX ? GT : PMAX * NN;
@@ -85,6 +94,7 @@ struct GatherSmem {
     double sN[NT][8][8];
     double sW[NT][8];
     double sLM[PMAX][2];      // lam, mu of each pair's element
+    int32_t sNH[NHK ? PMAX : 1];  // neo-Hookean flag of each pair's element
     int32_t sE[PMAX];
     int32_t sA[PMAX];         // local index of the row node in the element
     int32_t sT[MIX ? PMAX : 1];
@@ -108,6 +118,8 @@ struct GatherArgs {
     const uint8_t *n2a;
     const int32_t *gnodes;
     const uint8_t *desc;
+    const uint8_t *nh_flag;  // neo-Hookean kernels: per element
+    const double *u;         // and displacements, 3 per node
     const int32_t *tiles;  // tile records of this launch
     void *vals, *rhs;
     int out_f32;
@@ -135,22 +147,63 @@ __device__ inline void g_geometry(Sm &S, const GatherArgs &A, int p, int x0, int
     inv3(J, d, Ji);
     const int a = S.sA[p];
     const double da0 = S.sDN[tf][q][a][0], da1 = S.sDN[tf][q][a][1], da2 = S.sDN[tf][q][a][2];
-    const CT w = (CT)(S.sW[tf][q] * d);
+    const double wd = S.sW[tf][q] * d;
+    const CT w = (CT)wd;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const CT ga = (CT)(Ji[0][i] * da0 + Ji[1][i] * da1 + Ji[2][i] * da2);
-        S.sGa[g][i] = MODEL == FEA_POISSON ? ga : w * ga;
+        S.sGa[g][i] = (MODEL == FEA_POISSON || Sm::NHK) ? ga : w * ga;
 #pragma unroll
         for (int j = 0; j < 3; ++j) S.sJi[g][i * 3 + j] = Ji[i][j];
     }
     S.sWd[g] = w;
+    if constexpr (Sm::NHK) {
+        if (S.sNH[p]) {
+            // F = I + sum_c u_c (x) G_c, then F^-1, the pushed row gradient
+            // and the tangent coefficients (the element kernels' expressions)
+            double G[NN][3];
+#pragma unroll
+            for (int c = 0; c < NN; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    G[c][i] = Ji[0][i] * S.sDN[tf][q][c][0] + Ji[1][i] * S.sDN[tf][q][c][1] +
+                              Ji[2][i] * S.sDN[tf][q][c][2];
+            double Fd[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+                    for (int c = 0; c < NN; ++c) acc += S.sL[x0 + c].x[3 + i] * G[c][j];
+                    Fd[i][j] = acc;
+                }
+            const double jf = det3(Fd);
+            if (!(jf > 0.0)) atomicMin(A.status, S.sE[p]);
+            double Fi[3][3];
+            inv3(Fd, jf, Fi);
+            const double ga0 = Ji[0][0] * da0 + Ji[1][0] * da1 + Ji[2][0] * da2;
+            const double ga1 = Ji[0][1] * da0 + Ji[1][1] * da1 + Ji[2][1] * da2;
+            const double ga2 = Ji[0][2] * da0 + Ji[1][2] * da1 + Ji[2][2] * da2;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                S.sHa[g][j] = (CT)(ga0 * Fi[0][j] + ga1 * Fi[1][j] + ga2 * Fi[2][j]);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) S.sFi[g][i * 3 + j] = Fi[i][j];
+            }
+            const double lam = S.sLM[p][0], mu = S.sLM[p][1];
+            S.sCc[g][0] = (CT)(wd * lam);
+            S.sCc[g][1] = (CT)(wd * (mu - lam * log(jf)));
+            S.sCc[g][2] = (CT)(wd * mu);
+        }
+    }
 }
 
 // Accumulates, into acc, the Gauss points Q0 .. Q0 + QN - 1 of block K_ab
 // of pair p (a its row node) for element node b: Poisson wd G_a.G_b, else
 // S = wd G_a (x) G_b. Point q's record is g0 + q - Q0.
 template <int F, int Q0, int QN, typename Sm, typename CT>
-__device__ inline void g_strip_acc(Sm &S, CT *acc, int b, int g0, int tf)
+__device__ inline void g_strip_acc(Sm &S, CT *acc, int b, int g0, int tf, int nh)
 {
 #pragma unroll
     for (int q = Q0; q < Q0 + QN; ++q) {
@@ -163,12 +216,38 @@ __device__ inline void g_strip_acc(Sm &S, CT *acc, int b, int g0, int tf)
         if constexpr (Sm::B == 1) {
             const CT dot = S.sGa[g][0] * gb[0] + S.sGa[g][1] * gb[1] + S.sGa[g][2] * gb[2];
             acc[0] += S.sWd[g] * dot;
-        } else {
-            const CT ga[3] = {S.sGa[g][0], S.sGa[g][1], S.sGa[g][2]};
+        } else if (!Sm::NHK || !nh) {
+            CT ga[3] = {S.sGa[g][0], S.sGa[g][1], S.sGa[g][2]};
+            if constexpr (Sm::NHK) {
+                const CT w = S.sWd[g];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) ga[i] = w * ga[i];
+            }
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) acc[i * 3 + j] += ga[i] * gb[j];
+        } else if constexpr (Sm::NHK) {
+            // T1 += c1 h_a (x) h_b, T2 += c2 h_a (x) h_b, dsum += c0 G_a.G_b
+            const double *Fi = S.sFi[g];
+            double gd[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) gd[j] = Ji[j] * d0 + Ji[3 + j] * d1 + Ji[6 + j] * d2;
+            CT hb[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) hb[j] = (CT)(gd[0] * Fi[j] + gd[1] * Fi[3 + j] + gd[2] * Fi[6 + j]);
+            const CT c1 = S.sCc[g][0], c2 = S.sCc[g][1], c0 = S.sCc[g][2];
+            const CT ha[3] = {S.sHa[g][0], S.sHa[g][1], S.sHa[g][2]};
+            const CT dot = S.sGa[g][0] * gb[0] + S.sGa[g][1] * gb[1] + S.sGa[g][2] * gb[2];
+            acc[18] += c0 * dot;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const CT hh = ha[i] * hb[j];
+                    acc[i * 3 + j] += c1 * hh;
+                    acc[9 + i * 3 + j] += c2 * hh;
+                }
         }
     }
 }
@@ -180,6 +259,16 @@ __device__ inline void g_strip_out(Sm &S, const CT *acc, int p, int l)
 {
     if constexpr (Sm::B == 1) {
         S.sL[l].k[0] = acc[0];
+    } else if (Sm::NHK && S.sNH[p]) {
+        // K_ij = T1_ij + T2_ji + delta_ij dsum
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                CT v = acc[i * 3 + j] + acc[9 + j * 3 + i];
+                if (i == j) v += acc[18];
+                S.sL[l].k[i * 3 + j] = v;
+            }
     } else {
         const CT lam = (CT)S.sLM[p][0], mu = (CT)S.sLM[p][1];
         const CT tr = acc[0] + acc[4] + acc[8];
@@ -213,10 +302,10 @@ template <int F, typename Sm>
 __device__ inline void g_strip(Sm &S, int p, int b, int l, int g0, int tf)
 {
     using CT = typename Sm::CTy;
-    CT acc[Sm::BB];
+    CT acc[Sm::ACC];
 #pragma unroll
-    for (int c = 0; c < Sm::BB; ++c) acc[c] = 0;
-    g_strip_acc<F, 0, Fam<F>::NQ>(S, acc, b, g0, tf);
+    for (int c = 0; c < Sm::ACC; ++c) acc[c] = 0;
+    g_strip_acc<F, 0, Fam<F>::NQ>(S, acc, b, g0, tf, Sm::NHK ? S.sNH[p] : 0);
     g_strip_out(S, acc, p, l);
 }
 
@@ -254,8 +343,9 @@ struct Pre1 {
 template <int B>
 struct Pre2 {
     double x, y, z, E, nu;
+    double u[3];
     double f[B];
-    int t;
+    int t, nh;
 };
 
 __device__ inline TileRec load_rec(const int32_t *tiles, int64_t t)
@@ -283,7 +373,7 @@ __device__ inline Pre1 load1(const GatherArgs &A, const TileRec &R, int tid)
     return P;
 }
 
-template <int B, bool MIX>
+template <int B, bool MIX, bool NHK>
 __device__ inline Pre2<B> load2(const GatherArgs &A, const Pre1 &P)
 {
     Pre2<B> Q = {};
@@ -291,8 +381,13 @@ __device__ inline Pre2<B> load2(const GatherArgs &A, const Pre1 &P)
         Q.x = A.x[P.v];
         Q.y = A.y[P.v];
         Q.z = A.z[P.v];
+        if (NHK) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Q.u[c] = A.u[3 * (int64_t)P.v + c];
+        }
     }
     if (P.ok_p) {
+        if (NHK) Q.nh = A.nh_flag[P.e];
         Q.E = A.young ? A.young[P.e] : 1.0;
         if (A.nu) Q.nu = A.nu[P.e];
 #pragma unroll
@@ -311,9 +406,14 @@ __device__ inline void commit(GatherSmem<C, MODEL, CT> &S, const TileRec &R, con
         S.sL[tid].x[0] = Q.x;
         S.sL[tid].x[1] = Q.y;
         S.sL[tid].x[2] = Q.z;
+        if constexpr (GatherSmem<C, MODEL, CT>::NHK) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S.sL[tid].x[3 + c] = Q.u[c];
+        }
         S.sD[tid] = P.d;
     }
     if (P.ok_p) {
+        if constexpr (GatherSmem<C, MODEL, CT>::NHK) S.sNH[tid] = Q.nh;
         S.sE[tid] = P.e;
         S.sA[tid] = P.a;
         if constexpr (GatherSmem<C, MODEL, CT>::MIX) S.sT[tid] = Q.t;
@@ -345,7 +445,7 @@ __device__ inline void pure_chunk(Sm &S, const GatherArgs &A, const TileRec &R, 
         g_geometry<C>(S, A, p, p * NN, Q0 + qq, p * GS + qq, 0);
     }
     sync_lds();
-    if (tid < R.nj) g_strip_acc<C, Q0, QC>(S, acc, lb, lp * GS, 0);
+    if (tid < R.nj) g_strip_acc<C, Q0, QC>(S, acc, lb, lp * GS, 0, Sm::NHK ? S.sNH[lp] : 0);
     if (tid < R.np) g_rhs_acc<C, Q0, QC>(S, fr, tid, tid * GS, 0);
 }
 
@@ -354,13 +454,15 @@ __device__ inline void pure_chunk(Sm &S, const GatherArgs &A, const TileRec &R, 
 // one-family tiles (their LDS admits three workgroups per CU; a budget of
 // four waves spills), two for interface tiles.
 constexpr int G_WAVES[5] = {4, 3, 3, 3, 2};
-template <int C>
+// neo-Hookean kernels hold about twice the accumulators and LDS records
+constexpr int G_WAVES_NH[5] = {3, 2, 2, 2, 1};
+template <int C, int MODEL>
 struct GatherWaves {
-    static constexpr int value = G_WAVES[C];
+    static constexpr int value = MODEL == M_ELASTIC_NH ? G_WAVES_NH[C] : G_WAVES[C];
 };
 
 template <int C, int MODEL, typename CT>
-__global__ void __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(GatherWaves<C>::value)))
+__global__ void __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(GatherWaves<C, MODEL>::value)))
 k_gather(GatherArgs A, int64_t ntiles)
 {
     using Sm = GatherSmem<C, MODEL, CT>;
@@ -384,7 +486,7 @@ k_gather(GatherArgs A, int64_t ntiles)
     TileRec R = load_rec(A.tiles, t);
     {
         const Pre1 P = load1(A, R, tid);
-        commit<C, MODEL, CT>(S, R, P, load2<B, MIX>(A, P), tid);
+        commit<C, MODEL, CT>(S, R, P, load2<B, MIX, Sm::NHK>(A, P), tid);
     }
     int64_t tn = t + nW;
     TileRec Rn = {};
@@ -399,7 +501,7 @@ k_gather(GatherArgs A, int64_t ntiles)
         // next tile: second-stage loads; the tile after it: first stage
         const bool more = tn < c1;
         Pre2<B> Qn = {};
-        if (more) Qn = load2<B, MIX>(A, Pn);
+        if (more) Qn = load2<B, MIX, Sm::NHK>(A, Pn);
         const int64_t tnn = tn + nW;
         TileRec Rnn = {};
         Pre1 Pnn = {};
@@ -466,15 +568,23 @@ k_gather(GatherArgs A, int64_t ntiles)
             // per lane (pair, element node), right-hand side one per pair;
             // NCH chunks of Gauss points, partial sums in registers
             const int lp = tid / NN, lb = tid - lp * NN;
-            CT acc[BB], fr[B];
+            CT acc[Sm::ACC], fr[B];
 #pragma unroll
-            for (int c = 0; c < BB; ++c) acc[c] = 0;
+            for (int c = 0; c < Sm::ACC; ++c) acc[c] = 0;
 #pragma unroll
             for (int i = 0; i < B; ++i) fr[i] = 0;
             pure_chunk<0>(S, A, R, acc, fr, tid, lp, lb);
-            if constexpr (Sm::NCH == 2) {
+            if constexpr (Sm::NCH >= 2) {
                 sync_lds();  // the chunk's records are no longer read
                 pure_chunk<1>(S, A, R, acc, fr, tid, lp, lb);
+            }
+            if constexpr (Sm::NCH >= 3) {
+                sync_lds();
+                pure_chunk<2>(S, A, R, acc, fr, tid, lp, lb);
+            }
+            if constexpr (Sm::NCH >= 4) {
+                sync_lds();
+                pure_chunk<3>(S, A, R, acc, fr, tid, lp, lb);
             }
             if (tid < R.nj) g_strip_out(S, acc, lp, tid);
             if (tid < R.np) {
@@ -756,6 +866,7 @@ static int launch_classes(fea_graph *g, GatherArgs A, hipStream_t s, bool timing
 int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precision, bool out_f32,
                     bool timing, hipStream_t s, void *vals, void *rhs)
 {
+    if (model == FEA_ELASTIC && in.nh_flag) model = M_ELASTIC_NH;
     int rc = ensure_tables();
     if (rc) return rc;
     if (!g->gready && (rc = gather_prepare(g, in.types, in.conn_ptr, in.conn, s))) return rc;
@@ -774,6 +885,8 @@ int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precisio
     A.n2a = g->n2a;
     A.gnodes = g->gnodes;
     A.desc = g->gdesc;
+    A.nh_flag = in.nh_flag;
+    A.u = in.u;
     A.vals = vals;
     A.rhs = rhs;
     A.out_f32 = out_f32 ? 1 : 0;
@@ -786,9 +899,12 @@ int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precisio
     if (model == FEA_POISSON)
         rc = precision == FEA_FP64 ? launch_classes<FEA_POISSON, double>(g, A, s, timing)
                                    : launch_classes<FEA_POISSON, float>(g, A, s, timing);
-    else
+    else if (model == FEA_ELASTIC)
         rc = precision == FEA_FP64 ? launch_classes<FEA_ELASTIC, double>(g, A, s, timing)
                                    : launch_classes<FEA_ELASTIC, float>(g, A, s, timing);
+    else
+        rc = precision == FEA_FP64 ? launch_classes<M_ELASTIC_NH, double>(g, A, s, timing)
+                                   : launch_classes<M_ELASTIC_NH, float>(g, A, s, timing);
     if (rc) return rc;
     g->gtimed = timing;
     FEA_HIP(hipGetLastError());

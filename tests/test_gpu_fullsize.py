@@ -88,10 +88,19 @@ def test_hetero128_batched_sampled_rows_with_neo_hookean():
     rows = oracle_rows(mesh, sorted(set(nh_nodes.tolist())))
     gr = dm.graph()
     ex = gr.export()
+    row_ptr, col = ex["row_ptr"].cpu().numpy(), ex["col"].cpu().numpy()
     v, r, _ = b.assemble()
     torch.cuda.synchronize()
-    assert check_rows(mesh, rows, ex["row_ptr"].cpu().numpy(), ex["col"].cpu().numpy(),
-                      v, r, 3) <= 1e-12
+    assert check_rows(mesh, rows, row_ptr, col, v, r, 3) <= 1e-12
+    # the same rows through the row-gather form (one mesh, neo-Hookean bricks)
+    for prec in (fea.FP64, fea.MIXED):
+        outd = fea.F64 if prec == fea.FP64 else fea.F32
+        v, r, st = dm.assemble(gr, variant=fea.ROWGATHER, use_nh=True, precision=prec, out_dtype=outd)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -1
+        L = None if prec == fea.FP64 else fp32_bound_L(mesh.types)
+        worst = check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L)
+        assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (prec, worst)
 
 
 def test_hybrid256_batched_sampled_rows():
