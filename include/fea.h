@@ -217,9 +217,13 @@ int fea_batch_set_order(fea_batch *b, const int32_t *order);
  * then the block-value and right-hand-side reductions over all meshes.
  * vals/rhs: device buffers of the lengths from fea_batch_sizes, element
  * type opt->out_dtype, overwritten. status: device int32[n_meshes] (may be
- * NULL), per mesh the smallest rejected element id or -1. opt->variant must
- * be FEA_ROWOWNER. With opt->timing, fea_batch_last_ms reads the
- * persistent kernel's duration.
+ * NULL), per mesh the smallest rejected element id or -1. opt->variant:
+ * FEA_ROWOWNER as above, or FEA_ROWGATHER: the row tiles of all meshes in
+ * one persistent launch per tile class, written straight into vals/rhs
+ * (the first such call prepares every mesh's tiles and blocks on `stream`;
+ * no work queue, no cycle records, tiles and queue order do not apply).
+ * With opt->timing, fea_batch_last_ms reads the persistent kernels'
+ * duration.
  */
 int fea_batch_assemble(fea_batch *b, const fea_options *opt, hipStream_t stream, void *vals,
                        void *rhs, int32_t *status);

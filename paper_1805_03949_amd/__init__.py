@@ -341,16 +341,16 @@ class Batch:
                 torch.empty(max(1, len(self.meshes)), dtype=torch.int32, device=self.device))
 
     def assemble(self, precision=FP64, out_dtype=F64, vals=None, rhs=None, status=None, stream=None,
-                 timing=False):
+                 timing=False, variant=ROWOWNER):
         if vals is None:
             vals, rhs, status = self.outputs(out_dtype)
-        opt = Options(precision, ROWOWNER, out_dtype, int(bool(timing)))
+        opt = Options(precision, variant, out_dtype, int(bool(timing)))
         _check(_lib.fea_batch_assemble(self._h, ctypes.byref(opt), _stream(stream), _ptr(vals), _ptr(rhs),
                                        _ptr(status)))
         return vals, rhs, status
 
-    def capture(self, vals, rhs, status, precision=FP64, out_dtype=F64, stream=None):
-        opt = Options(precision, ROWOWNER, out_dtype, 0)
+    def capture(self, vals, rhs, status, precision=FP64, out_dtype=F64, stream=None, variant=ROWOWNER):
+        opt = Options(precision, variant, out_dtype, 0)
         _check(_lib.fea_batch_capture(self._h, ctypes.byref(opt), _stream(stream), _ptr(vals), _ptr(rhs),
                                       _ptr(status)))
 

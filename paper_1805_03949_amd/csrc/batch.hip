@@ -282,6 +282,7 @@ struct fea_batch {
     bool timed = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    GatherBatch *gbatch = nullptr;  // row-gather form, built on first use
 };
 
 namespace {
@@ -298,6 +299,7 @@ void destroy_batch(fea_batch *b)
 {
     if (!b) return;
     drop_graph(b);
+    gather_batch_destroy(b->gbatch);
     for (fea_graph *g : b->graphs)
         if (g) fea_graph_destroy(g);
     void *bufs[] = {b->d_meshes, b->d_items, b->d_order, b->d_head, b->d_status, b->d_vseg,
@@ -433,8 +435,37 @@ int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, 
     return FEA_OK;
 }
 
+// Row-gather form: the batch's tiles through one persistent launch per
+// tile class (no work queue: the tiles of a class are split statically
+// over the workgroups, per XCD).
+int dispatch_gather(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void *rhs, int32_t *status)
+{
+    int rc;
+    if (!b->gbatch) {
+        std::vector<GatherInput> in(b->n_meshes);
+        for (int m = 0; m < b->n_meshes; ++m) {
+            const fea_mesh_desc &d = b->desc[m];
+            in[m] = {d.x, d.y, d.z, d.types, d.conn_ptr, d.conn, d.young, d.nu, d.source, nullptr,
+                     b->model == FEA_ELASTIC ? d.nh_flag : nullptr, d.u};
+        }
+        if ((rc = gather_batch_build(&b->gbatch, b->n_meshes, b->graphs.data(), in.data(), b->vals_off.data(),
+                                     b->rhs_off.data(), s)))
+            return rc;
+    }
+    k_batch_begin<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_head, b->d_status, b->n_meshes);
+    if (o->timing) FEA_HIP(hipEventRecord(b->ev[0], s));
+    if ((rc = gather_batch_assemble(b->gbatch, b->model, b->has_nh, o->precision, o->out_dtype == FEA_F32, s, vals,
+                                    rhs, b->d_status)))
+        return rc;
+    if (o->timing) FEA_HIP(hipEventRecord(b->ev[1], s));
+    k_batch_end<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_status, b->n_meshes, status);
+    FEA_HIP(hipGetLastError());
+    return FEA_OK;
+}
+
 int dispatch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void *rhs, int32_t *status)
 {
+    if (o->variant == FEA_ROWGATHER) return dispatch_gather(b, o, s, vals, rhs, status);
     const bool f32 = o->out_dtype == FEA_F32;
     if (b->model == FEA_POISSON) {
         if (o->precision == FEA_FP64)
@@ -460,7 +491,8 @@ int dispatch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void
 int check_opts(const fea_batch *b, const fea_options *o)
 {
     if (!b || !o) return set_error(FEA_EINVAL, "batch and options are required");
-    if (o->variant != FEA_ROWOWNER) return set_error(FEA_EINVAL, "batched assembly is row-owner only");
+    if (o->variant != FEA_ROWOWNER && o->variant != FEA_ROWGATHER)
+        return set_error(FEA_EINVAL, "batched assembly is row-owner or row-gather");
     if (o->precision < 0 || o->precision > 1 || o->out_dtype < 0 || o->out_dtype > 1)
         return set_error(FEA_EINVAL, "bad option");
     int dev = 0;
@@ -617,6 +649,7 @@ extern "C" int fea_batch_autotune(fea_batch *b, const fea_options *opt, int reps
     clear_error();
     int rc = check_opts(b, opt);
     if (rc) return rc;
+    if (opt->variant != FEA_ROWOWNER) return set_error(FEA_EINVAL, "tiles are tuned for the row-owner work items");
     if (reps < 1) return set_error(FEA_EINVAL, "reps must be positive");
     if ((rc = ensure_tables())) return rc;
     const size_t esz = opt->out_dtype == FEA_F32 ? 4 : 8;

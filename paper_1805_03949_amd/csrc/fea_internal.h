@@ -127,3 +127,17 @@ namespace fea {
 int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precision, bool out_f32,
                     bool timing, hipStream_t s, void *vals, void *rhs);
 }  // namespace fea
+
+namespace fea {
+// Row-gather form of a batch (gather.hip): the tiles of every mesh in one
+// list per class, with each tile's mesh. Built once per batch from its
+// graphs (preparing each graph's tiles; blocks on the stream).
+struct GatherBatch;
+int gather_batch_build(GatherBatch **out, int n, fea_graph *const *graphs, const GatherInput *in,
+                       const int64_t *vals_off, const int64_t *rhs_off, hipStream_t s);
+// Enqueues the batch's class kernels: mesh m's values at vals + vals_off[m]
+// and status entry status[m] (set by atomic minimum; initialised by the caller).
+int gather_batch_assemble(const GatherBatch *gb, int model, bool nh, int precision, bool out_f32,
+                          hipStream_t s, void *vals, void *rhs, int32_t *status);
+void gather_batch_destroy(GatherBatch *gb);
+}  // namespace fea

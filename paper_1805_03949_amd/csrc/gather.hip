@@ -120,7 +120,10 @@ struct GatherArgs {
     const uint8_t *desc;
     const uint8_t *nh_flag;  // neo-Hookean kernels: per element
     const double *u;         // and displacements, 3 per node
-    const int32_t *tiles;  // tile records of this launch
+    int64_t vals_off, rhs_off;  // first value of this mesh in vals and rhs
+    int32_t mesh;               // index of this mesh's status entry
+    // launch: tile records, outputs, status entries (one per mesh)
+    const int32_t *tiles;
     void *vals, *rhs;
     int out_f32;
 };
@@ -129,7 +132,7 @@ struct GatherArgs {
 // (coordinates at lanes x0 ..), with the expressions of the element kernels
 // (same rounding in FP64).
 template <int F, typename Sm>
-__device__ inline void g_geometry(Sm &S, const GatherArgs &A, int p, int x0, int q, int g, int tf)
+__device__ inline void g_geometry(Sm &S, int32_t *status, int p, int x0, int q, int g, int tf)
 {
     using CT = typename Sm::CTy;
     constexpr int MODEL = Sm::B == 1 ? FEA_POISSON : FEA_ELASTIC;
@@ -142,7 +145,7 @@ __device__ inline void g_geometry(Sm &S, const GatherArgs &A, int p, int x0, int
 #pragma unroll
             for (int j = 0; j < 3; ++j) J[i][j] += S.sL[x0 + a].x[i] * S.sDN[tf][q][a][j];
     const double d = det3(J);
-    if (!(d > 0.0)) atomicMin(A.status, S.sE[p]);
+    if (!(d > 0.0)) atomicMin(status, S.sE[p]);
     double Ji[3][3];
     inv3(J, d, Ji);
     const int a = S.sA[p];
@@ -179,7 +182,7 @@ __device__ inline void g_geometry(Sm &S, const GatherArgs &A, int p, int x0, int
                     Fd[i][j] = acc;
                 }
             const double jf = det3(Fd);
-            if (!(jf > 0.0)) atomicMin(A.status, S.sE[p]);
+            if (!(jf > 0.0)) atomicMin(status, S.sE[p]);
             double Fi[3][3];
             inv3(Fd, jf, Fi);
             const double ga0 = Ji[0][0] * da0 + Ji[1][0] * da1 + Ji[2][0] * da2;
@@ -436,13 +439,13 @@ __device__ inline void commit(GatherSmem<C, MODEL, CT> &S, const TileRec &R, con
 // Chunk CH of a one-family tile: geometry of its Gauss points, then their
 // share of every lane's block and every pair's right-hand side.
 template <int CH, typename Sm>
-__device__ inline void pure_chunk(Sm &S, const GatherArgs &A, const TileRec &R, typename Sm::CTy *acc,
+__device__ inline void pure_chunk(Sm &S, int32_t *status, const TileRec &R, typename Sm::CTy *acc,
                                   typename Sm::CTy *fr, int tid, int lp, int lb)
 {
     constexpr int C = Sm::FAMILY, NN = Sm::NN, QC = Sm::QC, GS = Sm::GS, Q0 = CH * QC;
     for (int g = tid; g < R.np * QC; g += GT) {
         const int p = g / QC, qq = g - p * QC;
-        g_geometry<C>(S, A, p, p * NN, Q0 + qq, p * GS + qq, 0);
+        g_geometry<C>(S, status, p, p * NN, Q0 + qq, p * GS + qq, 0);
     }
     sync_lds();
     if (tid < R.nj) g_strip_acc<C, Q0, QC>(S, acc, lb, lp * GS, 0, Sm::NHK ? S.sNH[lp] : 0);
@@ -461,9 +464,12 @@ struct GatherWaves {
     static constexpr int value = MODEL == M_ELASTIC_NH ? G_WAVES_NH[C] : G_WAVES[C];
 };
 
-template <int C, int MODEL, typename CT>
+// BATCHED: the tiles of one launch belong to several meshes; tile t's mesh
+// view is meshes[tmesh[t]] (arrays, output offsets, status entry), and the
+// launch fields (tiles, outputs, status base, output type) come from L.
+template <int C, int MODEL, typename CT, bool BATCHED>
 __global__ void __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(GatherWaves<C, MODEL>::value)))
-k_gather(GatherArgs A, int64_t ntiles)
+k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t ntiles)
 {
     using Sm = GatherSmem<C, MODEL, CT>;
     __shared__ Sm S;
@@ -483,17 +489,26 @@ k_gather(GatherArgs A, int64_t ntiles)
         for (int j = 0; j < 3; ++j) S.sDN[tf][q][a][j] = c_ref.dN[ty][q][a][j];
         if (a == 0) S.sW[tf][q] = c_ref.w[ty][q];
     }
-    TileRec R = load_rec(A.tiles, t);
+    // mesh view of tile t (scalar loads; one mesh when not batched)
+    auto mesh_of = [&](int64_t tt) -> int32_t { return BATCHED ? tmesh[tt] : 0; };
+    auto M = [&](int32_t m) -> const GatherArgs & {
+        if constexpr (BATCHED) return meshes[m];
+        else return L;
+    };
+    TileRec R = load_rec(L.tiles, t);
+    int32_t mc = mesh_of(t);
     {
-        const Pre1 P = load1(A, R, tid);
-        commit<C, MODEL, CT>(S, R, P, load2<B, MIX, Sm::NHK>(A, P), tid);
+        const Pre1 P = load1(M(mc), R, tid);
+        commit<C, MODEL, CT>(S, R, P, load2<B, MIX, Sm::NHK>(M(mc), P), tid);
     }
     int64_t tn = t + nW;
     TileRec Rn = {};
     Pre1 Pn = {};
+    int32_t mn = 0;
     if (tn < c1) {
-        Rn = load_rec(A.tiles, tn);
-        Pn = load1(A, Rn, tid);
+        Rn = load_rec(L.tiles, tn);
+        mn = mesh_of(tn);
+        Pn = load1(M(mn), Rn, tid);
     }
     sync_lds();
 
@@ -501,14 +516,17 @@ k_gather(GatherArgs A, int64_t ntiles)
         // next tile: second-stage loads; the tile after it: first stage
         const bool more = tn < c1;
         Pre2<B> Qn = {};
-        if (more) Qn = load2<B, MIX, Sm::NHK>(A, Pn);
+        if (more) Qn = load2<B, MIX, Sm::NHK>(M(mn), Pn);
         const int64_t tnn = tn + nW;
         TileRec Rnn = {};
         Pre1 Pnn = {};
+        int32_t mnn = 0;
         if (tnn < c1) {
-            Rnn = load_rec(A.tiles, tnn);
-            Pnn = load1(A, Rnn, tid);
+            Rnn = load_rec(L.tiles, tnn);
+            mnn = mesh_of(tnn);
+            Pnn = load1(M(mnn), Rnn, tid);
         }
+        int32_t *const st = L.status + M(mc).mesh;
 
         if constexpr (MIX) {
             // lane and Gauss-point offsets of the pairs (np <= 64: one wave scans)
@@ -537,10 +555,10 @@ k_gather(GatherArgs A, int64_t ntiles)
             for (int g = tid; g < ng; g += GT) {
                 const int p = S.sGP[g], ty = S.sT[p], q = g - S.sGeo[p], x0 = S.sLane[p];
                 switch (ty) {
-                case 0: g_geometry<0>(S, A, p, x0, q, g, 0); break;
-                case 1: g_geometry<1>(S, A, p, x0, q, g, 1); break;
-                case 2: g_geometry<2>(S, A, p, x0, q, g, 2); break;
-                default: g_geometry<3>(S, A, p, x0, q, g, 3); break;
+                case 0: g_geometry<0>(S, st, p, x0, q, g, 0); break;
+                case 1: g_geometry<1>(S, st, p, x0, q, g, 1); break;
+                case 2: g_geometry<2>(S, st, p, x0, q, g, 2); break;
+                default: g_geometry<3>(S, st, p, x0, q, g, 3); break;
                 }
             }
             sync_lds();
@@ -573,18 +591,18 @@ k_gather(GatherArgs A, int64_t ntiles)
             for (int c = 0; c < Sm::ACC; ++c) acc[c] = 0;
 #pragma unroll
             for (int i = 0; i < B; ++i) fr[i] = 0;
-            pure_chunk<0>(S, A, R, acc, fr, tid, lp, lb);
+            pure_chunk<0>(S, st, R, acc, fr, tid, lp, lb);
             if constexpr (Sm::NCH >= 2) {
                 sync_lds();  // the chunk's records are no longer read
-                pure_chunk<1>(S, A, R, acc, fr, tid, lp, lb);
+                pure_chunk<1>(S, st, R, acc, fr, tid, lp, lb);
             }
             if constexpr (Sm::NCH >= 3) {
                 sync_lds();
-                pure_chunk<2>(S, A, R, acc, fr, tid, lp, lb);
+                pure_chunk<2>(S, st, R, acc, fr, tid, lp, lb);
             }
             if constexpr (Sm::NCH >= 4) {
                 sync_lds();
-                pure_chunk<3>(S, A, R, acc, fr, tid, lp, lb);
+                pure_chunk<3>(S, st, R, acc, fr, tid, lp, lb);
             }
             if (tid < R.nj) g_strip_out(S, acc, lp, tid);
             if (tid < R.np) {
@@ -625,20 +643,20 @@ k_gather(GatherArgs A, int64_t ntiles)
 #pragma unroll
                 for (int c = 0; c < B; ++c) s[c] += (double)src[c];
             }
-            const int64_t o = ((int64_t)R.k0 + k) * BB + i * B;
+            const int64_t o = M(mc).vals_off + ((int64_t)R.k0 + k) * BB + i * B;
 #pragma unroll
             for (int c = 0; c < B; ++c) {
-                if (A.out_f32) ((float *)A.vals)[o + c] = (float)s[c];
-                else ((double *)A.vals)[o + c] = s[c];
+                if (L.out_f32) ((float *)L.vals)[o + c] = (float)s[c];
+                else ((double *)L.vals)[o + c] = s[c];
             }
         }
         for (int idx = tid; idx < R.nr * B; idx += GT) {
             const int r = idx / B, c = idx - r * B;
             double s = 0.0;
             for (int p = S.sRP[r]; p < S.sRP[r + 1]; ++p) s += (double)S.sR[p][c];
-            const int64_t o = ((int64_t)R.r0 + r) * B + c;
-            if (A.out_f32) ((float *)A.rhs)[o] = (float)s;
-            else ((double *)A.rhs)[o] = s;
+            const int64_t o = M(mc).rhs_off + ((int64_t)R.r0 + r) * B + c;
+            if (L.out_f32) ((float *)L.rhs)[o] = (float)s;
+            else ((double *)L.rhs)[o] = s;
         }
         if (!more) break;
         sync_lds();  // the tile's LDS is no longer read
@@ -648,6 +666,8 @@ k_gather(GatherArgs A, int64_t ntiles)
         Rn = Rnn;
         Pn = Pnn;
         tn = tnn;
+        mc = mn;
+        mn = mnn;
     }
 }
 
@@ -819,8 +839,9 @@ static int gather_prepare(fea_graph *g, const uint8_t *types, const int64_t *con
     return FEA_OK;
 }
 
-template <int C, int MODEL, typename CT>
-static int launch_class(GatherArgs A, int64_t n, hipStream_t s)
+template <int C, int MODEL, typename CT, bool BATCHED>
+static int launch_class(const GatherArgs &L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n,
+                        hipStream_t s)
 {
     // persistent grid: as many workgroups as fit on the device at once, a
     // multiple of the 8 XCDs
@@ -831,36 +852,77 @@ static int launch_class(GatherArgs A, int64_t n, hipStream_t s)
     if (dev < 0 || dev >= 64) return set_error(FEA_EINVAL, "device index %d unsupported", dev);
     if (!per_cu[dev]) {
         int b = 0, c = 0;
-        FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_gather<C, MODEL, CT>, GT, 0));
+        FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_gather<C, MODEL, CT, BATCHED>, GT, 0));
         FEA_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
         cus[dev] = std::max(c, 8);
         per_cu[dev] = std::max(b, 1);
     }
     int64_t grid = std::min<int64_t>((int64_t)per_cu[dev] * cus[dev], (n + 7) / 8 * 8);
     grid = std::max<int64_t>(grid / 8 * 8, 8);
-    k_gather<C, MODEL, CT><<<(unsigned)grid, GT, 0, s>>>(A, n);
+    k_gather<C, MODEL, CT, BATCHED><<<(unsigned)grid, GT, 0, s>>>(L, meshes, tmesh, n);
     return FEA_OK;
 }
 
-template <int MODEL, typename CT>
-static int launch_classes(fea_graph *g, GatherArgs A, hipStream_t s, bool timing)
+// One launch per tile class; tiles of class c are tiles + 8 * off[c] ..
+// (and, batched, their meshes tmesh + off[c] ..). With gev, records an
+// event before each class and after the last.
+template <int MODEL, typename CT, bool BATCHED>
+static int launch_classes(GatherArgs L, const int32_t *tiles, const int64_t *off, const GatherArgs *meshes,
+                          const int32_t *tmesh, hipStream_t s, hipEvent_t *gev)
 {
     int rc = FEA_OK;
     for (int c = 0; c < 5 && !rc; ++c) {
-        if (timing) FEA_HIP(hipEventRecord(g->gev[c], s));
-        const int64_t n = g->gtile_off[c + 1] - g->gtile_off[c];
+        if (gev) FEA_HIP(hipEventRecord(gev[c], s));
+        const int64_t n = off[c + 1] - off[c];
         if (n <= 0) continue;
-        A.tiles = g->gtile + 8 * g->gtile_off[c];
+        L.tiles = tiles + 8 * off[c];
+        const int32_t *tm = BATCHED ? tmesh + off[c] : nullptr;
         switch (c) {
-        case 0: rc = launch_class<0, MODEL, CT>(A, n, s); break;
-        case 1: rc = launch_class<1, MODEL, CT>(A, n, s); break;
-        case 2: rc = launch_class<2, MODEL, CT>(A, n, s); break;
-        case 3: rc = launch_class<3, MODEL, CT>(A, n, s); break;
-        default: rc = launch_class<G_MIXED, MODEL, CT>(A, n, s); break;
+        case 0: rc = launch_class<0, MODEL, CT, BATCHED>(L, meshes, tm, n, s); break;
+        case 1: rc = launch_class<1, MODEL, CT, BATCHED>(L, meshes, tm, n, s); break;
+        case 2: rc = launch_class<2, MODEL, CT, BATCHED>(L, meshes, tm, n, s); break;
+        case 3: rc = launch_class<3, MODEL, CT, BATCHED>(L, meshes, tm, n, s); break;
+        default: rc = launch_class<G_MIXED, MODEL, CT, BATCHED>(L, meshes, tm, n, s); break;
         }
     }
-    if (!rc && timing) FEA_HIP(hipEventRecord(g->gev[5], s));
+    if (!rc && gev) FEA_HIP(hipEventRecord(gev[5], s));
     return rc;
+}
+
+template <bool BATCHED>
+static int launch_models(int model, int precision, const GatherArgs &L, const int32_t *tiles, const int64_t *off,
+                         const GatherArgs *meshes, const int32_t *tmesh, hipStream_t s, hipEvent_t *gev)
+{
+    if (model == FEA_POISSON)
+        return precision == FEA_FP64 ? launch_classes<FEA_POISSON, double, BATCHED>(L, tiles, off, meshes, tmesh, s, gev)
+                                     : launch_classes<FEA_POISSON, float, BATCHED>(L, tiles, off, meshes, tmesh, s, gev);
+    if (model == FEA_ELASTIC)
+        return precision == FEA_FP64 ? launch_classes<FEA_ELASTIC, double, BATCHED>(L, tiles, off, meshes, tmesh, s, gev)
+                                     : launch_classes<FEA_ELASTIC, float, BATCHED>(L, tiles, off, meshes, tmesh, s, gev);
+    return precision == FEA_FP64 ? launch_classes<M_ELASTIC_NH, double, BATCHED>(L, tiles, off, meshes, tmesh, s, gev)
+                                 : launch_classes<M_ELASTIC_NH, float, BATCHED>(L, tiles, off, meshes, tmesh, s, gev);
+}
+
+// Mesh view of one mesh and its prepared graph.
+static GatherArgs mesh_args(const fea_graph *g, const GatherInput &in)
+{
+    GatherArgs A = {};
+    A.x = in.x;
+    A.y = in.y;
+    A.z = in.z;
+    A.types = in.types;
+    A.young = in.young;
+    A.nu = in.nu;
+    A.source = in.source;
+    A.n2e_ptr = g->n2e_ptr;
+    A.inv_ptr = g->inv_ptr;
+    A.n2e = g->n2e;
+    A.n2a = g->n2a;
+    A.gnodes = g->gnodes;
+    A.desc = g->gdesc;
+    A.nh_flag = in.nh_flag;
+    A.u = in.u;
+    return A;
 }
 
 int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precision, bool out_f32,
@@ -870,50 +932,119 @@ int gather_assemble(fea_graph *g, const GatherInput &in, int model, int precisio
     int rc = ensure_tables();
     if (rc) return rc;
     if (!g->gready && (rc = gather_prepare(g, in.types, in.conn_ptr, in.conn, s))) return rc;
-    GatherArgs A = {};
-    A.x = in.x;
-    A.y = in.y;
-    A.z = in.z;
-    A.types = in.types;
-    A.young = in.young;
-    A.nu = in.nu;
-    A.source = in.source;
-    A.status = in.status;
-    A.n2e_ptr = g->n2e_ptr;
-    A.inv_ptr = g->inv_ptr;
-    A.n2e = g->n2e;
-    A.n2a = g->n2a;
-    A.gnodes = g->gnodes;
-    A.desc = g->gdesc;
-    A.nh_flag = in.nh_flag;
-    A.u = in.u;
-    A.vals = vals;
-    A.rhs = rhs;
-    A.out_f32 = out_f32 ? 1 : 0;
+    GatherArgs L = mesh_args(g, in);
+    L.status = in.status;
+    L.vals = vals;
+    L.rhs = rhs;
+    L.out_f32 = out_f32 ? 1 : 0;
     g->gtimed = false;
     if (timing) {
         for (hipEvent_t &e : g->gev)
             if (!e) FEA_HIP(hipEventCreate(&e));
         FEA_HIP(hipEventRecord(g->ev[0], s));
     }
-    if (model == FEA_POISSON)
-        rc = precision == FEA_FP64 ? launch_classes<FEA_POISSON, double>(g, A, s, timing)
-                                   : launch_classes<FEA_POISSON, float>(g, A, s, timing);
-    else if (model == FEA_ELASTIC)
-        rc = precision == FEA_FP64 ? launch_classes<FEA_ELASTIC, double>(g, A, s, timing)
-                                   : launch_classes<FEA_ELASTIC, float>(g, A, s, timing);
-    else
-        rc = precision == FEA_FP64 ? launch_classes<M_ELASTIC_NH, double>(g, A, s, timing)
-                                   : launch_classes<M_ELASTIC_NH, float>(g, A, s, timing);
-    if (rc) return rc;
-    g->gtimed = timing;
+    if ((rc = launch_models<false>(model, precision, L, g->gtile, g->gtile_off, nullptr, nullptr, s,
+                                   timing ? g->gev : nullptr)))
+        return rc;
     FEA_HIP(hipGetLastError());
+    g->gtimed = timing;
     if (timing) {
         // one fused kernel per class: no separate block-value phase
         FEA_HIP(hipEventRecord(g->ev[1], s));
         FEA_HIP(hipEventRecord(g->ev[2], s));
         FEA_HIP(hipEventRecord(g->ev[3], s));
     }
+    return FEA_OK;
+}
+
+struct GatherBatch {
+    int n_meshes = 0;
+    GatherArgs *d_meshes = nullptr;  // mesh views (outputs as offsets)
+    int32_t *d_tiles = nullptr;      // tile records of all meshes, by class
+    int32_t *d_tmesh = nullptr;      // mesh of every tile
+    int64_t off[6] = {0, 0, 0, 0, 0, 0};
+};
+
+void gather_batch_destroy(GatherBatch *gb)
+{
+    if (!gb) return;
+    dfree(gb->d_meshes);
+    dfree(gb->d_tiles);
+    dfree(gb->d_tmesh);
+    delete gb;
+}
+
+int gather_batch_build(GatherBatch **out, int n, fea_graph *const *graphs, const GatherInput *in,
+                       const int64_t *vals_off, const int64_t *rhs_off, hipStream_t s)
+{
+    *out = nullptr;
+    GatherBatch *gb = new GatherBatch();
+    gb->n_meshes = n;
+    int rc = FEA_OK;
+    std::vector<GatherArgs> views(n);
+    for (int m = 0; m < n && !rc; ++m) {
+        fea_graph *g = graphs[m];
+        if (!g->gready) rc = gather_prepare(g, in[m].types, in[m].conn_ptr, in[m].conn, s);
+        views[m] = mesh_args(g, in[m]);
+        views[m].vals_off = vals_off[m];
+        views[m].rhs_off = rhs_off[m];
+        views[m].mesh = m;
+    }
+    // tiles of class c: those of mesh 0, then mesh 1, ...
+    int64_t total = 0;
+    for (int c = 0; c < 5 && !rc; ++c) {
+        gb->off[c] = total;
+        for (int m = 0; m < n; ++m) total += graphs[m]->gtile_off[c + 1] - graphs[m]->gtile_off[c];
+    }
+    gb->off[5] = total;
+    if (!rc && (rc = dalloc((void **)&gb->d_meshes, sizeof(GatherArgs) * std::max(n, 1)))) {}
+    if (!rc && (rc = dalloc((void **)&gb->d_tiles, sizeof(int32_t) * 8 * std::max<int64_t>(total, 1)))) {}
+    if (!rc && (rc = dalloc((void **)&gb->d_tmesh, sizeof(int32_t) * std::max<int64_t>(total, 1)))) {}
+    if (!rc) {
+        std::vector<int32_t> tm(total);
+        int64_t at = 0;
+        for (int c = 0; c < 5 && !rc; ++c)
+            for (int m = 0; m < n; ++m) {
+                const fea_graph *g = graphs[m];
+                const int64_t k = g->gtile_off[c + 1] - g->gtile_off[c];
+                if (k <= 0) continue;
+                hipError_t e = hipMemcpyAsync(gb->d_tiles + 8 * at, g->gtile + 8 * g->gtile_off[c],
+                                              sizeof(int32_t) * 8 * k, hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) rc = set_error(FEA_EHIP, "tile copy failed: %s", hipGetErrorString(e));
+                std::fill(tm.begin() + at, tm.begin() + at + k, m);
+                at += k;
+            }
+        if (!rc && n) {
+            hipError_t e = hipMemcpyAsync(gb->d_meshes, views.data(), sizeof(GatherArgs) * n, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess && total)
+                e = hipMemcpyAsync(gb->d_tmesh, tm.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) rc = set_error(FEA_EHIP, "batch set-up failed: %s", hipGetErrorString(e));
+        }
+    }
+    if (rc) {
+        gather_batch_destroy(gb);
+        return rc;
+    }
+    *out = gb;
+    return FEA_OK;
+}
+
+int gather_batch_assemble(const GatherBatch *gb, int model, bool nh, int precision, bool out_f32,
+                          hipStream_t s, void *vals, void *rhs, int32_t *status)
+{
+    if (model == FEA_ELASTIC && nh) model = M_ELASTIC_NH;
+    int rc = ensure_tables();
+    if (rc) return rc;
+    GatherArgs L = {};
+    L.status = status;
+    L.vals = vals;
+    L.rhs = rhs;
+    L.out_f32 = out_f32 ? 1 : 0;
+    if ((rc = launch_models<true>(model, precision, L, gb->d_tiles, gb->off, gb->d_meshes, gb->d_tmesh, s,
+                                  nullptr)))
+        return rc;
+    FEA_HIP(hipGetLastError());
     return FEA_OK;
 }
 

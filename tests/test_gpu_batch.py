@@ -191,3 +191,74 @@ def test_full_size_batched_workload_sampled_meshes(mesh_ids):
         vm, rm = per_mesh(vals, rhs, b, m)
         L = fp32_bound_L(meshes[m].types)
         assert within_fp32_bound(vm, ov, tv, L, 1e-12 * row_scale(ov, og.row_ptr, 3)) <= 1.0
+
+
+@pytest.mark.parametrize("precision", [fea.FP64, fea.MIXED])
+@pytest.mark.parametrize("model", [fea.POISSON, fea.ELASTIC])
+def test_batch_rowgather_equals_single_mesh_rowgather(model, precision):
+    """The batched row-gather runs the one-mesh row-gather tiles of every
+    mesh in one launch per class: each mesh's values equal its own
+    row-gather assembly bitwise."""
+    st = state()
+    use_nh = model == fea.ELASTIC
+    b = fea.Batch(st["dms"], model=model, use_nh=use_nh)
+    out = fea.F64 if precision == fea.FP64 else fea.F32
+    vals, rhs, status = b.assemble(precision=precision, out_dtype=out, variant=fea.ROWGATHER)
+    torch.cuda.synchronize()
+    assert np.all(status.cpu().numpy() == -1)
+    for m, (dm, g) in enumerate(zip(st["dms"], st["graphs"])):
+        v1, r1, _ = dm.assemble(g, model=model, use_nh=use_nh, variant=fea.ROWGATHER,
+                                precision=precision, out_dtype=out)
+        torch.cuda.synchronize()
+        vb, rb = per_mesh(vals, rhs, b, m)
+        assert vb.tobytes() == v1.cpu().numpy().tobytes(), m
+        assert rb.tobytes() == r1.cpu().numpy().tobytes(), m
+
+
+def test_batch_rowgather_against_oracle_and_replay():
+    st = state()
+    b = fea.Batch(st["dms"], model=fea.ELASTIC, use_nh=True)
+    vals, rhs, _ = b.assemble(variant=fea.ROWGATHER)
+    torch.cuda.synchronize()
+    for m, mesh in enumerate(st["meshes"]):
+        og = oracle.mesh_graph(mesh)
+        ov, orr, tv, tr = oracle.assemble(mesh, og, with_terms=True)
+        vb, rb = per_mesh(vals, rhs, b, m)
+        ev, er = fp64_errors(vb, ov, og.row_ptr, 3, rb, orr)
+        assert ev <= 1e-12 and er <= 1e-12, (m, ev, er)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        v2, r2, st2 = b.outputs(fea.F32)
+        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=v2, rhs=r2, status=st2, variant=fea.ROWGATHER)
+        s.synchronize()
+        ref = (v2.cpu().numpy().tobytes(), r2.cpu().numpy().tobytes())
+        for m, mesh in enumerate(st["meshes"]):
+            og = oracle.mesh_graph(mesh)
+            ov, orr, tv, tr = oracle.assemble(mesh, og, with_terms=True)
+            vm, rm = per_mesh(v2, r2, b, m)
+            L = fp32_bound_L(mesh.types)
+            assert within_fp32_bound(vm, ov, tv, L, 1e-12 * row_scale(ov, og.row_ptr, 3)) <= 1.0
+            assert within_fp32_bound(rm, orr, tr, L, 1e-12 * np.abs(orr).max()) <= 1.0
+        b.capture(v2, r2, st2, precision=fea.MIXED, out_dtype=fea.F32, variant=fea.ROWGATHER)
+        for rep in range(3):
+            v2.fill_(float("nan"))
+            r2.fill_(float("nan"))
+            st2.fill_(123)
+            b.replay(1)
+            s.synchronize()
+            assert (v2.cpu().numpy().tobytes(), r2.cpu().numpy().tobytes()) == ref, rep
+            assert np.all(st2.cpu().numpy() == -1)
+
+
+def test_batch_rowgather_status_per_mesh():
+    meshes = [mg.cube_mesh(3, np.full(27, mg.TET4, dtype=np.uint8)) for _ in range(3)]
+    e = 29
+    c = meshes[1].conn.copy()
+    c[meshes[1].conn_ptr[e] + 1], c[meshes[1].conn_ptr[e] + 2] = c[meshes[1].conn_ptr[e] + 2], c[meshes[1].conn_ptr[e] + 1]
+    meshes[1].conn = c
+    b = fea.Batch([fea.DeviceMesh(m) for m in meshes], model=fea.ELASTIC)
+    _, _, status = b.assemble(variant=fea.ROWGATHER)
+    torch.cuda.synchronize()
+    assert list(status.cpu().numpy()) == [-1, e, -1]
+    with pytest.raises(fea.FeaError):
+        b.assemble(variant=fea.COLOUR)
