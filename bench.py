@@ -118,7 +118,8 @@ def _median_ms(fn, reps):
 def batched_workload(fea, mg, torch):
     """64 independent meshes (8^3..48^3 cells, random family mix, jitter
     0.25 h) in one persistent launch, mixed precision, tiles autotuned,
-    replayed 100 times from a HIP graph."""
+    replayed 100 times from a HIP graph; then the same batch in the
+    row-gather form (FP64 and mixed), also replayed from a graph."""
     import tempfile
     meshes = mg.batched(64)
     dms = [fea.DeviceMesh(m) for m in meshes]
@@ -144,13 +145,29 @@ def batched_workload(fea, mg, torch):
         side.synchronize()
         ms = e0.elapsed_time(e1) / 100
         ok = bool((status.cpu() == -1).all())
+        # the same batch in the row-gather form: one launch per tile class
+        gather = {}
+        for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
+            gv, gr, gs = b.outputs(o)
+            b.assemble(precision=p, out_dtype=o, vals=gv, rhs=gr, status=gs, variant=fea.ROWGATHER)
+            b.capture(gv, gr, gs, precision=p, out_dtype=o, variant=fea.ROWGATHER)
+            b.replay(3)
+            e0.record(side)
+            b.replay(100)
+            e1.record(side)
+            side.synchronize()
+            gms = e0.elapsed_time(e1) / 100
+            gather[f"rowgather_{pname}"] = {"ms_per_replay": round(gms, 4),
+                                            "elements_per_s": round(b.n_elems / (gms * 1e-3), 1),
+                                            "status_ok": bool((gs.cpu() == -1).all())}
+            del gv, gr, gs
     return {"workload": "batched64-elasticity (64 meshes, 8^3..48^3 cells, jitter 0.25h)",
             "elements": int(b.n_elems), "items": int(b.n_items), "items_default_tiles": int(n_items_default),
             "precision": "mixed", "tiles": [int(t) for t in tile],
             "persistent_kernel_ms_default_tiles": round(default_ms, 4),
             "persistent_kernel_ms_tuned_tiles": round(tuned_ms, 4),
             "ms_per_replay": round(ms, 4), "elements_per_s": round(b.n_elems / (ms * 1e-3), 1),
-            "replays": 100, "workers": b.workers(), "status_ok": ok}
+            "replays": 100, "workers": b.workers(), "status_ok": ok, **gather}
 
 
 def copy_bandwidth(torch):
@@ -328,6 +345,19 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
     d = (vl.double() - v64).norm() / v64.norm()
     out["mixed_vs_fp64_rel_frobenius"] = float(d.item())
     out["status_ok"] = bool((st64.cpu() == -1).all()) and bool((stl.cpu() == -1).all())
+    # the same mesh (neo-Hookean bricks included) in the row-gather form
+    g = dm.graph()
+    for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
+        gv, gr, gs = dm.assemble(g, variant=fea.ROWGATHER, use_nh=True, precision=p, out_dtype=o)
+        tot = []
+        for _ in range(5):
+            dm.assemble(g, variant=fea.ROWGATHER, use_nh=True, precision=p, out_dtype=o, vals=gv, rhs=gr,
+                        status=gs, timing=True)
+            tot.append(g.last_timing()[2])
+        out[f"rowgather_{pname}"] = {"total_ms": round(float(np.median(tot)), 4),
+                                     "status_ok": int(gs.item()) == -1}
+        del gv, gr, gs
+    g.destroy()
     return out
 
 

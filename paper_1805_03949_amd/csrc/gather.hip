@@ -102,6 +102,10 @@ struct GatherSmem {
     int32_t sGeo[MIX ? PMAX + 1 : 1];   // first Gauss-point record of each pair
     uint8_t sLP[MIX ? GT : 1];          // pair of each lane
     uint8_t sGP[MIX ? GMAX : 1];        // pair of each Gauss-point record
+    int32_t sSL[MIX ? PMAX : 1];        // place of each pair's first lane and
+    int32_t sSG[MIX ? PMAX : 1];        // first record in the family-sorted orders
+    uint8_t sLI[MIX ? GT : 1];          // lanes in family-sorted order
+    uint16_t sGI[MIX ? GMAX : 1];       // records in family-sorted order
     uint16_t sRP[G_RMAX + 1]; // first pair of each row
     uint16_t sIP[GT + 1];     // first contribution of each block
     uint8_t sD[GT];           // lane of each contribution, ascending element per block
@@ -330,6 +334,19 @@ __device__ inline void g_rhs(Sm &S, int p, int g0, int tf)
 // also wait for every outstanding global access).
 __device__ inline void sync_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Inclusive sum over the 64 lanes of the wave (every lane must call it);
+// total receives the sum over all lanes.
+__device__ inline int wave_scan_incl(int x, int &total)
+{
+    const int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(x, off, 64);
+        if (lane >= off) x += u;
+    }
+    total = __shfl(x, 63, 64);
+    return x;
+}
+
 struct TileRec {
     int32_t r0, nr, P0, np, k0, nk, j0, nj;
 };
@@ -529,30 +546,52 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
         int32_t *const st = L.status + M(mc).mesh;
 
         if constexpr (MIX) {
-            // lane and Gauss-point offsets of the pairs (np <= 64: one wave scans)
+            // lane and Gauss-point offsets of the pairs, and their places in
+            // family-sorted visiting orders (np <= 64: one wave scans)
             if (tid < 64) {
-                const int ty = tid < R.np ? S.sT[tid] : 0;
-                int cn = tid < R.np ? nodes_of(ty) : 0, cq = tid < R.np ? gauss_of(ty) : 0;
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int un = __shfl_up(cn, off, 64), uq = __shfl_up(cq, off, 64);
-                    if (tid >= off) {
-                        cn += un;
-                        cq += uq;
-                    }
-                }
+                const bool ok = tid < R.np;
+                const int ty = ok ? S.sT[tid] : 0;
+                const int n = ok ? nodes_of(ty) : 0, nq = ok ? gauss_of(ty) : 0;
+                int tn, tq;
+                const int cn = wave_scan_incl(n, tn), cq = wave_scan_incl(nq, tq);
                 S.sLane[tid + 1] = cn;
                 S.sGeo[tid + 1] = cq;
                 if (tid == 0) S.sLane[0] = S.sGeo[0] = 0;
+                int bn = 0, bq = 0, sl = 0, sg = 0;
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    int fn, fq;
+                    const int xn = ty == f ? n : 0, xq = ty == f ? nq : 0;
+                    const int in = wave_scan_incl(xn, fn), iq = wave_scan_incl(xq, fq);
+                    if (ty == f) {
+                        sl = bn + in - xn;
+                        sg = bq + iq - xq;
+                    }
+                    bn += fn;
+                    bq += fq;
+                }
+                if (ok) {
+                    S.sSL[tid] = sl;
+                    S.sSG[tid] = sg;
+                }
             }
             sync_lds();
             for (int p = tid; p < R.np; p += GT) {
-                for (int l = S.sLane[p]; l < S.sLane[p + 1]; ++l) S.sLP[l] = (uint8_t)p;
-                for (int g = S.sGeo[p]; g < S.sGeo[p + 1]; ++g) S.sGP[g] = (uint8_t)p;
+                for (int l = S.sLane[p]; l < S.sLane[p + 1]; ++l) {
+                    S.sLP[l] = (uint8_t)p;
+                    S.sLI[S.sSL[p] + l - S.sLane[p]] = (uint8_t)l;
+                }
+                for (int g = S.sGeo[p]; g < S.sGeo[p + 1]; ++g) {
+                    S.sGP[g] = (uint8_t)p;
+                    S.sGI[S.sSG[p] + g - S.sGeo[p]] = (uint16_t)g;
+                }
             }
             sync_lds();
             const int ng = S.sGeo[R.np];
-            // geometry: one thread per (pair, Gauss point)
-            for (int g = tid; g < ng; g += GT) {
+            // geometry: one thread per (pair, Gauss point), visited family by
+            // family so that a wave runs one family's code
+            for (int i = tid; i < ng; i += GT) {
+                const int g = S.sGI[i];
                 const int p = S.sGP[g], ty = S.sT[p], q = g - S.sGeo[p], x0 = S.sLane[p];
                 switch (ty) {
                 case 0: g_geometry<0>(S, st, p, x0, q, g, 0); break;
@@ -562,8 +601,10 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
                 }
             }
             sync_lds();
-            // strips: one thread per lane (pair, element node); right-hand side per pair
-            for (int l = tid; l < R.nj; l += GT) {
+            // strips: one thread per lane (pair, element node), family by
+            // family; right-hand side per pair
+            for (int i = tid; i < R.nj; i += GT) {
+                const int l = S.sLI[i];
                 const int p = S.sLP[l], ty = S.sT[p], b = l - S.sLane[p], g0 = S.sGeo[p];
                 switch (ty) {
                 case 0: g_strip<0>(S, p, b, l, g0, 0); break;
