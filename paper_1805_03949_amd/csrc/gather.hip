@@ -25,7 +25,13 @@
 
 namespace fea {
 
-constexpr int GT = 256;              // threads per workgroup = strip lanes per tile
+constexpr int GT = 256;              // threads of an interface-tile workgroup
+// Threads per workgroup of the one-family classes (tet4, pyr5, pen6, hex8):
+// at most one strip lane per thread, so a tile holds TPB / nodes pairs.
+// Measured on MI355X: 128-thread workgroups (twice as many, half-size
+// tiles) are no faster for pyr5/hex8 and slower for pen6.
+constexpr int G_TPB[4] = {256, 256, 256, 256};
+__host__ __device__ inline int gather_tpb(int c) { return c == 4 ? GT : G_TPB[c]; }
 constexpr int G_MIXED = 4;           // tile class of rows touching several families
 constexpr int G_RMAX = 64;           // rows per tile
 constexpr int G_PMAX_MIXED = 64;     // (row, element) pairs per interface tile
@@ -33,10 +39,12 @@ constexpr int G_GMAX_MIXED = 384;    // Gauss points per interface tile
 
 __host__ __device__ inline int gauss_of(int t) { return t == 0 ? 1 : (t == 2 ? 6 : 8); }
 
-// Pairs a tile of rows of one family may hold (at most GT / nodes: one
+// Pairs a tile of rows of one family may hold (at most TPB / nodes: one
 // strip lane per thread), and Gauss points a tile of class c may hold.
-constexpr int G_PMAX_PURE[4] = {64, 51, 42, 32};
-__host__ __device__ inline int gather_pmax(int c) { return c == G_MIXED ? G_PMAX_MIXED : G_PMAX_PURE[c]; }
+__host__ __device__ inline int gather_pmax(int c)
+{
+    return c == G_MIXED ? G_PMAX_MIXED : gather_tpb(c) / nodes_of(c);
+}
 __host__ __device__ inline int gather_gmax(int c)
 {
     return c == G_MIXED ? G_GMAX_MIXED : gather_pmax(c) * gauss_of(c);
@@ -48,8 +56,9 @@ struct GatherSmem {
     static constexpr int FAMILY = C;
     static constexpr int NN = MIX ? 8 : Fam<C>::NN;
     static constexpr int NQ = MIX ? 8 : Fam<C>::NQ;
-    static constexpr int PMAX = MIX ? G_PMAX_MIXED : G_PMAX_PURE[MIX ? 0 : C];
-    static_assert(PMAX * NN <= GT || MIX, "one strip lane per thread");
+    static constexpr int TPB = MIX ? GT : G_TPB[MIX ? 0 : C];
+    static constexpr int PMAX = MIX ? G_PMAX_MIXED : TPB / NN;
+    static_assert(PMAX * NN <= TPB || MIX, "one strip lane per thread");
     using CTy = CT;
     // One-family tiles take their Gauss points in NCH chunks of QC: the
     // geometry records of one chunk at a time live in LDS (the strips keep
@@ -107,8 +116,8 @@ struct GatherSmem {
     uint8_t sLI[MIX ? GT : 1];          // lanes in family-sorted order
     uint16_t sGI[MIX ? GMAX : 1];       // records in family-sorted order
     uint16_t sRP[G_RMAX + 1]; // first pair of each row
-    uint16_t sIP[GT + 1];     // first contribution of each block
-    uint8_t sD[GT];           // lane of each contribution, ascending element per block
+    uint16_t sIP[TPB + 1];    // first contribution of each block
+    uint8_t sD[TPB];          // lane of each contribution, ascending element per block
 };
 
 struct GatherArgs {
@@ -374,6 +383,7 @@ __device__ inline TileRec load_rec(const int32_t *tiles, int64_t t)
     return {T[0], T[1], T[2], T[3], T[4], T[5], T[6], T[7]};
 }
 
+template <int TPB>
 __device__ inline Pre1 load1(const GatherArgs &A, const TileRec &R, int tid)
 {
     Pre1 P = {};
@@ -388,7 +398,7 @@ __device__ inline Pre1 load1(const GatherArgs &A, const TileRec &R, int tid)
         P.a = A.n2a[(int64_t)R.P0 + tid];
     }
     if (tid <= R.nk) P.ip0 = A.inv_ptr[(int64_t)R.k0 + tid];
-    if (tid + GT <= R.nk) P.ip1 = A.inv_ptr[(int64_t)R.k0 + tid + GT];
+    if (tid + TPB <= R.nk) P.ip1 = A.inv_ptr[(int64_t)R.k0 + tid + TPB];
     if (tid <= R.nr) P.rp = A.n2e_ptr[(int64_t)R.r0 + tid];
     return P;
 }
@@ -445,7 +455,8 @@ __device__ inline void commit(GatherSmem<C, MODEL, CT> &S, const TileRec &R, con
         }
     }
     if (tid <= R.nk) S.sIP[tid] = (uint16_t)(P.ip0 - R.j0);
-    if (tid + GT <= R.nk) S.sIP[tid + GT] = (uint16_t)(P.ip1 - R.j0);
+    constexpr int TPB = GatherSmem<C, MODEL, CT>::TPB;
+    if (tid + TPB <= R.nk) S.sIP[tid + TPB] = (uint16_t)(P.ip1 - R.j0);
     if (tid <= R.nr) S.sRP[tid] = (uint16_t)(P.rp - R.P0);
 }
 
@@ -460,7 +471,7 @@ __device__ inline void pure_chunk(Sm &S, int32_t *status, const TileRec &R, type
                                   typename Sm::CTy *fr, int tid, int lp, int lb)
 {
     constexpr int C = Sm::FAMILY, NN = Sm::NN, QC = Sm::QC, GS = Sm::GS, Q0 = CH * QC;
-    for (int g = tid; g < R.np * QC; g += GT) {
+    for (int g = tid; g < R.np * QC; g += Sm::TPB) {
         const int p = g / QC, qq = g - p * QC;
         g_geometry<C>(S, status, p, p * NN, Q0 + qq, p * GS + qq, 0);
     }
@@ -485,20 +496,21 @@ struct GatherWaves {
 // view is meshes[tmesh[t]] (arrays, output offsets, status entry), and the
 // launch fields (tiles, outputs, status base, output type) come from L.
 template <int C, int MODEL, typename CT, bool BATCHED>
-__global__ void __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(GatherWaves<C, MODEL>::value)))
+__global__ void __launch_bounds__((GatherSmem<C, MODEL, CT>::TPB))
+__attribute__((amdgpu_waves_per_eu(GatherWaves<C, MODEL>::value)))
 k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t ntiles)
 {
     using Sm = GatherSmem<C, MODEL, CT>;
     __shared__ Sm S;
     constexpr bool MIX = Sm::MIX;
-    constexpr int NN = Sm::NN, NQ = Sm::NQ, B = Sm::B, BB = Sm::BB, GS = Sm::GS;
+    constexpr int NN = Sm::NN, NQ = Sm::NQ, B = Sm::B, BB = Sm::BB, GS = Sm::GS, TPB = Sm::TPB;
     const int tid = threadIdx.x;
     const int64_t nW = gridDim.x >> 3, x = blockIdx.x & 7;
     const int64_t c1 = (x + 1) * ntiles / 8;
     int64_t t = x * ntiles / 8 + (blockIdx.x >> 3);
     if (t >= c1) return;
 
-    for (int i = tid; i < Sm::NT * 64; i += GT) {
+    for (int i = tid; i < Sm::NT * 64; i += TPB) {
         const int tf = i >> 6, q = (i >> 3) & 7, a = i & 7;
         const int ty = MIX ? tf : C;
         S.sN[tf][q][a] = c_ref.N[ty][q][a];
@@ -515,7 +527,7 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
     TileRec R = load_rec(L.tiles, t);
     int32_t mc = mesh_of(t);
     {
-        const Pre1 P = load1(M(mc), R, tid);
+        const Pre1 P = load1<Sm::TPB>(M(mc), R, tid);
         commit<C, MODEL, CT>(S, R, P, load2<B, MIX, Sm::NHK>(M(mc), P), tid);
     }
     int64_t tn = t + nW;
@@ -525,7 +537,7 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
     if (tn < c1) {
         Rn = load_rec(L.tiles, tn);
         mn = mesh_of(tn);
-        Pn = load1(M(mn), Rn, tid);
+        Pn = load1<Sm::TPB>(M(mn), Rn, tid);
     }
     sync_lds();
 
@@ -541,7 +553,7 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
         if (tnn < c1) {
             Rnn = load_rec(L.tiles, tnn);
             mnn = mesh_of(tnn);
-            Pnn = load1(M(mnn), Rnn, tid);
+            Pnn = load1<Sm::TPB>(M(mnn), Rnn, tid);
         }
         int32_t *const st = L.status + M(mc).mesh;
 
@@ -576,7 +588,7 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
                 }
             }
             sync_lds();
-            for (int p = tid; p < R.np; p += GT) {
+            for (int p = tid; p < R.np; p += TPB) {
                 for (int l = S.sLane[p]; l < S.sLane[p + 1]; ++l) {
                     S.sLP[l] = (uint8_t)p;
                     S.sLI[S.sSL[p] + l - S.sLane[p]] = (uint8_t)l;
@@ -590,7 +602,7 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
             const int ng = S.sGeo[R.np];
             // geometry: one thread per (pair, Gauss point), visited family by
             // family so that a wave runs one family's code
-            for (int i = tid; i < ng; i += GT) {
+            for (int i = tid; i < ng; i += TPB) {
                 const int g = S.sGI[i];
                 const int p = S.sGP[g], ty = S.sT[p], q = g - S.sGeo[p], x0 = S.sLane[p];
                 switch (ty) {
@@ -603,7 +615,7 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
             sync_lds();
             // strips: one thread per lane (pair, element node), family by
             // family; right-hand side per pair
-            for (int i = tid; i < R.nj; i += GT) {
+            for (int i = tid; i < R.nj; i += TPB) {
                 const int l = S.sLI[i];
                 const int p = S.sLP[l], ty = S.sT[p], b = l - S.sLane[p], g0 = S.sGeo[p];
                 switch (ty) {
@@ -613,7 +625,7 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
                 default: g_strip<3>(S, p, b, l, g0, 3); break;
                 }
             }
-            for (int p = tid; p < R.np; p += GT) {
+            for (int p = tid; p < R.np; p += TPB) {
                 const int ty = S.sT[p], g0 = S.sGeo[p];
                 switch (ty) {
                 case 0: g_rhs<0>(S, p, g0, 0); break;
@@ -655,7 +667,7 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
 
         // blocks of the tile's rows, one thread per (block, block row): the
         // block's contributions summed in ascending element order
-        for (int idx = tid; idx < R.nk * B; idx += GT) {
+        for (int idx = tid; idx < R.nk * B; idx += TPB) {
             const int k = idx / B, i = idx - k * B;
             double s[B];
 #pragma unroll
@@ -691,7 +703,7 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
                 else ((double *)L.vals)[o + c] = s[c];
             }
         }
-        for (int idx = tid; idx < R.nr * B; idx += GT) {
+        for (int idx = tid; idx < R.nr * B; idx += TPB) {
             const int r = idx / B, c = idx - r * B;
             double s = 0.0;
             for (int p = S.sRP[r]; p < S.sRP[r + 1]; ++p) s += (double)S.sR[p][c];
@@ -826,7 +838,7 @@ static int gather_prepare(fea_graph *g, const uint8_t *types, const int64_t *con
         }
         const int c = rcl < 0 ? cls : rcl;
         const bool fits = rows < G_RMAX && (rcl < 0 || cls < 0 || c == cls) &&
-                          (c < 0 || (pairs + rp <= gather_pmax(c) && lanes + rl <= GT &&
+                          (c < 0 || (pairs + rp <= gather_pmax(c) && lanes + rl <= gather_tpb(c) &&
                                      geo + rg <= gather_gmax(c)));
         if (rows > 0 && !fits) {
             close(i);
@@ -884,6 +896,7 @@ template <int C, int MODEL, typename CT, bool BATCHED>
 static int launch_class(const GatherArgs &L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n,
                         hipStream_t s)
 {
+    constexpr int TPB = GatherSmem<C, MODEL, CT>::TPB;
     // persistent grid: as many workgroups as fit on the device at once, a
     // multiple of the 8 XCDs
     static int per_cu[64] = {0};
@@ -893,14 +906,14 @@ static int launch_class(const GatherArgs &L, const GatherArgs *meshes, const int
     if (dev < 0 || dev >= 64) return set_error(FEA_EINVAL, "device index %d unsupported", dev);
     if (!per_cu[dev]) {
         int b = 0, c = 0;
-        FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_gather<C, MODEL, CT, BATCHED>, GT, 0));
+        FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_gather<C, MODEL, CT, BATCHED>, TPB, 0));
         FEA_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
         cus[dev] = std::max(c, 8);
         per_cu[dev] = std::max(b, 1);
     }
     int64_t grid = std::min<int64_t>((int64_t)per_cu[dev] * cus[dev], (n + 7) / 8 * 8);
     grid = std::max<int64_t>(grid / 8 * 8, 8);
-    k_gather<C, MODEL, CT, BATCHED><<<(unsigned)grid, GT, 0, s>>>(L, meshes, tmesh, n);
+    k_gather<C, MODEL, CT, BATCHED><<<(unsigned)grid, TPB, 0, s>>>(L, meshes, tmesh, n);
     return FEA_OK;
 }
 
