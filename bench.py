@@ -551,6 +551,26 @@ def main():
                "sample": f"the whole workload ({mesh.n_elems} elements), FP64 C oracle, sequential "
                          f"Algorithm 1 order, graph build excluded; {cpu_s:.1f} s"}
 
+    # scatter HBM rate of the two-phase (row-owner) form: matrix and
+    # right-hand side, second phase
+    scatter = {"algorithmic_bytes": int(sb), "copy_GBps": copy_gbps,
+               "note": "row-owner form, second phase (block values and right-hand side)"}
+    if args.variant == "rowowner":
+        t2 = float(ph[2]) - elem_ms
+    elif "rowowner_" + args.precision in variants:
+        ro = variants["rowowner_" + args.precision]
+        t2 = ro["total_ms"] - ro["element_ms"]
+    else:
+        t2 = None
+    if t2:
+        eff = sb / (t2 * 1e-3) / 1e9
+        scatter.update({"effective_GBps": round(eff, 1), "frac_of_peak": round(eff / PEAK_HBM_GBS, 4),
+                        "frac_of_copy": round(eff / copy_gbps, 4), "ms": round(t2, 4)})
+    tr = traffic_from_profile("k_reduce_seg<9>", "assemble.hip")
+    if tr and t2:
+        scatter["counter_GBps_block_values"] = round(tr / (variants.get("rowowner_fp64", {}).get(
+            "block_value_kernel_ms", t2) * 1e-3) / 1e9, 1)
+
     value = mesh.n_elems / (ms_per_step * 1e-3)
     out = {
         "metric": METRIC,
@@ -570,9 +590,7 @@ def main():
                    "variant": args.variant, "precision": args.precision,
                    "out_dtype": "f64" if outd == fea.F64 else "f32"},
         "roofline": roofline,
-        "scatter": {"effective_GBps": round(sb / ((float(ph[2]) - elem_ms) * 1e-3) / 1e9, 1) if args.variant == "rowowner" else None,
-                    "frac_of_peak": round(sb / ((float(ph[2]) - elem_ms) * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if args.variant == "rowowner" else None,
-                    "algorithmic_bytes": int(sb), "note": "matrix and right-hand side, second phase of the row-owner form"},
+        "scatter": scatter,
         "gather_class_ms": class_ms,
         "element_phase": {"algorithmic_bytes": int(eb), "ms": round(elem_ms, 4),
                           "effective_GBps": round(eb / (elem_ms * 1e-3) / 1e9, 1)},
