@@ -1,0 +1,33 @@
+"""CPU checks of the benchmark's work accounting (no GPU): the roofline's
+flop and byte figures are sums that must add up."""
+import numpy as np
+
+import bench
+import meshgen as mg
+
+
+def test_class_flops_add_up_to_the_per_element_figures():
+    m = mg.hybrid_bands(8, seed=2)
+    alg, exe = bench.gather_class_flops(m, np)
+    # every (row, element) pair carries 1/n of its element: the classes
+    # together hold every element exactly once
+    total = sum(bench.ELEMENT_FLOPS[t] for t in m.types)
+    assert abs(sum(alg) - total) <= 1e-9 * total
+    per_pair = [bench.gather_pair_flops(t) for t in range(4)]
+    assert abs(sum(exe) - sum(per_pair[t] * bench.NODES[t] for t in m.types)) <= 1e-6 * sum(exe)
+    # one-family bands: the four one-family classes hold most of the work
+    assert sum(alg[:4]) > 0.6 * total
+
+
+def test_pair_flop_formula_by_hand():
+    # tet4: one Gauss point, four nodes: 1 * (18*4 + 77) + 4 * (33 + 33) + 4 * 9
+    assert bench.gather_pair_flops(0) == 149 + 264 + 36
+    # hex8: 8 * (18*8 + 77) + 8 * (8*33 + 33) + 8 * 9
+    assert bench.gather_pair_flops(3) == 8 * 221 + 8 * 297 + 72
+
+
+def test_reduce_bytes_definition():
+    class G:
+        map_len, nnz = 84_492_288, 22_156_129
+    b = bench.reduce_bytes(G, 3, 8, 8)
+    assert b == 84_492_288 * 72 + (22_156_129 + 1) * 8 + 22_156_129 * 72
