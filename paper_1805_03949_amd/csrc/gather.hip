@@ -3,21 +3,29 @@
 // Row i of A is the sum, over the elements that contain node i taken in
 // ascending element order (the order of Algorithm 1), of the element-matrix
 // rows of i; the same holds for entry i of b. A workgroup owns a tile of
-// consecutive rows [r0, r1). For every (row, incident element) pair of the
-// tile it recomputes the element's geometry at the Gauss points (one thread
-// per pair and point, FP64), then the pair's strip of blocks K_ab, a the row
-// node and b every node of the element (one thread per pair and b), keeps
-// the strips in LDS and forms every block of its rows as the ascending-order
-// sum of that block's contributions (one thread per block component). A and
-// b are written once, with no workspace and no atomics.
+// consecutive rows. For every (row, incident element) pair of the tile it
+// recomputes the element's geometry at the Gauss points (one thread per pair
+// and point, FP64), then the pair's strip of blocks K_ab, a the row node and
+// b every node of the element (one thread per pair and b), keeps the strips
+// in LDS and forms every block of its rows as the ascending-order sum of that
+// block's contributions (one thread per block and block row). A and b are
+// written once, with no workspace and no atomics: the paper's full-row
+// distribution (Section 3.1, halo elements computed by every owner) at the
+// scale of a workgroup.
 //
 // The price is that an element's geometry is recomputed once per incident
-// row: FP64 arithmetic, which this path has in excess, replaces the round
-// trip of every element block through HBM that bounds the row-owner form.
+// row: FP64 arithmetic replaces the round trip of every element block through
+// HBM that bounds the row-owner form.
 //
 // Tiles are built once per graph and come in five classes: rows whose
-// elements all belong to one family (tet4, pyr5, pen6, hex8), with every
-// loop bound known at compile time, and rows on family interfaces.
+// elements all belong to one family (tet4, pyr5, pen6, hex8), with every loop
+// bound known at compile time, and rows on family interfaces. Workgroups are
+// persistent: each walks a run of tiles of one XCD's share and loads the next
+// tile's data while it computes the current one. One-family tiles take their
+// Gauss points in chunks (records of one chunk in LDS, partial sums in
+// registers). A batched form runs the tiles of many meshes in one launch per
+// class; neo-Hookean kernels add F^-1 and the tangent coefficients to the
+// records.
 #include <algorithm>
 #include <vector>
 
@@ -60,10 +68,11 @@ struct GatherSmem {
     static constexpr int PMAX = MIX ? G_PMAX_MIXED : TPB / NN;
     static_assert(PMAX * NN <= TPB || MIX, "one strip lane per thread");
     using CTy = CT;
+    static constexpr bool NHK = MODEL == M_ELASTIC_NH;
     // One-family tiles take their Gauss points in NCH chunks of QC: the
     // geometry records of one chunk at a time live in LDS (the strips keep
-    // their partial sums in registers), which halves the records' LDS.
-    static constexpr bool NHK = MODEL == M_ELASTIC_NH;
+    // their partial sums in registers). Linear 6- and 8-point families: two
+    // chunks; neo-Hookean (larger records): two points per chunk.
     static constexpr int NCH = MIX ? 1 : (NQ < 6 ? 1 : (NHK ? NQ / 2 : 2));
     static constexpr int QC = NQ / NCH;
     static_assert(NQ % NCH == 0 && NCH <= 4, "whole chunks");
@@ -362,7 +371,7 @@ struct TileRec {
 
 // Per-thread prefetch of one tile: index data (first stage) and what it
 // points to (second stage). Thread tid holds lane tid, pair tid, the
-// inverse-map offsets of blocks tid and tid + 256, and row tid.
+// inverse-map offsets of blocks tid and tid + TPB, and row tid.
 struct Pre1 {
     int32_t v, e;
     int ok_l, ok_p;
@@ -460,10 +469,6 @@ __device__ inline void commit(GatherSmem<C, MODEL, CT> &S, const TileRec &R, con
     if (tid <= R.nr) S.sRP[tid] = (uint16_t)(P.rp - R.P0);
 }
 
-// Persistent workgroups: the tiles of this launch are split into eight
-// contiguous chunks, one per XCD (workgroup b runs on XCD b % 8), so that
-// tiles sharing nodes share an L2; a workgroup takes every nW-th tile of its
-// chunk and prefetches the next tile while it computes the current one.
 // Chunk CH of a one-family tile: geometry of its Gauss points, then their
 // share of every lane's block and every pair's right-hand side.
 template <int CH, typename Sm>
@@ -492,6 +497,10 @@ struct GatherWaves {
     static constexpr int value = MODEL == M_ELASTIC_NH ? G_WAVES_NH[C] : G_WAVES[C];
 };
 
+// Persistent workgroups: the tiles of this launch are split into eight
+// contiguous chunks, one per XCD (workgroup b runs on XCD b % 8), so that
+// tiles sharing nodes share an L2; a workgroup takes every nW-th tile of its
+// chunk and prefetches the next tile while it computes the current one.
 // BATCHED: the tiles of one launch belong to several meshes; tile t's mesh
 // view is meshes[tmesh[t]] (arrays, output offsets, status entry), and the
 // launch fields (tiles, outputs, status base, output type) come from L.
