@@ -60,8 +60,16 @@ enum fea_precision { FEA_FP64 = 0, FEA_MIXED = 1 };
  *             read-add-write (Algorithm 5); deterministic;
  *   ROWGATHER fused owner-computes: each row's owner recomputes the element
  *             rows that touch it and sums them in ascending element order
- *             (deterministic, no workspace, no atomics). */
-enum fea_variant { FEA_ROWOWNER = 0, FEA_ATOMIC = 1, FEA_COLOUR = 2, FEA_ROWGATHER = 3 };
+ *             (deterministic, no workspace, no atomics);
+ *   ROWSYM    row-owner on the upper triangle: every element matrix here is
+ *             symmetric (K_ba = K_ab^T), so each element computes its
+ *             n(n+1)/2 blocks a <= b and stores each one, or its transpose,
+ *             as the contribution to an upper block (i <= j); a lower block
+ *             (j, i) is written as the transpose of the ordered sum of block
+ *             (i, j). About 40% less element work and workspace traffic;
+ *             deterministic, and A is exactly symmetric. Single-mesh
+ *             assembly only. */
+enum fea_variant { FEA_ROWOWNER = 0, FEA_ATOMIC = 1, FEA_COLOUR = 2, FEA_ROWGATHER = 3, FEA_ROWSYM = 4 };
 enum fea_dtype { FEA_F64 = 0, FEA_F32 = 1 };
 enum fea_model { FEA_POISSON = 0, FEA_ELASTIC = 1 };
 enum fea_schedule { FEA_TYPE_SORTED = 0, FEA_LEARNED = 1, FEA_GP_WEIGHT = 2 };

@@ -6,6 +6,7 @@
 #include <mutex>
 
 #include "elem.h"
+#include "segsum.h"
 
 namespace fea {
 
@@ -15,35 +16,6 @@ __global__ void __launch_bounds__(256) k_element(ElemArgs A)
     __shared__ ElemSmem<T, MODEL, VAR, CT> S;
     constexpr int EPB = ElemSmem<T, MODEL, VAR, CT>::EPB;
     elem_tile<T, MODEL, VAR, CT>(A, xcd_tile(blockIdx.x, gridDim.x) * EPB, S);
-}
-
-// Row-owner second phase. The workspace holds every block's contributions
-// contiguously, in ascending element order (the order of Algorithm 1), so
-// block k's value is a plain sum over its segment: a streaming pass with
-// the result independent of how the element phase was scheduled.
-template <int W, typename CT, typename OT>
-__global__ void __launch_bounds__(256) k_reduce_seg(int64_t nseg, const int64_t *seg_ptr,
-                                                    const CT *data, OT *out)
-{
-    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= nseg * W) return;
-    int64_t k = t / W;
-    int c = (int)(t - k * W);
-    double s = 0.0;
-    const int64_t e = seg_ptr[k + 1];
-    const CT *d = data + c;
-    // four loads in flight per step; the additions stay in ascending order
-    for (int64_t j = seg_ptr[k]; j < e; j += 4) {
-        CT v0 = d[j * W];
-        CT v1 = j + 1 < e ? d[(j + 1) * W] : (CT)0;
-        CT v2 = j + 2 < e ? d[(j + 2) * W] : (CT)0;
-        CT v3 = j + 3 < e ? d[(j + 3) * W] : (CT)0;
-        s += (double)v0;
-        if (j + 1 < e) s += (double)v1;
-        if (j + 2 < e) s += (double)v2;
-        if (j + 3 < e) s += (double)v3;
-    }
-    out[t] = (OT)s;
 }
 
 __global__ void k_fill_f64(double *p, int64_t n, double v)
@@ -73,8 +45,7 @@ __global__ void k_status_final(int32_t *s)
 template <int T, int MODEL, int VAR, typename CT>
 static void launch_fam(const ElemArgs &a, hipStream_t s)
 {
-    constexpr int P = Fam<T>::NN * Fam<T>::NN;
-    constexpr int EPB = 256 / P;
+    constexpr int EPB = ElemSmem<T, MODEL, VAR, CT>::EPB;
     if (a.n <= 0) return;
     k_element<T, MODEL, VAR, CT><<<grid_for(a.n, EPB), 256, 0, s>>>(a);
 }
@@ -115,6 +86,35 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
     const int64_t nv = g->nnz * BB, nr = g->n_nodes * B;
     const bool f32 = o->out_dtype == FEA_F32;
     int rc;
+    if (o->variant == FEA_ROWSYM) {
+        if (!g->sready && (rc = sym_prepare(g, s))) return rc;
+        if ((rc = ensure_ws(&g->contrib, &g->contrib_bytes, sizeof(CT) * (size_t)std::max<int64_t>(g->ulen, 1) * BB))) return rc;
+        if ((rc = ensure_ws(&g->rcontrib, &g->rcontrib_bytes, sizeof(CT) * (size_t)g->conn_len * B))) return rc;
+        a.contrib = g->contrib;
+        a.rcontrib = g->rcontrib;
+        mark(g, 0, o, s);
+        for (int t = 0; t < 4; ++t) {
+            a.elems = g->perm + g->seg[t];
+            a.n = g->seg[t + 1] - g->seg[t];
+            a.pnodes = g->pnodes + g->node_base[t];
+            a.prdest = g->prdest + g->node_base[t];
+            a.pdest = g->pudest + g->slot_base[t];
+            launch_type<MODEL, V_ROWSYM, CT>(t, a, s);
+        }
+        mark(g, 1, o, s);
+        if (f32) {
+            if (g->nup) launch_segsum<BB, CT, float, true>(g->nup, g->ublk, g->lpart, g->usptr, (const CT *)g->contrib, (float *)vals, s);
+            mark(g, 2, o, s);
+            if (nr) launch_segsum<B, CT, float, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
+        } else {
+            if (g->nup) launch_segsum<BB, CT, double, true>(g->nup, g->ublk, g->lpart, g->usptr, (const CT *)g->contrib, (double *)vals, s);
+            mark(g, 2, o, s);
+            if (nr) launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
+        }
+        mark(g, 3, o, s);
+        FEA_HIP(hipGetLastError());
+        return FEA_OK;
+    }
     if (o->variant == FEA_ROWOWNER) {
         if ((rc = ensure_ws(&g->contrib, &g->contrib_bytes, sizeof(CT) * (size_t)g->map_len * BB))) return rc;
         if ((rc = ensure_ws(&g->rcontrib, &g->rcontrib_bytes, sizeof(CT) * (size_t)g->conn_len * B))) return rc;
@@ -131,13 +131,13 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         }
         mark(g, 1, o, s);
         if (f32) {
-            if (nv) k_reduce_seg<BB, CT, float><<<grid_for(nv, 256), 256, 0, s>>>(g->nnz, g->inv_ptr, (const CT *)g->contrib, (float *)vals);
+            if (nv) launch_segsum<BB, CT, float, false>(g->nnz, nullptr, nullptr, g->inv_ptr, (const CT *)g->contrib, (float *)vals, s);
             mark(g, 2, o, s);
-            if (nr) k_reduce_seg<B, CT, float><<<grid_for(nr, 256), 256, 0, s>>>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs);
+            if (nr) launch_segsum<B, CT, float, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
         } else {
-            if (nv) k_reduce_seg<BB, CT, double><<<grid_for(nv, 256), 256, 0, s>>>(g->nnz, g->inv_ptr, (const CT *)g->contrib, (double *)vals);
+            if (nv) launch_segsum<BB, CT, double, false>(g->nnz, nullptr, nullptr, g->inv_ptr, (const CT *)g->contrib, (double *)vals, s);
             mark(g, 2, o, s);
-            if (nr) k_reduce_seg<B, CT, double><<<grid_for(nr, 256), 256, 0, s>>>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs);
+            if (nr) launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
         }
         mark(g, 3, o, s);
         FEA_HIP(hipGetLastError());
@@ -198,7 +198,7 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     fea_options dflt = {0, 0, 0, 0};
     const fea_options *o = opt ? opt : &dflt;
     if (!g || !mat) return set_error(FEA_EINVAL, "graph and material are required");
-    if (o->precision < 0 || o->precision > 1 || o->variant < 0 || o->variant > 3 ||
+    if (o->precision < 0 || o->precision > 1 || o->variant < 0 || o->variant > 4 ||
         o->out_dtype < 0 || o->out_dtype > 1)
         return set_error(FEA_EINVAL, "bad option (precision %d, variant %d, out_dtype %d)",
                          o->precision, o->variant, o->out_dtype);

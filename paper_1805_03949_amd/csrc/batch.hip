@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "elem.h"
+#include "segsum.h"
 
 namespace fea {
 
@@ -107,30 +108,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
             cu[it] = (int32_t)__smid();
         }
     }
-}
-
-template <int W, typename CT, typename OT>
-__global__ void __launch_bounds__(256) k_breduce(int64_t nseg, const int64_t *seg_ptr,
-                                                 const CT *data, OT *out)
-{
-    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= nseg * W) return;
-    int64_t k = t / W;
-    int c = (int)(t - k * W);
-    double s = 0.0;
-    const int64_t e = seg_ptr[k + 1];
-    const CT *d = data + c;
-    for (int64_t j = seg_ptr[k]; j < e; j += 4) {
-        CT v0 = d[j * W];
-        CT v1 = j + 1 < e ? d[(j + 1) * W] : (CT)0;
-        CT v2 = j + 2 < e ? d[(j + 2) * W] : (CT)0;
-        CT v3 = j + 3 < e ? d[(j + 3) * W] : (CT)0;
-        s += (double)v0;
-        if (j + 1 < e) s += (double)v1;
-        if (j + 2 < e) s += (double)v2;
-        if (j + 3 < e) s += (double)v3;
-    }
-    out[t] = (OT)s;
 }
 
 // Concatenated segment bounds: out[i] = in[i] + off for i in [0, n].
@@ -428,8 +405,8 @@ int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, 
                                                       b->d_cycles, b->d_worker, b->d_cu);
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[1], s));
     const int64_t nv = b->total_blocks * BB, nr = b->rhs_off.back();
-    if (nv) k_breduce<BB, CT, OT><<<grid_for(nv, 256), 256, 0, s>>>(b->total_blocks, b->d_vseg, (const CT *)b->contrib, (OT *)vals);
-    if (nr) k_breduce<B, CT, OT><<<grid_for(nr, 256), 256, 0, s>>>(nr / B, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs);
+    if (nv) launch_segsum<BB, CT, OT, false>(b->total_blocks, nullptr, nullptr, b->d_vseg, (const CT *)b->contrib, (OT *)vals, s);
+    if (nr) launch_segsum<B, CT, OT, false>(nr / B, nullptr, nullptr, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs, s);
     k_batch_end<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_status, b->n_meshes, status);
     FEA_HIP(hipGetLastError());
     return FEA_OK;

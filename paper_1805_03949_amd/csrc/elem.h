@@ -176,7 +176,13 @@ struct ElemArgs {
     int32_t *status;
 };
 
-enum { V_ROWOWNER = 0, V_ATOMIC = 1, V_COLOUR = 2 };
+// V_ROWSYM: the row-owner layout restricted to the slots of upper blocks
+// (destination -1 elsewhere). A symmetric element matrix has block (b, a)
+// equal to block (a, b) transposed, so one thread per local pair a <= b
+// computes block (a, b) and stores it, or its transpose, in whichever of
+// the two slots belongs to an upper block (both when nodes a and b
+// coincide); the reduction forms lower blocks as transposes.
+enum { V_ROWOWNER = 0, V_ATOMIC = 1, V_COLOUR = 2, V_ROWSYM = 3 };
 
 // Kernel model codes: FEA_POISSON, FEA_ELASTIC (linear elements only) and
 // M_ELASTIC_NH (some elements use the neo-Hookean tangent; only these
@@ -228,13 +234,15 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t nblk)
 template <int T, int MODEL, int VAR, typename CT>
 struct ElemSmem {
     static constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
-    static constexpr int EPB = 256 / P;
+    // threads per element: all n*n blocks, or the n(n+1)/2 pairs a <= b
+    static constexpr int PW = VAR == V_ROWSYM ? NN * (NN + 1) / 2 : P;
+    static constexpr int EPB = 256 / PW;
     static constexpr bool ELAS = MODEL != FEA_POISSON;
     static constexpr bool NHK = MODEL == M_ELASTIC_NH;
     static constexpr int B = ELAS ? 3 : 1;
     static constexpr int BB = B * B;
     static constexpr int EU = NHK ? EPB : 1;
-    static constexpr bool RO = VAR == V_ROWOWNER;
+    static constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM;
 
     double sX[EPB][NN][3];
     double sU[EU][NN][3];
@@ -250,8 +258,8 @@ struct ElemSmem {
     // block's BB contiguous values. Measured per family on MI355X: a gain
     // everywhere except FP64 pyramids, where the extra LDS halves occupancy.
     static constexpr bool STAGE = RO && (sizeof(CT) == 4 || T != 1 || !NHK);
-    CT sK[STAGE ? EPB * P * BB : 1];
-    int32_t sD[STAGE ? EPB * P : 1];
+    CT sK[STAGE ? EPB * PW * BB : 1];
+    int32_t sD[STAGE ? EPB * PW : 1];
     double sDN[NQ][NN][3];   // reference gradients of this family
     double sNr[NQ][NN];      // reference shape functions
 
@@ -264,13 +272,15 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                           const int tid = threadIdx.x)
 {
     constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
-    constexpr int EPB = 256 / P;
+    constexpr int PW = ElemSmem<T, MODEL, VAR, CT>::PW;
+    constexpr int EPB = ElemSmem<T, MODEL, VAR, CT>::EPB;
     constexpr bool ELAS = MODEL != FEA_POISSON;
     constexpr bool NHK = MODEL == M_ELASTIC_NH;
     constexpr int B = ELAS ? 3 : 1;
     constexpr int BB = B * B;
     constexpr int EU = NHK ? EPB : 1;
-    constexpr bool RO = VAR == V_ROWOWNER;
+    constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM;
+    constexpr bool SYM = VAR == V_ROWSYM;
 
     auto &sX = S.sX;
     auto &sU = S.sU;
@@ -406,13 +416,35 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     }
     __syncthreads();
 
-    // element matrix: one thread per (element, block a-b)
-    if (tid < EPB * P) {
-        int el = tid / P, p = tid % P, a = p / NN, b = p % NN;
+    // element matrix: one thread per (element, block a-b), or per pair a <= b
+    if (tid < EPB * PW) {
+        const int el = tid / PW, w = tid % PW;
+        int a, b;
+        if constexpr (SYM) {
+            // w-th pair of the row-major upper triangle
+            a = 0;
+            int r = w;
+#pragma unroll
+            for (int k = 0; k < NN - 1; ++k) {
+                const bool step = r >= NN - a;
+                r -= step ? NN - a : 0;
+                a += step ? 1 : 0;
+            }
+            b = a + r;
+        } else {
+            a = w / NN;
+            b = w % NN;
+        }
+        const int p = a * NN + b, pt = b * NN + a;
         int32_t e = sE[el];
-        if (e >= 0) {
-            // destination of this block, fetched before the contraction
-            const int64_t dest = RO ? (int64_t)A.pdest[(first + el) * P + p] : (int64_t)A.e2nnz[sM[el] + p];
+        // destinations, fetched before the contraction: of block (a, b) and,
+        // for the symmetric form, of its transpose (b, a)
+        const int64_t dest = e < 0 ? -1
+                             : RO  ? (int64_t)A.pdest[(first + el) * P + p]
+                                   : (int64_t)A.e2nnz[sM[el] + p];
+        const int64_t dest_t = (!SYM || e < 0 || a == b) ? -1 : (int64_t)A.pdest[(first + el) * P + pt];
+        if constexpr (STAGE && SYM) sD[tid] = (int32_t)(dest >= 0 ? dest : dest_t);
+        if (dest >= 0 || dest_t >= 0) {
             CT K[BB];
             if constexpr (!ELAS) {
                 CT acc = 0;
@@ -479,7 +511,29 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                         K[i * 3 + j] = v;
                     }
             }
-            if constexpr (STAGE) {
+            if constexpr (STAGE && SYM) {
+                // the staged slot takes whichever of the two is an upper
+                // block; when nodes a and b coincide both are, and the
+                // transpose goes straight to the workspace
+#pragma unroll
+                for (int c = 0; c < BB; ++c) sK[tid * BB + c] = dest >= 0 ? K[c] : K[(c % B) * B + c / B];
+                if (dest >= 0 && dest_t >= 0) {
+                    CT *dst = (CT *)A.contrib + dest_t * BB;
+#pragma unroll
+                    for (int c = 0; c < BB; ++c) dst[c] = K[(c % B) * B + c / B];
+                }
+            } else if constexpr (SYM) {
+                if (dest >= 0) {
+                    CT *dst = (CT *)A.contrib + dest * BB;
+#pragma unroll
+                    for (int c = 0; c < BB; ++c) dst[c] = K[c];
+                }
+                if (dest_t >= 0) {
+                    CT *dst = (CT *)A.contrib + dest_t * BB;
+#pragma unroll
+                    for (int c = 0; c < BB; ++c) dst[c] = K[(c % B) * B + c / B];
+                }
+            } else if constexpr (STAGE) {
                 sD[el * P + p] = (int32_t)dest;
 #pragma unroll
                 for (int c = 0; c < BB; ++c) sK[(el * P + p) * BB + c] = K[c];
@@ -537,9 +591,10 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     if constexpr (STAGE) {
         __syncthreads();
         CT *out = (CT *)A.contrib;
-        for (int idx = tid; idx < EPB * P * BB; idx += 256) {
+        for (int idx = tid; idx < EPB * PW * BB; idx += 256) {
             const int blk = idx / BB;
-            if (first + blk / P < A.n) out[(int64_t)sD[blk] * BB + (idx - blk * BB)] = sK[idx];
+            if (first + blk / PW < A.n && (!SYM || sD[blk] >= 0))
+                out[(int64_t)sD[blk] * BB + (idx - blk * BB)] = sK[idx];
         }
     }
 }

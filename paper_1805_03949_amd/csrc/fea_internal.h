@@ -106,6 +106,22 @@ struct fea_graph {
     // assembly (gev[c] before class c, gev[5] after the last)
     hipEvent_t gev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool gtimed = false;
+    // Upper-triangle row-owner layout (built by the first FEA_ROWSYM
+    // assembly): upart[k] = block k itself if col >= row, else the block at
+    // the transposed position; usptr[k] .. usptr[k+1] = the compacted
+    // workspace range of an upper block's contributions (inverse-map order);
+    // pudest = destination of every slot in type-sorted order, -1 for the
+    // slots of lower blocks (not computed). ulen = workspace slots.
+    int32_t *upart = nullptr;
+    int64_t *usptr = nullptr;
+    int32_t *pudest = nullptr;
+    int64_t ulen = 0;
+    // upper blocks in CSR order (nup of them) and, for each block, its
+    // lower partner (-1 for diagonal and lower blocks)
+    int32_t *ublk = nullptr;
+    int32_t *lpart = nullptr;
+    int64_t nup = 0;
+    bool sready = false;
     // lazily allocated workspaces of the scatter variants
     void *contrib = nullptr;
     size_t contrib_bytes = 0;
@@ -140,4 +156,10 @@ int gather_batch_build(GatherBatch **out, int n, fea_graph *const *graphs, const
 int gather_batch_assemble(const GatherBatch *gb, int model, bool nh, int precision, bool out_f32,
                           hipStream_t s, void *vals, void *rhs, int32_t *status);
 void gather_batch_destroy(GatherBatch *gb);
+}  // namespace fea
+
+namespace fea {
+// Builds the upper-triangle row-owner layout of a graph (graph.hip; blocks
+// on the stream).
+int sym_prepare(fea_graph *g, hipStream_t s);
 }  // namespace fea

@@ -226,6 +226,138 @@ __global__ void k_position_maps(int64_t n_elems, Bases bs, const int32_t *perm, 
     for (int p = 0; p < n * n; ++p) pd[p] = e2pos[m0 + p];
 }
 
+struct TmpBuf {
+    void *p = nullptr;
+    ~TmpBuf() { dfree(p); }
+};
+
+// ---------------------------------------------- upper-triangle row-owner
+// Block k = (i, j): its transposed partner (j, i) lies in row j (the
+// pattern is structurally symmetric); upper blocks (j >= i) are their own.
+__global__ void k_sym_partner(int64_t n_nodes, const int64_t *row_ptr, const int32_t *col,
+                              const int64_t *inv_ptr, int32_t *upart, int32_t *ulen)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        const int32_t j = col[k];
+        if (j >= i) {
+            upart[k] = (int32_t)k;
+            ulen[k] = (int32_t)(inv_ptr[k + 1] - inv_ptr[k]);
+        } else {
+            int64_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (col[mid] < i) lo = mid + 1;
+                else hi = mid;
+            }
+            upart[k] = (int32_t)lo;
+            ulen[k] = 0;
+        }
+    }
+}
+
+// Lower partner of every upper block (-1 if none), and the upper blocks
+// listed in CSR order (uoff = exclusive count of upper blocks before k).
+__global__ void k_sym_lists(int64_t nnz, const int32_t *upart, const int64_t *uoff, int32_t *lpart,
+                            int32_t *ublk)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    const int32_t u = upart[k];
+    if (u == k) ublk[uoff[k]] = (int32_t)k;
+    else lpart[u] = (int32_t)k;
+}
+
+__global__ void k_flag_upper(int64_t nnz, const int32_t *upart, int32_t *flag)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) flag[k] = upart[k] == k ? 1 : 0;
+}
+
+// Compacted workspace position of every slot of an upper block (the
+// block's inverse-map segment, in order); other slots keep -1.
+__global__ void k_sym_e2pos(int64_t n_nodes, const int64_t *row_ptr, const int32_t *col,
+                            const int64_t *inv_ptr, const int32_t *inv, const int64_t *usptr,
+                            int32_t *e2upos)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        if (col[k] < i) continue;
+        for (int64_t jj = inv_ptr[k]; jj < inv_ptr[k + 1]; ++jj)
+            e2upos[inv[jj]] = (int32_t)(usptr[k] + (jj - inv_ptr[k]));
+    }
+}
+
+__global__ void k_sym_position(int64_t n_elems, Bases bs, const int32_t *perm, const int64_t *map_ptr,
+                               const int32_t *e2upos, int32_t *pudest)
+{
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= n_elems) return;
+    int t = 0;
+    while (t < 3 && pos >= bs.seg[t + 1]) ++t;
+    const int n = nodes_of(t);
+    const int64_t i = pos - bs.seg[t];
+    const int64_t m0 = map_ptr[perm[pos]];
+    int32_t *pd = pudest + bs.slot[t] + i * n * n;
+    for (int p = 0; p < n * n; ++p) pd[p] = e2upos[m0 + p];
+}
+
+int sym_prepare(fea_graph *g, hipStream_t s)
+{
+    constexpr int BS = 256;
+    const int64_t N = g->n_nodes, E = g->n_elems, nnz = g->nnz;
+    int rc;
+    dfree(g->upart);
+    dfree(g->usptr);
+    dfree(g->pudest);
+    g->upart = nullptr;
+    g->usptr = nullptr;
+    g->pudest = nullptr;
+    TmpBuf ulen, tmp, e2upos;
+    if ((rc = dalloc((void **)&g->upart, sizeof(int32_t) * std::max<int64_t>(nnz, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->usptr, sizeof(int64_t) * (nnz + 1)))) return rc;
+    if ((rc = dalloc((void **)&g->pudest, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
+    if ((rc = dalloc(&ulen.p, sizeof(int32_t) * std::max<int64_t>(nnz, 1)))) return rc;
+    if ((rc = dalloc(&tmp.p, sizeof(int64_t) * (scan_tmp_elems(std::max<int64_t>(nnz, 1)) + 64)))) return rc;
+    if ((rc = dalloc(&e2upos.p, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
+    if (N) k_sym_partner<<<grid_for(N, BS), BS, 0, s>>>(N, g->row_ptr, g->col, g->inv_ptr, g->upart, (int32_t *)ulen.p);
+    if ((rc = scan_to_ptr_i32((int32_t *)ulen.p, nnz, g->usptr, (int64_t *)tmp.p, s))) return rc;
+    if (g->map_len) FEA_HIP(hipMemsetAsync(e2upos.p, 0xff, sizeof(int32_t) * g->map_len, s));
+    if (N) k_sym_e2pos<<<grid_for(N, BS), BS, 0, s>>>(N, g->row_ptr, g->col, g->inv_ptr, g->inv, g->usptr, (int32_t *)e2upos.p);
+    Bases bs;
+    for (int t = 0; t <= 4; ++t) {
+        bs.seg[t] = g->seg[t];
+        bs.node[t] = g->node_base[t];
+        bs.slot[t] = g->slot_base[t];
+    }
+    if (E) k_sym_position<<<grid_for(E, BS), BS, 0, s>>>(E, bs, g->perm, g->map_ptr, (int32_t *)e2upos.p, g->pudest);
+    // upper-block list and lower partners (the ulen buffer, already
+    // scanned into usptr, is reused for the upper-block flags)
+    dfree(g->ublk);
+    dfree(g->lpart);
+    g->ublk = nullptr;
+    g->lpart = nullptr;
+    g->nup = 0;
+    TmpBuf uoff;
+    if ((rc = dalloc(&uoff.p, sizeof(int64_t) * (nnz + 1)))) return rc;
+    if ((rc = dalloc((void **)&g->lpart, sizeof(int32_t) * std::max<int64_t>(nnz, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->ublk, sizeof(int32_t) * std::max<int64_t>(nnz, 1)))) return rc;
+    if (nnz) {
+        k_flag_upper<<<grid_for(nnz, BS), BS, 0, s>>>(nnz, g->upart, (int32_t *)ulen.p);
+        if ((rc = scan_to_ptr_i32((int32_t *)ulen.p, nnz, (int64_t *)uoff.p, (int64_t *)tmp.p, s))) return rc;
+        FEA_HIP(hipMemsetAsync(g->lpart, 0xff, sizeof(int32_t) * nnz, s));
+        k_sym_lists<<<grid_for(nnz, BS), BS, 0, s>>>(nnz, g->upart, (const int64_t *)uoff.p, g->lpart, g->ublk);
+        FEA_HIP(hipMemcpyAsync(&g->nup, (int64_t *)uoff.p + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    }
+    FEA_HIP(hipGetLastError());
+    FEA_HIP(hipMemcpyAsync(&g->ulen, g->usptr + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    g->sready = true;
+    return FEA_OK;
+}
+
 // ------------------------------------------------------------- colouring
 // Greedy first-fit in element order (the colouring of Algorithm 5; any
 // valid colouring is correct, this one is deterministic). Sequential by
@@ -291,7 +423,7 @@ static void destroy(fea_graph *g)
     if (!g) return;
     void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv, g->pnodes, g->pdest, g->prdest,
                     g->n2e_ptr, g->n2e, g->n2a, g->perm, g->colour, g->cperm,
-                    g->contrib, g->rcontrib, g->acc64, g->gtile, g->gnodes, g->gdesc};
+                    g->contrib, g->rcontrib, g->acc64, g->gtile, g->gnodes, g->gdesc, g->upart, g->usptr, g->pudest, g->ublk, g->lpart};
     for (void *b : bufs) dfree(b);
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);
@@ -300,10 +432,6 @@ static void destroy(fea_graph *g)
     delete g;
 }
 
-struct TmpBuf {
-    void *p = nullptr;
-    ~TmpBuf() { dfree(p); }
-};
 
 static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn_ptr,
                  const int32_t *conn, hipStream_t s, fea_graph *g)

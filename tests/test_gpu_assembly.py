@@ -81,7 +81,7 @@ def test_graph_bit_exact(name):
     assert np.array_equal(ex["colour"], oc)
 
 
-VARIANTS = [fea.ROWOWNER, fea.ATOMIC, fea.COLOUR, fea.ROWGATHER]
+VARIANTS = [fea.ROWOWNER, fea.ATOMIC, fea.COLOUR, fea.ROWGATHER, fea.ROWSYM]
 
 
 def _nh(name, model, variant):
@@ -125,7 +125,7 @@ def test_mixed_within_fp32_bound(name, variant):
         assert rv <= 1.0 and rr <= 1.0, (out, rv, rr)
 
 
-@pytest.mark.parametrize("variant", [fea.ROWOWNER, fea.COLOUR, fea.ROWGATHER])
+@pytest.mark.parametrize("variant", [fea.ROWOWNER, fea.COLOUR, fea.ROWGATHER, fea.ROWSYM])
 def test_deterministic_variants_bitwise_repeatable(variant):
     m, og, dm, g = case("mix6_jitter")
     first = None
@@ -268,7 +268,7 @@ def test_rowgather_rejects_node_in_too_many_elements():
     assert ei.value.code == fea.FEA_ERANGE and "node 0 " in ei.value.msg
 
 
-@pytest.mark.parametrize("variant", [fea.ROWGATHER, fea.ROWOWNER])
+@pytest.mark.parametrize("variant", [fea.ROWGATHER, fea.ROWOWNER, fea.ROWSYM])
 def test_assembly_captured_in_a_graph_replays_eager_result(variant):
     """After its first call (tile or workspace set-up), an assembly
     allocates, synchronises and clears nothing, so a caller can capture it
@@ -298,3 +298,39 @@ def test_assembly_captured_in_a_graph_replays_eager_result(variant):
         assert int(st.item()) == -1
         assert vals.cpu().numpy().tobytes() == ref[0].tobytes()
         assert rhs.cpu().numpy().tobytes() == ref[1].tobytes()
+
+
+@pytest.mark.parametrize("name", ["bands8_jitter", "mix6_jitter", "tet_ragged", "hetero16", "poisson_hex16"])
+def test_rowsym_is_exactly_symmetric_and_matches_rowowner(name):
+    """The upper-triangle form writes block (j, i) as the transpose of the
+    ordered sum of block (i, j): A equals its transpose bitwise, and it
+    differs from the row-owner result only by the rounding of the lower
+    blocks' own products."""
+    m, og, dm, g = case(name)
+    model = fea.POISSON if name == "poisson_hex16" else fea.ELASTIC
+    nh = name == "hetero16"
+    B = 1 if model == fea.POISSON else 3
+    ex = g.export()
+    row_ptr, col = ex["row_ptr"].cpu().numpy(), ex["col"].cpu().numpy()
+    rows = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
+    # position of every block's transpose
+    key = rows.astype(np.int64) * (len(row_ptr)) + col
+    tkey = col.astype(np.int64) * (len(row_ptr)) + rows
+    order = np.argsort(key)
+    tpos = order[np.searchsorted(key[order], tkey)]
+    for prec, out in ((fea.FP64, fea.F64), (fea.MIXED, fea.F32)):
+        a = dm.assemble(g, model=model, use_nh=nh, variant=fea.ROWOWNER, precision=prec, out_dtype=out)
+        b = dm.assemble(g, model=model, use_nh=nh, variant=fea.ROWSYM, precision=prec, out_dtype=out)
+        torch.cuda.synchronize()
+        va = a[0].cpu().numpy().astype(np.float64).reshape(-1, B, B)
+        vb = b[0].cpu().numpy().reshape(-1, B, B)
+        # off-diagonal blocks: (j, i) is (i, j) transposed, bitwise; a diagonal
+        # block is its own partner, symmetric up to its elements' rounding
+        off = rows != col
+        assert vb[off].tobytes() == np.ascontiguousarray(vb[tpos][off].transpose(0, 2, 1)).tobytes()
+        vd = vb[~off].astype(np.float64)
+        assert np.abs(vd - vd.transpose(0, 2, 1)).max() <= 1e-6 * np.abs(vd).max()
+        assert b[1].cpu().numpy().tobytes() == a[1].cpu().numpy().tobytes()
+        tol = 1e-14 if prec == fea.FP64 else 1e-6
+        scale = np.abs(va).max()
+        assert np.abs(vb.astype(np.float64) - va).max() <= tol * scale, prec
