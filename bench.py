@@ -38,6 +38,32 @@ def reduce_bytes(g, B, s_c, s_v):
     return g.map_len * B * B * s_c + (g.nnz + 1) * 8 + g.nnz * B * B * s_v
 
 
+def sym_counts(mesh, nnz, np):
+    """(upper-triangle slots, upper and diagonal blocks) of the symmetric
+    row-owner form: per element the local pairs (a, b) with node(a) <=
+    node(b), and the blocks (i, j) with i <= j of the symmetric pattern
+    (half the off-diagonal blocks plus one diagonal block per node that
+    some element uses)."""
+    ulen = 0
+    for t in range(4):
+        idx = np.nonzero(mesh.types == t)[0]
+        if idx.size == 0:
+            continue
+        n = NODES[t]
+        c = mesh.conn[mesh.conn_ptr[idx][:, None] + np.arange(n)[None, :]]
+        ulen += int((c[:, :, None] <= c[:, None, :]).sum())
+    n_used = int(np.unique(mesh.conn).size)
+    return ulen, (nnz + n_used) // 2
+
+
+def sym_reduce_bytes(ulen, nup, nnz, B, s_c, s_v):
+    """Algorithmic bytes of one launch of the upper-triangle block-value
+    kernel: every upper-slot contribution read once, per upper block its
+    segment bound (int64), its block index and its lower partner (int32),
+    every block value (upper and transposed lower) written once."""
+    return ulen * B * B * s_c + (nup + 1) * 8 + nup * 8 + nnz * B * B * s_v
+
+
 def scatter_bytes(g, B, s_c, s_v, conn_len, n_nodes):
     """Algorithmic bytes of the whole scatter (matrix and right-hand side):
     reduce_bytes plus the right-hand-side contributions, node segment
@@ -45,14 +71,17 @@ def scatter_bytes(g, B, s_c, s_v, conn_len, n_nodes):
     return reduce_bytes(g, B, s_c, s_v) + conn_len * B * s_c + (n_nodes + 1) * 8 + n_nodes * B * s_v
 
 
-def element_bytes(g, B, s_c, s_v, conn_len, n_nodes, n_elems, variant):
+def element_bytes(g, B, s_c, s_v, conn_len, n_nodes, n_elems, variant, ulen=0):
     """Algorithmic bytes of the element phase: node coordinates once, the
     connectivity and per-element data once, and its outputs once (the slot
-    contributions for row-owner; for row-gather the final values, plus the
-    pair-ordered node lists, lane bytes and segment bounds it reads)."""
+    contributions for row-owner, the upper-triangle slots (ulen) for its
+    symmetric form; for row-gather the final values, plus the pair-ordered
+    node lists, lane bytes and segment bounds it reads)."""
     inputs = n_nodes * 24 + conn_len * 4 + n_elems * (8 + 4 + 8 + 16 + 8 * B)
     if variant == "rowowner":
         return inputs + g.map_len * B * B * s_c + conn_len * B * s_c
+    if variant == "rowsym":
+        return inputs + ulen * B * B * s_c + conn_len * B * s_c
     if variant == "rowgather":
         maps = g.map_len * (4 + 1) + conn_len * 5 + (g.nnz + 1) * 8 + (n_nodes + 1) * 8
         return inputs + maps + g.nnz * B * B * s_v + n_nodes * B * s_v
@@ -247,20 +276,22 @@ def large_workload(fea, mg, torch, np, cells=256):
     b.destroy()
     torch.cuda.empty_cache()
 
-    # the same mesh through the fused row-gather form (no workspace)
+    # the same mesh through the fused row-gather form (no workspace) and the
+    # upper-triangle row-owner form
     g = dm.graph()
-    for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
-        vals, rhs, st = dm.assemble(g, variant=fea.ROWGATHER, precision=p, out_dtype=o)
-        tot = []
-        for _ in range(5):
-            dm.assemble(g, variant=fea.ROWGATHER, precision=p, out_dtype=o, vals=vals, rhs=rhs, status=st,
-                        timing=True)
-            tot.append(g.last_timing()[2])
-        ok = int(st.item()) == -1
-        out[f"rowgather_{pname}"] = {"total_ms": round(float(np.median(tot)), 3),
-                                    "elements_per_s": round(mesh.n_elems / (float(np.median(tot)) * 1e-3), 1),
-                                    "status_ok": ok}
-        del vals, rhs, st
+    for vname in ("rowgather", "rowsym"):
+        for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
+            var = fea.VARIANTS[vname]
+            vals, rhs, st = dm.assemble(g, variant=var, precision=p, out_dtype=o)
+            tot = []
+            for _ in range(5):
+                dm.assemble(g, variant=var, precision=p, out_dtype=o, vals=vals, rhs=rhs, status=st, timing=True)
+                tot.append(g.last_timing()[2])
+            ok = int(st.item()) == -1
+            out[f"{vname}_{pname}"] = {"total_ms": round(float(np.median(tot)), 3),
+                                       "elements_per_s": round(mesh.n_elems / (float(np.median(tot)) * 1e-3), 1),
+                                       "status_ok": ok}
+            del vals, rhs, st
     g.destroy()
     return out
 
@@ -358,18 +389,21 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
     d = (vl.double() - v64).norm() / v64.norm()
     out["mixed_vs_fp64_rel_frobenius"] = float(d.item())
     out["status_ok"] = bool((st64.cpu() == -1).all()) and bool((stl.cpu() == -1).all())
-    # the same mesh (neo-Hookean bricks included) in the row-gather form
+    # the same mesh (neo-Hookean bricks included) in the row-gather and
+    # upper-triangle row-owner forms
     g = dm.graph()
-    for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
-        gv, gr, gs = dm.assemble(g, variant=fea.ROWGATHER, use_nh=True, precision=p, out_dtype=o)
-        tot = []
-        for _ in range(5):
-            dm.assemble(g, variant=fea.ROWGATHER, use_nh=True, precision=p, out_dtype=o, vals=gv, rhs=gr,
-                        status=gs, timing=True)
-            tot.append(g.last_timing()[2])
-        out[f"rowgather_{pname}"] = {"total_ms": round(float(np.median(tot)), 4),
-                                     "status_ok": int(gs.item()) == -1}
-        del gv, gr, gs
+    for vname in ("rowgather", "rowsym"):
+        var = fea.VARIANTS[vname]
+        for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
+            gv, gr, gs = dm.assemble(g, variant=var, use_nh=True, precision=p, out_dtype=o)
+            tot = []
+            for _ in range(5):
+                dm.assemble(g, variant=var, use_nh=True, precision=p, out_dtype=o, vals=gv, rhs=gr,
+                            status=gs, timing=True)
+                tot.append(g.last_timing()[2])
+            out[f"{vname}_{pname}"] = {"total_ms": round(float(np.median(tot)), 4),
+                                       "status_ok": int(gs.item()) == -1}
+            del gv, gr, gs
     g.destroy()
     return out
 
@@ -458,7 +492,8 @@ def main():
             classes.append(g.last_class_timing())
     ph = np.median(np.array(phases), axis=0)
     elem_ms, second_ms = float(ph[0]), float(ph[1])
-    eb = element_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes, mesh.n_elems, args.variant)
+    ulen, nup = sym_counts(mesh, g.nnz, np)
+    eb = element_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes, mesh.n_elems, args.variant, ulen)
     sb = scatter_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes)
     copy_gbps = copy_bandwidth(torch)
     class_ms = None
@@ -481,12 +516,16 @@ def main():
                     "note": "algorithmic: per-element element-matrix flops exploiting the sparsity of B, "
                             "1/n of an element per (row, element) pair; executed: the kernel's own "
                             "operations, geometry recomputed per pair"}
-    elif args.variant == "rowowner":
-        kernel, k_ms, k_bytes = "k_reduce_seg<9>", second_ms, reduce_bytes(g, B, s_c, s_v)
+    elif args.variant in ("rowowner", "rowsym"):
+        if args.variant == "rowowner":
+            kernel, k_bytes = "k_segsum<9>", reduce_bytes(g, B, s_c, s_v)
+        else:
+            kernel, k_bytes = "k_segsum<9,sym>", sym_reduce_bytes(ulen, nup, g.nnz, B, s_c, s_v)
+        k_ms = second_ms
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                    "traffic": traffic_from_profile(kernel, "assemble.hip"),
+                    "traffic": traffic_from_profile(kernel + ("" if prec == fea.FP64 else ",mixed"), "segsum.h"),
                     "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4),
                     "copy_GBps": copy_gbps, "frac_of_copy": round(achieved / copy_gbps, 4)}
     else:
@@ -498,7 +537,7 @@ def main():
 
     variants = {}
     if not args.no_variants:
-        for vname in ("rowgather", "rowowner", "atomic", "colour"):
+        for vname in ("rowgather", "rowsym", "rowowner", "atomic", "colour"):
             for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
                 vv, rr, ss = dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o)
                 dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o, vals=vv, rhs=rr, status=ss)
@@ -514,14 +553,18 @@ def main():
                                                 "elements_per_s": round(mesh.n_elems / (float(med[2]) * 1e-3), 1)}
                 del vv, rr, ss
         torch.cuda.synchronize()
-        ro = variants["rowowner_fp64"]
-        rb = reduce_bytes(g, B, 8, 8)
-        ra = rb / (ro["block_value_kernel_ms"] * 1e-3) / 1e9
-        variants["rowowner_fp64"]["roofline"] = {
-            "bound": "hbm", "kernel": "k_reduce_seg<9>", "achieved": round(ra, 1), "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": round(ra / PEAK_HBM_GBS, 4),
-            "traffic": traffic_from_profile("k_reduce_seg<9>", "assemble.hip"),
-            "algorithmic_bytes": int(rb), "copy_GBps": copy_gbps, "frac_of_copy": round(ra / copy_gbps, 4)}
+        # HBM rooflines of the block-value kernels of the two-phase forms
+        for vkey, kname, sc in (("rowowner_fp64", "k_segsum<9>", 8), ("rowowner_mixed", "k_segsum<9>,mixed", 4),
+                                ("rowsym_fp64", "k_segsum<9,sym>", 8), ("rowsym_mixed", "k_segsum<9,sym>,mixed", 4)):
+            ro = variants[vkey]
+            rb = (reduce_bytes(g, B, sc, sc) if vkey.startswith("rowowner")
+                  else sym_reduce_bytes(ulen, nup, g.nnz, B, sc, sc))
+            ra = rb / (ro["block_value_kernel_ms"] * 1e-3) / 1e9
+            variants[vkey]["roofline"] = {
+                "bound": "hbm", "kernel": kname, "achieved": round(ra, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(ra / PEAK_HBM_GBS, 4),
+                "traffic": traffic_from_profile(kname, "segsum.h"),
+                "algorithmic_bytes": int(rb), "copy_GBps": copy_gbps, "frac_of_copy": round(ra / copy_gbps, 4)}
 
     extras = {}
     if not args.no_extras:
@@ -566,7 +609,7 @@ def main():
         eff = sb / (t2 * 1e-3) / 1e9
         scatter.update({"effective_GBps": round(eff, 1), "frac_of_peak": round(eff / PEAK_HBM_GBS, 4),
                         "frac_of_copy": round(eff / copy_gbps, 4), "ms": round(t2, 4)})
-    tr = traffic_from_profile("k_reduce_seg<9>", "assemble.hip")
+    tr = traffic_from_profile("k_segsum<9>", "segsum.h")
     if tr and t2:
         scatter["counter_GBps_block_values"] = round(tr / (variants.get("rowowner_fp64", {}).get(
             "block_value_kernel_ms", t2) * 1e-3) / 1e9, 1)

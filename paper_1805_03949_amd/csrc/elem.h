@@ -248,7 +248,8 @@ struct ElemSmem {
     double sU[EU][NN][3];
     CT sG[EPB][NQ][NN][3];   // physical gradients
     CT sH[EU][NQ][NN][3];    // neo-Hookean: gradients pushed through F^-T
-    CT sC[EPB][NQ][4];       // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
+    static constexpr int NC = NHK ? 4 : 1;
+    CT sC[EPB][NQ][NC];      // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
     double sLM[ELAS ? EPB : 1][2];  // lam, mu of every element (elasticity)
     int32_t sE[EPB];
     int sNH[EPB];
@@ -256,8 +257,9 @@ struct ElemSmem {
     int64_t sCP[EPB];        // first conn position of each element
     // Row-owner stores staged in LDS so that BB consecutive threads write one
     // block's BB contiguous values. Measured per family on MI355X: a gain
-    // everywhere except FP64 pyramids, where the extra LDS halves occupancy.
-    static constexpr bool STAGE = RO && (sizeof(CT) == 4 || T != 1 || !NHK);
+    // everywhere except FP64 pyramids of the neo-Hookean and upper-triangle
+    // kernels, where the extra LDS costs more occupancy than it saves.
+    static constexpr bool STAGE = RO && (sizeof(CT) == 4 || T != 1 || (!NHK && VAR != V_ROWSYM));
     CT sK[STAGE ? EPB * PW * BB : 1];
     int32_t sD[STAGE ? EPB * PW : 1];
     double sDN[NQ][NN][3];   // reference gradients of this family

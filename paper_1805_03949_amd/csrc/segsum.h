@@ -11,61 +11,105 @@ namespace fea {
 
 // Segment k of the workspace holds the W-value contributions to output k in
 // ascending element order, segments back to back: ptr[k] .. ptr[k+1] (in
-// slots of W values). The n segments of a workgroup therefore form one
-// contiguous range, which the workgroup streams into LDS with coalesced
-// loads, a chunk at a time; each thread then adds one (segment, component)
-// from LDS in ascending order, starting from 0, in FP64. The sums are
-// bitwise those of a plain left-to-right loop over the segment.
+// slots of W values). The segments of a workgroup therefore form one
+// contiguous range, which the workgroup streams into LDS a chunk at a time
+// with coalesced loads of up to 16 bytes (data must be 16-byte aligned, as
+// every device allocation is); each thread then adds its (segment,
+// component) pairs, one per round, from LDS in ascending order, starting
+// from 0, in FP64. The sums are bitwise those of a plain left-to-right loop over the
+// segment.
 //
 // SYM: the upper-triangle form. Output m is block blk[m] (an upper or
 // diagonal block; the segments of all other blocks are empty, so the
 // segments of consecutive m are still adjacent), and the sum is also
 // written, transposed, to block lpart[blk[m]] when that is >= 0 (block
 // (j, i) of a symmetric matrix is block (i, j) transposed).
+// Launch shape per workspace type: bytes per load, rounds (segments per
+// thread) and LDS bytes per chunk. Measured on MI355X over the hybrid96
+// workspaces: FP64 streams best with 8-byte loads and one segment per
+// thread; FP32 segments are half as long, and 16-byte loads with four
+// segments per thread amortise the per-workgroup work (about 15% faster than
+// one 4-byte load per segment and thread).
+template <typename CT>
+struct SegCfg {
+    static constexpr int LOAD_BYTES = sizeof(CT) == 8 ? 8 : 16;
+    static constexpr int ROUNDS = sizeof(CT) == 8 ? 1 : 4;
+    static constexpr int CHUNK_BYTES = 16384;
+};
+
 template <int W, typename CT, typename OT, bool SYM>
 __global__ void __launch_bounds__(256) k_segsum(int64_t n, const int32_t *blk, const int32_t *lpart,
                                                 const int64_t *ptr, const CT *data, OT *out)
 {
-    constexpr int BPW = 256 / W;        // segments per workgroup
-    constexpr int LD = 8;               // loads per thread per chunk
-    constexpr int CAPS = 256 * LD / W;  // slots per chunk
-    __shared__ CT sv[CAPS * W];
+    constexpr int TPS = 256 / W;                // segments per round
+    constexpr int R = SegCfg<CT>::ROUNDS;       // rounds per workgroup
+    constexpr int BPW = TPS * R;                // segments per workgroup
+    constexpr int VEC = SegCfg<CT>::LOAD_BYTES / (int)sizeof(CT);  // values per load
+    constexpr int CAPV = SegCfg<CT>::CHUNK_BYTES / (int)sizeof(CT);  // staged values per chunk
+    constexpr int LV = CAPV / (256 * VEC);                    // loads per thread per chunk
+    constexpr int CAPS = (CAPV - VEC) / W;      // slots per chunk (room for the alignment shift)
+    struct alignas(VEC * sizeof(CT)) Vec {
+        CT x[VEC];
+    };
+    __shared__ Vec sv[CAPV / VEC];
+    const CT *svs = sv[0].x;
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * BPW;
     const int64_t mend = m0 + BPW < n ? m0 + BPW : n;
     const int lb = tid / W, c = tid - lb * W;
-    const int64_t m = m0 + lb;
-    const bool act = lb < BPW && m < mend;
-    const int64_t k = act ? (SYM ? (int64_t)blk[m] : m) : 0;
-    const int64_t j0 = act ? ptr[k] : 0, j1 = act ? ptr[k + 1] : 0;
+    int64_t k[R], j0[R], j1[R];
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t m = m0 + lb + r * TPS;
+        const bool act = lb < TPS && m < mend;
+        k[r] = act ? (SYM ? (int64_t)blk[m] : m) : -1;
+        j0[r] = act ? ptr[k[r]] : 0;
+        j1[r] = act ? ptr[k[r] + 1] : 0;
+        acc[r] = 0.0;
+    }
     const int64_t s0 = ptr[SYM ? (int64_t)blk[m0] : m0];
     const int64_t s1 = ptr[(SYM ? (int64_t)blk[mend - 1] : mend - 1) + 1];
-    double acc = 0.0;
     for (int64_t base = s0; base < s1; base += CAPS) {
-        const int ns = (int)(s1 - base < CAPS ? s1 - base : CAPS);
-        const int nv = ns * W;
-        const CT *src = data + base * W;
-        CT r[LD];
+        const int64_t ns = s1 - base < CAPS ? s1 - base : CAPS;
+        const int64_t f0 = base * W, f1 = f0 + ns * W;  // value range of this chunk
+        const int64_t a0 = f0 & ~(int64_t)(VEC - 1);      // aligned start
+        const int o = (int)(f0 - a0);
+        const int nvec = (int)((f1 - a0 + VEC - 1) / VEC);
+        Vec v[LV];
 #pragma unroll
-        for (int q = 0; q < LD; ++q) {
+        for (int q = 0; q < LV; ++q) {
             const int i = tid + q * 256;
-            r[q] = i < nv ? src[i] : (CT)0;
+            const int64_t g = a0 + (int64_t)i * VEC;
+            if (i < nvec && g >= f0 && g + VEC <= f1) {
+                v[q] = *reinterpret_cast<const Vec *>(data + g);
+            } else {
+                // the partial vectors at the two ends of the range
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    v[q].x[e] = (i < nvec && g + e >= f0 && g + e < f1) ? data[g + e] : (CT)0;
+            }
         }
         __syncthreads();  // the previous chunk's readers are done
 #pragma unroll
-        for (int q = 0; q < LD; ++q) {
+        for (int q = 0; q < LV; ++q) {
             const int i = tid + q * 256;
-            if (i < nv) sv[i] = r[q];
+            if (i < nvec) sv[i] = v[q];
         }
         __syncthreads();
-        const int64_t lo = j0 > base ? j0 : base, hi = j1 < base + ns ? j1 : base + ns;
-        for (int64_t j = lo; j < hi; ++j) acc += (double)sv[(j - base) * W + c];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t lo = j0[r] > base ? j0[r] : base, hi = j1[r] < base + ns ? j1[r] : base + ns;
+            for (int64_t j = lo; j < hi; ++j) acc[r] += (double)svs[o + (j - base) * W + c];
+        }
     }
-    if (act) {
-        out[k * W + c] = (OT)acc;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (k[r] < 0) continue;
+        out[k[r] * W + c] = (OT)acc[r];
         if constexpr (SYM) {
-            const int64_t l = lpart[k];
-            if (l >= 0) out[l * W + (W == 9 ? (c % 3) * 3 + c / 3 : c)] = (OT)acc;
+            const int64_t l = lpart[k[r]];
+            if (l >= 0) out[l * W + (W == 9 ? (c % 3) * 3 + c / 3 : c)] = (OT)acc[r];
         }
     }
 }
@@ -75,7 +119,7 @@ template <int W, typename CT, typename OT, bool SYM>
 inline void launch_segsum(int64_t n, const int32_t *blk, const int32_t *lpart, const int64_t *ptr,
                           const CT *data, OT *out, hipStream_t s)
 {
-    constexpr int BPW = 256 / W;
+    constexpr int BPW = (256 / W) * SegCfg<CT>::ROUNDS;
     const unsigned grid = (unsigned)((n + BPW - 1) / BPW);
     k_segsum<W, CT, OT, SYM><<<grid, 256, 0, s>>>(n, blk, lpart, ptr, data, out);
 }

@@ -31,3 +31,30 @@ def test_reduce_bytes_definition():
         map_len, nnz = 84_492_288, 22_156_129
     b = bench.reduce_bytes(G, 3, 8, 8)
     assert b == 84_492_288 * 72 + (22_156_129 + 1) * 8 + 22_156_129 * 72
+
+
+def _pattern(m):
+    """Brute-force block pattern and upper-triangle slot count."""
+    blocks, ulen = set(), 0
+    for e in range(m.n_elems):
+        nodes = m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]]
+        for a in nodes:
+            for b in nodes:
+                blocks.add((int(a), int(b)))
+                ulen += int(a <= b)
+    return blocks, ulen
+
+
+def test_sym_counts_match_brute_force():
+    m = mg.hybrid_bands(4, seed=2)
+    blocks, ulen = _pattern(m)
+    u, nup = bench.sym_counts(m, len(blocks), np)
+    assert u == ulen
+    assert nup == sum(1 for (i, j) in blocks if i <= j)
+    # distinct nodes per element: n(n+1)/2 upper pairs each
+    assert u == sum(bench.NODES[t] * (bench.NODES[t] + 1) // 2 for t in m.types)
+
+
+def test_sym_reduce_bytes_definition():
+    b = bench.sym_reduce_bytes(100, 10, 15, 3, 4, 8)
+    assert b == 100 * 9 * 4 + 11 * 8 + 10 * 8 + 15 * 9 * 8

@@ -46,14 +46,15 @@ def test_hybrid96_rowowner_fp64_and_mixed_sampled_rows():
     torch.cuda.synchronize()
     L = fp32_bound_L(mesh.types)
     assert check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L) <= 1.0
-    for variant in (fea.ATOMIC, fea.COLOUR, fea.ROWGATHER):
+    for variant in (fea.ATOMIC, fea.COLOUR, fea.ROWGATHER, fea.ROWSYM):
         v, r, st = dm.assemble(g, variant=variant)
         torch.cuda.synchronize()
         assert int(st.item()) == -1
         assert check_rows(mesh, rows, row_ptr, col, v, r, 3) <= 1e-12
-    v, r, _ = dm.assemble(g, variant=fea.ROWGATHER, precision=fea.MIXED, out_dtype=fea.F32)
-    torch.cuda.synchronize()
-    assert check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L) <= 1.0
+    for variant in (fea.ROWGATHER, fea.ROWSYM):
+        v, r, _ = dm.assemble(g, variant=variant, precision=fea.MIXED, out_dtype=fea.F32)
+        torch.cuda.synchronize()
+        assert check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L) <= 1.0
 
 
 def _batch_rows_check(mesh, b, precisions, seed, k=200):
@@ -92,15 +93,18 @@ def test_hetero128_batched_sampled_rows_with_neo_hookean():
     v, r, _ = b.assemble()
     torch.cuda.synchronize()
     assert check_rows(mesh, rows, row_ptr, col, v, r, 3) <= 1e-12
-    # the same rows through the row-gather form (one mesh, neo-Hookean bricks)
-    for prec in (fea.FP64, fea.MIXED):
-        outd = fea.F64 if prec == fea.FP64 else fea.F32
-        v, r, st = dm.assemble(gr, variant=fea.ROWGATHER, use_nh=True, precision=prec, out_dtype=outd)
-        torch.cuda.synchronize()
-        assert int(st.item()) == -1
-        L = None if prec == fea.FP64 else fp32_bound_L(mesh.types)
-        worst = check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L)
-        assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (prec, worst)
+    # the same rows through the row-gather and upper-triangle forms (one
+    # mesh, neo-Hookean bricks)
+    for variant in (fea.ROWGATHER, fea.ROWSYM):
+        for prec in (fea.FP64, fea.MIXED):
+            outd = fea.F64 if prec == fea.FP64 else fea.F32
+            v, r, st = dm.assemble(gr, variant=variant, use_nh=True, precision=prec, out_dtype=outd)
+            torch.cuda.synchronize()
+            assert int(st.item()) == -1
+            L = None if prec == fea.FP64 else fp32_bound_L(mesh.types)
+            worst = check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L)
+            assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (variant, prec, worst)
+            del v, r
 
 
 def test_hybrid256_batched_sampled_rows():
@@ -122,13 +126,14 @@ def test_hybrid256_batched_sampled_rows():
     ex = g.export()
     row_ptr, col = ex["row_ptr"].cpu().numpy(), ex["col"].cpu().numpy()
     del ex
-    for prec in (fea.FP64, fea.MIXED):
-        outd = fea.F64 if prec == fea.FP64 else fea.F32
-        print(f"[case] hybrid256 row-gather precision {prec}", flush=True)
-        v, r, st = dm.assemble(g, variant=fea.ROWGATHER, precision=prec, out_dtype=outd)
-        torch.cuda.synchronize()
-        assert int(st.item()) == -1
-        L = None if prec == fea.FP64 else fp32_bound_L(mesh.types)
-        worst = check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L)
-        assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (prec, worst)
-        del v, r
+    for variant in (fea.ROWGATHER, fea.ROWSYM):
+        for prec in (fea.FP64, fea.MIXED):
+            outd = fea.F64 if prec == fea.FP64 else fea.F32
+            print(f"[case] hybrid256 variant {variant} precision {prec}", flush=True)
+            v, r, st = dm.assemble(g, variant=variant, precision=prec, out_dtype=outd)
+            torch.cuda.synchronize()
+            assert int(st.item()) == -1
+            L = None if prec == fea.FP64 else fp32_bound_L(mesh.types)
+            worst = check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L)
+            assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (variant, prec, worst)
+            del v, r
