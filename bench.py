@@ -10,7 +10,7 @@ z-bands of 24 cell layers (hex8 / pen6 / tet4 / pyr5), E = 1, nu per element
 U[0.2, 0.35], body force (0, 0, -1); 3,317,760 elements, 1,133,857 nodes.
 
 Prints one JSON line. Usage:
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--variant rowgather]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--variant rowsym]
                   [--precision fp64|mixed] [--no-cpu] [--no-variants]
 """
 from __future__ import annotations
@@ -414,7 +414,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cells", type=int, default=96)
-    ap.add_argument("--variant", default="rowgather")
+    ap.add_argument("--variant", default="rowsym")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
