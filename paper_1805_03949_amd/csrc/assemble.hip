@@ -92,22 +92,26 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         if ((rc = ensure_ws(&g->rcontrib, &g->rcontrib_bytes, sizeof(CT) * (size_t)g->conn_len * B))) return rc;
         a.contrib = g->contrib;
         a.rcontrib = g->rcontrib;
+        a.tent = g->tent;
+        a.tb_eend = g->tb_eend;
+        a.tb_slot = g->tb_slot;
         mark(g, 0, o, s);
         for (int t = 0; t < 4; ++t) {
             a.elems = g->perm + g->seg[t];
             a.n = g->seg[t + 1] - g->seg[t];
             a.pnodes = g->pnodes + g->node_base[t];
             a.prdest = g->prdest + g->node_base[t];
-            a.pdest = g->pudest + g->slot_base[t];
+            a.tent_ptr = g->tent_ptr + g->tile_base[t];
+            a.ttb_ptr = g->ttb_ptr + g->tile_base[t];
             launch_type<MODEL, V_ROWSYM, CT>(t, a, s);
         }
         mark(g, 1, o, s);
         if (f32) {
-            if (g->nup) launch_segsum<BB, CT, float, true>(g->nup, g->ublk, g->lpart, g->usptr, (const CT *)g->contrib, (float *)vals, s);
+            if (g->nup) launch_segsum<BB, CT, float, true>(g->nup, g->ublk, g->lpart, g->ts_ptr, (const CT *)g->contrib, (float *)vals, s);
             mark(g, 2, o, s);
             if (nr) launch_segsum<B, CT, float, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
         } else {
-            if (g->nup) launch_segsum<BB, CT, double, true>(g->nup, g->ublk, g->lpart, g->usptr, (const CT *)g->contrib, (double *)vals, s);
+            if (g->nup) launch_segsum<BB, CT, double, true>(g->nup, g->ublk, g->lpart, g->ts_ptr, (const CT *)g->contrib, (double *)vals, s);
             mark(g, 2, o, s);
             if (nr) launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
         }

@@ -174,14 +174,23 @@ struct ElemArgs {
     void *contrib;   // ROWOWNER slot workspace (compute type)
     void *rcontrib;  // ROWOWNER right-hand-side workspace
     int32_t *status;
+    // upper-triangle form, indexed by the launch-local tile index: entry and
+    // tile-block ranges, entries (lane << 1 | transposed), tile-block entry
+    // ends and workspace slots
+    const int64_t *tent_ptr;
+    const int64_t *ttb_ptr;
+    const uint16_t *tent;
+    const uint16_t *tb_eend;
+    const int32_t *tb_slot;
 };
 
-// V_ROWSYM: the row-owner layout restricted to the slots of upper blocks
-// (destination -1 elsewhere). A symmetric element matrix has block (b, a)
-// equal to block (a, b) transposed, so one thread per local pair a <= b
-// computes block (a, b) and stores it, or its transpose, in whichever of
-// the two slots belongs to an upper block (both when nodes a and b
-// coincide); the reduction forms lower blocks as transposes.
+// V_ROWSYM: the row-owner scatter on the upper triangle. A symmetric
+// element matrix has block (b, a) equal to block (a, b) transposed, so one
+// thread per local pair a <= b computes block (a, b); the workgroup's tile
+// of elements then sums, per distinct upper block it touches, its lanes'
+// blocks (transposed where node a > node b) in ascending lane order and
+// writes one value per (tile, block) to the workspace; the reduction adds
+// the tile sums of each upper block and writes lower blocks as transposes.
 enum { V_ROWOWNER = 0, V_ATOMIC = 1, V_COLOUR = 2, V_ROWSYM = 3 };
 
 // Kernel model codes: FEA_POISSON, FEA_ELASTIC (linear elements only) and
@@ -244,10 +253,10 @@ struct ElemSmem {
     static constexpr int EU = NHK ? EPB : 1;
     static constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM;
 
+    static constexpr bool SYM = VAR == V_ROWSYM;
+    static_assert(!SYM || EPB == sym_epb(T), "tile size of the upper-triangle layout");
     double sX[EPB][NN][3];
     double sU[EU][NN][3];
-    CT sG[EPB][NQ][NN][3];   // physical gradients
-    CT sH[EU][NQ][NN][3];    // neo-Hookean: gradients pushed through F^-T
     static constexpr int NC = NHK ? 4 : 1;
     CT sC[EPB][NQ][NC];      // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
     double sLM[ELAS ? EPB : 1][2];  // lam, mu of every element (elasticity)
@@ -257,11 +266,20 @@ struct ElemSmem {
     int64_t sCP[EPB];        // first conn position of each element
     // Row-owner stores staged in LDS so that BB consecutive threads write one
     // block's BB contiguous values. Measured per family on MI355X: a gain
-    // everywhere except FP64 pyramids of the neo-Hookean and upper-triangle
-    // kernels, where the extra LDS costs more occupancy than it saves.
-    static constexpr bool STAGE = RO && (sizeof(CT) == 4 || T != 1 || (!NHK && VAR != V_ROWSYM));
-    CT sK[STAGE ? EPB * PW * BB : 1];
-    int32_t sD[STAGE ? EPB * PW : 1];
+    // everywhere except FP64 pyramids of the neo-Hookean kernel, where the
+    // extra LDS costs more occupancy than it saves. The upper-triangle form
+    // always stages (its tile sums read the staged blocks).
+    static constexpr bool STAGE = RO && (SYM || sizeof(CT) == 4 || T != 1 || !NHK);
+    // physical gradients sG[EPB][NQ][NN][3], neo-Hookean gradients pushed
+    // through F^-T sH[EU][NQ][NN][3], staged blocks sK[EPB * PW * BB]; in the
+    // upper-triangle form the blocks overwrite the gradients once every lane
+    // has read them
+    static constexpr int NG = EPB * NQ * NN * 3, NHG = EU * NQ * NN * 3, NK = STAGE ? EPB * PW * BB : 1;
+    static constexpr int NBUF = SYM ? (NG + NHG > NK ? NG + NHG : NK) : NG + NHG + NK;
+    CT buf[NBUF];
+    int32_t sD[STAGE && !SYM ? EPB * PW : 1];
+    uint16_t sEnt[SYM ? 2 * EPB * PW : 1];   // the tile's entries
+    uint16_t sEend[SYM ? 2 * EPB * PW : 1];  // and tile-block ends
     double sDN[NQ][NN][3];   // reference gradients of this family
     double sNr[NQ][NN];      // reference shape functions
 
@@ -284,17 +302,18 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM;
     constexpr bool SYM = VAR == V_ROWSYM;
 
+    using Smem = ElemSmem<T, MODEL, VAR, CT>;
     auto &sX = S.sX;
     auto &sU = S.sU;
-    auto &sG = S.sG;
-    auto &sH = S.sH;
+    auto &sG = *reinterpret_cast<CT(*)[EPB][NQ][NN][3]>(S.buf);
+    auto &sH = *reinterpret_cast<CT(*)[EU][NQ][NN][3]>(S.buf + Smem::NG);
+    CT *sK = S.buf + (SYM ? 0 : Smem::NG + Smem::NHG);
     auto &sC = S.sC;
     auto &sLM = S.sLM;
     auto &sE = S.sE;
     auto &sNH = S.sNH;
     auto &sM = S.sM;
     auto &sCP = S.sCP;
-    auto &sK = S.sK;
     auto &sD = S.sD;
     constexpr bool STAGE = ElemSmem<T, MODEL, VAR, CT>::STAGE;
     auto &sDN = S.sDN;
@@ -339,6 +358,14 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                     for (int c = 0; c < 3; ++c) sU[el][a][c] = A.u[3 * (int64_t)v + c];
                 }
             }
+        }
+        if constexpr (SYM) {
+            // the tile's entries and tile-block ends (at most two entries per lane)
+            const int64_t tl = first / EPB;
+            const int64_t e0 = A.tent_ptr[tl], d0 = A.ttb_ptr[tl];
+            const int ne = (int)(A.tent_ptr[tl + 1] - e0), nd = (int)(A.ttb_ptr[tl + 1] - d0);
+            for (int i = tid; i < ne; i += 256) S.sEnt[i] = A.tent[e0 + i];
+            for (int i = tid; i < nd; i += 256) S.sEend[i] = A.tb_eend[d0 + i];
         }
         __syncthreads();
     } else {
@@ -419,6 +446,9 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     __syncthreads();
 
     // element matrix: one thread per (element, block a-b), or per pair a <= b
+    CT Ks[SYM ? BB : 1];  // the upper-triangle form's block, staged after the barrier below
+#pragma unroll
+    for (int c = 0; c < (SYM ? BB : 1); ++c) Ks[c] = 0;
     if (tid < EPB * PW) {
         const int el = tid / PW, w = tid % PW;
         int a, b;
@@ -437,16 +467,15 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
             a = w / NN;
             b = w % NN;
         }
-        const int p = a * NN + b, pt = b * NN + a;
+        const int p = a * NN + b;
         int32_t e = sE[el];
-        // destinations, fetched before the contraction: of block (a, b) and,
-        // for the symmetric form, of its transpose (b, a)
+        // destination of this block, fetched before the contraction (the
+        // upper-triangle form's destinations are its tile-blocks)
         const int64_t dest = e < 0 ? -1
+                             : SYM ? 0
                              : RO  ? (int64_t)A.pdest[(first + el) * P + p]
                                    : (int64_t)A.e2nnz[sM[el] + p];
-        const int64_t dest_t = (!SYM || e < 0 || a == b) ? -1 : (int64_t)A.pdest[(first + el) * P + pt];
-        if constexpr (STAGE && SYM) sD[tid] = (int32_t)(dest >= 0 ? dest : dest_t);
-        if (dest >= 0 || dest_t >= 0) {
+        if (dest >= 0) {
             CT K[BB];
             if constexpr (!ELAS) {
                 CT acc = 0;
@@ -513,28 +542,9 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                         K[i * 3 + j] = v;
                     }
             }
-            if constexpr (STAGE && SYM) {
-                // the staged slot takes whichever of the two is an upper
-                // block; when nodes a and b coincide both are, and the
-                // transpose goes straight to the workspace
+            if constexpr (SYM) {
 #pragma unroll
-                for (int c = 0; c < BB; ++c) sK[tid * BB + c] = dest >= 0 ? K[c] : K[(c % B) * B + c / B];
-                if (dest >= 0 && dest_t >= 0) {
-                    CT *dst = (CT *)A.contrib + dest_t * BB;
-#pragma unroll
-                    for (int c = 0; c < BB; ++c) dst[c] = K[(c % B) * B + c / B];
-                }
-            } else if constexpr (SYM) {
-                if (dest >= 0) {
-                    CT *dst = (CT *)A.contrib + dest * BB;
-#pragma unroll
-                    for (int c = 0; c < BB; ++c) dst[c] = K[c];
-                }
-                if (dest_t >= 0) {
-                    CT *dst = (CT *)A.contrib + dest_t * BB;
-#pragma unroll
-                    for (int c = 0; c < BB; ++c) dst[c] = K[(c % B) * B + c / B];
-                }
+                for (int c = 0; c < BB; ++c) Ks[c] = K[c];
             } else if constexpr (STAGE) {
                 sD[el * P + p] = (int32_t)dest;
 #pragma unroll
@@ -590,13 +600,34 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     }
 
 
-    if constexpr (STAGE) {
+    if constexpr (SYM) {
+        __syncthreads();  // every lane has read the gradients that sK overwrites
+        if (tid < EPB * PW) {
+#pragma unroll
+            for (int c = 0; c < BB; ++c) sK[tid * BB + c] = Ks[c];
+        }
+        __syncthreads();
+        // tile sums: one thread per (tile-block, component), the block's
+        // entries added in ascending lane (element) order, in FP64
+        const int64_t tl = first / EPB;
+        const int64_t d0 = A.ttb_ptr[tl];
+        const int nd = (int)(A.ttb_ptr[tl + 1] - d0);
+        CT *out = (CT *)A.contrib;
+        for (int idx = tid; idx < nd * BB; idx += 256) {
+            const int d = idx / BB, c = idx - d * BB, ct = (c % B) * B + c / B;
+            double acc = 0.0;
+            for (int q = d ? S.sEend[d - 1] : 0; q < S.sEend[d]; ++q) {
+                const int u = S.sEnt[q];
+                acc += (double)sK[(u >> 1) * BB + ((u & 1) ? ct : c)];
+            }
+            out[(int64_t)A.tb_slot[d0 + d] * BB + c] = (CT)acc;
+        }
+    } else if constexpr (STAGE) {
         __syncthreads();
         CT *out = (CT *)A.contrib;
         for (int idx = tid; idx < EPB * PW * BB; idx += 256) {
             const int blk = idx / BB;
-            if (first + blk / PW < A.n && (!SYM || sD[blk] >= 0))
-                out[(int64_t)sD[blk] * BB + (idx - blk * BB)] = sK[idx];
+            if (first + blk / PW < A.n) out[(int64_t)sD[blk] * BB + (idx - blk * BB)] = sK[idx];
         }
     }
 }

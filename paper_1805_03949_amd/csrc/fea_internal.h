@@ -12,7 +12,10 @@
 namespace fea {
 
 // Nodes per family: tet4, pyr5, pen6, hex8.
-__host__ __device__ inline int nodes_of(int t) { return 4 + t + (t == 3); }
+__host__ __device__ constexpr inline int nodes_of(int t) { return 4 + t + (t == 3); }
+// Elements per tile of the upper-triangle form: one lane per local pair
+// a <= b, 256 lanes per workgroup.
+__host__ __device__ constexpr inline int sym_epb(int t) { return 256 / (nodes_of(t) * (nodes_of(t) + 1) / 2); }
 
 // Records a message for fea_last_error() and returns `code`.
 int set_error(int code, const char *fmt, ...);
@@ -106,21 +109,34 @@ struct fea_graph {
     // assembly (gev[c] before class c, gev[5] after the last)
     hipEvent_t gev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool gtimed = false;
-    // Upper-triangle row-owner layout (built by the first FEA_ROWSYM
-    // assembly): upart[k] = block k itself if col >= row, else the block at
-    // the transposed position; usptr[k] .. usptr[k+1] = the compacted
-    // workspace range of an upper block's contributions (inverse-map order);
-    // pudest = destination of every slot in type-sorted order, -1 for the
-    // slots of lower blocks (not computed). ulen = workspace slots.
+    // Upper-triangle layout (built by the first FEA_ROWSYM assembly).
+    // upart[k] = block k itself if col >= row, else the block at the
+    // transposed position; ublk = the nup upper (and diagonal) blocks in CSR
+    // order; lpart[k] = lower partner of upper block k (-1 for diagonal and
+    // lower blocks).
     int32_t *upart = nullptr;
-    int64_t *usptr = nullptr;
-    int32_t *pudest = nullptr;
-    int64_t ulen = 0;
-    // upper blocks in CSR order (nup of them) and, for each block, its
-    // lower partner (-1 for diagonal and lower blocks)
     int32_t *ublk = nullptr;
     int32_t *lpart = nullptr;
     int64_t nup = 0;
+    // Element tiles: family t's elements in type-sorted order, EPB_t =
+    // 256 / (n(n+1)/2) consecutive ones per tile, tiles tile_base[t] ..
+    // tile_base[t+1]. Lane l = el * n(n+1)/2 + w of a tile is the w-th local
+    // pair a <= b of its el-th element. Tile τ's entries tent[tent_ptr[τ] ..
+    // tent_ptr[τ+1]) (lane << 1 | transposed) are sorted by destination
+    // upper block, then lane; its distinct blocks are tile-blocks ttb_ptr[τ]
+    // .. ttb_ptr[τ+1], tile-block d holding entries up to tb_eend[d]
+    // (exclusive, within the tile), block id tb_blk[d] and workspace slot
+    // tb_slot[d]. The workspace lies sorted by block, then tile: block k's
+    // tile sums are ts_ptr[k] .. ts_ptr[k+1]; ulen = tile-blocks.
+    int64_t tile_base[5] = {0, 0, 0, 0, 0};
+    int64_t *tent_ptr = nullptr;
+    int64_t *ttb_ptr = nullptr;
+    uint16_t *tent = nullptr;
+    uint16_t *tb_eend = nullptr;
+    int32_t *tb_blk = nullptr;
+    int32_t *tb_slot = nullptr;
+    int64_t *ts_ptr = nullptr;
+    int64_t ulen = 0;
     bool sready = false;
     // lazily allocated workspaces of the scatter variants
     void *contrib = nullptr;

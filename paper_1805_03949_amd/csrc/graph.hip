@@ -234,8 +234,7 @@ struct TmpBuf {
 // ---------------------------------------------- upper-triangle row-owner
 // Block k = (i, j): its transposed partner (j, i) lies in row j (the
 // pattern is structurally symmetric); upper blocks (j >= i) are their own.
-__global__ void k_sym_partner(int64_t n_nodes, const int64_t *row_ptr, const int32_t *col,
-                              const int64_t *inv_ptr, int32_t *upart, int32_t *ulen)
+__global__ void k_sym_partner(int64_t n_nodes, const int64_t *row_ptr, const int32_t *col, int32_t *upart)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_nodes) return;
@@ -243,7 +242,6 @@ __global__ void k_sym_partner(int64_t n_nodes, const int64_t *row_ptr, const int
         const int32_t j = col[k];
         if (j >= i) {
             upart[k] = (int32_t)k;
-            ulen[k] = (int32_t)(inv_ptr[k + 1] - inv_ptr[k]);
         } else {
             int64_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1;
             while (lo < hi) {
@@ -252,7 +250,6 @@ __global__ void k_sym_partner(int64_t n_nodes, const int64_t *row_ptr, const int
                 else hi = mid;
             }
             upart[k] = (int32_t)lo;
-            ulen[k] = 0;
         }
     }
 }
@@ -275,85 +272,241 @@ __global__ void k_flag_upper(int64_t nnz, const int32_t *upart, int32_t *flag)
     if (k < nnz) flag[k] = upart[k] == k ? 1 : 0;
 }
 
-// Compacted workspace position of every slot of an upper block (the
-// block's inverse-map segment, in order); other slots keep -1.
-__global__ void k_sym_e2pos(int64_t n_nodes, const int64_t *row_ptr, const int32_t *col,
-                            const int64_t *inv_ptr, const int32_t *inv, const int64_t *usptr,
-                            int32_t *e2upos)
+struct TileBases {
+    int64_t seg[5], node[5], tile[5];
+};
+
+// One workgroup per tile: the tile's contributions (lane, transposed?) keyed
+// by destination upper block, sorted (bitonic, in LDS) by block then lane.
+// Pass 1 (!WRITE) stores the entry and distinct-block counts; pass 2 writes
+// the entries and the tile-blocks at the scanned offsets.
+template <bool WRITE>
+__global__ void __launch_bounds__(256) k_tile_entries(TileBases tb, const int32_t *perm, const int32_t *pnodes,
+                                                      const int64_t *map_ptr, const int32_t *e2nnz,
+                                                      int32_t *cnt_ent, int32_t *cnt_blk, const int64_t *tent_ptr,
+                                                      const int64_t *ttb_ptr, uint16_t *tent, int32_t *tb_blk,
+                                                      uint16_t *tb_eend)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_nodes) return;
-    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-        if (col[k] < i) continue;
-        for (int64_t jj = inv_ptr[k]; jj < inv_ptr[k + 1]; ++jj)
-            e2upos[inv[jj]] = (int32_t)(usptr[k] + (jj - inv_ptr[k]));
+    constexpr int K = 512;
+    constexpr uint64_t NONE = ~0ull;
+    __shared__ uint64_t key[K];
+    __shared__ int part[256];
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    int t = 0;
+    while (t < 3 && tile >= tb.tile[t + 1]) ++t;
+    const int n = nodes_of(t), pw = n * (n + 1) / 2, epb = 256 / pw;
+    const int64_t first = tb.seg[t] + (tile - tb.tile[t]) * epb;
+    uint64_t k0 = NONE, k1 = NONE;
+    if (tid < epb * pw) {
+        const int el = tid / pw;
+        int w = tid - el * pw, a = 0;
+        while (w >= n - a) {
+            w -= n - a;
+            ++a;
+        }
+        const int b = a + w;
+        const int64_t p = first + el;
+        if (p < tb.seg[t + 1]) {
+            const int32_t *pn = pnodes + tb.node[t] + (p - tb.seg[t]) * n;
+            const int32_t na = pn[a], nb = pn[b];
+            const int64_t m0 = map_ptr[perm[p]];
+            const uint64_t kab = (uint64_t)e2nnz[m0 + a * n + b];
+            const uint64_t lane = (uint64_t)tid << 1;
+            if (a == b || na < nb) {
+                k0 = kab << 10 | lane;
+            } else if (na > nb) {
+                k0 = (uint64_t)e2nnz[m0 + b * n + a] << 10 | lane | 1;
+            } else {  // coincident nodes: both blocks land on the diagonal
+                k0 = kab << 10 | lane;
+                k1 = kab << 10 | lane | 1;
+            }
+        }
+    }
+    key[tid] = k0;
+    key[tid + 256] = k1;
+    __syncthreads();
+    for (int size = 2; size <= K; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < K; i += 256) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const uint64_t x = key[i], y = key[j];
+                    if ((x > y) == ((i & size) == 0)) {
+                        key[i] = y;
+                        key[j] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    // new-block flags of entries 2 tid and 2 tid + 1, and their scan
+    int f[2];
+    for (int q = 0; q < 2; ++q) {
+        const int i = 2 * tid + q;
+        f[q] = key[i] != NONE && (i == 0 || (key[i] >> 10) != (key[i - 1] >> 10));
+    }
+    part[tid] = f[0] + f[1];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    const int nblk = part[255];
+    const int nent = __syncthreads_count(key[2 * tid] != NONE) + __syncthreads_count(key[2 * tid + 1] != NONE);
+    if constexpr (!WRITE) {
+        if (tid == 0) {
+            cnt_ent[tile] = nent;
+            cnt_blk[tile] = nblk;
+        }
+    } else {
+        const int64_t e0 = tent_ptr[tile], d0 = ttb_ptr[tile];
+        int d = part[tid] - f[0] - f[1] - 1;  // tile-block of the entry before 2 tid
+        for (int q = 0; q < 2; ++q) {
+            const int i = 2 * tid + q;
+            if (key[i] == NONE) break;
+            d += f[q];
+            tent[e0 + i] = (uint16_t)(key[i] & 1023);
+            if (i + 1 == nent || (key[i + 1] >> 10) != (key[i] >> 10)) {
+                tb_blk[d0 + d] = (int32_t)(key[i] >> 10);
+                tb_eend[d0 + d] = (uint16_t)(i + 1);
+            }
+        }
     }
 }
 
-__global__ void k_sym_position(int64_t n_elems, Bases bs, const int32_t *perm, const int64_t *map_ptr,
-                               const int32_t *e2upos, int32_t *pudest)
+__global__ void k_tb_count(int64_t ntb, const int32_t *tb_blk, int32_t *cnt)
 {
-    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= n_elems) return;
-    int t = 0;
-    while (t < 3 && pos >= bs.seg[t + 1]) ++t;
-    const int n = nodes_of(t);
-    const int64_t i = pos - bs.seg[t];
-    const int64_t m0 = map_ptr[perm[pos]];
-    int32_t *pd = pudest + bs.slot[t] + i * n * n;
-    for (int p = 0; p < n * n; ++p) pd[p] = e2upos[m0 + p];
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d < ntb) atomicAdd(&cnt[tb_blk[d]], 1);
+}
+
+__global__ void k_tb_fill(int64_t ntb, const int32_t *tb_blk, const int64_t *ts_ptr, int32_t *fill, int32_t *lst)
+{
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= ntb) return;
+    const int32_t k = tb_blk[d];
+    lst[ts_ptr[k] + atomicAdd(&fill[k], 1)] = (int32_t)d;
+}
+
+// Each block's tile-blocks in ascending tile order (tile-blocks are numbered
+// tile by tile), then every tile-block's workspace slot.
+__global__ void k_tb_slots(int64_t nnz, const int64_t *ts_ptr, int32_t *lst, int32_t *tb_slot)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    const int64_t b = ts_ptr[k], e = ts_ptr[k + 1];
+    for (int64_t i = b + 1; i < e; ++i) {
+        const int32_t v = lst[i];
+        int64_t j = i - 1;
+        while (j >= b && lst[j] > v) {
+            lst[j + 1] = lst[j];
+            --j;
+        }
+        lst[j + 1] = v;
+    }
+    for (int64_t i = b; i < e; ++i) tb_slot[lst[i]] = (int32_t)i;
 }
 
 int sym_prepare(fea_graph *g, hipStream_t s)
 {
     constexpr int BS = 256;
-    const int64_t N = g->n_nodes, E = g->n_elems, nnz = g->nnz;
+    const int64_t N = g->n_nodes, nnz = g->nnz;
     int rc;
-    dfree(g->upart);
-    dfree(g->usptr);
-    dfree(g->pudest);
-    g->upart = nullptr;
-    g->usptr = nullptr;
-    g->pudest = nullptr;
-    TmpBuf ulen, tmp, e2upos;
-    if ((rc = dalloc((void **)&g->upart, sizeof(int32_t) * std::max<int64_t>(nnz, 1)))) return rc;
-    if ((rc = dalloc((void **)&g->usptr, sizeof(int64_t) * (nnz + 1)))) return rc;
-    if ((rc = dalloc((void **)&g->pudest, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
-    if ((rc = dalloc(&ulen.p, sizeof(int32_t) * std::max<int64_t>(nnz, 1)))) return rc;
-    if ((rc = dalloc(&tmp.p, sizeof(int64_t) * (scan_tmp_elems(std::max<int64_t>(nnz, 1)) + 64)))) return rc;
-    if ((rc = dalloc(&e2upos.p, sizeof(int32_t) * std::max<int64_t>(g->map_len, 1)))) return rc;
-    if (N) k_sym_partner<<<grid_for(N, BS), BS, 0, s>>>(N, g->row_ptr, g->col, g->inv_ptr, g->upart, (int32_t *)ulen.p);
-    if ((rc = scan_to_ptr_i32((int32_t *)ulen.p, nnz, g->usptr, (int64_t *)tmp.p, s))) return rc;
-    if (g->map_len) FEA_HIP(hipMemsetAsync(e2upos.p, 0xff, sizeof(int32_t) * g->map_len, s));
-    if (N) k_sym_e2pos<<<grid_for(N, BS), BS, 0, s>>>(N, g->row_ptr, g->col, g->inv_ptr, g->inv, g->usptr, (int32_t *)e2upos.p);
-    Bases bs;
-    for (int t = 0; t <= 4; ++t) {
-        bs.seg[t] = g->seg[t];
-        bs.node[t] = g->node_base[t];
-        bs.slot[t] = g->slot_base[t];
+    void **bufs[] = {(void **)&g->upart, (void **)&g->ublk,    (void **)&g->lpart,  (void **)&g->tent_ptr,
+                     (void **)&g->ttb_ptr, (void **)&g->tent,  (void **)&g->tb_eend, (void **)&g->tb_blk,
+                     (void **)&g->tb_slot, (void **)&g->ts_ptr};
+    for (void **b : bufs) {
+        dfree(*b);
+        *b = nullptr;
     }
-    if (E) k_sym_position<<<grid_for(E, BS), BS, 0, s>>>(E, bs, g->perm, g->map_ptr, (int32_t *)e2upos.p, g->pudest);
-    // upper-block list and lower partners (the ulen buffer, already
-    // scanned into usptr, is reused for the upper-block flags)
-    dfree(g->ublk);
-    dfree(g->lpart);
-    g->ublk = nullptr;
-    g->lpart = nullptr;
     g->nup = 0;
-    TmpBuf uoff;
+    g->ulen = 0;
+    g->sready = false;
+    // partners and the upper-block list
+    TmpBuf flag, uoff, tmp;
+    const int64_t nn1 = std::max<int64_t>(nnz, 1);
+    if ((rc = dalloc((void **)&g->upart, sizeof(int32_t) * nn1))) return rc;
+    if ((rc = dalloc((void **)&g->lpart, sizeof(int32_t) * nn1))) return rc;
+    if ((rc = dalloc((void **)&g->ublk, sizeof(int32_t) * nn1))) return rc;
+    if ((rc = dalloc(&flag.p, sizeof(int32_t) * nn1))) return rc;
     if ((rc = dalloc(&uoff.p, sizeof(int64_t) * (nnz + 1)))) return rc;
-    if ((rc = dalloc((void **)&g->lpart, sizeof(int32_t) * std::max<int64_t>(nnz, 1)))) return rc;
-    if ((rc = dalloc((void **)&g->ublk, sizeof(int32_t) * std::max<int64_t>(nnz, 1)))) return rc;
+    // the scan scratch serves the tile and block scans below as well
+    TileBases tb;
+    int64_t nt = 0;
+    for (int t = 0; t < 4; ++t) {
+        tb.seg[t] = g->seg[t];
+        tb.node[t] = g->node_base[t];
+        tb.tile[t] = nt;
+        const int epb = sym_epb(t);
+        nt += (g->seg[t + 1] - g->seg[t] + epb - 1) / epb;
+    }
+    tb.seg[4] = g->seg[4];
+    tb.node[4] = g->node_base[4];
+    tb.tile[4] = nt;
+    for (int t = 0; t < 5; ++t) g->tile_base[t] = tb.tile[t];
+    const int64_t nscan = std::max<int64_t>(std::max<int64_t>(nnz, nt), 1);
+    if ((rc = dalloc(&tmp.p, sizeof(int64_t) * (scan_tmp_elems(nscan) + 64)))) return rc;
+    if (N) k_sym_partner<<<grid_for(N, BS), BS, 0, s>>>(N, g->row_ptr, g->col, g->upart);
     if (nnz) {
-        k_flag_upper<<<grid_for(nnz, BS), BS, 0, s>>>(nnz, g->upart, (int32_t *)ulen.p);
-        if ((rc = scan_to_ptr_i32((int32_t *)ulen.p, nnz, (int64_t *)uoff.p, (int64_t *)tmp.p, s))) return rc;
+        k_flag_upper<<<grid_for(nnz, BS), BS, 0, s>>>(nnz, g->upart, (int32_t *)flag.p);
+        if ((rc = scan_to_ptr_i32((int32_t *)flag.p, nnz, (int64_t *)uoff.p, (int64_t *)tmp.p, s))) return rc;
         FEA_HIP(hipMemsetAsync(g->lpart, 0xff, sizeof(int32_t) * nnz, s));
         k_sym_lists<<<grid_for(nnz, BS), BS, 0, s>>>(nnz, g->upart, (const int64_t *)uoff.p, g->lpart, g->ublk);
         FEA_HIP(hipMemcpyAsync(&g->nup, (int64_t *)uoff.p + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     }
     FEA_HIP(hipGetLastError());
-    FEA_HIP(hipMemcpyAsync(&g->ulen, g->usptr + nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    // tiles: entry and tile-block counts, offsets, then the entries
+    TmpBuf cent, cblk;
+    if ((rc = dalloc(&cent.p, sizeof(int32_t) * std::max<int64_t>(nt, 1)))) return rc;
+    if ((rc = dalloc(&cblk.p, sizeof(int32_t) * std::max<int64_t>(nt, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->tent_ptr, sizeof(int64_t) * (nt + 1)))) return rc;
+    if ((rc = dalloc((void **)&g->ttb_ptr, sizeof(int64_t) * (nt + 1)))) return rc;
+    int64_t nent = 0, ntb = 0;
+    if (nt) {
+        k_tile_entries<false><<<(unsigned)nt, 256, 0, s>>>(tb, g->perm, g->pnodes, g->map_ptr, g->e2nnz,
+                                                          (int32_t *)cent.p, (int32_t *)cblk.p, nullptr, nullptr,
+                                                          nullptr, nullptr, nullptr);
+        if ((rc = scan_to_ptr_i32((int32_t *)cent.p, nt, g->tent_ptr, (int64_t *)tmp.p, s))) return rc;
+        if ((rc = scan_to_ptr_i32((int32_t *)cblk.p, nt, g->ttb_ptr, (int64_t *)tmp.p, s))) return rc;
+        FEA_HIP(hipMemcpyAsync(&nent, g->tent_ptr + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        FEA_HIP(hipMemcpyAsync(&ntb, g->ttb_ptr + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    } else {
+        FEA_HIP(hipMemsetAsync(g->tent_ptr, 0, sizeof(int64_t), s));
+        FEA_HIP(hipMemsetAsync(g->ttb_ptr, 0, sizeof(int64_t), s));
+    }
     FEA_HIP(hipStreamSynchronize(s));
+    if (ntb > INT32_MAX) return set_error(FEA_ERANGE, "%lld tile-blocks exceed the int32 slot range", (long long)ntb);
+    if ((rc = dalloc((void **)&g->tent, sizeof(uint16_t) * std::max<int64_t>(nent, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->tb_eend, sizeof(uint16_t) * std::max<int64_t>(ntb, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->tb_blk, sizeof(int32_t) * std::max<int64_t>(ntb, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->tb_slot, sizeof(int32_t) * std::max<int64_t>(ntb, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->ts_ptr, sizeof(int64_t) * (nnz + 1)))) return rc;
+    if (nt)
+        k_tile_entries<true><<<(unsigned)nt, 256, 0, s>>>(tb, g->perm, g->pnodes, g->map_ptr, g->e2nnz, nullptr,
+                                                         nullptr, g->tent_ptr, g->ttb_ptr, g->tent, g->tb_blk,
+                                                         g->tb_eend);
+    // workspace segments: per block its tile-blocks, ascending tile
+    TmpBuf lst;
+    if ((rc = dalloc(&lst.p, sizeof(int32_t) * std::max<int64_t>(ntb, 1)))) return rc;
+    if (nnz) {
+        FEA_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t) * nnz, s));
+        if (ntb) k_tb_count<<<grid_for(ntb, BS), BS, 0, s>>>(ntb, g->tb_blk, (int32_t *)flag.p);
+        if ((rc = scan_to_ptr_i32((int32_t *)flag.p, nnz, g->ts_ptr, (int64_t *)tmp.p, s))) return rc;
+        FEA_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t) * nnz, s));
+        if (ntb) {
+            k_tb_fill<<<grid_for(ntb, BS), BS, 0, s>>>(ntb, g->tb_blk, g->ts_ptr, (int32_t *)flag.p,
+                                                       (int32_t *)lst.p);
+            k_tb_slots<<<grid_for(nnz, BS), BS, 0, s>>>(nnz, g->ts_ptr, (int32_t *)lst.p, g->tb_slot);
+        }
+    } else {
+        FEA_HIP(hipMemsetAsync(g->ts_ptr, 0, sizeof(int64_t), s));
+    }
+    FEA_HIP(hipGetLastError());
+    FEA_HIP(hipStreamSynchronize(s));
+    g->ulen = ntb;
     g->sready = true;
     return FEA_OK;
 }
@@ -423,7 +576,8 @@ static void destroy(fea_graph *g)
     if (!g) return;
     void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv, g->pnodes, g->pdest, g->prdest,
                     g->n2e_ptr, g->n2e, g->n2a, g->perm, g->colour, g->cperm,
-                    g->contrib, g->rcontrib, g->acc64, g->gtile, g->gnodes, g->gdesc, g->upart, g->usptr, g->pudest, g->ublk, g->lpart};
+                    g->contrib, g->rcontrib, g->acc64, g->gtile, g->gnodes, g->gdesc, g->upart, g->ublk, g->lpart, g->tent_ptr, g->ttb_ptr,
+                    g->tent, g->tb_eend, g->tb_blk, g->tb_slot, g->ts_ptr};
     for (void *b : bufs) dfree(b);
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);
