@@ -38,27 +38,32 @@ def reduce_bytes(g, B, s_c, s_v):
     return g.map_len * B * B * s_c + (g.nnz + 1) * 8 + g.nnz * B * B * s_v
 
 
-def sym_counts(mesh, nnz, np):
-    """(upper-triangle slots, upper and diagonal blocks) of the symmetric
-    row-owner form: per element the local pairs (a, b) with node(a) <=
-    node(b), and the blocks (i, j) with i <= j of the symmetric pattern
-    (half the off-diagonal blocks plus one diagonal block per node that
-    some element uses)."""
-    ulen = 0
+def sym_tile_blocks(mesh, np):
+    """(entries, tile-blocks) of the upper-triangle layout, from its
+    definition: per family the type-sorted elements in tiles of
+    256 // (n(n+1)/2); per element one entry per local pair a <= b (two where
+    its nodes coincide); tile-blocks = distinct (tile, upper block) pairs."""
+    order = np.argsort(mesh.types, kind="stable")
+    ent, keys, tile0, N = 0, [], 0, int(mesh.n_nodes)
     for t in range(4):
-        idx = np.nonzero(mesh.types == t)[0]
+        idx = order[mesh.types[order] == t]
         if idx.size == 0:
             continue
         n = NODES[t]
-        c = mesh.conn[mesh.conn_ptr[idx][:, None] + np.arange(n)[None, :]]
-        ulen += int((c[:, :, None] <= c[:, None, :]).sum())
-    n_used = int(np.unique(mesh.conn).size)
-    return ulen, (nnz + n_used) // 2
+        epb = 256 // (n * (n + 1) // 2)
+        c = mesh.conn[mesh.conn_ptr[idx][:, None] + np.arange(n)[None, :]].astype(np.int64)
+        a, b = np.triu_indices(n)
+        na, nb = c[:, a], c[:, b]
+        tile = tile0 + (np.arange(idx.size, dtype=np.int64) // epb)[:, None]
+        ent += na.size + int(((na == nb) & (a != b)[None, :]).sum())
+        keys.append(((tile * N + np.minimum(na, nb)) * N + np.maximum(na, nb)).ravel())
+        tile0 += (idx.size + epb - 1) // epb
+    return ent, int(np.unique(np.concatenate(keys)).size) if keys else 0
 
 
 def sym_reduce_bytes(ulen, nup, nnz, B, s_c, s_v):
     """Algorithmic bytes of one launch of the upper-triangle block-value
-    kernel: every upper-slot contribution read once, per upper block its
+    kernel: every tile sum (ulen tile-blocks) read once, per upper block its
     segment bound (int64), its block index and its lower partner (int32),
     every block value (upper and transposed lower) written once."""
     return ulen * B * B * s_c + (nup + 1) * 8 + nup * 8 + nnz * B * B * s_v
@@ -71,17 +76,19 @@ def scatter_bytes(g, B, s_c, s_v, conn_len, n_nodes):
     return reduce_bytes(g, B, s_c, s_v) + conn_len * B * s_c + (n_nodes + 1) * 8 + n_nodes * B * s_v
 
 
-def element_bytes(g, B, s_c, s_v, conn_len, n_nodes, n_elems, variant, ulen=0):
+def element_bytes(g, B, s_c, s_v, conn_len, n_nodes, n_elems, variant, sym=None):
     """Algorithmic bytes of the element phase: node coordinates once, the
     connectivity and per-element data once, and its outputs once (the slot
-    contributions for row-owner, the upper-triangle slots (ulen) for its
-    symmetric form; for row-gather the final values, plus the pair-ordered
-    node lists, lane bytes and segment bounds it reads)."""
+    contributions for row-owner; for the upper-triangle form the tile sums
+    plus its tile entries (2 bytes), tile-block ends and slots (6 bytes) and
+    tile ranges (16 bytes); for row-gather the final values, plus the
+    pair-ordered node lists, lane bytes and segment bounds it reads)."""
     inputs = n_nodes * 24 + conn_len * 4 + n_elems * (8 + 4 + 8 + 16 + 8 * B)
     if variant == "rowowner":
         return inputs + g.map_len * B * B * s_c + conn_len * B * s_c
     if variant == "rowsym":
-        return inputs + ulen * B * B * s_c + conn_len * B * s_c
+        return (inputs + sym["tile_blocks"] * (B * B * s_c + 6) + sym["entries"] * 2 + sym["tiles"] * 16
+                + conn_len * B * s_c)
     if variant == "rowgather":
         maps = g.map_len * (4 + 1) + conn_len * 5 + (g.nnz + 1) * 8 + (n_nodes + 1) * 8
         return inputs + maps + g.nnz * B * B * s_v + n_nodes * B * s_v
@@ -492,8 +499,12 @@ def main():
             classes.append(g.last_class_timing())
     ph = np.median(np.array(phases), axis=0)
     elem_ms, second_ms = float(ph[0]), float(ph[1])
-    ulen, nup = sym_counts(mesh, g.nnz, np)
-    eb = element_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes, mesh.n_elems, args.variant, ulen)
+    # sizes of the upper-triangle layout (built by its first assembly)
+    vs, rs, ss = dm.assemble(g, variant=fea.ROWSYM)
+    del vs, rs, ss
+    sym = g.sym_sizes()
+    ulen, nup = sym["tile_blocks"], sym["upper_blocks"]
+    eb = element_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes, mesh.n_elems, args.variant, sym)
     sb = scatter_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes)
     copy_gbps = copy_bandwidth(torch)
     class_ms = None

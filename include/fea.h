@@ -114,6 +114,16 @@ int fea_graph_build(int64_t n_nodes, int64_t n_elems, const uint8_t *types,
 int fea_graph_sizes(const fea_graph *g, int64_t *n_nodes, int64_t *n_elems,
                     int64_t *nnz_blocks, int64_t *map_len, int *n_colours);
 
+/* Sizes of the upper-triangle (FEA_ROWSYM) layout, built by the first
+ * FEA_ROWSYM assembly on the graph: element tiles (per family, 256 / (n(n+1)/2)
+ * consecutive elements of the type-sorted order), tile entries (one per
+ * (element, local pair a <= b), two where nodes a and b coincide), tile-blocks
+ * (distinct (tile, upper block) pairs = workspace slots, each 3x3 or 1x1) and
+ * upper blocks (col >= row). Any output pointer may be NULL. FEA_EINVAL if the
+ * layout has not been built yet. */
+int fea_graph_sym_sizes(const fea_graph *g, int64_t *tiles, int64_t *entries, int64_t *tile_blocks,
+                        int64_t *upper_blocks);
+
 /* Copies graph arrays into caller-owned DEVICE buffers (any may be NULL):
  * row_ptr[n_nodes+1], col[nnz], map_ptr[n_elems+1], e2nnz[map_len],
  * inv_ptr[nnz+1], inv[map_len], colour[n_elems], type_perm[n_elems]

@@ -47,6 +47,7 @@ _lib.fea_graph_build.argtypes = [_I64, _I64, _P, _P, _P, _P, ctypes.POINTER(_P)]
 _lib.fea_graph_build.restype = ctypes.c_int
 _lib.fea_graph_sizes.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                  ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int)]
+_lib.fea_graph_sym_sizes.argtypes = [_P] + [ctypes.POINTER(_I64)] * 4
 _lib.fea_graph_export.argtypes = [_P] * 9 + [ctypes.POINTER(_I64), _P]
 _lib.fea_graph_destroy.argtypes = [_P]
 _lib.fea_graph_destroy.restype = None
@@ -105,7 +106,7 @@ TYPE_SORTED, LEARNED, GP_WEIGHT = 0, 1, 2
 N_FEATURES, N_PARAMS = 12, 5057
 
 # every exported symbol declared in include/fea.h
-EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_export", "fea_graph_destroy",
+EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_sym_sizes", "fea_graph_export", "fea_graph_destroy",
            "fea_assemble", "fea_last_timing", "fea_last_class_timing", "fea_last_error", "fea_version",
            "fea_batch_build", "fea_batch_sizes", "fea_batch_offsets", "fea_batch_items",
            "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_assemble", "fea_batch_capture",
@@ -191,6 +192,13 @@ class Graph:
                                      seg, _stream(stream)))
         out["type_seg"] = list(seg)
         return out
+
+    def sym_sizes(self):
+        """Sizes of the upper-triangle layout (after the first ROWSYM
+        assembly): tiles, entries, tile_blocks, upper_blocks."""
+        v = [_I64() for _ in range(4)]
+        _check(_lib.fea_graph_sym_sizes(self.handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("tiles", "entries", "tile_blocks", "upper_blocks"), (x.value for x in v)))
 
     def last_timing(self):
         """(element ms, second-phase ms, total ms) of the last timed assemble."""

@@ -136,7 +136,7 @@ struct fea_graph {
     int32_t *tb_blk = nullptr;
     int32_t *tb_slot = nullptr;
     int64_t *ts_ptr = nullptr;
-    int64_t ulen = 0;
+    int64_t ulen = 0, nent = 0;
     bool sready = false;
     // lazily allocated workspaces of the scatter variants
     void *contrib = nullptr;

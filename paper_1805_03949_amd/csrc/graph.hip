@@ -424,6 +424,7 @@ int sym_prepare(fea_graph *g, hipStream_t s)
     }
     g->nup = 0;
     g->ulen = 0;
+    g->nent = 0;
     g->sready = false;
     // partners and the upper-block list
     TmpBuf flag, uoff, tmp;
@@ -507,6 +508,7 @@ int sym_prepare(fea_graph *g, hipStream_t s)
     FEA_HIP(hipGetLastError());
     FEA_HIP(hipStreamSynchronize(s));
     g->ulen = ntb;
+    g->nent = nent;
     g->sready = true;
     return FEA_OK;
 }
@@ -760,6 +762,20 @@ extern "C" int fea_graph_sizes(const fea_graph *g, int64_t *n_nodes, int64_t *n_
     if (nnz_blocks) *nnz_blocks = g->nnz;
     if (map_len) *map_len = g->map_len;
     if (n_colours) *n_colours = g->n_colours;
+    return FEA_OK;
+}
+
+extern "C" int fea_graph_sym_sizes(const fea_graph *g, int64_t *tiles, int64_t *entries, int64_t *tile_blocks,
+                                   int64_t *upper_blocks)
+{
+    clear_error();
+    if (!g) return set_error(FEA_EINVAL, "graph is NULL");
+    if (!g->sready)
+        return set_error(FEA_EINVAL, "the upper-triangle layout is built by the first FEA_ROWSYM assembly");
+    if (tiles) *tiles = g->tile_base[4];
+    if (entries) *entries = g->nent;
+    if (tile_blocks) *tile_blocks = g->ulen;
+    if (upper_blocks) *upper_blocks = g->nup;
     return FEA_OK;
 }
 

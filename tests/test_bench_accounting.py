@@ -33,26 +33,32 @@ def test_reduce_bytes_definition():
     assert b == 84_492_288 * 72 + (22_156_129 + 1) * 8 + 22_156_129 * 72
 
 
-def _pattern(m):
-    """Brute-force block pattern and upper-triangle slot count."""
-    blocks, ulen = set(), 0
-    for e in range(m.n_elems):
-        nodes = m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]]
-        for a in nodes:
-            for b in nodes:
-                blocks.add((int(a), int(b)))
-                ulen += int(a <= b)
-    return blocks, ulen
+def _tile_blocks_brute_force(m):
+    """Tile entries and distinct (tile, upper block) pairs, element by
+    element in type-sorted order with Python sets."""
+    order = sorted(range(m.n_elems), key=lambda e: int(m.types[e]))
+    seen, ent, tile0 = set(), 0, 0
+    for t in range(4):
+        elems = [e for e in order if m.types[e] == t]
+        n = bench.NODES[t]
+        epb = 256 // (n * (n + 1) // 2)
+        for r, e in enumerate(elems):
+            nodes = [int(v) for v in m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]]]
+            for a in range(n):
+                for b in range(a, n):
+                    ent += 1 + (a != b and nodes[a] == nodes[b])
+                    seen.add((tile0 + r // epb, min(nodes[a], nodes[b]), max(nodes[a], nodes[b])))
+        tile0 += (len(elems) + epb - 1) // epb
+    return ent, len(seen)
 
 
-def test_sym_counts_match_brute_force():
+def test_sym_tile_blocks_match_brute_force():
     m = mg.hybrid_bands(4, seed=2)
-    blocks, ulen = _pattern(m)
-    u, nup = bench.sym_counts(m, len(blocks), np)
-    assert u == ulen
-    assert nup == sum(1 for (i, j) in blocks if i <= j)
-    # distinct nodes per element: n(n+1)/2 upper pairs each
-    assert u == sum(bench.NODES[t] * (bench.NODES[t] + 1) // 2 for t in m.types)
+    assert bench.sym_tile_blocks(m, np) == _tile_blocks_brute_force(m)
+    ent, tb = bench.sym_tile_blocks(m, np)
+    # distinct nodes per element: n(n+1)/2 entries each; tiles share blocks
+    assert ent == sum(bench.NODES[t] * (bench.NODES[t] + 1) // 2 for t in m.types)
+    assert tb < ent
 
 
 def test_sym_reduce_bytes_definition():

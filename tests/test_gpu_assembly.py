@@ -301,6 +301,28 @@ def test_assembly_captured_in_a_graph_replays_eager_result(variant):
 
 
 @pytest.mark.parametrize("name", ["bands8_jitter", "mix6_jitter", "tet_ragged", "hetero16", "poisson_hex16"])
+def test_rowsym_layout_sizes_match_its_definition(name):
+    """The tile layout the library builds has the entry and tile-block
+    counts that its definition gives (counted on the host from the mesh)."""
+    import bench
+    m, _, dm, _ = case(name)
+    g = dm.graph()  # a fresh graph: no upper-triangle layout yet
+    with pytest.raises(fea.FeaError):
+        g.sym_sizes()
+    model = fea.POISSON if name == "poisson_hex16" else fea.ELASTIC
+    dm.assemble(g, model=model, variant=fea.ROWSYM)
+    torch.cuda.synchronize()
+    sz = g.sym_sizes()
+    ent, tb = bench.sym_tile_blocks(m, np)
+    tiles = sum(-(-int((m.types == t).sum()) // (256 // (n * (n + 1) // 2)))
+                for t, n in enumerate(bench.NODES))
+    n_used = np.unique(m.conn).size
+    assert (sz["entries"], sz["tile_blocks"], sz["tiles"]) == (ent, tb, tiles)
+    assert sz["upper_blocks"] == (g.nnz + n_used) // 2
+    g.destroy()
+
+
+@pytest.mark.parametrize("name", ["bands8_jitter", "mix6_jitter", "tet_ragged", "hetero16", "poisson_hex16"])
 def test_rowsym_is_exactly_symmetric_and_matches_rowowner(name):
     """The upper-triangle form writes block (j, i) as the transpose of the
     ordered sum of block (i, j): A equals its transpose bitwise, and it
