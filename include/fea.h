@@ -199,7 +199,10 @@ typedef struct fea_batch fea_batch;
  * Builds a graph per mesh and the work items of one persistent launch. A
  * work item is `count` consecutive elements of one family of one mesh, in
  * that mesh's type-sorted element order; tile[f] (elements per item for
- * family f = tet4, pyr5, pen6, hex8; NULL = defaults) sets the item sizes.
+ * family f = tet4, pyr5, pen6, hex8; NULL = defaults 75, 34, 24, 14) sets
+ * the item sizes, each rounded up to a multiple of the family's
+ * upper-triangle tile (25, 17, 12, 7 elements), so that items start on
+ * tile boundaries in every form.
  * The paper's dynamic schedule with a chunk size (Section 5.1, chunk study)
  * is the analogue: items are chunks handed out by a device work queue.
  * The queue order starts type-sorted (family, mesh, first element).
@@ -236,7 +239,11 @@ int fea_batch_set_order(fea_batch *b, const int32_t *order);
  * vals/rhs: device buffers of the lengths from fea_batch_sizes, element
  * type opt->out_dtype, overwritten. status: device int32[n_meshes] (may be
  * NULL), per mesh the smallest rejected element id or -1. opt->variant:
- * FEA_ROWOWNER as above, or FEA_ROWGATHER: the row tiles of all meshes in
+ * FEA_ROWOWNER as above; FEA_ROWSYM: the same items run as element tiles
+ * with their LDS tile sums (upper-triangle form, as in fea_assemble; the
+ * first such call builds every mesh's tile layout, blocking on `stream`),
+ * then the upper-triangle block values over all meshes, bitwise equal to
+ * one-mesh FEA_ROWSYM assemblies; or FEA_ROWGATHER: the row tiles of all meshes in
  * one persistent launch per tile class, written straight into vals/rhs
  * (the first such call prepares every mesh's tiles and blocks on `stream`;
  * no work queue, no cycle records, tiles and queue order do not apply).
@@ -274,9 +281,10 @@ void fea_batch_destroy(fea_batch *b);
  * timing the batch's persistent kernel (the GPU counterpart of the paper's
  * chunk-size study, Section 5.1). Coordinate descent: for each family in
  * turn the candidates EPB*{1,2,4,8,16,32} are tried with the other tiles
- * fixed (EPB = elements one workgroup pass holds: 16 tet4, 10 pyr5, 7 pen6,
- * 4 hex8), two sweeps, each candidate timed as the median of `reps`
- * launches. The best tiles are applied to the batch, returned in tile_out
+ * fixed (EPB = the upper-triangle tile: 25 tet4, 17 pyr5, 12 pen6, 7 hex8),
+ * two sweeps, each candidate timed as the median of `reps`
+ * launches of opt->variant (FEA_ROWOWNER or FEA_ROWSYM). The best tiles
+ * are applied to the batch, returned in tile_out
  * (HOST int32[4]) and, if table_path is not NULL, stored in that text file
  * under the key (gfx950, model, precision). Allocates temporary outputs.
  */

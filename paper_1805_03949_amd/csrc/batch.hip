@@ -10,6 +10,10 @@
 // per-item cost (Section 4.1, measured load balance) that the cost model
 // learns from. Results are deterministic: each block is summed by the
 // row-owner reduction in ascending element order, whatever the queue order.
+// The upper-triangle form (FEA_ROWSYM) runs the same items as element
+// tiles with their LDS tile sums; item starts are multiples of the family's
+// tile size, so its tiles, and its results, are those of the one-mesh
+// assembly.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -30,22 +34,24 @@ struct BatchMesh {
     int64_t node_base[5], slot_base[5];  // family starts in pnodes/prdest and pdest
     int64_t coff;    // first slot of this mesh in the slot workspace
     int64_t roff;    // first incidence of this mesh in the rhs workspace
+    int64_t tile_base[5];  // upper-triangle form: family starts in the tile ranges
+    int64_t scoff;         // first tile-block of this mesh in its workspace
 };
 
-template <int MODEL, typename CT>
+template <int MODEL, typename CT, int VAR>
 union BatchSmem {
-    ElemSmem<0, MODEL, V_ROWOWNER, CT> s0;
-    ElemSmem<1, MODEL, V_ROWOWNER, CT> s1;
-    ElemSmem<2, MODEL, V_ROWOWNER, CT> s2;
-    ElemSmem<3, MODEL, V_ROWOWNER, CT> s3;
+    ElemSmem<0, MODEL, VAR, CT> s0;
+    ElemSmem<1, MODEL, VAR, CT> s1;
+    ElemSmem<2, MODEL, VAR, CT> s2;
+    ElemSmem<3, MODEL, VAR, CT> s3;
 };
 
-template <int T, int MODEL, typename CT>
-__device__ inline void run_item(ElemArgs &A, int32_t count, ElemSmem<T, MODEL, V_ROWOWNER, CT> &S)
+template <int T, int MODEL, typename CT, int VAR>
+__device__ inline void run_item(ElemArgs &A, int32_t count, ElemSmem<T, MODEL, VAR, CT> &S)
 {
-    constexpr int EPB = ElemSmem<T, MODEL, V_ROWOWNER, CT>::EPB;
+    constexpr int EPB = ElemSmem<T, MODEL, VAR, CT>::EPB;
 #pragma nounroll
-    for (int32_t sub = 0; sub < count; sub += EPB) elem_tile<T, MODEL, V_ROWOWNER, CT>(A, sub, S, opaque_tid());
+    for (int32_t sub = 0; sub < count; sub += EPB) elem_tile<T, MODEL, VAR, CT>(A, sub, S, opaque_tid());
 }
 
 // Persistent kernel: every workgroup dequeues items until the queue is
@@ -53,7 +59,7 @@ __device__ inline void run_item(ElemArgs &A, int32_t count, ElemSmem<T, MODEL, V
 // register budget is capped at three waves per SIMD: the four element
 // families inlined into one loop would otherwise take the whole register
 // file (one wave per SIMD).
-template <int MODEL, typename CT>
+template <int MODEL, typename CT, int VAR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_batch(const BatchMesh *meshes, const int4 *items,
                                                const int32_t *order, int32_t n_items,
                                                int32_t *head, const int32_t *part, CT *contrib,
@@ -61,7 +67,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
                                                int32_t *worker, int32_t *cu)
 {
     constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
-    __shared__ BatchSmem<MODEL, CT> U;
+    __shared__ BatchSmem<MODEL, CT, VAR> U;
     __shared__ int32_t s_item;
     // static partition: this workgroup runs order[part[w] .. part[w+1])
     int32_t next = part ? part[blockIdx.x] : 0;
@@ -84,8 +90,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
                                  __builtin_amdgcn_readfirstlane(wv.z), __builtin_amdgcn_readfirstlane(wv.w));
         const BatchMesh &M = meshes[w.x];
         ElemArgs A = M.a;
-        A.contrib = contrib + M.coff * B * B;
+        A.contrib = contrib + (VAR == V_ROWSYM ? M.scoff : M.coff) * B * B;
         A.rcontrib = rcontrib + M.roff * B;
+        if constexpr (VAR == V_ROWSYM) {
+            // the item starts at a tile boundary
+            const int64_t tl = M.tile_base[w.y] + w.z / sym_epb(w.y);
+            A.tent_ptr = M.a.tent_ptr + tl;
+            A.ttb_ptr = M.a.ttb_ptr + tl;
+        }
         A.elems = M.a.elems + M.seg[w.y] + w.z;
         A.n = w.w;
         {
@@ -96,10 +108,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
         }
         A.status = status + w.x;
         switch (w.y) {
-        case 0: run_item<0, MODEL, CT>(A, w.w, U.s0); break;
-        case 1: run_item<1, MODEL, CT>(A, w.w, U.s1); break;
-        case 2: run_item<2, MODEL, CT>(A, w.w, U.s2); break;
-        default: run_item<3, MODEL, CT>(A, w.w, U.s3); break;
+        case 0: run_item<0, MODEL, CT, VAR>(A, w.w, U.s0); break;
+        case 1: run_item<1, MODEL, CT, VAR>(A, w.w, U.s1); break;
+        case 2: run_item<2, MODEL, CT, VAR>(A, w.w, U.s2); break;
+        default: run_item<3, MODEL, CT, VAR>(A, w.w, U.s3); break;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -115,6 +127,13 @@ __global__ void k_offset_ptr(const int64_t *in, int64_t n, int64_t off, int64_t 
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i <= n) out[i] = in[i] + off;
+}
+
+// Concatenated block indices: out[i] = in[i] + off for i in [0, n), -1 kept.
+__global__ void k_offset_idx(const int32_t *in, int64_t n, int64_t off, int32_t *out)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = in[i] < 0 ? -1 : (int32_t)(in[i] + off);
 }
 
 __global__ void k_batch_begin(int32_t *head, int32_t *status, int n_meshes)
@@ -231,7 +250,7 @@ struct fea_batch {
     std::vector<fea_graph *> graphs;
     std::vector<int64_t> vals_off, rhs_off, slot_off, inc_off;  // scalars / slots / incidences
     int64_t n_elems = 0, total_blocks = 0, total_slots = 0, total_inc = 0;
-    int32_t tile[4] = {64, 40, 28, 16};
+    int32_t tile[4] = {75, 34, 24, 14};  // multiples of the upper-triangle tile
     std::vector<int32_t> items;  // 4 per item
     std::vector<int32_t> order;
     // device
@@ -260,6 +279,14 @@ struct fea_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     GatherBatch *gbatch = nullptr;  // row-gather form, built on first use
+    // upper-triangle form, built on first use: per-mesh views (host copy),
+    // the concatenated upper-block list, lower partners and tile-block
+    // segment bounds (global block indices and slots)
+    std::vector<BatchMesh> hmeshes;
+    bool sym_ready = false;
+    int64_t total_sym_slots = 0, total_nup = 0;
+    int32_t *d_sym_ublk = nullptr, *d_sym_lpart = nullptr;
+    int64_t *d_sym_ptr = nullptr;
 };
 
 namespace {
@@ -281,11 +308,20 @@ void destroy_batch(fea_batch *b)
         if (g) fea_graph_destroy(g);
     void *bufs[] = {b->d_meshes, b->d_items, b->d_order, b->d_head, b->d_status, b->d_vseg,
                     b->d_rseg, b->d_cycles, b->d_worker, b->d_cu, b->contrib, b->rcontrib,
-                    b->d_part};
+                    b->d_part, b->d_sym_ublk, b->d_sym_lpart, b->d_sym_ptr};
     for (void *p : bufs) dfree(p);
     for (hipEvent_t e : b->ev)
         if (e) (void)hipEventDestroy(e);
     delete b;
+}
+
+// Elements per item of family t: the requested count rounded up to a
+// multiple of the upper-triangle tile, so that items start on tile
+// boundaries in both forms.
+int64_t item_size(int32_t tile, int t)
+{
+    const int64_t e = sym_epb(t);
+    return (tile + e - 1) / e * e;
 }
 
 int build_items(fea_batch *b)
@@ -295,11 +331,12 @@ int build_items(fea_batch *b)
         for (int m = 0; m < b->n_meshes; ++m) {
             const fea_graph *g = b->graphs[m];
             const int64_t n = g->seg[t + 1] - g->seg[t];
-            for (int64_t s = 0; s < n; s += b->tile[t]) {
+            const int64_t tile = item_size(b->tile[t], t);
+            for (int64_t s = 0; s < n; s += tile) {
                 b->items.push_back(m);
                 b->items.push_back(t);
                 b->items.push_back((int32_t)s);
-                b->items.push_back((int32_t)std::min<int64_t>(b->tile[t], n - s));
+                b->items.push_back((int32_t)std::min<int64_t>(tile, n - s));
             }
         }
     const size_t ni = b->items.size() / 4;
@@ -357,29 +394,82 @@ int make_partition(fea_batch *b)
     return FEA_OK;
 }
 
-template <int MODEL, typename CT>
+template <int MODEL, typename CT, int VAR>
 int worker_count(fea_batch *b)
 {
-    const int key = MODEL * 2 + (sizeof(CT) == 4);  // MODEL 0..2
+    const int key = (MODEL * 2 + (sizeof(CT) == 4)) * 4 + VAR;  // MODEL 0..2
     if (b->workers_for == key) return FEA_OK;
     int cus = 0, per = 0;
     FEA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
-    FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<MODEL, CT>, 256, 0));
+    FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<MODEL, CT, VAR>, 256, 0));
     b->workers = std::max(1, cus * std::max(1, per));
     b->workers_for = key;
     if (!b->part_w.empty()) return make_partition(b);
     return FEA_OK;
 }
 
-template <int MODEL, typename CT, typename OT>
+// Upper-triangle layout of every mesh (built once; blocks on the stream),
+// the mesh views' tile fields and the concatenated block lists.
+int sym_prepare_batch(fea_batch *b, hipStream_t s)
+{
+    if (b->sym_ready) return FEA_OK;
+    int rc;
+    const int n = b->n_meshes;
+    std::vector<int64_t> soff(n + 1, 0), uoff(n + 1, 0), koff(n + 1, 0);
+    for (int m = 0; m < n; ++m) {
+        fea_graph *g = b->graphs[m];
+        if (!g->sready && (rc = sym_prepare(g, s))) return rc;
+        soff[m + 1] = soff[m] + g->ulen;
+        uoff[m + 1] = uoff[m] + g->nup;
+        koff[m + 1] = koff[m] + g->nnz;
+        BatchMesh &M = b->hmeshes[m];
+        M.a.tent_ptr = g->tent_ptr;
+        M.a.ttb_ptr = g->ttb_ptr;
+        M.a.tent = g->tent;
+        M.a.tb_eend = g->tb_eend;
+        M.a.tb_slot = g->tb_slot;
+        std::copy(g->tile_base, g->tile_base + 5, M.tile_base);
+        M.scoff = soff[m];
+    }
+    dfree(b->d_sym_ublk);
+    dfree(b->d_sym_lpart);
+    dfree(b->d_sym_ptr);
+    b->d_sym_ublk = b->d_sym_lpart = nullptr;
+    b->d_sym_ptr = nullptr;
+    if ((rc = dalloc((void **)&b->d_sym_ublk, sizeof(int32_t) * std::max<int64_t>(uoff[n], 1)))) return rc;
+    if ((rc = dalloc((void **)&b->d_sym_lpart, sizeof(int32_t) * std::max<int64_t>(koff[n], 1)))) return rc;
+    if ((rc = dalloc((void **)&b->d_sym_ptr, sizeof(int64_t) * (koff[n] + 1)))) return rc;
+    if (koff[n] > INT32_MAX) return set_error(FEA_ERANGE, "batch has more than 2^31 blocks");
+    int64_t zero = 0;
+    FEA_HIP(hipMemcpy(b->d_sym_ptr, &zero, sizeof(int64_t), hipMemcpyHostToDevice));
+    for (int m = 0; m < n; ++m) {
+        const fea_graph *g = b->graphs[m];
+        if (g->nup) k_offset_idx<<<grid_for(g->nup, 256), 256, 0, s>>>(g->ublk, g->nup, koff[m], b->d_sym_ublk + uoff[m]);
+        if (g->nnz) {
+            k_offset_idx<<<grid_for(g->nnz, 256), 256, 0, s>>>(g->lpart, g->nnz, koff[m], b->d_sym_lpart + koff[m]);
+            k_offset_ptr<<<grid_for(g->nnz + 1, 256), 256, 0, s>>>(g->ts_ptr, g->nnz, soff[m], b->d_sym_ptr + koff[m]);
+        }
+    }
+    FEA_HIP(hipGetLastError());
+    if (n) FEA_HIP(hipMemcpy(b->d_meshes, b->hmeshes.data(), sizeof(BatchMesh) * n, hipMemcpyHostToDevice));
+    FEA_HIP(hipStreamSynchronize(s));
+    b->total_sym_slots = soff[n];
+    b->total_nup = uoff[n];
+    b->sym_ready = true;
+    return FEA_OK;
+}
+
+template <int MODEL, typename CT, typename OT, int VAR>
 int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void *rhs,
                  int32_t *status)
 {
     constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
     constexpr int BB = B * B;
+    constexpr bool SYM = VAR == V_ROWSYM;
     int rc;
-    if ((rc = worker_count<MODEL, CT>(b))) return rc;
-    const size_t need_c = sizeof(CT) * (size_t)b->total_slots * BB;
+    if (SYM && (rc = sym_prepare_batch(b, s))) return rc;
+    if ((rc = worker_count<MODEL, CT, VAR>(b))) return rc;
+    const size_t need_c = sizeof(CT) * (size_t)std::max<int64_t>(SYM ? b->total_sym_slots : b->total_slots, 1) * BB;
     const size_t need_r = sizeof(CT) * (size_t)b->total_inc * B;
     if (b->contrib_bytes < need_c) {
         dfree(b->contrib);
@@ -399,13 +489,19 @@ int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, 
     k_batch_begin<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_head, b->d_status, b->n_meshes);
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[0], s));
     if (ni)
-        k_batch<MODEL, CT><<<b->workers, 256, 0, s>>>(b->d_meshes, b->d_items, b->d_order, ni, b->d_head,
+        k_batch<MODEL, CT, VAR><<<b->workers, 256, 0, s>>>(b->d_meshes, b->d_items, b->d_order, ni, b->d_head,
                                                       b->part_for == b->workers ? b->d_part : nullptr,
                                                       (CT *)b->contrib, (CT *)b->rcontrib, b->d_status,
                                                       b->d_cycles, b->d_worker, b->d_cu);
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[1], s));
     const int64_t nv = b->total_blocks * BB, nr = b->rhs_off.back();
-    if (nv) launch_segsum<BB, CT, OT, false>(b->total_blocks, nullptr, nullptr, b->d_vseg, (const CT *)b->contrib, (OT *)vals, s);
+    if (SYM) {
+        if (b->total_nup)
+            launch_segsum<BB, CT, OT, true>(b->total_nup, b->d_sym_ublk, b->d_sym_lpart, b->d_sym_ptr,
+                                            (const CT *)b->contrib, (OT *)vals, s);
+    } else if (nv) {
+        launch_segsum<BB, CT, OT, false>(b->total_blocks, nullptr, nullptr, b->d_vseg, (const CT *)b->contrib, (OT *)vals, s);
+    }
     if (nr) launch_segsum<B, CT, OT, false>(nr / B, nullptr, nullptr, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs, s);
     k_batch_end<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_status, b->n_meshes, status);
     FEA_HIP(hipGetLastError());
@@ -440,36 +536,43 @@ int dispatch_gather(fea_batch *b, const fea_options *o, hipStream_t s, void *val
     return FEA_OK;
 }
 
-int dispatch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void *rhs, int32_t *status)
+template <int VAR>
+int dispatch_var(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void *rhs, int32_t *status)
 {
-    if (o->variant == FEA_ROWGATHER) return dispatch_gather(b, o, s, vals, rhs, status);
     const bool f32 = o->out_dtype == FEA_F32;
     if (b->model == FEA_POISSON) {
         if (o->precision == FEA_FP64)
-            return f32 ? launch_batch<FEA_POISSON, double, float>(b, o, s, vals, rhs, status)
-                       : launch_batch<FEA_POISSON, double, double>(b, o, s, vals, rhs, status);
-        return f32 ? launch_batch<FEA_POISSON, float, float>(b, o, s, vals, rhs, status)
-                   : launch_batch<FEA_POISSON, float, double>(b, o, s, vals, rhs, status);
+            return f32 ? launch_batch<FEA_POISSON, double, float, VAR>(b, o, s, vals, rhs, status)
+                       : launch_batch<FEA_POISSON, double, double, VAR>(b, o, s, vals, rhs, status);
+        return f32 ? launch_batch<FEA_POISSON, float, float, VAR>(b, o, s, vals, rhs, status)
+                   : launch_batch<FEA_POISSON, float, double, VAR>(b, o, s, vals, rhs, status);
     }
     if (b->has_nh) {
         if (o->precision == FEA_FP64)
-            return f32 ? launch_batch<M_ELASTIC_NH, double, float>(b, o, s, vals, rhs, status)
-                       : launch_batch<M_ELASTIC_NH, double, double>(b, o, s, vals, rhs, status);
-        return f32 ? launch_batch<M_ELASTIC_NH, float, float>(b, o, s, vals, rhs, status)
-                   : launch_batch<M_ELASTIC_NH, float, double>(b, o, s, vals, rhs, status);
+            return f32 ? launch_batch<M_ELASTIC_NH, double, float, VAR>(b, o, s, vals, rhs, status)
+                       : launch_batch<M_ELASTIC_NH, double, double, VAR>(b, o, s, vals, rhs, status);
+        return f32 ? launch_batch<M_ELASTIC_NH, float, float, VAR>(b, o, s, vals, rhs, status)
+                   : launch_batch<M_ELASTIC_NH, float, double, VAR>(b, o, s, vals, rhs, status);
     }
     if (o->precision == FEA_FP64)
-        return f32 ? launch_batch<FEA_ELASTIC, double, float>(b, o, s, vals, rhs, status)
-                   : launch_batch<FEA_ELASTIC, double, double>(b, o, s, vals, rhs, status);
-    return f32 ? launch_batch<FEA_ELASTIC, float, float>(b, o, s, vals, rhs, status)
-               : launch_batch<FEA_ELASTIC, float, double>(b, o, s, vals, rhs, status);
+        return f32 ? launch_batch<FEA_ELASTIC, double, float, VAR>(b, o, s, vals, rhs, status)
+                   : launch_batch<FEA_ELASTIC, double, double, VAR>(b, o, s, vals, rhs, status);
+    return f32 ? launch_batch<FEA_ELASTIC, float, float, VAR>(b, o, s, vals, rhs, status)
+               : launch_batch<FEA_ELASTIC, float, double, VAR>(b, o, s, vals, rhs, status);
+}
+
+int dispatch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void *rhs, int32_t *status)
+{
+    if (o->variant == FEA_ROWGATHER) return dispatch_gather(b, o, s, vals, rhs, status);
+    if (o->variant == FEA_ROWSYM) return dispatch_var<V_ROWSYM>(b, o, s, vals, rhs, status);
+    return dispatch_var<V_ROWOWNER>(b, o, s, vals, rhs, status);
 }
 
 int check_opts(const fea_batch *b, const fea_options *o)
 {
     if (!b || !o) return set_error(FEA_EINVAL, "batch and options are required");
-    if (o->variant != FEA_ROWOWNER && o->variant != FEA_ROWGATHER)
-        return set_error(FEA_EINVAL, "batched assembly is row-owner or row-gather");
+    if (o->variant != FEA_ROWOWNER && o->variant != FEA_ROWGATHER && o->variant != FEA_ROWSYM)
+        return set_error(FEA_EINVAL, "batched assembly is row-owner, upper-triangle or row-gather");
     if (o->precision < 0 || o->precision > 1 || o->out_dtype < 0 || o->out_dtype > 1)
         return set_error(FEA_EINVAL, "bad option");
     int dev = 0;
@@ -552,6 +655,7 @@ int build(int n, const fea_mesh_desc *md, int model, const int32_t *tile, hipStr
         bm[m].coff = b->slot_off[m];
         bm[m].roff = b->inc_off[m];
     }
+    b->hmeshes = bm;
     if ((rc = dalloc((void **)&b->d_meshes, sizeof(BatchMesh) * std::max(n, 1)))) return rc;
     if (n) FEA_HIP(hipMemcpy(b->d_meshes, bm.data(), sizeof(BatchMesh) * n, hipMemcpyHostToDevice));
     if ((rc = dalloc((void **)&b->d_head, sizeof(int32_t)))) return rc;
@@ -580,7 +684,8 @@ int build(int n, const fea_mesh_desc *md, int model, const int32_t *tile, hipStr
 
 namespace {
 
-const int kEPB[4] = {16, 10, 7, 4};
+// item sizes tried by the autotuner: multiples of the upper-triangle tile
+const int kEPB[4] = {sym_epb(0), sym_epb(1), sym_epb(2), sym_epb(3)};
 const int kNQ[4] = {1, 8, 6, 8};
 
 int upload_order(fea_batch *b)
@@ -626,7 +731,8 @@ extern "C" int fea_batch_autotune(fea_batch *b, const fea_options *opt, int reps
     clear_error();
     int rc = check_opts(b, opt);
     if (rc) return rc;
-    if (opt->variant != FEA_ROWOWNER) return set_error(FEA_EINVAL, "tiles are tuned for the row-owner work items");
+    if (opt->variant != FEA_ROWOWNER && opt->variant != FEA_ROWSYM)
+        return set_error(FEA_EINVAL, "tiles are tuned for the row-owner and upper-triangle work items");
     if (reps < 1) return set_error(FEA_EINVAL, "reps must be positive");
     if ((rc = ensure_tables())) return rc;
     const size_t esz = opt->out_dtype == FEA_F32 ? 4 : 8;

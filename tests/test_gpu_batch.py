@@ -102,6 +102,7 @@ def test_queue_order_and_tiles_do_not_change_results():
         b.set_order(rng.permutation(b.n_items))
         v, r, _ = b.assemble()
         assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
+    sym_epb = (25, 17, 12, 7)
     for tile in ([16, 10, 7, 4], [1, 3, 5, 7], [256, 160, 112, 64]):
         b.set_tiles(tile)
         counts = b.items[:, 3]
@@ -109,7 +110,10 @@ def test_queue_order_and_tiles_do_not_change_results():
         for t in range(4):
             sel = fam == t
             if sel.any():
-                assert counts[sel].max() <= tile[t]
+                # items are whole upper-triangle tiles (the last one of a
+                # family may be partial) and start on tile boundaries
+                assert counts[sel].max() <= -(-tile[t] // sym_epb[t]) * sym_epb[t]
+                assert np.all(b.items[sel, 2] % sym_epb[t] == 0)
         v, r, _ = b.assemble()
         assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
     with pytest.raises(fea.FeaError):
@@ -240,6 +244,82 @@ def test_batch_rowgather_against_oracle_and_replay():
             assert within_fp32_bound(vm, ov, tv, L, 1e-12 * row_scale(ov, og.row_ptr, 3)) <= 1.0
             assert within_fp32_bound(rm, orr, tr, L, 1e-12 * np.abs(orr).max()) <= 1.0
         b.capture(v2, r2, st2, precision=fea.MIXED, out_dtype=fea.F32, variant=fea.ROWGATHER)
+        for rep in range(3):
+            v2.fill_(float("nan"))
+            r2.fill_(float("nan"))
+            st2.fill_(123)
+            b.replay(1)
+            s.synchronize()
+            assert (v2.cpu().numpy().tobytes(), r2.cpu().numpy().tobytes()) == ref, rep
+            assert np.all(st2.cpu().numpy() == -1)
+
+
+@pytest.mark.parametrize("precision", [fea.FP64, fea.MIXED])
+@pytest.mark.parametrize("model", [fea.POISSON, fea.ELASTIC])
+def test_batch_rowsym_matches_single_mesh_rowsym(model, precision):
+    """The batched upper-triangle form runs the one-mesh tiles (items start
+    on tile boundaries) with the same summation order; the persistent and
+    one-mesh kernels are compiled separately, so FMA contraction may differ
+    in the last bits: compared at 1e-13 of the row scale (FP64) or 1e-6
+    (mixed)."""
+    st = state()
+    use_nh = model == fea.ELASTIC
+    b = fea.Batch(st["dms"], model=model, use_nh=use_nh)
+    out = fea.F64 if precision == fea.FP64 else fea.F32
+    vals, rhs, status = b.assemble(precision=precision, out_dtype=out, variant=fea.ROWSYM)
+    torch.cuda.synchronize()
+    assert np.all(status.cpu().numpy() == -1)
+    B = 1 if model == fea.POISSON else 3
+    for m, (dm, g) in enumerate(zip(st["dms"], st["graphs"])):
+        v1, r1, _ = dm.assemble(g, model=model, use_nh=use_nh, variant=fea.ROWSYM,
+                                precision=precision, out_dtype=out)
+        torch.cuda.synchronize()
+        vb, rb = per_mesh(vals, rhs, b, m)
+        ev, er = fp64_errors(vb.astype(np.float64), v1.cpu().numpy().astype(np.float64),
+                             g.export()["row_ptr"].cpu().numpy(), B, rb.astype(np.float64),
+                             r1.cpu().numpy().astype(np.float64))
+        tol = 1e-13 if precision == fea.FP64 else 1e-6
+        assert ev <= tol and er <= tol, (m, ev, er)
+
+
+def test_batch_rowsym_against_oracle_order_tiles_and_replay():
+    st = state()
+    b = fea.Batch(st["dms"], model=fea.ELASTIC, use_nh=True)
+    vals, rhs, _ = b.assemble(variant=fea.ROWSYM)
+    torch.cuda.synchronize()
+    ref64 = (vals.cpu().numpy().tobytes(), rhs.cpu().numpy().tobytes())
+    for m, mesh in enumerate(st["meshes"]):
+        og = oracle.mesh_graph(mesh)
+        ov, orr, tv, tr = oracle.assemble(mesh, og, with_terms=True)
+        vb, rb = per_mesh(vals, rhs, b, m)
+        ev, er = fp64_errors(vb, ov, og.row_ptr, 3, rb, orr)
+        assert ev <= 1e-12 and er <= 1e-12, (m, ev, er)
+    # queue order, static partitions and item sizes do not change the result
+    rng = np.random.default_rng(11)
+    b.set_order(rng.permutation(b.n_items))
+    v, r, _ = b.assemble(variant=fea.ROWSYM)
+    assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref64
+    b.set_tiles([50, 17, 36, 28])
+    v, r, _ = b.assemble(variant=fea.ROWSYM)
+    assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref64
+    b.order(fea.GP_WEIGHT)
+    b.partition(fea.GP_WEIGHT)
+    v, r, _ = b.assemble(variant=fea.ROWSYM)
+    assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref64
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        v2, r2, st2 = b.outputs(fea.F32)
+        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=v2, rhs=r2, status=st2, variant=fea.ROWSYM)
+        s.synchronize()
+        ref = (v2.cpu().numpy().tobytes(), r2.cpu().numpy().tobytes())
+        for m, mesh in enumerate(st["meshes"]):
+            og = oracle.mesh_graph(mesh)
+            ov, orr, tv, tr = oracle.assemble(mesh, og, with_terms=True)
+            vm, rm = per_mesh(v2, r2, b, m)
+            L = fp32_bound_L(mesh.types)
+            assert within_fp32_bound(vm, ov, tv, L, 1e-12 * row_scale(ov, og.row_ptr, 3)) <= 1.0
+            assert within_fp32_bound(rm, orr, tr, L, 1e-12 * np.abs(orr).max()) <= 1.0
+        b.capture(v2, r2, st2, precision=fea.MIXED, out_dtype=fea.F32, variant=fea.ROWSYM)
         for rep in range(3):
             v2.fill_(float("nan"))
             r2.fill_(float("nan"))

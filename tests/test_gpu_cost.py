@@ -134,7 +134,7 @@ def test_autotune_picks_candidates_and_persists():
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tiles.txt")
         tile = b.autotune(precision=fea.MIXED, out_dtype=fea.F32, reps=3, table_path=path)
-        epb = (16, 10, 7, 4)
+        epb = (25, 17, 12, 7)
         for t in range(4):
             assert tile[t] % epb[t] == 0 and tile[t] // epb[t] in (1, 2, 4, 8, 16, 32)
         assert list(fea.tile_table_load(path, fea.ELASTIC, fea.MIXED)) == list(tile)
