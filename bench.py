@@ -166,9 +166,10 @@ def _median_ms(fn, reps):
 
 def batched_workload(fea, mg, torch):
     """64 independent meshes (8^3..48^3 cells, random family mix, jitter
-    0.25 h) in one persistent launch, mixed precision, tiles autotuned,
-    replayed 100 times from a HIP graph; then the same batch in the
-    row-gather form (FP64 and mixed), also replayed from a graph."""
+    0.25 h) in one persistent launch of the upper-triangle form, mixed
+    precision, tiles autotuned, replayed 100 times from a HIP graph; then
+    the same batch in the row-owner and row-gather forms, also replayed
+    from graphs."""
     import tempfile
     meshes = mg.batched(64)
     dms = [fea.DeviceMesh(m) for m in meshes]
@@ -177,15 +178,19 @@ def batched_workload(fea, mg, torch):
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         vals, rhs, status = b.outputs(fea.F32)
-        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs, status=status, timing=True)
+        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs, status=status, timing=True,
+                   variant=fea.ROWSYM)
         side.synchronize()
         default_ms = _median_ms(lambda: (b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs,
-                                                    status=status, timing=True), b.last_ms())[1], 5)
+                                                    status=status, timing=True, variant=fea.ROWSYM),
+                                         b.last_ms())[1], 5)
         with tempfile.TemporaryDirectory() as d:
-            tile = b.autotune(precision=fea.MIXED, out_dtype=fea.F32, reps=3, table_path=f"{d}/tiles.txt")
+            tile = b.autotune(precision=fea.MIXED, out_dtype=fea.F32, reps=3, table_path=f"{d}/tiles.txt",
+                              variant=fea.ROWSYM)
         tuned_ms = _median_ms(lambda: (b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs,
-                                                  status=status, timing=True), b.last_ms())[1], 5)
-        b.capture(vals, rhs, status, precision=fea.MIXED, out_dtype=fea.F32)
+                                                  status=status, timing=True, variant=fea.ROWSYM),
+                                       b.last_ms())[1], 5)
+        b.capture(vals, rhs, status, precision=fea.MIXED, out_dtype=fea.F32, variant=fea.ROWSYM)
         b.replay(3)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(side)
@@ -194,8 +199,19 @@ def batched_workload(fea, mg, torch):
         side.synchronize()
         ms = e0.elapsed_time(e1) / 100
         ok = bool((status.cpu() == -1).all())
-        # the same batch in the row-gather form: one launch per tile class
+        # the same batch in the row-owner form (same items) and the
+        # row-gather form (one launch per tile class)
         gather = {}
+        b.capture(vals, rhs, status, precision=fea.MIXED, out_dtype=fea.F32, variant=fea.ROWOWNER)
+        b.replay(3)
+        e0.record(side)
+        b.replay(100)
+        e1.record(side)
+        side.synchronize()
+        oms = e0.elapsed_time(e1) / 100
+        gather["rowowner_mixed"] = {"ms_per_replay": round(oms, 4),
+                                    "elements_per_s": round(b.n_elems / (oms * 1e-3), 1),
+                                    "status_ok": bool((status.cpu() == -1).all())}
         for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
             gv, gr, gs = b.outputs(o)
             b.assemble(precision=p, out_dtype=o, vals=gv, rhs=gr, status=gs, variant=fea.ROWGATHER)
@@ -212,7 +228,7 @@ def batched_workload(fea, mg, torch):
             del gv, gr, gs
     return {"workload": "batched64-elasticity (64 meshes, 8^3..48^3 cells, jitter 0.25h)",
             "elements": int(b.n_elems), "items": int(b.n_items), "items_default_tiles": int(n_items_default),
-            "precision": "mixed", "tiles": [int(t) for t in tile],
+            "precision": "mixed", "variant": "rowsym", "tiles": [int(t) for t in tile],
             "persistent_kernel_ms_default_tiles": round(default_ms, 4),
             "persistent_kernel_ms_tuned_tiles": round(tuned_ms, 4),
             "ms_per_replay": round(ms, 4), "elements_per_s": round(b.n_elems / (ms * 1e-3), 1),
@@ -239,8 +255,9 @@ def copy_bandwidth(torch):
 
 def large_workload(fea, mg, torch, np, cells=256):
     """53.9M-element hybrid mesh (40/30/20/10 hex/tet/pen/pyr layers) through
-    the persistent path (plain FP64 against mixed precision with the learned
-    schedule), then through the fused row-gather form."""
+    the persistent path in the upper-triangle form (plain FP64 against mixed
+    precision with the learned schedule; row-owner FP64 for reference), then
+    one-mesh assemblies in the row-gather and upper-triangle forms."""
     mesh = mg.hybrid_split(cells, seed=5)
     dm = fea.DeviceMesh(mesh)
     b = fea.Batch([dm], model=fea.ELASTIC)
@@ -248,15 +265,15 @@ def large_workload(fea, mg, torch, np, cells=256):
            "elements": int(mesh.n_elems), "nodes": int(mesh.n_nodes), "nnz_blocks": int(b.vals_len // 9),
            "items": int(b.n_items)}
 
-    def run(precision, reps=5):
+    def run(precision, reps=5, variant=fea.ROWSYM):
         outd = fea.F64 if precision == fea.FP64 else fea.F32
         vals, rhs, st = b.outputs(outd)
-        b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st)
+        b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st, variant=variant)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         tot = []
         for _ in range(reps):
             e0.record()
-            b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st)
+            b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st, variant=variant)
             e1.record()
             torch.cuda.synchronize()
             tot.append(e0.elapsed_time(e1))
@@ -265,6 +282,7 @@ def large_workload(fea, mg, torch, np, cells=256):
         return {"total_ms": round(float(np.median(tot)), 3),
                 "elements_per_s": round(mesh.n_elems / (float(np.median(tot)) * 1e-3), 1), "status_ok": ok}
 
+    out["fp64_type_sorted_rowowner"] = run(fea.FP64, variant=fea.ROWOWNER)
     out["fp64_type_sorted"] = run(fea.FP64)
     out["mixed_type_sorted"] = run(fea.MIXED)
     c, _, _ = b.cycles()
@@ -313,15 +331,16 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
     dm = fea.DeviceMesh(mesh)
     b = fea.Batch([dm], model=fea.ELASTIC, use_nh=True)
 
-    def run(precision, reps=9):
+    def run(precision, reps=9, variant=fea.ROWSYM):
         outd = fea.F64 if precision == fea.FP64 else fea.F32
         vals, rhs, st = b.outputs(outd)
-        b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st)
+        b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st, variant=variant)
         kern, tot = [], []
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         for _ in range(reps):
             e0.record()
-            b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st, timing=True)
+            b.assemble(precision=precision, out_dtype=outd, vals=vals, rhs=rhs, status=st, timing=True,
+                       variant=variant)
             e1.record()
             torch.cuda.synchronize()
             kern.append(b.last_ms())
@@ -335,7 +354,9 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
                 "load_balance": round(float(busy.sum() / (busy.size * busy.max())), 4)}, vals, st
 
     out = {"workload": f"hetero{cells}-elasticity (30% neo-Hookean bricks, 40/30/20/10 hex/tet/pen/pyr)",
-           "elements": int(mesh.n_elems), "items": int(b.n_items), "workers": 0}
+           "elements": int(mesh.n_elems), "items": int(b.n_items), "workers": 0,
+           "variant": "rowsym (persistent kernel)"}
+    out["fp64_type_sorted_rowowner"], _, _ = run(fea.FP64, variant=fea.ROWOWNER)
     fp64_ts, v64, st64 = run(fea.FP64)
     out["fp64_type_sorted"] = fp64_ts
     mix_ts, vmx, stm = run(fea.MIXED)
@@ -346,7 +367,7 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
     vals, rhs, st = b.outputs(fea.F32)
     logs = []
     for _ in range(5):
-        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs, status=st)
+        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs, status=st, variant=fea.ROWSYM)
         c, _, _ = b.cycles()
         logs.append(fea.CostModel.log_cycles(c))
     target = torch.stack(logs).mean(dim=0).contiguous()

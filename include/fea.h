@@ -229,12 +229,15 @@ int fea_batch_items(const fea_batch *b, int32_t *items);
 int fea_batch_set_tiles(fea_batch *b, const int32_t *tile);
 
 /* Sets the queue order: HOST permutation of 0..n_items-1, item order[j] is
- * dequeued j-th. Drops a captured graph. FEA_EINVAL if not a permutation. */
+ * dequeued j-th among the items of its family (each family has its own
+ * persistent launch and queue, in family order). Returns to the dynamic
+ * queue and drops a captured graph. FEA_EINVAL if not a permutation. */
 int fea_batch_set_order(fea_batch *b, const int32_t *order);
 
 /*
- * One batched assembly on `stream`: reset the queue head, one persistent
- * kernel (row-owner slot contributions, FP64 or mixed per opt->precision),
+ * One batched assembly on `stream`: reset the queue heads, one persistent
+ * kernel per element family, each dequeuing that family's items in queue
+ * order (row-owner slot contributions, FP64 or mixed per opt->precision),
  * then the block-value and right-hand-side reductions over all meshes.
  * vals/rhs: device buffers of the lengths from fea_batch_sizes, element
  * type opt->out_dtype, overwritten. status: device int32[n_meshes] (may be
@@ -309,9 +312,10 @@ int fea_batch_order(fea_batch *b, int schedule, const float *pred, hipStream_t s
 
 /*
  * Static partition instead of the dynamic queue: the items, in type-sorted
- * order (neighbouring elements stay together), are split into one
- * contiguous range per persistent workgroup with nearly equal total weight,
- * and every workgroup runs its own range without touching the queue head.
+ * order (neighbouring elements stay together), are split, family by
+ * family, into one contiguous range per persistent workgroup of that
+ * family's launch with nearly equal total weight, and every workgroup runs
+ * its own range without touching the queue head.
  * The counterpart of the paper's weighted partitions (Section 4.1):
  * weights = FEA_TYPE_SORTED: element count (non-weighted); FEA_GP_WEIGHT:
  * Gauss points x elements; FEA_LEARNED: exp(pred[item]) with pred a

@@ -377,9 +377,11 @@ class Batch:
         _check(_lib.fea_batch_last_ms(self._h, ctypes.byref(ms)))
         return float(ms.value)
 
-    def autotune(self, precision=FP64, out_dtype=F64, reps=5, table_path=None, stream=None):
+    def autotune(self, precision=FP64, out_dtype=F64, reps=5, table_path=None, stream=None, variant=ROWOWNER):
         import numpy as np
-        opt = Options(precision, ROWOWNER, out_dtype, 0)
+        if isinstance(variant, str):
+            variant = VARIANTS[variant]
+        opt = Options(precision, variant, out_dtype, 0)
         tile = np.zeros(4, dtype=np.int32)
         path = table_path.encode() if table_path else None
         _check(_lib.fea_batch_autotune(self._h, ctypes.byref(opt), int(reps), path, _stream(stream),

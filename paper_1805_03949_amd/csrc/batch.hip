@@ -38,14 +38,6 @@ struct BatchMesh {
     int64_t scoff;         // first tile-block of this mesh in its workspace
 };
 
-template <int MODEL, typename CT, int VAR>
-union BatchSmem {
-    ElemSmem<0, MODEL, VAR, CT> s0;
-    ElemSmem<1, MODEL, VAR, CT> s1;
-    ElemSmem<2, MODEL, VAR, CT> s2;
-    ElemSmem<3, MODEL, VAR, CT> s3;
-};
-
 template <int T, int MODEL, typename CT, int VAR>
 __device__ inline void run_item(ElemArgs &A, int32_t count, ElemSmem<T, MODEL, VAR, CT> &S)
 {
@@ -54,20 +46,21 @@ __device__ inline void run_item(ElemArgs &A, int32_t count, ElemSmem<T, MODEL, V
     for (int32_t sub = 0; sub < count; sub += EPB) elem_tile<T, MODEL, VAR, CT>(A, sub, S, opaque_tid());
 }
 
-// Persistent kernel: every workgroup dequeues items until the queue is
-// empty (each workgroup reaches the exit test after every item). The
-// register budget is capped at three waves per SIMD: the four element
-// families inlined into one loop would otherwise take the whole register
-// file (one wave per SIMD).
-template <int MODEL, typename CT, int VAR>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_batch(const BatchMesh *meshes, const int4 *items,
+// Persistent kernel of one element family: every workgroup dequeues items
+// of family T until that family's queue is empty (each workgroup reaches
+// the exit test after every item). One launch per family keeps each
+// family's registers and LDS as small as its own element code needs: one
+// kernel holding all four families' code paths took more than 128 VGPRs
+// and ran 1.5x slower.
+template <int T, int MODEL, typename CT, int VAR>
+__global__ void __launch_bounds__(256) k_batch(const BatchMesh *meshes, const int4 *items,
                                                const int32_t *order, int32_t n_items,
                                                int32_t *head, const int32_t *part, CT *contrib,
                                                CT *rcontrib, int32_t *status, uint64_t *cycles,
                                                int32_t *worker, int32_t *cu)
 {
     constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
-    __shared__ BatchSmem<MODEL, CT, VAR> U;
+    __shared__ ElemSmem<T, MODEL, VAR, CT> S;
     __shared__ int32_t s_item;
     // static partition: this workgroup runs order[part[w] .. part[w+1])
     int32_t next = part ? part[blockIdx.x] : 0;
@@ -94,25 +87,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
         A.rcontrib = rcontrib + M.roff * B;
         if constexpr (VAR == V_ROWSYM) {
             // the item starts at a tile boundary
-            const int64_t tl = M.tile_base[w.y] + w.z / sym_epb(w.y);
+            const int64_t tl = M.tile_base[T] + w.z / sym_epb(T);
             A.tent_ptr = M.a.tent_ptr + tl;
             A.ttb_ptr = M.a.ttb_ptr + tl;
         }
-        A.elems = M.a.elems + M.seg[w.y] + w.z;
+        A.elems = M.a.elems + M.seg[T] + w.z;
         A.n = w.w;
         {
-            const int64_t nn = nodes_of(w.y);
-            A.pnodes = M.a.pnodes + M.node_base[w.y] + (int64_t)w.z * nn;
-            A.prdest = M.a.prdest + M.node_base[w.y] + (int64_t)w.z * nn;
-            A.pdest = M.a.pdest + M.slot_base[w.y] + (int64_t)w.z * nn * nn;
+            constexpr int64_t nn = nodes_of(T);
+            A.pnodes = M.a.pnodes + M.node_base[T] + (int64_t)w.z * nn;
+            A.prdest = M.a.prdest + M.node_base[T] + (int64_t)w.z * nn;
+            A.pdest = M.a.pdest + M.slot_base[T] + (int64_t)w.z * nn * nn;
         }
         A.status = status + w.x;
-        switch (w.y) {
-        case 0: run_item<0, MODEL, CT, VAR>(A, w.w, U.s0); break;
-        case 1: run_item<1, MODEL, CT, VAR>(A, w.w, U.s1); break;
-        case 2: run_item<2, MODEL, CT, VAR>(A, w.w, U.s2); break;
-        default: run_item<3, MODEL, CT, VAR>(A, w.w, U.s3); break;
-        }
+        run_item<T, MODEL, CT, VAR>(A, w.w, S);
         __syncthreads();
         if (threadIdx.x == 0) {
             cycles[it] = clock64() - t0;
@@ -139,7 +127,7 @@ __global__ void k_offset_idx(const int32_t *in, int64_t n, int64_t off, int32_t 
 __global__ void k_batch_begin(int32_t *head, int32_t *status, int n_meshes)
 {
     int i = blockIdx.x * 256 + threadIdx.x;
-    if (i == 0) *head = 0;
+    if (i < 4) head[i] = 0;  // one queue head per family
     if (i < n_meshes) status[i] = INT_MAX;
 }
 
@@ -267,8 +255,14 @@ struct fea_batch {
     size_t contrib_bytes = 0;
     void *rcontrib = nullptr;
     size_t rcontrib_bytes = 0;
-    int workers = 0;
-    int workers_for = -1;  // (model, precision) the worker count was computed for
+    int workers = 0;       // the largest of the per-family worker counts
+    int fworkers[4] = {0, 0, 0, 0};
+    int workers_for = -1;  // (model, precision, form) the worker counts were computed for
+    // the device queue holds the order grouped by family (stable): family
+    // t's items are d_order[foff[t] .. foff[t+1]); its static partition
+    // (fworkers[t] + 1 bounds) starts at d_part[poff[t]]
+    int64_t foff[5] = {0, 0, 0, 0, 0};
+    int64_t poff[5] = {0, 0, 0, 0, 0};
     // static partition of the order over the workers (used when part_for
     // equals the current worker count; -1 = dynamic queue)
     std::vector<double> part_w;  // item weights of the requested partition
@@ -315,6 +309,24 @@ void destroy_batch(fea_batch *b)
     delete b;
 }
 
+// Uploads the queue order grouped by family (stable: within a family the
+// order is kept) and records the family offsets.
+int upload_grouped_order(fea_batch *b)
+{
+    const size_t ni = b->items.size() / 4;
+    std::vector<int32_t> g;
+    g.reserve(ni);
+    b->foff[0] = 0;
+    for (int t = 0; t < 4; ++t) {
+        for (size_t j = 0; j < ni; ++j)
+            if (b->items[4 * (size_t)b->order[j] + 1] == t) g.push_back(b->order[j]);
+        b->foff[t + 1] = (int64_t)g.size();
+    }
+    if (ni) FEA_HIP(hipMemcpy(b->d_order, g.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice));
+    drop_graph(b);
+    return FEA_OK;
+}
+
 // Elements per item of family t: the requested count rounded up to a
 // multiple of the upper-triangle tile, so that items start on tile
 // boundaries in both forms.
@@ -359,38 +371,56 @@ int build_items(fea_batch *b)
         if ((rc = dalloc((void **)&b->d_cu, sizeof(int32_t) * ni))) return rc;
         b->items_cap = ni;
     }
-    if (ni) {
-        FEA_HIP(hipMemcpy(b->d_items, b->items.data(), sizeof(int4) * ni, hipMemcpyHostToDevice));
-        FEA_HIP(hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice));
+    if (ni) FEA_HIP(hipMemcpy(b->d_items, b->items.data(), sizeof(int4) * ni, hipMemcpyHostToDevice));
+    return upload_grouped_order(b);
+}
+
+// Splits each family's part of the queue order into that family's worker
+// count of contiguous ranges of nearly equal total weight (cut where the
+// running sum crosses k * total / workers).
+int make_partition(fea_batch *b)
+{
+    const size_t ni = b->order.size();
+    std::vector<int32_t> g;
+    g.reserve(ni);
+    for (int t = 0; t < 4; ++t)
+        for (size_t j = 0; j < ni; ++j)
+            if (b->items[4 * (size_t)b->order[j] + 1] == t) g.push_back(b->order[j]);
+    std::vector<int32_t> part;
+    for (int t = 0; t < 4; ++t) {
+        const int W = std::max(1, b->fworkers[t]);
+        const int64_t j0 = b->foff[t], n = b->foff[t + 1] - j0;
+        b->poff[t] = (int64_t)part.size();
+        std::vector<int32_t> pt(W + 1, 0);
+        double total = 0.0;
+        for (int64_t j = 0; j < n; ++j) total += b->part_w[g[j0 + j]];
+        double run = 0.0;
+        int k = 1;
+        for (int64_t j = 0; j < n && k < W; ++j) {
+            const double wj = b->part_w[g[j0 + j]];
+            while (k < W && run + 0.5 * wj >= total * k / W) pt[k++] = (int32_t)j;
+            run += wj;
+        }
+        while (k <= W) pt[k++] = (int32_t)n;
+        part.insert(part.end(), pt.begin(), pt.end());
     }
+    b->poff[4] = (int64_t)part.size();
+    dfree(b->d_part);
+    b->d_part = nullptr;
+    int rc = dalloc((void **)&b->d_part, sizeof(int32_t) * part.size());
+    if (rc) return rc;
+    FEA_HIP(hipMemcpy(b->d_part, part.data(), sizeof(int32_t) * part.size(), hipMemcpyHostToDevice));
+    b->part_for = b->workers_for;
     drop_graph(b);
     return FEA_OK;
 }
 
-// Splits the current order into `workers` contiguous ranges of nearly equal
-// total weight (cut where the running sum crosses k * total / workers).
-int make_partition(fea_batch *b)
+template <int T, int MODEL, typename CT, int VAR>
+int family_workers(int cus, int *w)
 {
-    const int W = b->workers;
-    const size_t ni = b->order.size();
-    std::vector<int32_t> part(W + 1, 0);
-    double total = 0.0;
-    for (size_t j = 0; j < ni; ++j) total += b->part_w[b->order[j]];
-    double run = 0.0;
-    int k = 1;
-    for (size_t j = 0; j < ni && k < W; ++j) {
-        const double wj = b->part_w[b->order[j]];
-        while (k < W && run + 0.5 * wj >= total * k / W) part[k++] = (int32_t)j;
-        run += wj;
-    }
-    while (k <= W) part[k++] = (int32_t)ni;
-    dfree(b->d_part);
-    b->d_part = nullptr;
-    int rc = dalloc((void **)&b->d_part, sizeof(int32_t) * (W + 1));
-    if (rc) return rc;
-    FEA_HIP(hipMemcpy(b->d_part, part.data(), sizeof(int32_t) * (W + 1), hipMemcpyHostToDevice));
-    b->part_for = W;
-    drop_graph(b);
+    int per = 0;
+    FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<T, MODEL, CT, VAR>, 256, 0));
+    *w = std::max(1, cus * std::max(1, per));
     return FEA_OK;
 }
 
@@ -399,10 +429,13 @@ int worker_count(fea_batch *b)
 {
     const int key = (MODEL * 2 + (sizeof(CT) == 4)) * 4 + VAR;  // MODEL 0..2
     if (b->workers_for == key) return FEA_OK;
-    int cus = 0, per = 0;
+    int cus = 0, rc;
     FEA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
-    FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<MODEL, CT, VAR>, 256, 0));
-    b->workers = std::max(1, cus * std::max(1, per));
+    if ((rc = family_workers<0, MODEL, CT, VAR>(cus, &b->fworkers[0]))) return rc;
+    if ((rc = family_workers<1, MODEL, CT, VAR>(cus, &b->fworkers[1]))) return rc;
+    if ((rc = family_workers<2, MODEL, CT, VAR>(cus, &b->fworkers[2]))) return rc;
+    if ((rc = family_workers<3, MODEL, CT, VAR>(cus, &b->fworkers[3]))) return rc;
+    b->workers = *std::max_element(b->fworkers, b->fworkers + 4);
     b->workers_for = key;
     if (!b->part_w.empty()) return make_partition(b);
     return FEA_OK;
@@ -459,6 +492,17 @@ int sym_prepare_batch(fea_batch *b, hipStream_t s)
     return FEA_OK;
 }
 
+template <int T, int MODEL, typename CT, int VAR>
+void launch_family(fea_batch *b, bool part, hipStream_t s)
+{
+    const int64_t n = b->foff[T + 1] - b->foff[T];
+    if (n <= 0) return;
+    k_batch<T, MODEL, CT, VAR><<<b->fworkers[T], 256, 0, s>>>(
+        b->d_meshes, b->d_items, b->d_order + b->foff[T], (int32_t)n, b->d_head + T,
+        part ? b->d_part + b->poff[T] : nullptr, (CT *)b->contrib, (CT *)b->rcontrib, b->d_status, b->d_cycles,
+        b->d_worker, b->d_cu);
+}
+
 template <int MODEL, typename CT, typename OT, int VAR>
 int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, void *rhs,
                  int32_t *status)
@@ -488,11 +532,14 @@ int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, 
     const int32_t ni = (int32_t)(b->items.size() / 4);
     k_batch_begin<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_head, b->d_status, b->n_meshes);
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[0], s));
-    if (ni)
-        k_batch<MODEL, CT, VAR><<<b->workers, 256, 0, s>>>(b->d_meshes, b->d_items, b->d_order, ni, b->d_head,
-                                                      b->part_for == b->workers ? b->d_part : nullptr,
-                                                      (CT *)b->contrib, (CT *)b->rcontrib, b->d_status,
-                                                      b->d_cycles, b->d_worker, b->d_cu);
+    if (ni) {
+        // one persistent launch per family, each over its part of the queue
+        const bool part = b->part_for == b->workers_for;
+        launch_family<0, MODEL, CT, VAR>(b, part, s);
+        launch_family<1, MODEL, CT, VAR>(b, part, s);
+        launch_family<2, MODEL, CT, VAR>(b, part, s);
+        launch_family<3, MODEL, CT, VAR>(b, part, s);
+    }
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[1], s));
     const int64_t nv = b->total_blocks * BB, nr = b->rhs_off.back();
     if (SYM) {
@@ -658,7 +705,7 @@ int build(int n, const fea_mesh_desc *md, int model, const int32_t *tile, hipStr
     b->hmeshes = bm;
     if ((rc = dalloc((void **)&b->d_meshes, sizeof(BatchMesh) * std::max(n, 1)))) return rc;
     if (n) FEA_HIP(hipMemcpy(b->d_meshes, bm.data(), sizeof(BatchMesh) * n, hipMemcpyHostToDevice));
-    if ((rc = dalloc((void **)&b->d_head, sizeof(int32_t)))) return rc;
+    if ((rc = dalloc((void **)&b->d_head, sizeof(int32_t) * 4))) return rc;
     if ((rc = dalloc((void **)&b->d_status, sizeof(int32_t) * std::max(n, 1)))) return rc;
     if ((rc = dalloc((void **)&b->d_vseg, sizeof(int64_t) * (b->total_blocks + 1)))) return rc;
     if ((rc = dalloc((void **)&b->d_rseg, sizeof(int64_t) * (b->rhs_off.back() / B + 1)))) return rc;
@@ -688,13 +735,7 @@ namespace {
 const int kEPB[4] = {sym_epb(0), sym_epb(1), sym_epb(2), sym_epb(3)};
 const int kNQ[4] = {1, 8, 6, 8};
 
-int upload_order(fea_batch *b)
-{
-    const size_t ni = b->items.size() / 4;
-    if (ni) FEA_HIP(hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice));
-    drop_graph(b);
-    return FEA_OK;
-}
+int upload_order(fea_batch *b) { return upload_grouped_order(b); }
 
 // median duration (ms) of the persistent kernel over `reps` launches
 int time_batch(fea_batch *b, const fea_options *o, int reps, hipStream_t s, void *vals, void *rhs, float *ms)
@@ -959,9 +1000,9 @@ extern "C" int fea_batch_set_order(fea_batch *b, const int32_t *order)
         seen[order[j]] = 1;
     }
     b->order.assign(order, order + ni);
-    if (ni) FEA_HIP(hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice));
-    drop_graph(b);
-    return FEA_OK;
+    b->part_for = -1;
+    b->part_w.clear();
+    return upload_grouped_order(b);
 }
 
 extern "C" int fea_batch_assemble(fea_batch *b, const fea_options *opt, hipStream_t stream, void *vals,

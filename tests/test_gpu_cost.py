@@ -187,8 +187,11 @@ def test_static_partitions_keep_results_and_ranges():
         assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
         _, w, _ = b.cycles()
         w = w.cpu().numpy()
-        # every workgroup ran one contiguous range of the type-sorted items
-        assert np.all(np.diff(w) >= 0)
+        # every workgroup of a family's launch ran one contiguous range of
+        # that family's type-sorted items
+        fam = b.items[:, 1]
+        for t in range(4):
+            assert np.all(np.diff(w[fam == t]) >= 0), t
     b.order(fea.TYPE_SORTED)
     v, r, _ = b.assemble()
     assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
