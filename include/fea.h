@@ -68,8 +68,17 @@ enum fea_precision { FEA_FP64 = 0, FEA_MIXED = 1 };
  *             (j, i) is written as the transpose of the ordered sum of block
  *             (i, j). About 40% less element work and workspace traffic;
  *             deterministic, and A is exactly symmetric. Single-mesh
- *             assembly only. */
-enum fea_variant { FEA_ROWOWNER = 0, FEA_ATOMIC = 1, FEA_COLOUR = 2, FEA_ROWGATHER = 3, FEA_ROWSYM = 4 };
+ *             assembly only;
+ *   TILECOLOUR the GPU counterpart of commutative multidependences
+ *             (Algorithm 7): the ROWSYM element tiles, greedily coloured so
+ *             that no two tiles of a colour share a node (built by the
+ *             first such call, on the host); one launch per (colour,
+ *             family), each tile adding its LDS tile sums and their
+ *             transposes straight into FP64 block values (no block
+ *             workspace, no atomics); right-hand side as ROWOWNER;
+ *             deterministic. Single-mesh assembly only. */
+enum fea_variant { FEA_ROWOWNER = 0, FEA_ATOMIC = 1, FEA_COLOUR = 2, FEA_ROWGATHER = 3, FEA_ROWSYM = 4,
+                   FEA_TILECOLOUR = 5 };
 enum fea_dtype { FEA_F64 = 0, FEA_F32 = 1 };
 enum fea_model { FEA_POISSON = 0, FEA_ELASTIC = 1 };
 enum fea_schedule { FEA_TYPE_SORTED = 0, FEA_LEARNED = 1, FEA_GP_WEIGHT = 2 };
@@ -160,7 +169,7 @@ int fea_assemble(const fea_graph *g, const double *x, const double *y, const dou
 /* Phase durations of the graph's last fea_assemble call made with
  * opt->timing set, in milliseconds, measured with HIP events on that call's
  * stream: ms[0] element kernels (with the fused scatter for ATOMIC and
- * COLOUR, and all of ROWGATHER), ms[1] the one kernel that forms the matrix
+ * COLOUR and TILECOLOUR, and all of ROWGATHER), ms[1] the one kernel that forms the matrix
  * values after them (row-owner: the segmented reduction of the block
  * values; ATOMIC/COLOUR with FP32 output: the conversion; otherwise empty),
  * ms[2] the whole call including zero-fill and the right-hand side. Waits

@@ -25,10 +25,11 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 FEA_OK, FEA_EINVAL, FEA_EMESH, FEA_ENOMEM, FEA_EHIP, FEA_ERANGE = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
-ROWOWNER, ATOMIC, COLOUR, ROWGATHER, ROWSYM = 0, 1, 2, 3, 4
+ROWOWNER, ATOMIC, COLOUR, ROWGATHER, ROWSYM, TILECOLOUR = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
 POISSON, ELASTIC = 0, 1
-VARIANTS = {"rowowner": ROWOWNER, "atomic": ATOMIC, "colour": COLOUR, "rowgather": ROWGATHER, "rowsym": ROWSYM}
+VARIANTS = {"rowowner": ROWOWNER, "atomic": ATOMIC, "colour": COLOUR, "rowgather": ROWGATHER, "rowsym": ROWSYM,
+            "tilecolour": TILECOLOUR}
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64

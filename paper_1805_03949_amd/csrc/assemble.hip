@@ -15,7 +15,8 @@ __global__ void __launch_bounds__(256) k_element(ElemArgs A)
 {
     __shared__ ElemSmem<T, MODEL, VAR, CT> S;
     constexpr int EPB = ElemSmem<T, MODEL, VAR, CT>::EPB;
-    elem_tile<T, MODEL, VAR, CT>(A, xcd_tile(blockIdx.x, gridDim.x) * EPB, S);
+    const int64_t b = xcd_tile(blockIdx.x, gridDim.x);
+    elem_tile<T, MODEL, VAR, CT>(A, (VAR == V_TILECOL ? (int64_t)A.tiles[b] : b) * EPB, S);
 }
 
 __global__ void k_fill_f64(double *p, int64_t n, double v)
@@ -47,6 +48,10 @@ static void launch_fam(const ElemArgs &a, hipStream_t s)
 {
     constexpr int EPB = ElemSmem<T, MODEL, VAR, CT>::EPB;
     if (a.n <= 0) return;
+    if (VAR == V_TILECOL) {
+        if (a.ntiles > 0) k_element<T, MODEL, VAR, CT><<<(unsigned)a.ntiles, 256, 0, s>>>(a);
+        return;
+    }
     k_element<T, MODEL, VAR, CT><<<grid_for(a.n, EPB), 256, 0, s>>>(a);
 }
 
@@ -114,6 +119,50 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
             if (g->nup) launch_segsum<BB, CT, double, true>(g->nup, g->ublk, g->lpart, g->ts_ptr, (const CT *)g->contrib, (double *)vals, s);
             mark(g, 2, o, s);
             if (nr) launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
+        }
+        mark(g, 3, o, s);
+        FEA_HIP(hipGetLastError());
+        return FEA_OK;
+    }
+    if (o->variant == FEA_TILECOLOUR) {
+        if (!g->sready && (rc = sym_prepare(g, s))) return rc;
+        if (!g->tcready && (rc = tile_colour_prepare(g, s))) return rc;
+        if ((rc = ensure_ws(&g->rcontrib, &g->rcontrib_bytes, sizeof(CT) * (size_t)g->conn_len * B))) return rc;
+        double *tv = (double *)vals;
+        if (f32) {
+            if ((rc = ensure_ws((void **)&g->acc64, &g->acc64_bytes, sizeof(double) * (size_t)std::max<int64_t>(nv, 1)))) return rc;
+            tv = g->acc64;
+        }
+        a.rcontrib = g->rcontrib;
+        a.vals = tv;
+        a.tent = g->tent;
+        a.tb_eend = g->tb_eend;
+        a.tb_blk = g->tb_blk;
+        a.lpart = g->lpart;
+        mark(g, 0, o, s);
+        if (nv) k_fill_f64<<<grid_for(nv, 256), 256, 0, s>>>(tv, nv, 0.0);
+        const int nc = g->tc_colours;
+        for (int c = 0; c < nc; ++c)
+            for (int t = 0; t < 4; ++t) {
+                const int64_t b = g->tcseg[(size_t)t * (nc + 1) + c], e = g->tcseg[(size_t)t * (nc + 1) + c + 1];
+                a.elems = g->perm + g->seg[t];
+                a.n = g->seg[t + 1] - g->seg[t];
+                a.pnodes = g->pnodes + g->node_base[t];
+                a.prdest = g->prdest + g->node_base[t];
+                a.tent_ptr = g->tent_ptr + g->tile_base[t];
+                a.ttb_ptr = g->ttb_ptr + g->tile_base[t];
+                a.tiles = g->ctile + b;
+                a.ntiles = e - b;
+                launch_type<MODEL, V_TILECOL, CT>(t, a, s);
+            }
+        mark(g, 1, o, s);
+        if (f32 && nv) k_to_f32<<<grid_for(nv, 256), 256, 0, s>>>(tv, (float *)vals, nv);
+        mark(g, 2, o, s);
+        if (nr) {
+            if (f32)
+                launch_segsum<B, CT, float, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
+            else
+                launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
         }
         mark(g, 3, o, s);
         FEA_HIP(hipGetLastError());
@@ -202,7 +251,7 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     fea_options dflt = {0, 0, 0, 0};
     const fea_options *o = opt ? opt : &dflt;
     if (!g || !mat) return set_error(FEA_EINVAL, "graph and material are required");
-    if (o->precision < 0 || o->precision > 1 || o->variant < 0 || o->variant > 4 ||
+    if (o->precision < 0 || o->precision > 1 || o->variant < 0 || o->variant > 5 ||
         o->out_dtype < 0 || o->out_dtype > 1)
         return set_error(FEA_EINVAL, "bad option (precision %d, variant %d, out_dtype %d)",
                          o->precision, o->variant, o->out_dtype);

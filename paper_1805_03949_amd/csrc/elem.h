@@ -182,6 +182,13 @@ struct ElemArgs {
     const uint16_t *tent;
     const uint16_t *tb_eend;
     const int32_t *tb_slot;
+    // tile-coloured form: the launch's tiles (launch-local tile indices,
+    // ntiles of them), every tile-block's block and every block's lower
+    // partner (-1 if none)
+    const int32_t *tiles;
+    int64_t ntiles;
+    const int32_t *tb_blk;
+    const int32_t *lpart;
 };
 
 // V_ROWSYM: the row-owner scatter on the upper triangle. A symmetric
@@ -191,7 +198,11 @@ struct ElemArgs {
 // blocks (transposed where node a > node b) in ascending lane order and
 // writes one value per (tile, block) to the workspace; the reduction adds
 // the tile sums of each upper block and writes lower blocks as transposes.
-enum { V_ROWOWNER = 0, V_ATOMIC = 1, V_COLOUR = 2, V_ROWSYM = 3 };
+// V_TILECOL: the same tiles and tile sums, coloured so that the tiles of a
+// colour share no node (and so no block); a tile adds its sums, and their
+// transposes for the lower partners, straight into FP64 block values, one
+// colour at a time (the commutative tile accumulation of Algorithm 7).
+enum { V_ROWOWNER = 0, V_ATOMIC = 1, V_COLOUR = 2, V_ROWSYM = 3, V_TILECOL = 4 };
 
 // Kernel model codes: FEA_POISSON, FEA_ELASTIC (linear elements only) and
 // M_ELASTIC_NH (some elements use the neo-Hookean tangent; only these
@@ -244,16 +255,16 @@ template <int T, int MODEL, int VAR, typename CT>
 struct ElemSmem {
     static constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
     // threads per element: all n*n blocks, or the n(n+1)/2 pairs a <= b
-    static constexpr int PW = VAR == V_ROWSYM ? NN * (NN + 1) / 2 : P;
+    static constexpr int PW = (VAR == V_ROWSYM || VAR == V_TILECOL) ? NN * (NN + 1) / 2 : P;
     static constexpr int EPB = 256 / PW;
     static constexpr bool ELAS = MODEL != FEA_POISSON;
     static constexpr bool NHK = MODEL == M_ELASTIC_NH;
     static constexpr int B = ELAS ? 3 : 1;
     static constexpr int BB = B * B;
     static constexpr int EU = NHK ? EPB : 1;
-    static constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM;
+    static constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM || VAR == V_TILECOL;
 
-    static constexpr bool SYM = VAR == V_ROWSYM;
+    static constexpr bool SYM = VAR == V_ROWSYM || VAR == V_TILECOL;  // tile sums
     static_assert(!SYM || EPB == sym_epb(T), "tile size of the upper-triangle layout");
     double sX[EPB][NN][3];
     double sU[EU][NN][3];
@@ -299,8 +310,9 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     constexpr int B = ELAS ? 3 : 1;
     constexpr int BB = B * B;
     constexpr int EU = NHK ? EPB : 1;
-    constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM;
-    constexpr bool SYM = VAR == V_ROWSYM;
+    constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM || VAR == V_TILECOL;
+    constexpr bool SYM = VAR == V_ROWSYM || VAR == V_TILECOL;  // tile sums
+    constexpr bool TCOL = VAR == V_TILECOL;
 
     using Smem = ElemSmem<T, MODEL, VAR, CT>;
     auto &sX = S.sX;
@@ -620,7 +632,14 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                 const int u = S.sEnt[q];
                 acc += (double)sK[(u >> 1) * BB + ((u & 1) ? ct : c)];
             }
-            out[(int64_t)A.tb_slot[d0 + d] * BB + c] = (CT)acc;
+            if constexpr (TCOL) {
+                // no other tile of this colour touches the block or its partner
+                const int64_t k = A.tb_blk[d0 + d], l = A.lpart[k];
+                A.vals[k * BB + c] += acc;
+                if (l >= 0) A.vals[l * BB + ct] += acc;
+            } else {
+                out[(int64_t)A.tb_slot[d0 + d] * BB + c] = (CT)acc;
+            }
         }
     } else if constexpr (STAGE) {
         __syncthreads();

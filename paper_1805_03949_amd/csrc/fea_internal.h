@@ -137,6 +137,15 @@ struct fea_graph {
     int32_t *tb_slot = nullptr;
     int64_t *ts_ptr = nullptr;
     int64_t ulen = 0, nent = 0;
+    // Tile colouring (built by the first FEA_TILECOLOUR assembly): greedy
+    // first-fit over the tiles in tile order, no two tiles of a colour
+    // sharing a node; bucket (t, c) = family t's tiles of colour c,
+    // ctile[tcseg[t*(tc_colours+1)+c] .. tcseg[t*(tc_colours+1)+c+1])
+    // (family-local tile indices, ascending; tcseg is a host copy).
+    int32_t *ctile = nullptr;
+    std::vector<int64_t> tcseg;
+    int tc_colours = 0;
+    bool tcready = false;
     bool sready = false;
     // lazily allocated workspaces of the scatter variants
     void *contrib = nullptr;
@@ -178,4 +187,7 @@ namespace fea {
 // Builds the upper-triangle row-owner layout of a graph (graph.hip; blocks
 // on the stream).
 int sym_prepare(fea_graph *g, hipStream_t s);
+// Colours the upper-triangle tiles (graph.hip; needs sym_prepare; blocks
+// on the stream).
+int tile_colour_prepare(fea_graph *g, hipStream_t s);
 }  // namespace fea

@@ -426,6 +426,7 @@ int sym_prepare(fea_graph *g, hipStream_t s)
     g->ulen = 0;
     g->nent = 0;
     g->sready = false;
+    g->tcready = false;
     // partners and the upper-block list
     TmpBuf flag, uoff, tmp;
     const int64_t nn1 = std::max<int64_t>(nnz, 1);
@@ -513,6 +514,70 @@ int sym_prepare(fea_graph *g, hipStream_t s)
     return FEA_OK;
 }
 
+// Greedy first-fit colouring of the upper-triangle tiles in tile order (a
+// tile's nodes are its elements' nodes); the tiles of one colour share no
+// node, so no block either. Sequential by definition: on the host.
+int tile_colour_prepare(fea_graph *g, hipStream_t s)
+{
+    const int64_t N = g->n_nodes, C = g->conn_len;
+    std::vector<int32_t> pn(std::max<int64_t>(C, 1));
+    if (C) FEA_HIP(hipMemcpyAsync(pn.data(), g->pnodes, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    constexpr int kWords = 4;  // up to 256 colours
+    std::vector<uint64_t> used((size_t)N * kWords, 0);
+    const int64_t nt = g->tile_base[4];
+    std::vector<int16_t> colour(std::max<int64_t>(nt, 1));
+    int ncol = 0;
+    for (int t = 0; t < 4; ++t) {
+        const int n = nodes_of(t), epb = sym_epb(t);
+        const int64_t ne = g->seg[t + 1] - g->seg[t];
+        for (int64_t i = 0; i < g->tile_base[t + 1] - g->tile_base[t]; ++i) {
+            const int64_t e0 = i * epb, e1 = std::min<int64_t>(ne, e0 + epb);
+            const int32_t *p0 = pn.data() + g->node_base[t] + e0 * n, *p1 = pn.data() + g->node_base[t] + e1 * n;
+            uint64_t m[kWords] = {0, 0, 0, 0};
+            for (const int32_t *p = p0; p < p1; ++p)
+                for (int w = 0; w < kWords; ++w) m[w] |= used[(size_t)*p * kWords + w];
+            int c = -1;
+            for (int w = 0; w < kWords && c < 0; ++w)
+                if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
+            if (c < 0) return set_error(FEA_ERANGE, "tile %lld needs more than 256 colours", (long long)i);
+            colour[g->tile_base[t] + i] = (int16_t)c;
+            ncol = std::max(ncol, c + 1);
+            for (const int32_t *p = p0; p < p1; ++p) used[(size_t)*p * kWords + c / 64] |= 1ull << (c % 64);
+        }
+    }
+    // stable buckets by (family, colour) of family-local tile indices
+    std::vector<int64_t> seg((size_t)4 * (ncol + 1), 0);
+    for (int t = 0; t < 4; ++t)
+        for (int64_t i = g->tile_base[t]; i < g->tile_base[t + 1]; ++i) seg[(size_t)t * (ncol + 1) + colour[i] + 1]++;
+    int64_t run = 0;
+    for (int t = 0; t < 4; ++t)
+        for (int c = 0; c <= ncol; ++c) {
+            int64_t &v = seg[(size_t)t * (ncol + 1) + c];
+            if (c == 0) {
+                v = run;
+                continue;
+            }
+            run += v;
+            v = run;
+        }
+    std::vector<int64_t> cur(seg);
+    std::vector<int32_t> ctile(std::max<int64_t>(nt, 1));
+    for (int t = 0; t < 4; ++t)
+        for (int64_t i = g->tile_base[t]; i < g->tile_base[t + 1]; ++i)
+            ctile[cur[(size_t)t * (ncol + 1) + colour[i]]++] = (int32_t)(i - g->tile_base[t]);
+    dfree(g->ctile);
+    g->ctile = nullptr;
+    int rc;
+    if ((rc = dalloc((void **)&g->ctile, sizeof(int32_t) * std::max<int64_t>(nt, 1)))) return rc;
+    if (nt) FEA_HIP(hipMemcpyAsync(g->ctile, ctile.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    g->tc_colours = ncol;
+    g->tcseg = std::move(seg);
+    g->tcready = true;
+    return FEA_OK;
+}
+
 // ------------------------------------------------------------- colouring
 // Greedy first-fit in element order (the colouring of Algorithm 5; any
 // valid colouring is correct, this one is deterministic). Sequential by
@@ -579,7 +644,7 @@ static void destroy(fea_graph *g)
     void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv, g->pnodes, g->pdest, g->prdest,
                     g->n2e_ptr, g->n2e, g->n2a, g->perm, g->colour, g->cperm,
                     g->contrib, g->rcontrib, g->acc64, g->gtile, g->gnodes, g->gdesc, g->upart, g->ublk, g->lpart, g->tent_ptr, g->ttb_ptr,
-                    g->tent, g->tb_eend, g->tb_blk, g->tb_slot, g->ts_ptr};
+                    g->tent, g->tb_eend, g->tb_blk, g->tb_slot, g->ts_ptr, g->ctile};
     for (void *b : bufs) dfree(b);
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);

@@ -81,7 +81,7 @@ def test_graph_bit_exact(name):
     assert np.array_equal(ex["colour"], oc)
 
 
-VARIANTS = [fea.ROWOWNER, fea.ATOMIC, fea.COLOUR, fea.ROWGATHER, fea.ROWSYM]
+VARIANTS = [fea.ROWOWNER, fea.ATOMIC, fea.COLOUR, fea.ROWGATHER, fea.ROWSYM, fea.TILECOLOUR]
 
 
 def _nh(name, model, variant):
@@ -125,7 +125,7 @@ def test_mixed_within_fp32_bound(name, variant):
         assert rv <= 1.0 and rr <= 1.0, (out, rv, rr)
 
 
-@pytest.mark.parametrize("variant", [fea.ROWOWNER, fea.COLOUR, fea.ROWGATHER, fea.ROWSYM])
+@pytest.mark.parametrize("variant", [fea.ROWOWNER, fea.COLOUR, fea.ROWGATHER, fea.ROWSYM, fea.TILECOLOUR])
 def test_deterministic_variants_bitwise_repeatable(variant):
     m, og, dm, g = case("mix6_jitter")
     first = None
@@ -268,7 +268,7 @@ def test_rowgather_rejects_node_in_too_many_elements():
     assert ei.value.code == fea.FEA_ERANGE and "node 0 " in ei.value.msg
 
 
-@pytest.mark.parametrize("variant", [fea.ROWGATHER, fea.ROWOWNER, fea.ROWSYM])
+@pytest.mark.parametrize("variant", [fea.ROWGATHER, fea.ROWOWNER, fea.ROWSYM, fea.TILECOLOUR])
 def test_assembly_captured_in_a_graph_replays_eager_result(variant):
     """After its first call (tile or workspace set-up), an assembly
     allocates, synchronises and clears nothing, so a caller can capture it
@@ -298,6 +298,34 @@ def test_assembly_captured_in_a_graph_replays_eager_result(variant):
         assert int(st.item()) == -1
         assert vals.cpu().numpy().tobytes() == ref[0].tobytes()
         assert rhs.cpu().numpy().tobytes() == ref[1].tobytes()
+
+
+@pytest.mark.parametrize("name", ["bands8_jitter", "mix6_jitter", "tet_ragged", "hetero16", "poisson_hex16"])
+def test_tilecolour_equals_rowsym_up_to_addition_order(name):
+    """The tile-coloured form adds the same tile sums as the upper-triangle
+    form, per block in colour order instead of tile order, and writes the
+    lower blocks as transposes too: A is exactly symmetric off the
+    diagonal and equal to the upper-triangle result up to the rounding of
+    the reordered additions."""
+    m, og, dm, g = case(name)
+    model = fea.POISSON if name == "poisson_hex16" else fea.ELASTIC
+    nh = name == "hetero16"
+    B = 1 if model == fea.POISSON else 3
+    a = dm.assemble(g, model=model, use_nh=nh, variant=fea.ROWSYM)
+    b = dm.assemble(g, model=model, use_nh=nh, variant=fea.TILECOLOUR)
+    torch.cuda.synchronize()
+    va, vb = a[0].cpu().numpy().reshape(-1, B, B), b[0].cpu().numpy().reshape(-1, B, B)
+    ex = g.export()
+    row_ptr, col = ex["row_ptr"].cpu().numpy(), ex["col"].cpu().numpy()
+    rows = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
+    key = rows.astype(np.int64) * len(row_ptr) + col
+    tkey = col.astype(np.int64) * len(row_ptr) + rows
+    order = np.argsort(key)
+    tpos = order[np.searchsorted(key[order], tkey)]
+    off = rows != col
+    assert vb[off].tobytes() == np.ascontiguousarray(vb[tpos][off].transpose(0, 2, 1)).tobytes()
+    assert np.abs(vb - va).max() <= 1e-14 * np.abs(va).max()
+    assert b[1].cpu().numpy().tobytes() == a[1].cpu().numpy().tobytes()
 
 
 @pytest.mark.parametrize("name", ["bands8_jitter", "mix6_jitter", "tet_ragged", "hetero16", "poisson_hex16"])
