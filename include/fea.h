@@ -168,12 +168,14 @@ int fea_assemble(const fea_graph *g, const double *x, const double *y, const dou
 
 /* Phase durations of the graph's last fea_assemble call made with
  * opt->timing set, in milliseconds, measured with HIP events on that call's
- * stream: ms[0] element kernels (with the fused scatter for ATOMIC and
- * COLOUR and TILECOLOUR, and all of ROWGATHER), ms[1] the one kernel that forms the matrix
- * values after them (row-owner: the segmented reduction of the block
- * values; ATOMIC/COLOUR with FP32 output: the conversion; otherwise empty),
- * ms[2] the whole call including zero-fill and the right-hand side. Waits
- * for the events. FEA_EINVAL if no timed call was made. */
+ * stream: ms[0] element kernels (with the fused scatter for ATOMIC, COLOUR
+ * and TILECOLOUR, and all of ROWGATHER; for ROWOWNER and ROWSYM also the
+ * right-hand-side reduction, which runs first), ms[1] the one kernel that
+ * forms the matrix values after them (ROWOWNER/ROWSYM: the segmented
+ * reduction of the block values; ATOMIC/COLOUR/TILECOLOUR with FP32 output:
+ * the conversion; otherwise empty), ms[2] the whole call including
+ * zero-fill and the right-hand side. Waits for the events. FEA_EINVAL if no
+ * timed call was made. */
 int fea_last_timing(const fea_graph *g, float *ms);
 
 /* Durations (ms, HIP events on the call's stream) of the five kernels of

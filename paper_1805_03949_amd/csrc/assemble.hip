@@ -110,16 +110,18 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
             a.ttb_ptr = g->ttb_ptr + g->tile_base[t];
             launch_type<MODEL, V_ROWSYM, CT>(t, a, s);
         }
-        mark(g, 1, o, s);
+        // the right-hand side first, while its workspace (just written) is
+        // still in the caches; then the block values
         if (f32) {
-            if (g->nup) launch_segsum<BB, CT, float, true>(g->nup, g->ublk, g->lpart, g->ts_ptr, (const CT *)g->contrib, (float *)vals, s);
-            mark(g, 2, o, s);
             if (nr) launch_segsum<B, CT, float, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
+            mark(g, 1, o, s);
+            if (g->nup) launch_segsum<BB, CT, float, true>(g->nup, g->ublk, g->lpart, g->ts_ptr, (const CT *)g->contrib, (float *)vals, s);
         } else {
-            if (g->nup) launch_segsum<BB, CT, double, true>(g->nup, g->ublk, g->lpart, g->ts_ptr, (const CT *)g->contrib, (double *)vals, s);
-            mark(g, 2, o, s);
             if (nr) launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
+            mark(g, 1, o, s);
+            if (g->nup) launch_segsum<BB, CT, double, true>(g->nup, g->ublk, g->lpart, g->ts_ptr, (const CT *)g->contrib, (double *)vals, s);
         }
+        mark(g, 2, o, s);
         mark(g, 3, o, s);
         FEA_HIP(hipGetLastError());
         return FEA_OK;
@@ -182,16 +184,17 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
             a.pdest = g->pdest + g->slot_base[t];
             launch_type<MODEL, V_ROWOWNER, CT>(t, a, s);
         }
-        mark(g, 1, o, s);
+        // the right-hand side first (its workspace is still cached)
         if (f32) {
-            if (nv) launch_segsum<BB, CT, float, false>(g->nnz, nullptr, nullptr, g->inv_ptr, (const CT *)g->contrib, (float *)vals, s);
-            mark(g, 2, o, s);
             if (nr) launch_segsum<B, CT, float, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
+            mark(g, 1, o, s);
+            if (nv) launch_segsum<BB, CT, float, false>(g->nnz, nullptr, nullptr, g->inv_ptr, (const CT *)g->contrib, (float *)vals, s);
         } else {
-            if (nv) launch_segsum<BB, CT, double, false>(g->nnz, nullptr, nullptr, g->inv_ptr, (const CT *)g->contrib, (double *)vals, s);
-            mark(g, 2, o, s);
             if (nr) launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
+            mark(g, 1, o, s);
+            if (nv) launch_segsum<BB, CT, double, false>(g->nnz, nullptr, nullptr, g->inv_ptr, (const CT *)g->contrib, (double *)vals, s);
         }
+        mark(g, 2, o, s);
         mark(g, 3, o, s);
         FEA_HIP(hipGetLastError());
         return FEA_OK;

@@ -542,6 +542,8 @@ int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, 
     }
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[1], s));
     const int64_t nv = b->total_blocks * BB, nr = b->rhs_off.back();
+    // the right-hand side first, while its workspace is still cached
+    if (nr) launch_segsum<B, CT, OT, false>(nr / B, nullptr, nullptr, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs, s);
     if (SYM) {
         if (b->total_nup)
             launch_segsum<BB, CT, OT, true>(b->total_nup, b->d_sym_ublk, b->d_sym_lpart, b->d_sym_ptr,
@@ -549,7 +551,6 @@ int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, 
     } else if (nv) {
         launch_segsum<BB, CT, OT, false>(b->total_blocks, nullptr, nullptr, b->d_vseg, (const CT *)b->contrib, (OT *)vals, s);
     }
-    if (nr) launch_segsum<B, CT, OT, false>(nr / B, nullptr, nullptr, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs, s);
     k_batch_end<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_status, b->n_meshes, status);
     FEA_HIP(hipGetLastError());
     return FEA_OK;

@@ -251,6 +251,18 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t nblk)
     return x * q + (x < rem ? x : rem) + r;
 }
 
+// Gradients of one element at its Gauss points, optionally padded by one
+// value (see ElemSmem).
+template <typename CT, int NQ, int NN, bool PAD>
+struct GradRecT {
+    CT v[NQ][NN][3];
+};
+template <typename CT, int NQ, int NN>
+struct GradRecT<CT, NQ, NN, true> {
+    CT v[NQ][NN][3];
+    CT pad;
+};
+
 template <int T, int MODEL, int VAR, typename CT>
 struct ElemSmem {
     static constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
@@ -285,7 +297,13 @@ struct ElemSmem {
     // through F^-T sH[EU][NQ][NN][3], staged blocks sK[EPB * PW * BB]; in the
     // upper-triangle form the blocks overwrite the gradients once every lane
     // has read them
-    static constexpr int NG = EPB * NQ * NN * 3, NHG = EU * NQ * NN * 3, NK = STAGE ? EPB * PW * BB : 1;
+    // Per-element gradient records are padded by one value where their size
+    // is a multiple of the 64 LDS banks (hex8: 192 values): the lanes of a
+    // wave span two elements, whose same-position reads would otherwise
+    // fall in the same banks (36% of LDS cycles lost to conflicts).
+    using GradRec = GradRecT<CT, NQ, NN, (NQ * NN * 3 * (int)sizeof(CT) / 4) % 64 == 0>;
+    static constexpr int NG = EPB * (int)(sizeof(GradRec) / sizeof(CT)), NHG = EU * (int)(sizeof(GradRec) / sizeof(CT)),
+                         NK = STAGE ? EPB * PW * BB : 1;
     static constexpr int NBUF = SYM ? (NG + NHG > NK ? NG + NHG : NK) : NG + NHG + NK;
     CT buf[NBUF];
     int32_t sD[STAGE && !SYM ? EPB * PW : 1];
@@ -317,8 +335,9 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     using Smem = ElemSmem<T, MODEL, VAR, CT>;
     auto &sX = S.sX;
     auto &sU = S.sU;
-    auto &sG = *reinterpret_cast<CT(*)[EPB][NQ][NN][3]>(S.buf);
-    auto &sH = *reinterpret_cast<CT(*)[EU][NQ][NN][3]>(S.buf + Smem::NG);
+    using GradRec = typename Smem::GradRec;
+    GradRec *sG = reinterpret_cast<GradRec *>(S.buf);
+    GradRec *sH = reinterpret_cast<GradRec *>(S.buf + Smem::NG);
     CT *sK = S.buf + (SYM ? 0 : Smem::NG + Smem::NHG);
     auto &sC = S.sC;
     auto &sLM = S.sLM;
@@ -331,6 +350,12 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     auto &sDN = S.sDN;
     auto &sNr = S.sNr;
     __syncthreads();  // the previous tile's readers of S are done
+    // upper-triangle form: slot (tile-coloured form: block) of the first
+    // tile-sum item of this thread
+    constexpr int KPRE = 1;  // deeper prefetch measured slower (registers)
+    int32_t spre[KPRE];
+#pragma unroll
+    for (int k = 0; k < KPRE; ++k) spre[k] = 0;
 
     for (int i = tid; i < NQ * NN; i += 256) {
         const int q = i / NN, a = i % NN;
@@ -372,12 +397,20 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
             }
         }
         if constexpr (SYM) {
-            // the tile's entries and tile-block ends (at most two entries per lane)
+            // the tile's entries and tile-block ends (at most two entries per
+            // lane), and the slots (blocks) of this thread's first tile sums,
+            // fetched with the other loads rather than after the contraction
             const int64_t tl = first / EPB;
             const int64_t e0 = A.tent_ptr[tl], d0 = A.ttb_ptr[tl];
             const int ne = (int)(A.tent_ptr[tl + 1] - e0), nd = (int)(A.ttb_ptr[tl + 1] - d0);
             for (int i = tid; i < ne; i += 256) S.sEnt[i] = A.tent[e0 + i];
             for (int i = tid; i < nd; i += 256) S.sEend[i] = A.tb_eend[d0 + i];
+            const int32_t *tbv = TCOL ? A.tb_blk : A.tb_slot;
+#pragma unroll
+            for (int k = 0; k < KPRE; ++k) {
+                const int idx = tid + k * 256;
+                spre[k] = idx < nd * BB ? tbv[d0 + idx / BB] : 0;
+            }
         }
         __syncthreads();
     } else {
@@ -421,7 +454,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     G[a][i] = Ji[0][i] * sDN[q][a][0] + Ji[1][i] * sDN[q][a][1] + Ji[2][i] * sDN[q][a][2];
-                    sG[el][q][a][i] = (CT)G[a][i];
+                    sG[el].v[q][a][i] = (CT)G[a][i];
                 }
             double wd = c_ref.w[T][q] * d;
             sC[el][q][0] = (CT)wd;
@@ -446,7 +479,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                     for (int a = 0; a < NN; ++a)
 #pragma unroll
                         for (int j = 0; j < 3; ++j)
-                            sH[el][q][a][j] =
+                            sH[el].v[q][a][j] =
                                 (CT)(G[a][0] * Fi[0][j] + G[a][1] * Fi[1][j] + G[a][2] * Fi[2][j]);
                     sC[el][q][1] = (CT)(wd * lam);
                     sC[el][q][2] = (CT)(wd * (mu - lam * log(jf)));
@@ -493,8 +526,8 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                 CT acc = 0;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    CT dot = sG[el][q][a][0] * sG[el][q][b][0] + sG[el][q][a][1] * sG[el][q][b][1] +
-                             sG[el][q][a][2] * sG[el][q][b][2];
+                    CT dot = sG[el].v[q][a][0] * sG[el].v[q][b][0] + sG[el].v[q][a][1] * sG[el].v[q][b][1] +
+                             sG[el].v[q][a][2] * sG[el].v[q][b][2];
                     acc += sC[el][q][0] * dot;
                 }
                 K[0] = acc;
@@ -506,8 +539,8 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     CT w = sC[el][q][0];
-                    CT ga[3] = {w * sG[el][q][a][0], w * sG[el][q][a][1], w * sG[el][q][a][2]};
-                    CT gb[3] = {sG[el][q][b][0], sG[el][q][b][1], sG[el][q][b][2]};
+                    CT ga[3] = {w * sG[el].v[q][a][0], w * sG[el].v[q][a][1], w * sG[el].v[q][a][2]};
+                    CT gb[3] = {sG[el].v[q][b][0], sG[el].v[q][b][1], sG[el].v[q][b][2]};
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -531,10 +564,10 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     CT c1 = sC[el][q][1], c2 = sC[el][q][2], c0 = sC[el][q][3];
-                    CT ha[3] = {sH[el][q][a][0], sH[el][q][a][1], sH[el][q][a][2]};
-                    CT hb[3] = {sH[el][q][b][0], sH[el][q][b][1], sH[el][q][b][2]};
-                    CT dot = sG[el][q][a][0] * sG[el][q][b][0] + sG[el][q][a][1] * sG[el][q][b][1] +
-                             sG[el][q][a][2] * sG[el][q][b][2];
+                    CT ha[3] = {sH[el].v[q][a][0], sH[el].v[q][a][1], sH[el].v[q][a][2]};
+                    CT hb[3] = {sH[el].v[q][b][0], sH[el].v[q][b][1], sH[el].v[q][b][2]};
+                    CT dot = sG[el].v[q][a][0] * sG[el].v[q][b][0] + sG[el].v[q][a][1] * sG[el].v[q][b][1] +
+                             sG[el].v[q][a][2] * sG[el].v[q][b][2];
                     dsum += c0 * dot;
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
@@ -625,7 +658,8 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
         const int64_t d0 = A.ttb_ptr[tl];
         const int nd = (int)(A.ttb_ptr[tl + 1] - d0);
         CT *out = (CT *)A.contrib;
-        for (int idx = tid; idx < nd * BB; idx += 256) {
+        const int32_t *tbv = TCOL ? A.tb_blk : A.tb_slot;
+        auto tile_sum = [&](int idx, int64_t v) {
             const int d = idx / BB, c = idx - d * BB, ct = (c % B) * B + c / B;
             double acc = 0.0;
             for (int q = d ? S.sEend[d - 1] : 0; q < S.sEend[d]; ++q) {
@@ -633,14 +667,21 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                 acc += (double)sK[(u >> 1) * BB + ((u & 1) ? ct : c)];
             }
             if constexpr (TCOL) {
-                // no other tile of this colour touches the block or its partner
-                const int64_t k = A.tb_blk[d0 + d], l = A.lpart[k];
-                A.vals[k * BB + c] += acc;
+                // v is the block; no other tile of this colour touches it or
+                // its partner
+                const int64_t l = A.lpart[v];
+                A.vals[v * BB + c] += acc;
                 if (l >= 0) A.vals[l * BB + ct] += acc;
             } else {
-                out[(int64_t)A.tb_slot[d0 + d] * BB + c] = (CT)acc;
+                out[v * BB + c] = (CT)acc;
             }
+        };
+#pragma unroll
+        for (int k = 0; k < KPRE; ++k) {
+            const int idx = tid + k * 256;
+            if (idx < nd * BB) tile_sum(idx, spre[k]);
         }
+        for (int idx = tid + KPRE * 256; idx < nd * BB; idx += 256) tile_sum(idx, tbv[d0 + idx / BB]);
     } else if constexpr (STAGE) {
         __syncthreads();
         CT *out = (CT *)A.contrib;
