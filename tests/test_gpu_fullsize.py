@@ -46,7 +46,7 @@ def test_hybrid96_rowowner_fp64_and_mixed_sampled_rows():
     torch.cuda.synchronize()
     L = fp32_bound_L(mesh.types)
     assert check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L) <= 1.0
-    for variant in (fea.ATOMIC, fea.COLOUR, fea.ROWGATHER, fea.ROWSYM):
+    for variant in (fea.ATOMIC, fea.COLOUR, fea.ROWGATHER, fea.ROWSYM, fea.TILECOLOUR):
         v, r, st = dm.assemble(g, variant=variant)
         torch.cuda.synchronize()
         assert int(st.item()) == -1
