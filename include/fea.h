@@ -99,7 +99,15 @@ typedef struct fea_material {
     const double *young;    /* Young's modulus per element; NULL = 1.0      */
     const double *nu;       /* Poisson ratio per element (elasticity)       */
     const uint8_t *nh_flag; /* NULL, or 1 = neo-Hookean tangent at u        */
-    const double *u;        /* required when nh_flag is given               */
+    const double *u;        /* required when nh_flag is given or residual   */
+    int residual;           /* nonzero: rhs is the Newton residual
+                               b = f_ext - f_int(u) (Section 2.2), f_int the
+                               neo-Hookean internal force sum_q w detJ P
+                               grad N_a where nh_flag is set, the linear-
+                               elastic one (sum_q w detJ sigma grad N_a =
+                               K^e u^e) elsewhere; FEA_ELASTIC, FP64 and
+                               the element-tile scatter forms only (not
+                               FEA_ROWGATHER): FEA_EINVAL otherwise */
 } fea_material;
 
 typedef struct fea_graph fea_graph;

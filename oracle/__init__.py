@@ -62,6 +62,8 @@ def lib():
         L.or_assemble.argtypes = [i64, i64, P, P, P, P, P, P, ctypes.c_int, P, P, P, P, P,
                                   P, P, P, P, P, P, P]
         L.or_assemble.restype = i64
+        L.or_residual.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.or_residual.restype = i64
         _lib = L
     return _lib
 
@@ -201,6 +203,24 @@ def assemble(mesh, g, model=ELASTIC, with_terms=False, use_nh=True):
     if with_terms:
         return vals, rhs, tv, tr
     return vals, rhs
+
+
+def residual(mesh, use_nh=True):
+    """Newton residual b = f_ext - f_int(mesh.u) of the elastic solid
+    (neo-Hookean internal force where nh_flag is set and use_nh, linear
+    K^e u^e elsewhere), node-major rhs[3 * n_nodes]."""
+    if mesh.source.shape[1] < 3:
+        raise ValueError("elasticity needs a 3-component source per element")
+    src = np.ascontiguousarray(mesh.source[:, :3], dtype=np.float64)
+    nh = np.ascontiguousarray(mesh.nh_flag, dtype=np.uint8) if use_nh else None
+    u = np.ascontiguousarray(mesh.u, dtype=np.float64)
+    rhs = np.zeros(mesh.n_nodes * 3)
+    rc = lib().or_residual(mesh.n_nodes, mesh.n_elems, _p(mesh.types), _p(mesh.conn_ptr), _p(mesh.conn),
+                           _p(mesh.x), _p(mesh.y), _p(mesh.z), _p(mesh.young), _p(mesh.nu), _p(nh), _p(u),
+                           _p(src), _p(rhs))
+    if rc != 0:
+        raise MeshError(-rc - 1)
+    return rhs
 
 
 def to_dense(g, vals, B, n_nodes):

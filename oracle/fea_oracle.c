@@ -354,6 +354,49 @@ int or_element_fint(int type, const double *X, double young, double nu, const do
     return 0;
 }
 
+/* Newton residual b = f_ext - f_int(u) of the solid (Section 2.2: Newton
+ * iterations on the internal force; A is its Jacobian): for every element
+ * in ascending order, its body-force vector minus its internal force --
+ * the neo-Hookean one, sum_q w detJ P grad N_a, where nh_flag is set, else
+ * the linear-elastic one, K^e u^e with this file's element matrix -- added
+ * into rhs[3 * n_nodes]. Returns 0, or -(1 + e) for a rejected element. */
+int64_t or_residual(int64_t n_nodes, int64_t n_elems, const uint8_t *types, const int64_t *conn_ptr,
+                    const int32_t *conn, const double *x, const double *y, const double *z,
+                    const double *young, const double *nu, const uint8_t *nh_flag, const double *u,
+                    const double *source, double *rhs)
+{
+    double X[24], U[24], Ke[64 * 9], fe[24], fint[24];
+    int64_t e;
+    memset(rhs, 0, sizeof(double) * (size_t)(n_nodes * 3));
+    for (e = 0; e < n_elems; ++e) {
+        int nn = or_nodes(types[e]), a, b, i, j;
+        double E = young ? young[e] : 1.0;
+        for (a = 0; a < nn; ++a) {
+            int32_t v = conn[conn_ptr[e] + a];
+            X[3 * a + 0] = x[v]; X[3 * a + 1] = y[v]; X[3 * a + 2] = z[v];
+            for (i = 0; i < 3; ++i) U[3 * a + i] = u[3 * (int64_t)v + i];
+        }
+        if (or_element(types[e], OR_ELASTIC, 0, X, E, nu[e], U, &source[e * 3], Ke, fe, NULL, NULL))
+            return -(1 + e);
+        if (nh_flag && nh_flag[e]) {
+            if (or_element_fint(types[e], X, E, nu[e], U, fint)) return -(1 + e);
+        } else {
+            for (a = 0; a < nn; ++a)
+                for (i = 0; i < 3; ++i) {
+                    double acc = 0.0;
+                    for (b = 0; b < nn; ++b)
+                        for (j = 0; j < 3; ++j) acc += Ke[((a * nn + b) * 3 + i) * 3 + j] * U[3 * b + j];
+                    fint[3 * a + i] = acc;
+                }
+        }
+        for (a = 0; a < nn; ++a) {
+            int32_t r = conn[conn_ptr[e] + a];
+            for (i = 0; i < 3; ++i) rhs[(int64_t)r * 3 + i] += fe[3 * a + i] - fint[3 * a + i];
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------ *
  * Sparsity pattern, element-to-nonzero map and inverse map.           *
  * ------------------------------------------------------------------ */

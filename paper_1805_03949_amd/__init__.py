@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
 
 
 class Material(ctypes.Structure):
-    _fields_ = [("model", ctypes.c_int), ("young", _P), ("nu", _P), ("nh_flag", _P), ("u", _P)]
+    _fields_ = [("model", ctypes.c_int), ("young", _P), ("nu", _P), ("nh_flag", _P), ("u", _P),
+                ("residual", ctypes.c_int)]
 
 
 _lib.fea_graph_build.argtypes = [_I64, _I64, _P, _P, _P, _P, ctypes.POINTER(_P)]
@@ -228,8 +229,9 @@ class Graph:
 
 def assemble(graph, x, y, z, types, conn_ptr, conn, source, model=ELASTIC, young=None, nu=None,
              nh_flag=None, u=None, precision=FP64, variant=ROWOWNER, out_dtype=F64, vals=None,
-             rhs=None, status=None, stream=None, timing=False):
-    """Assembles (vals, rhs, status) on the GPU; all tensors on the graph's device."""
+             rhs=None, status=None, stream=None, timing=False, residual=False):
+    """Assembles (vals, rhs, status) on the GPU; all tensors on the graph's device.
+    residual: rhs is the Newton residual f_ext - f_int(u) (elasticity, FP64)."""
     B = 1 if model == POISSON else 3
     odt = torch.float64 if out_dtype == F64 else torch.float32
     d = graph.device
@@ -250,7 +252,7 @@ def assemble(graph, x, y, z, types, conn_ptr, conn, source, model=ELASTIC, young
         _dev(nh_flag, torch.uint8)
     _dev(vals, odt)
     _dev(rhs, odt)
-    mat = Material(model, _ptr(young), _ptr(nu), _ptr(nh_flag), _ptr(u))
+    mat = Material(model, _ptr(young), _ptr(nu), _ptr(nh_flag), _ptr(u), int(bool(residual)))
     opt = Options(precision, variant, out_dtype, int(bool(timing)))
     _check(_lib.fea_assemble(graph.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(types), _ptr(conn_ptr),
                              _ptr(conn), ctypes.byref(mat), _ptr(source), ctypes.byref(opt),
@@ -275,7 +277,7 @@ class DeviceMesh:
     def graph(self, stream=None):
         return Graph(self.n_nodes, self.types, self.conn_ptr, self.conn, stream=stream)
 
-    def assemble(self, graph, model=ELASTIC, use_nh=False, **kw):
+    def assemble(self, graph, model=ELASTIC, use_nh=False, residual=False, **kw):
         src = self.source
         if model == POISSON:
             src = src[:, :1].contiguous()
@@ -283,7 +285,8 @@ class DeviceMesh:
                         src, model=model, young=self.young,
                         nu=self.nu if model == ELASTIC else None,
                         nh_flag=self.nh_flag if (use_nh and model == ELASTIC) else None,
-                        u=self.u if (use_nh and model == ELASTIC) else None, **kw)
+                        u=self.u if ((use_nh or residual) and model == ELASTIC) else None,
+                        residual=residual, **kw)
 
 
 def _np_i32(a):

@@ -266,6 +266,12 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
         if (mat->model == FEA_ELASTIC && !mat->nu) return set_error(FEA_EINVAL, "nu is required");
         if (mat->nh_flag && !mat->u) return set_error(FEA_EINVAL, "u is required with nh_flag");
     }
+    if (mat->residual) {
+        if (mat->model != FEA_ELASTIC || (g->n_elems > 0 && !mat->u))
+            return set_error(FEA_EINVAL, "the residual needs the elastic model and u");
+        if (o->precision != FEA_FP64 || o->variant == FEA_ROWGATHER)
+            return set_error(FEA_EINVAL, "the residual is assembled in FP64 by the element-tile forms only");
+    }
     if ((g->nnz > 0 && !vals) || (g->n_nodes > 0 && !rhs))
         return set_error(FEA_EINVAL, "NULL output argument");
     int dev = 0;
@@ -300,6 +306,7 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     a.u = mat->u;
     a.source = source;
     a.status = st;
+    a.residual = mat->residual ? 1 : 0;
 
     if (g->n_elems > 0 && o->variant == FEA_ROWGATHER) {
         GatherInput in = {x, y, z, types, conn_ptr, conn, mat->young, mat->nu, source, st, a.nh_flag, mat->u};
@@ -310,7 +317,7 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
         if (mat->model == FEA_POISSON)
             rc = o->precision == FEA_FP64 ? run<FEA_POISSON, double>(g, a, o, stream, vals, rhs)
                                           : run<FEA_POISSON, float>(g, a, o, stream, vals, rhs);
-        else if (!a.nh_flag)
+        else if (!a.nh_flag && !a.residual)
             rc = o->precision == FEA_FP64 ? run<FEA_ELASTIC, double>(g, a, o, stream, vals, rhs)
                                           : run<FEA_ELASTIC, float>(g, a, o, stream, vals, rhs);
         else

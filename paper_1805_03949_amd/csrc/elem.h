@@ -189,6 +189,9 @@ struct ElemArgs {
     int64_t ntiles;
     const int32_t *tb_blk;
     const int32_t *lpart;
+    // nonzero (neo-Hookean-capable FP64 kernels): the right-hand side is the
+    // Newton residual f_ext - f_int(u)
+    int residual;
 };
 
 // V_ROWSYM: the row-owner scatter on the upper triangle. A symmetric
@@ -424,7 +427,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                 sX[el][a][1] = A.y[v];
                 sX[el][a][2] = A.z[v];
                 if constexpr (NHK) {
-                    bool nh = sNH[el] != 0;
+                    bool nh = sNH[el] != 0 || A.residual;
                     for (int c = 0; c < 3; ++c) sU[el][a][c] = nh ? A.u[3 * (int64_t)v + c] : 0.0;
                 }
             }
@@ -625,6 +628,46 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                 CT wn = sC[el][q][0] * (CT)sNr[q][a];
 #pragma unroll
                 for (int i = 0; i < B; ++i) f[i] += wn * (CT)A.source[(int64_t)e * B + i];
+            }
+            if constexpr (NHK && sizeof(CT) == 8) {
+                if (A.residual) {
+                    // f -= f_int_a = sum_q w detJ P grad N_a. Neo-Hookean:
+                    // P grad N_a = mu F grad N_a + (lam ln J - mu) F^-T grad N_a,
+                    // with F grad N_a = grad N_a + sum_b u_b (grad N_b . grad N_a)
+                    // and h_a = F^-T grad N_a from the tangent's records.
+                    // Linear: sigma = lam tr(H) I + mu (H + H^T), H = sum_b u_b (x) grad N_b.
+                    const bool nh = sNH[el] != 0;
+                    const double lam = sLM[el][0], mu = sLM[el][1];
+                    for (int q = 0; q < NQ; ++q) {
+                        const double ga[3] = {sG[el].v[q][a][0], sG[el].v[q][a][1], sG[el].v[q][a][2]};
+                        double uh[3] = {0.0, 0.0, 0.0};  // sum_b u_b (G_b . G_a)
+                        double hu[3] = {0.0, 0.0, 0.0};  // sum_b (u_b . G_a) G_b
+                        double trh = 0.0;                // sum_b u_b . G_b
+#pragma unroll
+                        for (int b = 0; b < NN; ++b) {
+                            const double gb[3] = {sG[el].v[q][b][0], sG[el].v[q][b][1], sG[el].v[q][b][2]};
+                            const double ub[3] = {sU[el][b][0], sU[el][b][1], sU[el][b][2]};
+                            const double gg = gb[0] * ga[0] + gb[1] * ga[1] + gb[2] * ga[2];
+                            const double ug = ub[0] * ga[0] + ub[1] * ga[1] + ub[2] * ga[2];
+                            trh += ub[0] * gb[0] + ub[1] * gb[1] + ub[2] * gb[2];
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) {
+                                uh[i] += ub[i] * gg;
+                                hu[i] += ug * gb[i];
+                            }
+                        }
+                        if (nh) {
+                            const double c0 = sC[el][q][3], c2 = sC[el][q][2];
+#pragma unroll
+                            for (int i = 0; i < 3; ++i)
+                                f[i] -= c0 * (ga[i] + uh[i]) - c2 * (double)sH[el].v[q][a][i];
+                        } else {
+                            const double wd = sC[el][q][0];
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) f[i] -= wd * (lam * trh * ga[i] + mu * (uh[i] + hu[i]));
+                        }
+                    }
+                }
             }
             if constexpr (RO) {
                 CT *dst = (CT *)A.rcontrib + (int64_t)A.prdest[(first + el) * NN + a] * B;

@@ -384,3 +384,58 @@ def test_rowsym_is_exactly_symmetric_and_matches_rowowner(name):
         tol = 1e-14 if prec == fea.FP64 else 1e-6
         scale = np.abs(va).max()
         assert np.abs(vb.astype(np.float64) - va).max() <= tol * scale, prec
+
+
+def _displaced(m, seed, amp=0.03):
+    rng = np.random.default_rng(seed)
+    X = np.stack([m.x, m.y, m.z], axis=1)
+    k, ph = rng.integers(1, 3, size=(3, 3)), rng.uniform(0, 2 * np.pi, size=3)
+    u = amp * np.stack([np.sin(2 * np.pi * X @ k[i] + ph[i]) for i in range(3)], axis=1)
+    m.u = u.reshape(-1).copy()
+    return m
+
+
+_res_cache = {}
+
+
+def _residual_case(name):
+    if name not in _res_cache:
+        if name == "hetero8_nh":
+            m = mg.heterogeneous(8, seed=5, brick=2, jitter=0.1)
+            use_nh = True
+        else:
+            m = _displaced(mg.hybrid_bands(4, seed=3, jitter=0.2), seed=4)
+            use_nh = False
+        og = oracle.mesh_graph(m)
+        _, f_ext = oracle.assemble(m, og, model=oracle.ELASTIC, use_nh=use_nh)
+        ref = oracle.residual(m, use_nh=use_nh)
+        dm = fea.DeviceMesh(m, device="cuda:0")
+        _res_cache[name] = (m, og, dm, dm.graph(), use_nh, f_ext, ref)
+    return _res_cache[name]
+
+
+@pytest.mark.parametrize("variant", [fea.ROWOWNER, fea.ATOMIC, fea.COLOUR, fea.ROWSYM, fea.TILECOLOUR])
+@pytest.mark.parametrize("name", ["hetero8_nh", "bands4_displaced"])
+def test_residual_fp64_parity(name, variant):
+    """Newton residual f_ext - f_int(u): neo-Hookean internal force where
+    flagged, linear K^e u^e elsewhere, against the oracle (scaled by the
+    larger of |f_ext| and |f_int|, since the two partly cancel)."""
+    m, og, dm, g, use_nh, f_ext, ref = _residual_case(name)
+    vals, rhs, st = dm.assemble(g, model=fea.ELASTIC, use_nh=use_nh, residual=True, variant=variant)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -1
+    scale = max(np.abs(f_ext).max(), np.abs(f_ext - ref).max())
+    err = np.abs(rhs.cpu().numpy() - ref).max() / scale
+    assert err <= 1e-12, err
+    # the matrix is the ordinary tangent
+    v0, _, _ = dm.assemble(g, model=fea.ELASTIC, use_nh=use_nh, variant=variant)
+    torch.cuda.synchronize()
+    assert np.abs(vals.cpu().numpy() - v0.cpu().numpy()).max() <= 1e-14 * np.abs(v0.cpu().numpy()).max()
+
+
+def test_residual_rejects_mixed_precision_and_row_gather():
+    m, og, dm, g, use_nh, f_ext, ref = _residual_case("hetero8_nh")
+    for kw in ({"precision": fea.MIXED, "out_dtype": fea.F32}, {"variant": fea.ROWGATHER}):
+        with pytest.raises(fea.FeaError) as ei:
+            dm.assemble(g, model=fea.ELASTIC, use_nh=True, residual=True, **kw)
+        assert ei.value.code == fea.FEA_EINVAL

@@ -497,3 +497,48 @@ def test_table2_load_balance_golden():
     lbs = [avg / mx for mx, _, avg in r100]
     np.testing.assert_allclose(lbs, [0.345, 0.252, 0.247], atol=1e-3)
     assert abs(sched.load_balance([1.0, 2.0, 3.0]) - 6.0 / 9.0) < 1e-15
+
+
+# ---------------------------------------------------------------- residual
+def _with_u(m, seed, amp=0.03):
+    rng = np.random.default_rng(seed)
+    X = np.stack([m.x, m.y, m.z], axis=1)
+    k, ph = rng.integers(1, 3, size=(3, 3)), rng.uniform(0, 2 * np.pi, size=3)
+    u = amp * np.stack([np.sin(2 * np.pi * X @ k[i] + ph[i]) for i in range(3)], axis=1)
+    m.u = u.reshape(-1).copy()
+    return m
+
+
+def test_residual_at_rest_is_the_external_force():
+    """f_int(0) = 0 for both materials (P(I) = 0, K u = 0): the residual at
+    u = 0 is exactly the assembled right-hand side."""
+    m = mg.heterogeneous(8, seed=5, brick=2, jitter=0.1)
+    m.u = np.zeros_like(m.u)
+    og = oracle.mesh_graph(m)
+    _, rhs = oracle.assemble(m, og, model=oracle.ELASTIC)
+    assert np.array_equal(oracle.residual(m), rhs)
+
+
+def test_residual_of_a_linear_solid_is_f_minus_A_u():
+    """Linear elasticity: f_int = K u, so the residual equals f - A u with
+    the assembled global matrix."""
+    m = _with_u(mg.hybrid_bands(4, seed=3, jitter=0.2), seed=4)
+    og = oracle.mesh_graph(m)
+    vals, rhs = oracle.assemble(m, og, model=oracle.ELASTIC, use_nh=False)
+    A = oracle.to_dense(og, vals, 3, m.n_nodes)
+    ref = rhs - A @ m.u
+    r = oracle.residual(m, use_nh=False)
+    assert np.abs(r - ref).max() <= 1e-12 * np.abs(A).max() * np.abs(m.u).max() * 10
+
+
+def test_residual_internal_forces_sum_to_zero():
+    """Every element's internal force sums to zero over its nodes (the shape
+    functions sum to one), so the residual's total is the external force's."""
+    m = mg.heterogeneous(8, seed=6, brick=2, jitter=0.1)
+    og = oracle.mesh_graph(m)
+    _, rhs = oracle.assemble(m, og, model=oracle.ELASTIC)
+    r = oracle.residual(m)
+    assert not np.allclose(r, rhs)  # the displacement field is not zero
+    scale = np.abs(r).sum()
+    for i in range(3):
+        assert abs(r[i::3].sum() - rhs[i::3].sum()) <= 1e-12 * scale
