@@ -306,7 +306,6 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     a.u = mat->u;
     a.source = source;
     a.status = st;
-    a.residual = mat->residual ? 1 : 0;
 
     if (g->n_elems > 0 && o->variant == FEA_ROWGATHER) {
         GatherInput in = {x, y, z, types, conn_ptr, conn, mat->young, mat->nu, source, st, a.nh_flag, mat->u};
@@ -317,7 +316,9 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
         if (mat->model == FEA_POISSON)
             rc = o->precision == FEA_FP64 ? run<FEA_POISSON, double>(g, a, o, stream, vals, rhs)
                                           : run<FEA_POISSON, float>(g, a, o, stream, vals, rhs);
-        else if (!a.nh_flag && !a.residual)
+        else if (mat->residual)
+            rc = run<M_ELASTIC_RES, double>(g, a, o, stream, vals, rhs);
+        else if (!a.nh_flag)
             rc = o->precision == FEA_FP64 ? run<FEA_ELASTIC, double>(g, a, o, stream, vals, rhs)
                                           : run<FEA_ELASTIC, float>(g, a, o, stream, vals, rhs);
         else

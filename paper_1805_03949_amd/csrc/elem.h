@@ -189,9 +189,6 @@ struct ElemArgs {
     int64_t ntiles;
     const int32_t *tb_blk;
     const int32_t *lpart;
-    // nonzero (neo-Hookean-capable FP64 kernels): the right-hand side is the
-    // Newton residual f_ext - f_int(u)
-    int residual;
 };
 
 // V_ROWSYM: the row-owner scatter on the upper triangle. A symmetric
@@ -211,6 +208,10 @@ enum { V_ROWOWNER = 0, V_ATOMIC = 1, V_COLOUR = 2, V_ROWSYM = 3, V_TILECOL = 4 }
 // M_ELASTIC_NH (some elements use the neo-Hookean tangent; only these
 // kernels carry the displacement and pushed-gradient LDS arrays).
 constexpr int M_ELASTIC_NH = 2;
+// M_ELASTIC_RES: as M_ELASTIC_NH, and the right-hand side is the Newton
+// residual f_ext - f_int(u) (its own instantiations: the internal-force
+// code would otherwise raise every neo-Hookean kernel's register count)
+constexpr int M_ELASTIC_RES = 3;
 
 
 __device__ inline double det3(const double J[3][3])
@@ -273,7 +274,7 @@ struct ElemSmem {
     static constexpr int PW = (VAR == V_ROWSYM || VAR == V_TILECOL) ? NN * (NN + 1) / 2 : P;
     static constexpr int EPB = 256 / PW;
     static constexpr bool ELAS = MODEL != FEA_POISSON;
-    static constexpr bool NHK = MODEL == M_ELASTIC_NH;
+    static constexpr bool NHK = MODEL == M_ELASTIC_NH || MODEL == M_ELASTIC_RES;
     static constexpr int B = ELAS ? 3 : 1;
     static constexpr int BB = B * B;
     static constexpr int EU = NHK ? EPB : 1;
@@ -327,7 +328,8 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     constexpr int PW = ElemSmem<T, MODEL, VAR, CT>::PW;
     constexpr int EPB = ElemSmem<T, MODEL, VAR, CT>::EPB;
     constexpr bool ELAS = MODEL != FEA_POISSON;
-    constexpr bool NHK = MODEL == M_ELASTIC_NH;
+    constexpr bool NHK = MODEL == M_ELASTIC_NH || MODEL == M_ELASTIC_RES;
+    constexpr bool RES = MODEL == M_ELASTIC_RES && sizeof(CT) == 8;
     constexpr int B = ELAS ? 3 : 1;
     constexpr int BB = B * B;
     constexpr int EU = NHK ? EPB : 1;
@@ -427,7 +429,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                 sX[el][a][1] = A.y[v];
                 sX[el][a][2] = A.z[v];
                 if constexpr (NHK) {
-                    bool nh = sNH[el] != 0 || A.residual;
+                    bool nh = sNH[el] != 0 || MODEL == M_ELASTIC_RES;
                     for (int c = 0; c < 3; ++c) sU[el][a][c] = nh ? A.u[3 * (int64_t)v + c] : 0.0;
                 }
             }
@@ -629,8 +631,8 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
 #pragma unroll
                 for (int i = 0; i < B; ++i) f[i] += wn * (CT)A.source[(int64_t)e * B + i];
             }
-            if constexpr (NHK && sizeof(CT) == 8) {
-                if (A.residual) {
+            if constexpr (RES) {
+                {
                     // f -= f_int_a = sum_q w detJ P grad N_a. Neo-Hookean:
                     // P grad N_a = mu F grad N_a + (lam ln J - mu) F^-T grad N_a,
                     // with F grad N_a = grad N_a + sum_b u_b (grad N_b . grad N_a)
