@@ -8,7 +8,8 @@ Contents:
   fea_oracle.c   plain FP64 C: shape functions, Gauss rules, element
                  matrices (Poisson, linear elasticity, neo-Hookean tangent),
                  sparsity pattern / element-to-nonzero map / inverse map,
-                 greedy colouring, Algorithm 1 assembly with |term| sums
+                 greedy colouring, Algorithm 1 assembly with |term| sums,
+                 the Newton residual and the element-wise subgrid scale
   dense.py       a second, independent formulation (dense Voigt B^T D B) for
                  tiny meshes, used to cross-check fea_oracle.c
   mlp.py         FP64 NumPy forward/backward/Adam for the cost model
@@ -64,6 +65,11 @@ def lib():
         L.or_assemble.restype = i64
         L.or_residual.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P, P, P]
         L.or_residual.restype = i64
+        L.or_shape2.argtypes = [ctypes.c_int, P, P]
+        L.or_element_subscale.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_double, ctypes.c_double,
+                                          P, P, P]
+        L.or_subscale.argtypes = [i64, P, P, P, P, P, P, ctypes.c_int, P, P, P, P, P, P]
+        L.or_subscale.restype = i64
         _lib = L
     return _lib
 
@@ -221,6 +227,56 @@ def residual(mesh, use_nh=True):
     if rc != 0:
         raise MeshError(-rc - 1)
     return rhs
+
+
+def shape2(etype, xi):
+    """Second reference derivatives D2[a, j, l] = d2 N_a / dxi_j dxi_l."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    D2 = np.zeros((8, 3, 3))
+    nn = lib().or_shape2(etype, _p(xi), _p(D2))
+    return D2[:nn].copy()
+
+
+def element_subscale(etype, X, u, model=ELASTIC, young=1.0, nu=0.3, f=None):
+    """Subgrid scale of one element at its Gauss points, shape (nq, B):
+    tau_e (f + L(u_h)(x_q)), L the Laplacian (Poisson) or div sigma
+    (linear elasticity), tau_e = V_e^(2/3) / (4 k), k = 1 or mu."""
+    nn = NODES[etype]
+    B = 1 if model == POISSON else 3
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(nn, 3)
+    U = np.ascontiguousarray(u, dtype=np.float64).reshape(nn * B)
+    if f is None:
+        f = np.ones(1) if B == 1 else np.array([0.0, 0.0, -1.0])
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(8 * B)
+    rc = lib().or_element_subscale(etype, model, _p(X), young, nu, _p(U), _p(f), _p(out))
+    if rc != 0:
+        raise ValueError(f"element rejected (code {rc}): detJ <= 0")
+    nq = rule(etype)[0].shape[0]
+    return out[:nq * B].reshape(nq, B).copy()
+
+
+def subscale(mesh, u, model=ELASTIC):
+    """Subgrid scale of every element (element loop, nothing assembled).
+    u: nodal field, B values per node (node-major). Returns (gp_ptr, out)
+    with element e's Gauss points at rows gp_ptr[e] .. gp_ptr[e+1] of
+    out[n_points, B]."""
+    B = 1 if model == POISSON else 3
+    if mesh.source.shape[1] < B:
+        raise ValueError("elasticity needs a 3-component source per element")
+    src = np.ascontiguousarray(mesh.source[:, :B], dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    if u.shape[0] != mesh.n_nodes * B:
+        raise ValueError("u must hold B values per node")
+    gp_ptr = np.zeros(mesh.n_elems + 1, dtype=np.int64)
+    n_pts = int(sum(rule(t)[0].shape[0] * int(np.count_nonzero(mesh.types == t)) for t in range(4)))
+    out = np.zeros(n_pts * B)
+    rc = lib().or_subscale(mesh.n_elems, _p(mesh.types), _p(mesh.conn_ptr), _p(mesh.conn), _p(mesh.x),
+                           _p(mesh.y), _p(mesh.z), model, _p(mesh.young), _p(mesh.nu), _p(u), _p(src),
+                           _p(gp_ptr), _p(out))
+    if rc != 0:
+        raise MeshError(-rc - 1)
+    return gp_ptr, out.reshape(n_pts, B)
 
 
 def to_dense(g, vals, B, n_nodes):

@@ -28,6 +28,10 @@
  *       F = I + sum_a u_a (x) grad N_a,  P = mu (F - F^-T) + lam ln(det F) F^-T,
  *       AA_iJjL = mu d_ij d_JL + (mu - lam ln J) Finv_Jj Finv_Li + lam Finv_Ji Finv_Lj,
  *       K_(a,i)(b,j) = sum_q w detJ sum_JL dN_a/dX_J AA_iJjL dN_b/dX_L.
+ * It also evaluates, element by element with nothing assembled, the
+ * subgrid scale of Section 2.1.2 read for these problems (the strong
+ * residual f + L(u_h) at every Gauss point scaled by an element constant;
+ * or_element_subscale states the reading).
  * Alongside the values it assembles T, the same sums taken over the
  * absolute value of every product term (for the neo-Hookean tangent, of
  * each of its three parts separately); a computation in a lower precision
@@ -393,6 +397,192 @@ int64_t or_residual(int64_t n_nodes, int64_t n_elems, const uint8_t *types, cons
             int32_t r = conn[conn_ptr[e] + a];
             for (i = 0; i < 3; ++i) rhs[(int64_t)r * 3 + i] += fe[3 * a + i] - fint[3 * a + i];
         }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ *
+ * Subgrid scale: an element loop with no assembly.                    *
+ * ------------------------------------------------------------------ */
+
+/* Second reference derivatives at xi: D2[(a*3 + j)*3 + l] = d2 N_a / dxi_j dxi_l,
+ * all nine entries, from the shape functions of or_shape differentiated
+ * twice. */
+int or_shape2(int type, const double *xi, double *D2)
+{
+    double r = xi[0], s = xi[1], t = xi[2];
+    int a, j, l;
+    switch (type) {
+    case OR_TET4:
+        /* linear: every second derivative vanishes */
+        for (a = 0; a < 36; ++a) D2[a] = 0.0;
+        return 4;
+    case OR_HEX8:
+        for (a = 0; a < 8; ++a) {
+            double sx = hex_sign[a][0], sy = hex_sign[a][1], sz = hex_sign[a][2];
+            double f[3] = {1.0 + sx * r, 1.0 + sy * s, 1.0 + sz * t};
+            double d[3] = {sx, sy, sz}; /* d f_j / d xi_j; d2 f_j / d xi_j^2 = 0 */
+            for (j = 0; j < 3; ++j)
+                for (l = 0; l < 3; ++l) {
+                    double v;
+                    if (j == l) {
+                        v = 0.0;
+                    } else {
+                        int m = 3 - j - l; /* the third direction */
+                        v = d[j] * d[l] * f[m] / 8.0;
+                    }
+                    D2[(a * 3 + j) * 3 + l] = v;
+                }
+        }
+        return 8;
+    case OR_PEN6: {
+        /* N = L_k(r, s) g(t): L linear in (r, s), g linear in t */
+        double L[3] = {1.0 - r - s, r, s};
+        double dL[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+        for (a = 0; a < 6; ++a) {
+            int k = a % 3;
+            double dg = (a < 3) ? -0.5 : 0.5;
+            double H[3][3];
+            H[0][0] = 0.0; H[1][1] = 0.0; H[0][1] = H[1][0] = 0.0;
+            H[0][2] = H[2][0] = dL[k][0] * dg;
+            H[1][2] = H[2][1] = dL[k][1] * dg;
+            H[2][2] = L[k] * 0.0;
+            for (j = 0; j < 3; ++j)
+                for (l = 0; l < 3; ++l) D2[(a * 3 + j) * 3 + l] = H[j][l];
+        }
+        return 6;
+    }
+    case OR_PYR5:
+        for (a = 0; a < 4; ++a) {
+            double sx = hex_sign[a][0], sy = hex_sign[a][1];
+            double fx = 1.0 + sx * r, fy = 1.0 + sy * s, fz = 1.0 - t;
+            double H[3][3];
+            H[0][0] = 0.0; H[1][1] = 0.0; H[2][2] = 0.0;
+            H[0][1] = H[1][0] = sx * sy * fz / 8.0;
+            H[0][2] = H[2][0] = -sx * fy / 8.0;
+            H[1][2] = H[2][1] = -fx * sy / 8.0;
+            for (j = 0; j < 3; ++j)
+                for (l = 0; l < 3; ++l) D2[(a * 3 + j) * 3 + l] = H[j][l];
+        }
+        for (j = 0; j < 9; ++j) D2[36 + j] = 0.0; /* apex (1 + t) / 2 */
+        return 5;
+    }
+    return -1;
+}
+
+/*
+ * Subgrid scale of one element (Section 2.1.2: the subgrid scale comes from
+ * an element-wise equation, utilde = tau^-1 (R u + b) with a diagonal tau
+ * and a rectangular R, in a plain loop over elements, no system formed).
+ * Read for the problems assembled here: at Gauss point q,
+ *   utilde_q = tau_e (f_e + L(u_h)(x_q)),
+ * L(u) = Laplacian of u (Poisson, -Lap u = f) or div sigma(u) =
+ * mu Lap u + (lam + mu) grad div u (linear elasticity), u_h = sum_a N_a u_a,
+ * tau_e = h_e^2 / (4 k), h_e = V_e^(1/3), V_e = sum_q w_q detJ_q, k = 1
+ * (Poisson) or mu_e (elasticity). The paper's diagonal matrix is 1/tau_e on
+ * every (Gauss point, component); R u + b is the strong residual.
+ * Physical second derivatives of u_h follow from differentiating
+ * u(x(xi)) twice: H_xi = J^T H_x J + sum_k (du/dx_k) H_xi(x_k), so
+ * H_x = J^-T (H_xi(u) - sum_k (du/dx_k) H_xi(x_k)) J^-1.
+ * U[a*B + c]: nodal values; out[q*B + c]. Returns 0, or 1 + q when
+ * detJ <= 0 at Gauss point q.
+ */
+int or_element_subscale(int type, int model, const double *X, double young, double nu,
+                        const double *U, const double *f, double *out)
+{
+    double pts[8 * 3], w[8], N[8], dN[24], D2[72], G[8][3], Ji[3][3], Jm[3][3];
+    double r[8][3];
+    int nn = or_nodes(type), nq = or_rule(type, pts, w), B = (model == OR_POISSON) ? 1 : 3;
+    int a, c, i, j, k, l, m, q;
+    double lam = 0.0, mu = 1.0, V = 0.0;
+    if (model != OR_POISSON) lame(young, nu, &lam, &mu);
+    for (q = 0; q < nq; ++q) {
+        or_shape(type, &pts[3 * q], N, dN);
+        or_shape2(type, &pts[3 * q], D2);
+        double detJ = point_geometry(nn, X, dN, G);
+        if (!(detJ > 0.0)) return 1 + q;
+        for (i = 0; i < 3; ++i)
+            for (j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (a = 0; a < nn; ++a) acc += X[3 * a + i] * dN[3 * a + j];
+                Jm[i][j] = acc;
+            }
+        inv3(Jm, Ji);
+        V += w[q] * detJ;
+        double gu[3][3], Hx_geo[3][3][3], H[3][3][3];
+        /* du_c/dx_k */
+        for (c = 0; c < B; ++c)
+            for (k = 0; k < 3; ++k) {
+                double acc = 0.0;
+                for (a = 0; a < nn; ++a) acc += U[a * B + c] * G[a][k];
+                gu[c][k] = acc;
+            }
+        /* second xi-derivatives of the geometry x_k(xi) */
+        for (k = 0; k < 3; ++k)
+            for (j = 0; j < 3; ++j)
+                for (l = 0; l < 3; ++l) {
+                    double acc = 0.0;
+                    for (a = 0; a < nn; ++a) acc += X[3 * a + k] * D2[(a * 3 + j) * 3 + l];
+                    Hx_geo[k][j][l] = acc;
+                }
+        for (c = 0; c < B; ++c) {
+            double M[3][3];
+            for (j = 0; j < 3; ++j)
+                for (l = 0; l < 3; ++l) {
+                    double acc = 0.0;
+                    for (a = 0; a < nn; ++a) acc += U[a * B + c] * D2[(a * 3 + j) * 3 + l];
+                    for (k = 0; k < 3; ++k) acc -= gu[c][k] * Hx_geo[k][j][l];
+                    M[j][l] = acc;
+                }
+            /* H = J^-T M J^-1 */
+            for (i = 0; i < 3; ++i)
+                for (m = 0; m < 3; ++m) {
+                    double acc = 0.0;
+                    for (j = 0; j < 3; ++j)
+                        for (l = 0; l < 3; ++l) acc += Ji[j][i] * M[j][l] * Ji[l][m];
+                    H[c][i][m] = acc;
+                }
+        }
+        if (B == 1) {
+            r[q][0] = f[0] + (H[0][0][0] + H[0][1][1] + H[0][2][2]);
+        } else {
+            for (i = 0; i < 3; ++i) {
+                double lap = H[i][0][0] + H[i][1][1] + H[i][2][2];
+                double gdiv = H[0][i][0] + H[1][i][1] + H[2][i][2];
+                r[q][i] = f[i] + (mu * lap + (lam + mu) * gdiv);
+            }
+        }
+    }
+    double h = cbrt(V);
+    double tau = h * h / (4.0 * (model == OR_POISSON ? 1.0 : mu));
+    for (q = 0; q < nq; ++q)
+        for (c = 0; c < B; ++c) out[q * B + c] = tau * r[q][c];
+    return 0;
+}
+
+/* Subgrid scale of every element, in element order: element e's Gauss
+ * points at gp_ptr[e] .. gp_ptr[e+1] (gp_ptr[0] = 0, its Gauss-point counts
+ * summed), out[(gp_ptr[e] + q) * B + c]. u: nodal field, B values per node
+ * (node-major). Returns 0, or -(1 + e) for a rejected element. */
+int64_t or_subscale(int64_t n_elems, const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
+                    const double *x, const double *y, const double *z, int model, const double *young,
+                    const double *nu, const double *u, const double *source, int64_t *gp_ptr, double *out)
+{
+    double X[24], U[24], pts[24], w[8];
+    int B = (model == OR_POISSON) ? 1 : 3;
+    int64_t e;
+    gp_ptr[0] = 0;
+    for (e = 0; e < n_elems; ++e) gp_ptr[e + 1] = gp_ptr[e] + or_rule(types[e], pts, w);
+    for (e = 0; e < n_elems; ++e) {
+        int nn = or_nodes(types[e]), a, c;
+        for (a = 0; a < nn; ++a) {
+            int32_t v = conn[conn_ptr[e] + a];
+            X[3 * a + 0] = x[v]; X[3 * a + 1] = y[v]; X[3 * a + 2] = z[v];
+            for (c = 0; c < B; ++c) U[a * B + c] = u[(int64_t)v * B + c];
+        }
+        if (or_element_subscale(types[e], model, X, young ? young[e] : 1.0, nu ? nu[e] : 0.0, U,
+                                &source[e * B], &out[gp_ptr[e] * B]))
+            return -(1 + e);
     }
     return 0;
 }

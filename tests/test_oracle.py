@@ -542,3 +542,187 @@ def test_residual_internal_forces_sum_to_zero():
     scale = np.abs(r).sum()
     for i in range(3):
         assert abs(r[i::3].sum() - rhs[i::3].sum()) <= 1e-12 * scale
+
+
+# ---------------------------------------------------------------- subgrid scale
+# The element-wise subgrid scale (Section 2.1.2), read for Poisson and linear
+# elasticity: tau_e (f + L(u_h)) at every Gauss point, tau_e = V_e^(2/3)/(4k).
+
+# physical volume of the element whose nodes sit at REF_NODES[t]
+PHYS_VOLUME = {TET4: 1 / 6, PYR5: 8 / 3, PEN6: 1.0, HEX8: 8.0}
+
+
+def _ref_map(t, xi):
+    """Position of reference point xi in the element with nodes REF_NODES[t]:
+    the identity for tet4, pen6 and hex8, the collapsed-hexahedron map for
+    the pyramid (base at z = -1, apex at z = 1)."""
+    r, s, z = xi
+    if t == PYR5:
+        return np.array([r * (1 - z) / 2, s * (1 - z) / 2, z])
+    return np.array([r, s, z])
+
+
+def _field(t, p, k):
+    """Value and exact Hessian at p of a field that the family's shape
+    functions represent exactly on the REF_NODES element (k picks one of
+    three variants). tet4: linear only (zero Hessian)."""
+    p1, p2, p3 = p
+    c = [(1.0, 2.0, -1.0, 3.0), (-0.5, 1.0, 2.0, -1.0), (2.0, -1.5, 0.5, 1.0)][k]
+    H = np.zeros((3, 3))
+    if t == HEX8:   # multilinear
+        v = c[0] * p1 * p2 + c[1] * p2 * p3 + c[2] * p1 * p3 + c[3] * p1 * p2 * p3
+        H[0, 1] = c[0] + c[3] * p3
+        H[1, 2] = c[1] + c[3] * p1
+        H[0, 2] = c[2] + c[3] * p2
+    elif t == PEN6:  # linear in (p1, p2) times linear in p3
+        v = c[0] * p1 * p3 + c[1] * p2 * p3
+        H[0, 2] = c[0]
+        H[1, 2] = c[1]
+    elif t == PYR5:  # the pyramid's rational mode p1 p2 / (1 - p3), 0 at the apex
+        d = 1.0 - p3
+        v = c[0] * p1 * p2 / d if d > 0 else 0.0
+        if d > 0:  # Gauss points lie below the apex
+            H[0, 1] = c[0] / d
+            H[0, 2] = c[0] * p2 / d ** 2
+            H[1, 2] = c[0] * p1 / d ** 2
+            H[2, 2] = 2 * c[0] * p1 * p2 / d ** 3
+    else:
+        v = 0.0
+    v += c[1] * p1 - c[2] * p2 + c[3] * p3 + c[0]
+    return v, H + np.triu(H, 1).T
+
+
+@pytest.mark.parametrize("t", [TET4, PYR5, PEN6, HEX8])
+def test_subscale_closed_form_on_affine_images(t):
+    """Affine image x = A p + b of the reference-node element (A not
+    symmetric), field u(x) = phi(A^-1 (x - b)) with phi exactly
+    representable: the physical Hessian is A^-T H_p A^-1 at every Gauss
+    point, the volume |det A| times the reference volume."""
+    rng = np.random.default_rng(40 + t)
+    A = np.eye(3) + 0.3 * rng.standard_normal((3, 3))
+    if np.linalg.det(A) < 0:
+        A[:, 0] *= -1
+    b = rng.standard_normal(3)
+    Ai = np.linalg.inv(A)
+    Xr = REF_NODES[t]
+    X = Xr @ A.T + b
+    pts, _ = oracle.rule(t)
+    V = abs(np.linalg.det(A)) * PHYS_VOLUME[t]
+    young, nu = 1.7, 0.28
+    lam = young * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = young / (2 * (1 + nu))
+    # Poisson
+    u = np.array([_field(t, p, 0)[0] for p in Xr])
+    got = oracle.element_subscale(t, X, u, model=oracle.POISSON, f=np.array([0.7]))
+    tau = V ** (2 / 3) / 4
+    for q, xi in enumerate(pts):
+        Hx = Ai.T @ _field(t, _ref_map(t, xi), 0)[1] @ Ai
+        assert abs(got[q, 0] - tau * (0.7 + np.trace(Hx))) <= 1e-13 * tau * (1 + np.abs(Hx).max())
+    # elasticity: component i uses variant i
+    u3 = np.array([[_field(t, p, i)[0] for i in range(3)] for p in Xr])
+    f = np.array([0.1, -0.2, -1.0])
+    got = oracle.element_subscale(t, X, u3, model=oracle.ELASTIC, young=young, nu=nu, f=f)
+    tau = V ** (2 / 3) / (4 * mu)
+    for q, xi in enumerate(pts):
+        H = [Ai.T @ _field(t, _ref_map(t, xi), i)[1] @ Ai for i in range(3)]
+        L = np.array([mu * np.trace(H[i]) + (lam + mu) * sum(H[k][i, k] for k in range(3)) for i in range(3)])
+        scale = tau * (1 + (lam + mu) * max(np.abs(h).max() for h in H))
+        np.testing.assert_allclose(got[q], tau * (f + L), rtol=0, atol=1e-13 * scale)
+    if t != TET4:  # the closed forms are not trivially zero
+        assert np.abs(got / tau - f).max() > 0.1
+
+
+@pytest.mark.parametrize("t", [TET4, PYR5, PEN6, HEX8])
+def test_subscale_of_linear_fields_on_distorted_elements(t):
+    """Isoparametric elements reproduce linear fields, so L(u_h) = 0 on any
+    valid element: at every Gauss point the subgrid scale is tau_e f. On a
+    non-affine element this needs the geometric term of the second
+    derivatives to cancel the reference ones exactly. V_e is taken from the
+    element right-hand side (sum_a f_a = V_e f for f = 1)."""
+    rng = np.random.default_rng(50 + t)
+    X = REF_NODES[t] * 0.3 + rng.uniform(-0.04, 0.04, REF_NODES[t].shape)
+    _, fe = oracle.element(t, X, model=oracle.POISSON, f=np.ones(1))
+    V = fe.sum()
+    G = rng.standard_normal((3, 3))
+    u3 = X @ G.T + rng.standard_normal(3)
+    f = np.array([0.3, 0.5, -1.0])
+    young, nu = 2.1, 0.33
+    mu = young / (2 * (1 + nu))
+    got = oracle.element_subscale(t, X, u3, model=oracle.ELASTIC, young=young, nu=nu, f=f)
+    tau = V ** (2 / 3) / (4 * mu)
+    lam_mu = young * nu / ((1 + nu) * (1 - 2 * nu)) + mu
+    # rounding of second derivatives of size |G| / h^2 amplified by lam + mu
+    np.testing.assert_allclose(got, np.tile(tau * f, (len(got), 1)), rtol=0,
+                               atol=1e-12 * tau * lam_mu * np.abs(G).max() / 0.3 ** 2)
+    up = X @ G[0] + 0.4
+    got = oracle.element_subscale(t, X, up, model=oracle.POISSON, f=np.array([2.0]))
+    np.testing.assert_allclose(got[:, 0], V ** (2 / 3) / 4 * 2.0, rtol=1e-11)
+    if t != TET4:  # the reference second derivatives alone do not vanish
+        D2 = oracle.shape2(t, oracle.rule(t)[0][0])
+        assert np.abs(np.einsum("ajl,a->jl", D2, up)).max() > 1e-3
+
+
+@pytest.mark.parametrize("t", [TET4, PYR5, PEN6, HEX8])
+def test_shape_second_derivatives_central_difference(t):
+    rng = np.random.default_rng(60 + t)
+    h = 1e-5
+    for _ in range(3):
+        xi = random_ref_point(t, rng) * 0.9
+        D2 = oracle.shape2(t, xi)
+        for j in range(3):
+            e = np.zeros(3)
+            e[j] = h
+            fd = (oracle.shape(t, xi + e)[1] - oracle.shape(t, xi - e)[1]) / (2 * h)
+            np.testing.assert_allclose(D2[:, j, :], fd, atol=1e-8)
+
+
+def test_subscale_mesh_layout_on_a_hex_grid():
+    """Axis-aligned cubes and a global multilinear field: each element's
+    interpolant is the field itself, so every Gauss point holds the exact
+    tau_e (f_e + div sigma(u)) at its own position; Gauss points are laid
+    out element by element in element order."""
+    m = mg.tiny_mesh(np.full((3, 3, 3), HEX8), jitter=0.0, seed=13)
+    rng = np.random.default_rng(7)
+    m.young[:] = rng.uniform(1.0, 2.0, m.n_elems)
+    m.nu[:] = rng.uniform(0.2, 0.35, m.n_elems)
+    m.source = rng.standard_normal((m.n_elems, 3))
+    X = np.stack([m.x, m.y, m.z], axis=1)
+    x, y, z = X.T
+    u = np.stack([x * y + 2 * x * y * z, y * z - x * z, x * z + 3 * x * y], axis=1)
+    gp_ptr, got = oracle.subscale(m, u.reshape(-1), model=oracle.ELASTIC)
+    assert np.array_equal(gp_ptr, 8 * np.arange(m.n_elems + 1))
+    pts, _ = oracle.rule(HEX8)
+    for e in range(m.n_elems):
+        nodes = m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]]
+        lo, hi = X[nodes].min(0), X[nodes].max(0)
+        V = np.prod(hi - lo)
+        E, nu = m.young[e], m.nu[e]
+        lam, mu = E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+        tau = V ** (2 / 3) / (4 * mu)
+        for q, xi in enumerate(pts):
+            # the cube's nodes follow the reference order, so x = lo + (xi + 1)/2 (hi - lo)
+            px, py, pz = lo + (xi + 1) / 2 * (hi - lo)
+            # div u = y + 2yz + z + x; Lap u = 0 for multilinear components
+            gdiv = np.array([1.0, 1.0 + 2 * pz, 1.0 + 2 * py])
+            L = (lam + mu) * gdiv
+            np.testing.assert_allclose(got[gp_ptr[e] + q], tau * (m.source[e] + L), rtol=1e-12,
+                                       atol=1e-12 * tau * (lam + mu))
+
+
+def test_subscale_mesh_volumes_and_scalar_field():
+    """Unjittered hybrid bands: every element of a family has the same
+    volume (h^3 for hex8, h^3/2 for pen6, h^3/6 for tet4 and pyr5); with a
+    linear field L(u_h) = 0 and each Gauss point holds tau_e f_e."""
+    n = 4
+    m = mg.hybrid_bands(n, seed=3, jitter=0.0)
+    h = 1.0 / n
+    vol = {HEX8: h ** 3, PEN6: h ** 3 / 2, TET4: h ** 3 / 6, PYR5: h ** 3 / 6}
+    X = np.stack([m.x, m.y, m.z], axis=1)
+    m.source[:, 0] = np.random.default_rng(8).uniform(0.5, 1.5, m.n_elems)
+    nq = {TET4: 1, PYR5: 8, PEN6: 6, HEX8: 8}
+    up = X @ np.array([0.3, -0.7, 1.1]) + 0.2
+    gp_ptr, got = oracle.subscale(m, up, model=oracle.POISSON)
+    assert np.array_equal(np.diff(gp_ptr), [nq[int(t)] for t in m.types])
+    for e in range(m.n_elems):
+        tau = vol[int(m.types[e])] ** (2 / 3) / 4
+        np.testing.assert_allclose(got[gp_ptr[e]:gp_ptr[e + 1], 0], tau * m.source[e, 0], rtol=1e-12)
