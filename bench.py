@@ -151,6 +151,77 @@ def traffic_from_profile(kernel_key, source):
     return float(v) if v else None
 
 
+SUB_NN = (4, 5, 6, 8)   # nodes per family (tet4, pyr5, pen6, hex8)
+SUB_NQ = (1, 8, 6, 8)   # Gauss points per family
+
+
+def subscale_flops_per_point(t, B):
+    """Algorithmic flops of the subgrid scale at one Gauss point of family t
+    (FMA = 2): per node J (9 FMA) and, unless the family is affine (tet4),
+    the mixed second derivatives of x (9) and grad / mixed second
+    derivatives of u (3B + 3B); then J^-1 with its determinant and w detJ
+    (43), the second-derivative transform and the operator (282 for
+    elasticity, 56 for Poisson; tet4: none), the volume sum (1) and tau r
+    (B)."""
+    per_node = 18 + (0 if t == 0 else 18 + 12 * B)
+    post = 0 if t == 0 else (282 if B == 3 else 56)
+    return SUB_NN[t] * per_node + 43 + post + 1 + B
+
+
+def subscale_work(mesh, B, np):
+    """(algorithmic bytes, algorithmic flops) of one subgrid-scale call:
+    per element its id (4 B), node ids (4 B each), material (young and nu,
+    16 B, elasticity only), source (8B), Gauss-point offset (8) and outputs
+    (8B per Gauss point); per node its coordinates and field (24 + 8B),
+    read once."""
+    cnt = np.bincount(mesh.types, minlength=4)
+    byts, flops = mesh.n_nodes * (24 + 8 * B), 0
+    for t in range(4):
+        per_elem = 4 + 4 * SUB_NN[t] + (16 if B == 3 else 0) + 8 * B + 8 + 8 * B * SUB_NQ[t]
+        byts += int(cnt[t]) * per_elem
+        flops += int(cnt[t]) * SUB_NQ[t] * subscale_flops_per_point(t, B)
+    return byts, flops
+
+
+def subscale_workload(fea, mg, torch, np, mesh, dm, g, reps=20):
+    """The element-wise subgrid scale of linear elasticity on the headline
+    mesh at a smooth displacement field: four family launches, nothing
+    assembled."""
+    u = torch.from_numpy(mg.smooth_field(mesh, 3, seed=11)).to(dm.x.device)
+    out, st = dm.subscale(g, u)
+    for _ in range(3):
+        dm.subscale(g, u, out=out, status=st)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dm.subscale(g, u, out=out, status=st)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    byts, flops = subscale_work(mesh, 3, np)
+    gbs = byts / (ms * 1e-3) / 1e9
+    tfs = flops / (ms * 1e-3) / 1e12
+    n_pts = int(out.shape[0])
+    alu = flops / (PEAK_FP64_TFLOPS * 1e12) >= byts / (PEAK_HBM_GBS * 1e9)
+    roof = ({"bound": "alu", "achieved": round(tfs, 2), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+             "frac": round(tfs / PEAK_FP64_TFLOPS, 4)} if alu else
+            {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "frac": round(gbs / PEAK_HBM_GBS, 4)})
+    roof.update({"kernel": "k_subscale<family, elasticity> (4 launches)",
+                 "traffic": traffic_from_profile("k_subscale,elastic", "subscale.hip"),
+                 "algorithmic_bytes": int(byts), "algorithmic_flops": int(flops),
+                 "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+                 "fp64_TFLOPs": round(tfs, 2), "fp64_frac": round(tfs / PEAK_FP64_TFLOPS, 4)})
+    res = {"workload": "hybrid96 elasticity, smooth displacement field, FP64", "ms": round(ms, 4),
+           "elements_per_s": round(mesh.n_elems / (ms * 1e-3), 1),
+           "gauss_points_per_s": round(n_pts / (ms * 1e-3), 1), "gauss_points": n_pts,
+           "roofline": roof, "status_ok": int(st.item()) == -1}
+    return res, u
+
+
 def _median_ms(fn, reps):
     import numpy as np
     vals = [fn() for _ in range(reps)]
@@ -618,6 +689,9 @@ def main():
                 "traffic": traffic_from_profile(kname, "segsum.h"),
                 "algorithmic_bytes": int(rb), "copy_GBps": copy_gbps, "frac_of_copy": round(ra / copy_gbps, 4)}
 
+    print("[bench] subgrid scale", file=sys.stderr, flush=True)
+    sub, sub_u = subscale_workload(fea, mg, torch, np, mesh, dm, g)
+
     extras = {}
     if not args.no_extras:
         del vals, rhs
@@ -645,6 +719,12 @@ def main():
                "kind": "oracle",
                "sample": f"the whole workload ({mesh.n_elems} elements), FP64 C oracle, sequential "
                          f"Algorithm 1 order, graph build excluded; {cpu_s:.1f} s"}
+        t0 = time.perf_counter()
+        oracle.subscale(mesh, sub_u.cpu().numpy(), model=oracle.ELASTIC)
+        sub_s = time.perf_counter() - t0
+        sub["cpu_baseline"] = {"value": round(mesh.n_elems / sub_s, 1), "unit": "elements/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the whole subgrid-scale workload, FP64 C oracle; {sub_s:.1f} s"}
 
     # scatter HBM rate of the two-phase (row-owner) form: its block-value
     # kernel (the right-hand-side reduction runs before it, inside the
@@ -694,6 +774,7 @@ def main():
                       "total": round(float(ph[2]), 4)},
         "graph_build_ms": round(graph_ms, 2),
         "variants": variants,
+        "subscale": sub,
         **extras,
         "cpu_baseline": cpu,
     }

@@ -194,6 +194,42 @@ int fea_last_timing(const fea_graph *g, float *ms);
 int fea_last_class_timing(const fea_graph *g, float *ms);
 
 /* ------------------------------------------------------------------ *
+ * Subgrid scale: an element loop with nothing assembled.              *
+ * ------------------------------------------------------------------ */
+
+/* Gauss-point layout of a graph's elements (the first call builds it on
+ * `stream` and blocks on it once): *n_points (may be NULL) = total Gauss
+ * points (tet4 1, pyr5 8, pen6 6, hex8 8 per element); gp_ptr (caller-owned
+ * DEVICE buffer of n_elems+1 int64, may be NULL) receives the offsets in
+ * element order, element e's points at gp_ptr[e] .. gp_ptr[e+1], enqueued on
+ * `stream`. Errors: FEA_EINVAL, FEA_ENOMEM, FEA_EHIP. */
+int fea_graph_gauss_points(const fea_graph *g, int64_t *n_points, int64_t *gp_ptr, hipStream_t stream);
+
+/*
+ * Subgrid scale (Section 2.1.2: the subscale is obtained element by element
+ * from the strong residual at the Gauss points and a diagonal stabilisation
+ * matrix, in a loop over the elements that forms no system). For the linear
+ * models, at every Gauss point q of every element e, in FP64:
+ *   out[(gp_ptr[e] + q)*b + c] = tau_e (f_e,c + L(u_h)_c(x_q)),
+ * L = Laplacian (FEA_POISSON, b = 1) or div sigma = mu Lap u +
+ * (lam + mu) grad div u (FEA_ELASTIC, b = 3, lam and mu from young and nu
+ * per element); u_h interpolates the nodal field u; tau_e = V_e^(2/3) / (4k)
+ * with V_e = sum_q w_q detJ_q and k = 1 (Poisson) or mu_e (elasticity).
+ * x, y, z: device FP64 node coordinates; u: device FP64 nodal field, b
+ * values per node (node-major); source: device FP64, b values per element;
+ * out: caller-owned device FP64 buffer of n_points*b values (gp_ptr and
+ * n_points from fea_graph_gauss_points), overwritten. mat->nh_flag must be
+ * NULL (FEA_EINVAL); mat->u and mat->residual are not used. status (device
+ * int32, may be NULL) receives the smallest element id with detJ <= 0 at a
+ * Gauss point (that element's outputs are then unspecified), or -1.
+ * Enqueued on `stream` (the first call on a graph builds the Gauss-point
+ * layout and blocks once). Errors: FEA_EINVAL, FEA_ENOMEM, FEA_EHIP.
+ */
+int fea_subscale(const fea_graph *g, const double *x, const double *y, const double *z,
+                 const fea_material *mat, const double *u, const double *source, hipStream_t stream,
+                 double *out, int32_t *status);
+
+/* ------------------------------------------------------------------ *
  * Batched assembly: many independent meshes in one persistent launch. *
  * ------------------------------------------------------------------ */
 

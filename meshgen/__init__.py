@@ -346,17 +346,37 @@ def heterogeneous(n=128, seed=4, nh_fraction=0.3, brick=8, grad_bound=0.1,
     ci = elem_cell % n
     bid = (ci // brick) + nb * ((cj // brick) + nb * (ck // brick))
     mesh.nh_flag = brick_nh[bid].astype(np.uint8)
+    mesh.u = _sine_field(mesh, rng, 3, grad_bound)
+    return mesh
+
+
+def _sine_field(mesh, rng, components, grad_bound):
+    """u(X) = A sum_{m<3} a_m sin(2 pi k_m . X + phi_m), k_m in {1,2}^3,
+    a_m ~ U[-1,1]^components, phi_m ~ U[0, 2 pi), A scaling the analytic
+    gradient bound to grad_bound; node-major, components values per node."""
     k = rng.integers(1, 3, size=(3, 3)).astype(np.float64)
-    a = rng.uniform(-1.0, 1.0, size=(3, 3))
+    a = rng.uniform(-1.0, 1.0, size=(3, components))
     phi = rng.uniform(0.0, 2.0 * np.pi, size=3)
     scale = sum(np.linalg.norm(a[m]) * 2 * np.pi * np.linalg.norm(k[m]) for m in range(3))
     A = grad_bound / scale
     X = np.stack([mesh.x, mesh.y, mesh.z], axis=1)
-    u = np.zeros_like(X)
+    u = np.zeros((mesh.n_nodes, components))
     for m in range(3):
         u += A * np.outer(np.sin(2 * np.pi * X @ k[m] + phi[m]), a[m])
-    mesh.u = u.reshape(-1).copy()
-    return mesh
+    return u.reshape(-1).copy()
+
+
+def smooth_field(mesh, components=3, seed=0, grad_bound=0.1, noise=0.0):
+    """A seeded nodal field for element loops that read one (the subgrid
+    scale): the smooth sine field above, plus, if noise > 0, independent
+    normal nodal values of that standard deviation times the mean cell size
+    (a field that is not smooth on the mesh scale)."""
+    rng = np.random.default_rng(seed)
+    u = _sine_field(mesh, rng, components, grad_bound)
+    if noise > 0:
+        h = 1.0 / max(getattr(mesh, "n_cells", 1), 1)
+        u = u + noise * h * rng.standard_normal(u.shape[0])
+    return u
 
 
 def tiny_mesh(cell_types_grid, jitter=0.0, seed=0, dofs=3):

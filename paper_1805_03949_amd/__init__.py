@@ -56,6 +56,8 @@ _lib.fea_graph_destroy.restype = None
 _lib.fea_assemble.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Material), _P,
                               ctypes.POINTER(Options), _P, _P, _P, _P]
 _lib.fea_last_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
+_lib.fea_graph_gauss_points.argtypes = [_P, ctypes.POINTER(_I64), _P, _P]
+_lib.fea_subscale.argtypes = [_P, _P, _P, _P, ctypes.POINTER(Material), _P, _P, _P, _P, _P]
 _lib.fea_last_class_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.fea_last_error.restype = ctypes.c_char_p
 _lib.fea_version.restype = ctypes.c_char_p
@@ -109,7 +111,7 @@ N_FEATURES, N_PARAMS = 12, 5057
 
 # every exported symbol declared in include/fea.h
 EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_sym_sizes", "fea_graph_export", "fea_graph_destroy",
-           "fea_assemble", "fea_last_timing", "fea_last_class_timing", "fea_last_error", "fea_version",
+           "fea_assemble", "fea_last_timing", "fea_graph_gauss_points", "fea_subscale", "fea_last_class_timing", "fea_last_error", "fea_version",
            "fea_batch_build", "fea_batch_sizes", "fea_batch_offsets", "fea_batch_items",
            "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_assemble", "fea_batch_capture",
            "fea_batch_replay", "fea_batch_cycles", "fea_batch_last_ms", "fea_batch_workers",
@@ -202,6 +204,14 @@ class Graph:
         _check(_lib.fea_graph_sym_sizes(self.handle, *[ctypes.byref(x) for x in v]))
         return dict(zip(("tiles", "entries", "tile_blocks", "upper_blocks"), (x.value for x in v)))
 
+    def gauss_points(self, stream=None):
+        """(n_points, gp_ptr): total Gauss points and the device offsets of
+        each element's points, in element order."""
+        n = _I64()
+        gp_ptr = torch.empty(self.n_elems + 1, dtype=torch.int64, device=self.device)
+        _check(_lib.fea_graph_gauss_points(self.handle, ctypes.byref(n), _ptr(gp_ptr), _stream(stream)))
+        return n.value, gp_ptr
+
     def last_timing(self):
         """(element ms, second-phase ms, total ms) of the last timed assemble."""
         ms = (ctypes.c_float * 3)()
@@ -260,6 +270,31 @@ def assemble(graph, x, y, z, types, conn_ptr, conn, source, model=ELASTIC, young
     return vals, rhs, status
 
 
+def subscale(graph, x, y, z, u, source, model=ELASTIC, young=None, nu=None, out=None, status=None,
+             stream=None):
+    """Element-wise subgrid scale tau_e (f_e + L(u_h)) at every Gauss point,
+    FP64, out[n_points, B] with element e's points at rows gp_ptr[e] ..
+    gp_ptr[e+1] (Graph.gauss_points). u: nodal field, B values per node."""
+    B = 1 if model == POISSON else 3
+    d = graph.device
+    if u.numel() != graph.n_nodes * B or source.numel() != graph.n_elems * B:
+        raise ValueError(f"u needs {B} values per node and source {B} per element")
+    n_pts, _ = graph.gauss_points(stream) if out is None else (None, None)
+    if out is None:
+        out = torch.empty((n_pts, B), dtype=torch.float64, device=d)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=d)
+    for t in (x, y, z, u, source, out):
+        _dev(t, torch.float64)
+    for t in (young, nu):
+        if t is not None:
+            _dev(t, torch.float64)
+    mat = Material(model, _ptr(young), _ptr(nu), None, None, 0)
+    _check(_lib.fea_subscale(graph.handle, _ptr(x), _ptr(y), _ptr(z), ctypes.byref(mat), _ptr(u), _ptr(source),
+                             _stream(stream), _ptr(out), _ptr(status)))
+    return out, status
+
+
 class DeviceMesh:
     """Device copies of a mesh's arrays (connectivity, coordinates, material)."""
 
@@ -287,6 +322,16 @@ class DeviceMesh:
                         nh_flag=self.nh_flag if (use_nh and model == ELASTIC) else None,
                         u=self.u if ((use_nh or residual) and model == ELASTIC) else None,
                         residual=residual, **kw)
+
+
+    def subscale(self, graph, u, model=ELASTIC, **kw):
+        """Subgrid scale of every element for the nodal field u (B values per
+        node, a device FP64 tensor)."""
+        src = self.source
+        if model == POISSON:
+            src = src[:, :1].contiguous()
+        return subscale(graph, self.x, self.y, self.z, u, src, model=model, young=self.young,
+                        nu=self.nu if model == ELASTIC else None, **kw)
 
 
 def _np_i32(a):

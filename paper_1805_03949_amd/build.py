@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfea.so")
-SOURCES = ["common.hip", "graph.hip", "assemble.hip", "gather.hip", "batch.hip", "cost.hip"]
+SOURCES = ["common.hip", "graph.hip", "assemble.hip", "gather.hip", "batch.hip", "cost.hip", "subscale.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -93,36 +93,43 @@ static void shape_host(int t, const double p[3], double N[8], double dN[8][3])
     }
 }
 
+// Gauss rule of family t (points as above); returns the number of points.
+static int rule_host(int t, double pts[8][3], double w[8])
+{
+    const double g = 0.57735026918962576451;  // 1/sqrt(3)
+    int nq = 0;
+    if (t == 0) {
+        pts[0][0] = pts[0][1] = pts[0][2] = 0.25;
+        w[0] = 1.0 / 6.0;
+        nq = 1;
+    } else if (t == 2) {
+        const double tr[3][2] = {{1.0 / 6, 1.0 / 6}, {2.0 / 3, 1.0 / 6}, {1.0 / 6, 2.0 / 3}};
+        for (int k = 0; k < 2; ++k)
+            for (int i = 0; i < 3; ++i, ++nq) {
+                pts[nq][0] = tr[i][0];
+                pts[nq][1] = tr[i][1];
+                pts[nq][2] = k ? g : -g;
+                w[nq] = 1.0 / 6.0;
+            }
+    } else {
+        for (int k = 0; k < 2; ++k)
+            for (int j = 0; j < 2; ++j)
+                for (int i = 0; i < 2; ++i, ++nq) {
+                    pts[nq][0] = i ? g : -g;
+                    pts[nq][1] = j ? g : -g;
+                    pts[nq][2] = k ? g : -g;
+                    w[nq] = 1.0;
+                }
+    }
+    return nq;
+}
+
 static void build_tables(RefTables *R)
 {
     memset(R, 0, sizeof(*R));
-    const double g = 0.57735026918962576451;  // 1/sqrt(3)
     for (int t = 0; t < 4; ++t) {
         double pts[8][3], w[8];
-        int nq = 0;
-        if (t == 0) {
-            pts[0][0] = pts[0][1] = pts[0][2] = 0.25;
-            w[0] = 1.0 / 6.0;
-            nq = 1;
-        } else if (t == 2) {
-            const double tr[3][2] = {{1.0 / 6, 1.0 / 6}, {2.0 / 3, 1.0 / 6}, {1.0 / 6, 2.0 / 3}};
-            for (int k = 0; k < 2; ++k)
-                for (int i = 0; i < 3; ++i, ++nq) {
-                    pts[nq][0] = tr[i][0];
-                    pts[nq][1] = tr[i][1];
-                    pts[nq][2] = k ? g : -g;
-                    w[nq] = 1.0 / 6.0;
-                }
-        } else {
-            for (int k = 0; k < 2; ++k)
-                for (int j = 0; j < 2; ++j)
-                    for (int i = 0; i < 2; ++i, ++nq) {
-                        pts[nq][0] = i ? g : -g;
-                        pts[nq][1] = j ? g : -g;
-                        pts[nq][2] = k ? g : -g;
-                        w[nq] = 1.0;
-                    }
-        }
+        const int nq = rule_host(t, pts, w);
         for (int q = 0; q < nq; ++q) {
             double N[8] = {0}, dN[8][3] = {{0}};
             shape_host(t, pts[q], N, dN);

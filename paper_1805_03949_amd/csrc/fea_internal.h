@@ -147,6 +147,11 @@ struct fea_graph {
     int tc_colours = 0;
     bool tcready = false;
     bool sready = false;
+    // Gauss-point offsets in element order (built by the first subgrid-scale
+    // call or query): element e's points are gp_ptr[e] .. gp_ptr[e+1]
+    int64_t *gp_ptr = nullptr;
+    int64_t n_gp = 0;
+    bool gpready = false;
     // lazily allocated workspaces of the scatter variants
     void *contrib = nullptr;
     size_t contrib_bytes = 0;

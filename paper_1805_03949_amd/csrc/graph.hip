@@ -644,7 +644,7 @@ static void destroy(fea_graph *g)
     void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv, g->pnodes, g->pdest, g->prdest,
                     g->n2e_ptr, g->n2e, g->n2a, g->perm, g->colour, g->cperm,
                     g->contrib, g->rcontrib, g->acc64, g->gtile, g->gnodes, g->gdesc, g->upart, g->ublk, g->lpart, g->tent_ptr, g->ttb_ptr,
-                    g->tent, g->tb_eend, g->tb_blk, g->tb_slot, g->ts_ptr, g->ctile};
+                    g->tent, g->tb_eend, g->tb_blk, g->tb_slot, g->ts_ptr, g->ctile, g->gp_ptr};
     for (void *b : bufs) dfree(b);
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);

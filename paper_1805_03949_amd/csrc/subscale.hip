@@ -1,0 +1,421 @@
+// Element-wise subgrid scale (Section 2.1.2): the subscale comes from an
+// equation posed element by element -- the strong residual at the Gauss
+// points times a diagonal stabilisation matrix -- evaluated in a plain loop
+// over the elements with no system formed and nothing scattered. Read for
+// the problems this library assembles:
+//   utilde_q = tau_e (f_e + L(u_h)(x_q)),   tau_e = V_e^(2/3) / (4 k),
+// L the Laplacian (Poisson, -Lap u = f, k = 1) or div sigma(u) =
+// mu Lap u + (lam + mu) grad div u (linear elasticity, k = mu_e), u_h the
+// interpolated nodal field, V_e = sum_q w_q detJ_q.
+//
+// Physical second derivatives: differentiating u(x(xi)) twice gives
+//   H_xi(u) = J^T H_x(u) J + sum_k (du/dx_k) H_xi(x_k),
+// so H_x(u) = J^-T M J^-1 with M = H_xi(u) - sum_k (du/dx_k) H_xi(x_k).
+// Every shape function here is linear in each reference coordinate taken
+// alone (tet4 linear, hex8 and the collapsed-hexahedron pyramid
+// multilinear, pen6 linear in (r, s) times linear in t), so the pure
+// second reference derivatives vanish and M has only its three mixed
+// entries (xi eta, xi zeta, eta zeta). For tet4 all of them vanish:
+// L(u_h) = 0 identically and u is not read.
+//
+// Work layout: one launch per element family over its type-sorted
+// elements; one lane per (element, Gauss point), NQ consecutive lanes per
+// element, 256 / NQ elements per workgroup. The element's first NN lanes
+// each gather one node's coordinates and field values into LDS (one
+// dependent load chain per lane instead of one per node: gathers walked
+// node by node left the kernel waiting on memory latency); every lane then
+// accumulates J, grad_xi u and the mixed reference second derivatives of
+// x and u in registers from LDS, with the reference tables of its Gauss
+// point in LDS too. (tet4, one lane per element and no second
+// derivatives, reads its four nodes directly.) The element volume is
+// summed over the element's Gauss points in ascending order through LDS,
+// and each lane writes its B values at the element's Gauss-point offset.
+#include <climits>
+#include <mutex>
+
+#include "elem.h"
+
+namespace fea {
+
+// Mixed second reference derivatives d2 N_a / dxi_j dxi_l for the pairs
+// (j, l) = (0, 1), (0, 2), (1, 2), per family, Gauss point and node.
+struct SubTables {
+    double d2[4][8][8][3];
+};
+static __constant__ SubTables c_sub;
+
+// Same shape functions as shape_host, differentiated twice (hexahedron
+// factors f = (1 + s xi) / 2 per direction; the pyramid's apex is the sum
+// of the collapsed top nodes).
+static void shape2_host(int t, const double p[3], double d2[8][3])
+{
+    static const int sg[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                 {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+    for (int a = 0; a < 8; ++a)
+        for (int m = 0; m < 3; ++m) d2[a][m] = 0.0;
+    if (t == 3 || t == 1) {
+        double h[8][3];
+        for (int a = 0; a < 8; ++a) {
+            const double fx = 0.5 * (1 + sg[a][0] * p[0]), fy = 0.5 * (1 + sg[a][1] * p[1]),
+                         fz = 0.5 * (1 + sg[a][2] * p[2]);
+            h[a][0] = 0.25 * sg[a][0] * sg[a][1] * fz;
+            h[a][1] = 0.25 * sg[a][0] * sg[a][2] * fy;
+            h[a][2] = 0.25 * sg[a][1] * sg[a][2] * fx;
+        }
+        const int nb = t == 3 ? 8 : 4;
+        for (int a = 0; a < nb; ++a)
+            for (int m = 0; m < 3; ++m) d2[a][m] = h[a][m];
+        if (t == 1)
+            for (int m = 0; m < 3; ++m) d2[4][m] = h[4][m] + h[5][m] + h[6][m] + h[7][m];
+    } else if (t == 2) {
+        const double dL[3][2] = {{-1, -1}, {1, 0}, {0, 1}};
+        for (int a = 0; a < 6; ++a) {
+            const int k = a % 3;
+            const double s = a < 3 ? -1.0 : 1.0;
+            d2[a][1] = 0.5 * s * dL[k][0];
+            d2[a][2] = 0.5 * s * dL[k][1];
+        }
+    }
+}
+
+static int ensure_sub_tables()
+{
+    static std::mutex mtx;
+    static bool done[64] = {false};
+    int dev = 0;
+    FEA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(FEA_EINVAL, "device index %d unsupported", dev);
+    std::lock_guard<std::mutex> lock(mtx);
+    if (done[dev]) return FEA_OK;
+    SubTables S;
+    memset(&S, 0, sizeof(S));
+    for (int t = 0; t < 4; ++t) {
+        double pts[8][3], w[8];
+        const int nq = rule_host(t, pts, w);
+        for (int q = 0; q < nq; ++q) {
+            double d2[8][3];
+            shape2_host(t, pts[q], d2);
+            for (int a = 0; a < 8; ++a)
+                for (int m = 0; m < 3; ++m) S.d2[t][q][a][m] = d2[a][m];
+        }
+    }
+    FEA_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_sub), &S, sizeof(S), 0, hipMemcpyHostToDevice));
+    done[dev] = true;
+    return FEA_OK;
+}
+
+struct SubArgs {
+    const double *x, *y, *z;
+    const double *u;       // B values per node, node-major
+    const double *young;   // per element, NULL = 1
+    const double *nu;      // per element (elasticity)
+    const double *source;  // B values per element
+    const int32_t *perm;   // this family's element ids (type-sorted order)
+    const int32_t *pnodes; // their node ids, NN per element
+    const int64_t *gp_ptr; // Gauss-point offsets in element order
+    int64_t n;             // elements in this launch
+    double *out;           // out[(gp_ptr[e] + q) * B + c]
+    int32_t *status;       // smallest element id with detJ <= 0
+};
+
+template <int T, int MODEL>
+__global__ void __launch_bounds__(256) k_subscale(SubArgs A)
+{
+    constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, EPW = 256 / NQ;
+    constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
+    __shared__ double sDN[NQ][NN][3];
+    __shared__ double sD2[NQ][NN][3];
+    __shared__ double sWq[NQ];
+    __shared__ double sWd[256];
+    // node coordinates and field values of the workgroup's elements
+    constexpr int NV = 3 + B;
+    __shared__ double sNode[T == 0 ? 1 : EPW][NN][NV];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < NQ * NN * 3; i += 256) {
+        const int q = i / (NN * 3), a = (i / 3) % NN, j = i % 3;
+        sDN[q][a][j] = c_ref.dN[T][q][a][j];
+        sD2[q][a][j] = c_sub.d2[T][q][a][j];
+    }
+    if (tid < NQ) sWq[tid] = c_ref.w[T][tid];
+    __syncthreads();
+
+    const int el = tid / NQ, q = tid - el * NQ;
+    const int64_t p = (int64_t)blockIdx.x * EPW + el;
+    const bool act = el < EPW && p < A.n;
+    const int32_t e = act ? A.perm[p] : 0;
+    double wd = 0.0, kmat = 1.0;  // w_q detJ; tau's material constant k
+    double r[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) r[c] = 0.0;
+    if constexpr (T != 0) {
+        if (act && q < NN) {
+            const int32_t v = A.pnodes[p * NN + q];
+            sNode[el][q][0] = A.x[v];
+            sNode[el][q][1] = A.y[v];
+            sNode[el][q][2] = A.z[v];
+#pragma unroll
+            for (int c = 0; c < B; ++c) sNode[el][q][3 + c] = A.u[(int64_t)v * B + c];
+        }
+        __syncthreads();  // every lane, active or not
+    }
+    if (act) {
+        const int32_t *pn = A.pnodes + p * NN;
+        double J[3][3] = {}, Dx[3][3] = {}, Gu[B][3] = {}, Du[B][3] = {};
+        // a rolled node loop (one LDS read set per node): unrolled, the
+        // compiler hoists every node's values into registers (up to 256
+        // VGPRs, two waves per SIMD), and the kernel ran 25% slower
+#pragma unroll 1
+        for (int a = 0; a < NN; ++a) {
+            double X[3], U[B];
+            if constexpr (T == 0) {
+                const int32_t v = pn[a];
+                X[0] = A.x[v];
+                X[1] = A.y[v];
+                X[2] = A.z[v];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) X[i] = sNode[el][a][i];
+#pragma unroll
+                for (int c = 0; c < B; ++c) U[c] = sNode[el][a][3 + c];
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double dn = sDN[q][a][j];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) J[i][j] += X[i] * dn;
+                if constexpr (T != 0) {
+                    const double d2 = sD2[q][a][j];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) Dx[i][j] += X[i] * d2;
+#pragma unroll
+                    for (int c = 0; c < B; ++c) {
+                        Gu[c][j] += U[c] * dn;
+                        Du[c][j] += U[c] * d2;
+                    }
+                }
+            }
+        }
+        // J^-1 by the adjugate
+        double Ji[3][3];
+        Ji[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        Ji[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        Ji[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        Ji[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        Ji[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        Ji[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        Ji[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        Ji[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        Ji[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double det = J[0][0] * Ji[0][0] + J[0][1] * Ji[1][0] + J[0][2] * Ji[2][0];
+        if (!(det > 0.0)) atomicMin(A.status, e);
+        const double id = 1.0 / det;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Ji[i][j] *= id;
+        wd = sWq[q] * det;
+
+        double lam = 0.0, mu = 1.0;
+        if constexpr (MODEL != FEA_POISSON) {
+            const double E = A.young ? A.young[e] : 1.0, nu = A.nu[e];
+            lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+            mu = E / (2.0 * (1.0 + nu));
+            kmat = mu;
+        }
+#pragma unroll
+        for (int c = 0; c < B; ++c) r[c] = A.source[(int64_t)e * B + c];
+        if constexpr (T != 0) {
+            constexpr int PJ[3] = {0, 0, 1}, PL[3] = {1, 2, 2};  // mixed pairs (j, l)
+            // M^c on the mixed pairs: H_xi(u_c) - sum_k du_c/dx_k H_xi(x_k)
+            double M[B][3];
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                double g[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) g[k] = Gu[c][0] * Ji[0][k] + Gu[c][1] * Ji[1][k] + Gu[c][2] * Ji[2][k];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) M[c][m] = Du[c][m] - (g[0] * Dx[0][m] + g[1] * Dx[1][m] + g[2] * Dx[2][m]);
+            }
+            // Lap u_c = tr(J^-T M^c J^-1) = 2 sum_m M^c_m (J^-1 J^-T)_(j_m, l_m)
+            double S[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                S[m] = Ji[PJ[m]][0] * Ji[PL[m]][0] + Ji[PJ[m]][1] * Ji[PL[m]][1] + Ji[PJ[m]][2] * Ji[PL[m]][2];
+            if constexpr (MODEL == FEA_POISSON) {
+                r[0] += 2.0 * (M[0][0] * S[0] + M[0][1] * S[1] + M[0][2] * S[2]);
+            } else {
+                // (grad div u)_i = sum_k (H_x u_k)_ik = sum_j Ji[j][i] W_j with
+                // W_j = sum_k sum_l M^k_jl Ji[l][k] (M^k symmetric, zero diagonal)
+                double W[3];
+                W[0] = W[1] = W[2] = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    W[0] += M[k][0] * Ji[1][k] + M[k][1] * Ji[2][k];
+                    W[1] += M[k][0] * Ji[0][k] + M[k][2] * Ji[2][k];
+                    W[2] += M[k][1] * Ji[0][k] + M[k][2] * Ji[1][k];
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const double lap = 2.0 * (M[i][0] * S[0] + M[i][1] * S[1] + M[i][2] * S[2]);
+                    const double gdiv = Ji[0][i] * W[0] + Ji[1][i] * W[1] + Ji[2][i] * W[2];
+                    r[i] += mu * lap + (lam + mu) * gdiv;
+                }
+            }
+        }
+    }
+    // every lane reaches the barrier, active or not
+    sWd[tid] = wd;
+    __syncthreads();
+    if (!act) return;
+    double V = 0.0;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) V += sWd[el * NQ + k];
+    const double h = cbrt(V);
+    const double tau = h * h / (4.0 * kmat);
+    double *o = A.out + (A.gp_ptr[e] + q) * B;
+#pragma unroll
+    for (int c = 0; c < B; ++c) o[c] = tau * r[c];
+}
+
+__global__ void k_sub_status_init(int32_t *s) { *s = INT_MAX; }
+__global__ void k_sub_status_final(int32_t *s)
+{
+    if (*s == INT_MAX) *s = -1;
+}
+
+// Gauss points per element, in element order, from the type segmentation.
+template <int T>
+__global__ void k_gp_counts(const int32_t *perm, int64_t n, uint8_t *cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) cnt[perm[i]] = (uint8_t)Fam<T>::NQ;
+}
+
+struct SubTmp {
+    void *p = nullptr;
+    ~SubTmp() { dfree(p); }
+};
+
+static int gauss_points_prepare(fea_graph *g, hipStream_t s)
+{
+    if (g->gpready) return FEA_OK;
+    int rc;
+    const int64_t E = g->n_elems;
+    if (!g->gp_ptr && (rc = dalloc((void **)&g->gp_ptr, sizeof(int64_t) * (E + 1)))) return rc;
+    int64_t n_gp = 0;
+    for (int t = 0; t < 4; ++t) {
+        const int nq = t == 0 ? 1 : (t == 2 ? 6 : 8);
+        n_gp += (g->seg[t + 1] - g->seg[t]) * nq;
+    }
+    if (E > 0) {
+        SubTmp cnt, tmp;
+        if ((rc = dalloc(&cnt.p, (size_t)E))) return rc;
+        if ((rc = dalloc(&tmp.p, sizeof(int64_t) * (scan_tmp_elems(E) + 64)))) return rc;
+        uint8_t *c = (uint8_t *)cnt.p;
+        const int64_t n0 = g->seg[1] - g->seg[0], n1 = g->seg[2] - g->seg[1], n2 = g->seg[3] - g->seg[2],
+                      n3 = g->seg[4] - g->seg[3];
+        if (n0) k_gp_counts<0><<<grid_for(n0, 256), 256, 0, s>>>(g->perm + g->seg[0], n0, c);
+        if (n1) k_gp_counts<1><<<grid_for(n1, 256), 256, 0, s>>>(g->perm + g->seg[1], n1, c);
+        if (n2) k_gp_counts<2><<<grid_for(n2, 256), 256, 0, s>>>(g->perm + g->seg[2], n2, c);
+        if (n3) k_gp_counts<3><<<grid_for(n3, 256), 256, 0, s>>>(g->perm + g->seg[3], n3, c);
+        if ((rc = scan_to_ptr_u8(c, E, g->gp_ptr, (int64_t *)tmp.p, s))) return rc;
+        FEA_HIP(hipGetLastError());
+        // the temporaries are freed on return: wait for their readers
+        FEA_HIP(hipStreamSynchronize(s));
+    } else {
+        FEA_HIP(hipMemsetAsync(g->gp_ptr, 0, sizeof(int64_t), s));
+        FEA_HIP(hipStreamSynchronize(s));
+    }
+    g->n_gp = n_gp;
+    g->gpready = true;
+    return FEA_OK;
+}
+
+template <int T, int MODEL>
+static void launch_sub(const fea_graph *g, SubArgs a, hipStream_t s)
+{
+    constexpr int EPW = 256 / Fam<T>::NQ;
+    a.n = g->seg[T + 1] - g->seg[T];
+    if (a.n == 0) return;
+    a.perm = g->perm + g->seg[T];
+    a.pnodes = g->pnodes + g->node_base[T];
+    k_subscale<T, MODEL><<<grid_for(a.n, EPW), 256, 0, s>>>(a);
+}
+
+template <int MODEL>
+static void run_sub(const fea_graph *g, const SubArgs &a, hipStream_t s)
+{
+    // the costliest family first, so the cheap launches fill the tail
+    launch_sub<1, MODEL>(g, a, s);
+    launch_sub<3, MODEL>(g, a, s);
+    launch_sub<2, MODEL>(g, a, s);
+    launch_sub<0, MODEL>(g, a, s);
+}
+
+}  // namespace fea
+
+using namespace fea;
+
+extern "C" int fea_graph_gauss_points(const fea_graph *gc, int64_t *n_points, int64_t *gp_ptr, hipStream_t stream)
+{
+    clear_error();
+    fea_graph *g = const_cast<fea_graph *>(gc);
+    if (!g) return set_error(FEA_EINVAL, "graph is required");
+    int dev = 0;
+    FEA_HIP(hipGetDevice(&dev));
+    if (dev != g->device) return set_error(FEA_EINVAL, "graph lives on device %d, current is %d", g->device, dev);
+    int rc = gauss_points_prepare(g, stream);
+    if (rc) return rc;
+    if (n_points) *n_points = g->n_gp;
+    if (gp_ptr)
+        FEA_HIP(hipMemcpyAsync(gp_ptr, g->gp_ptr, sizeof(int64_t) * (g->n_elems + 1), hipMemcpyDeviceToDevice,
+                               stream));
+    return FEA_OK;
+}
+
+extern "C" int fea_subscale(const fea_graph *gc, const double *x, const double *y, const double *z,
+                            const fea_material *mat, const double *u, const double *source,
+                            hipStream_t stream, double *out, int32_t *status)
+{
+    clear_error();
+    fea_graph *g = const_cast<fea_graph *>(gc);
+    if (!g || !mat) return set_error(FEA_EINVAL, "graph and material are required");
+    if (mat->model != FEA_POISSON && mat->model != FEA_ELASTIC)
+        return set_error(FEA_EINVAL, "unknown model %d", mat->model);
+    if (mat->nh_flag) return set_error(FEA_EINVAL, "the subgrid scale is defined for the linear models only");
+    if (g->n_elems > 0) {
+        if (!x || !y || !z || !u || !source || !out) return set_error(FEA_EINVAL, "NULL array argument");
+        if (mat->model == FEA_ELASTIC && !mat->nu) return set_error(FEA_EINVAL, "nu is required");
+    }
+    int dev = 0;
+    FEA_HIP(hipGetDevice(&dev));
+    if (dev != g->device) return set_error(FEA_EINVAL, "graph lives on device %d, current is %d", g->device, dev);
+    int rc;
+    if ((rc = ensure_tables()) || (rc = ensure_sub_tables()) || (rc = gauss_points_prepare(g, stream))) return rc;
+
+    int32_t *st = status;
+    if (!st) {
+        static thread_local int32_t *own[64] = {nullptr};
+        if (!own[dev] && (rc = dalloc((void **)&own[dev], sizeof(int32_t)))) return rc;
+        st = own[dev];
+    }
+    k_sub_status_init<<<1, 1, 0, stream>>>(st);
+    if (g->n_elems > 0) {
+        SubArgs a = {};
+        a.x = x; a.y = y; a.z = z;
+        a.u = u;
+        a.young = mat->young;
+        a.nu = mat->nu;
+        a.source = source;
+        a.gp_ptr = g->gp_ptr;
+        a.out = out;
+        a.status = st;
+        if (mat->model == FEA_POISSON)
+            run_sub<FEA_POISSON>(g, a, stream);
+        else
+            run_sub<FEA_ELASTIC>(g, a, stream);
+    }
+    k_sub_status_final<<<1, 1, 0, stream>>>(st);
+    FEA_HIP(hipGetLastError());
+    return FEA_OK;
+}
