@@ -524,6 +524,16 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
             out[f"{vname}_{pname}"] = {"total_ms": round(float(np.median(tot)), 4),
                                        "status_ok": int(gs.item()) == -1}
             del gv, gr, gs
+    # one Newton step's assembly: the tangent A and the residual
+    # b = f_ext - f_int(u) together (upper-triangle form, FP64)
+    gv, gr, gs = dm.assemble(g, variant=fea.ROWSYM, use_nh=True, residual=True)
+    tot = []
+    for _ in range(5):
+        dm.assemble(g, variant=fea.ROWSYM, use_nh=True, residual=True, vals=gv, rhs=gr, status=gs, timing=True)
+        tot.append(g.last_timing()[2])
+    out["rowsym_fp64_newton_residual"] = {"total_ms": round(float(np.median(tot)), 4),
+                                          "status_ok": int(gs.item()) == -1}
+    del gv, gr, gs
     g.destroy()
     return out
 

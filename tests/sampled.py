@@ -20,8 +20,12 @@ def incident_elements(mesh, nodes):
     return {n: sorted(v) for n, v in out.items()}
 
 
-def oracle_rows(mesh, nodes, model=oracle.ELASTIC, use_nh=True):
-    """{node: (cols, blocks[ncol, B, B], terms[ncol, B, B], rhs[B], rhs_terms[B])}."""
+def oracle_rows(mesh, nodes, model=oracle.ELASTIC, use_nh=True, residual=False):
+    """{node: (cols, blocks[ncol, B, B], terms[ncol, B, B], rhs[B], rhs_terms[B])}.
+    residual: rhs is the Newton residual f_ext - f_int(mesh.u) (elasticity):
+    f_int the neo-Hookean internal force where flagged, K^e u^e elsewhere;
+    rhs_terms then holds the larger of |f_ext| and |f_int| per component
+    (the scale of a residual whose two parts partly cancel)."""
     B = 1 if model == oracle.POISSON else 3
     X = np.stack([mesh.x, mesh.y, mesh.z], axis=1)
     U = mesh.u.reshape(-1, 3)
@@ -44,8 +48,20 @@ def oracle_rows(mesh, nodes, model=oracle.ELASTIC, use_nh=True):
                 tb = T[a * B:(a + 1) * B, b * B:(b + 1) * B]
                 acc[int(j)] = acc.get(int(j), 0.0) + blk
                 tacc[int(j)] = tacc.get(int(j), 0.0) + tb
-            rhs += fe[a * B:(a + 1) * B]
-            trhs += Tf[a * B:(a + 1) * B]
+            if residual:
+                if nh:
+                    fint = oracle.element_fint(int(mesh.types[e]), X[nodes_e], float(mesh.young[e]),
+                                               float(mesh.nu[e]), U[nodes_e])
+                else:
+                    Kl, _ = oracle.element(int(mesh.types[e]), X[nodes_e], model=model,
+                                           young=float(mesh.young[e]), nu=float(mesh.nu[e]), f=mesh.source[e, :B])
+                    fint = Kl @ U[nodes_e].reshape(-1)
+                fa, ia = fe[a * B:(a + 1) * B], fint[a * B:(a + 1) * B]
+                rhs += fa - ia
+                trhs += np.maximum(np.abs(fa), np.abs(ia))
+            else:
+                rhs += fe[a * B:(a + 1) * B]
+                trhs += Tf[a * B:(a + 1) * B]
         cols = np.array(sorted(acc))
         out[i] = (cols, np.array([acc[c] for c in cols]), np.array([tacc[c] for c in cols]), rhs, trhs)
     return out

@@ -175,3 +175,35 @@ def test_hybrid96_subscale_sampled_elements():
         scale = (lam + 2 * mu) / (4 * mu) * np.abs(U[nodes]).max()
         worst = max(worst, float((np.abs(got - ref) / (1e-11 * (np.abs(ref) + scale))).max()))
     assert worst <= 1.0, worst
+
+
+def test_hetero128_newton_residual_sampled_rows():
+    """One Newton step's assembly at the hetero128 size in the configuration
+    the bench times (upper-triangle form, FP64, neo-Hookean bricks): the
+    matrix rows are the tangent's and the right-hand side is the residual
+    f_ext - f_int(u), checked on sampled rows inside and outside the
+    neo-Hookean bricks that the oracle computes element by element (scaled
+    by the larger of |f_ext| and |f_int|, which partly cancel)."""
+    mesh = mg.heterogeneous(128, seed=4)
+    print(f"[case] hetero128 residual: {mesh.n_elems} elements", flush=True)
+    dm = fea.DeviceMesh(mesh)
+    g = dm.graph()
+    ex = g.export()
+    row_ptr, col = ex["row_ptr"].cpu().numpy(), ex["col"].cpu().numpy()
+    rng = np.random.default_rng(9)
+    nodes = set(rng.choice(mesh.n_nodes, 120, replace=False).tolist())
+    nodes.update(mesh.conn[mesh.conn_ptr[np.nonzero(mesh.nh_flag)[0][:40]]].tolist())
+    rows = oracle_rows(mesh, sorted(nodes), residual=True)
+    v, r, st = dm.assemble(g, variant=fea.ROWSYM, use_nh=True, residual=True)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -1
+    worst_a, worst_b = 0.0, 0.0
+    for i, (cols, blocks, _, r_ref, r_scale) in rows.items():
+        k0, k1 = int(row_ptr[i]), int(row_ptr[i + 1])
+        assert np.array_equal(col[k0:k1], cols), i
+        got = v[k0 * 9:k1 * 9].cpu().numpy().reshape(-1, 3, 3)
+        scale = np.abs(blocks).max(axis=(0, 2))[None, :, None]
+        worst_a = max(worst_a, float(np.max(np.abs(got - blocks) / scale)))
+        rg = r[3 * i:3 * i + 3].cpu().numpy()
+        worst_b = max(worst_b, float(np.max(np.abs(rg - r_ref)) / r_scale.max()))
+    assert worst_a <= 1e-12 and worst_b <= 1e-12, (worst_a, worst_b)
