@@ -647,12 +647,16 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                     // Linear: sigma = lam tr(H) I + mu (H + H^T), H = sum_b u_b (x) grad N_b.
                     const bool nh = sNH[el] != 0;
                     const double lam = sLM[el][0], mu = sLM[el][1];
+#pragma unroll 1
                     for (int q = 0; q < NQ; ++q) {
                         const double ga[3] = {sG[el].v[q][a][0], sG[el].v[q][a][1], sG[el].v[q][a][2]};
                         double uh[3] = {0.0, 0.0, 0.0};  // sum_b u_b (G_b . G_a)
                         double hu[3] = {0.0, 0.0, 0.0};  // sum_b (u_b . G_a) G_b
                         double trh = 0.0;                // sum_b u_b . G_b
-#pragma unroll
+                        // both loops rolled: unrolled, every node's gradient
+                        // and displacement is hoisted into registers for the
+                        // whole kernel (residual instances at 133-188 VGPRs)
+#pragma unroll 1
                         for (int b = 0; b < NN; ++b) {
                             const double gb[3] = {sG[el].v[q][b][0], sG[el].v[q][b][1], sG[el].v[q][b][2]};
                             const double ub[3] = {sU[el][b][0], sU[el][b][1], sU[el][b][2]};
