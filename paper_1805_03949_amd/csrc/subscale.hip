@@ -123,18 +123,24 @@ __global__ void __launch_bounds__(256) k_subscale(SubArgs A)
 {
     constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, EPW = 256 / NQ;
     constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
-    __shared__ double sDN[NQ][NN][3];
-    __shared__ double sD2[NQ][NN][3];
+    // LDS strides padded to 2 (mod 4) doubles: the 8 Gauss points or
+    // elements that a wave reads at once then start in distinct 16-byte
+    // bank slots (hex8's 48-double element records aliased every second
+    // element)
+    constexpr int SQ = NN * 3 + ((2 - (NN * 3) % 4) + 4) % 4;  // per Gauss point of a table
+    __shared__ double sDN[NQ * SQ];
+    __shared__ double sD2[NQ * SQ];
     __shared__ double sWq[NQ];
     __shared__ double sWd[256];
     // node coordinates and field values of the workgroup's elements
     constexpr int NV = 3 + B;
-    __shared__ double sNode[T == 0 ? 1 : EPW][NN][NV];
+    constexpr int SE = NN * NV + ((2 - (NN * NV) % 4) + 4) % 4;  // per element
+    __shared__ double sNode[(T == 0 ? 1 : EPW) * SE];
     const int tid = threadIdx.x;
     for (int i = tid; i < NQ * NN * 3; i += 256) {
         const int q = i / (NN * 3), a = (i / 3) % NN, j = i % 3;
-        sDN[q][a][j] = c_ref.dN[T][q][a][j];
-        sD2[q][a][j] = c_sub.d2[T][q][a][j];
+        sDN[q * SQ + a * 3 + j] = c_ref.dN[T][q][a][j];
+        sD2[q * SQ + a * 3 + j] = c_sub.d2[T][q][a][j];
     }
     if (tid < NQ) sWq[tid] = c_ref.w[T][tid];
     __syncthreads();
@@ -150,11 +156,12 @@ __global__ void __launch_bounds__(256) k_subscale(SubArgs A)
     if constexpr (T != 0) {
         if (act && q < NN) {
             const int32_t v = A.pnodes[p * NN + q];
-            sNode[el][q][0] = A.x[v];
-            sNode[el][q][1] = A.y[v];
-            sNode[el][q][2] = A.z[v];
+            double *rec = sNode + el * SE + q * NV;
+            rec[0] = A.x[v];
+            rec[1] = A.y[v];
+            rec[2] = A.z[v];
 #pragma unroll
-            for (int c = 0; c < B; ++c) sNode[el][q][3 + c] = A.u[(int64_t)v * B + c];
+            for (int c = 0; c < B; ++c) rec[3 + c] = A.u[(int64_t)v * B + c];
         }
         __syncthreads();  // every lane, active or not
     }
@@ -174,17 +181,17 @@ __global__ void __launch_bounds__(256) k_subscale(SubArgs A)
                 X[2] = A.z[v];
             } else {
 #pragma unroll
-                for (int i = 0; i < 3; ++i) X[i] = sNode[el][a][i];
+                for (int i = 0; i < 3; ++i) X[i] = sNode[el * SE + a * NV + i];
 #pragma unroll
-                for (int c = 0; c < B; ++c) U[c] = sNode[el][a][3 + c];
+                for (int c = 0; c < B; ++c) U[c] = sNode[el * SE + a * NV + 3 + c];
             }
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const double dn = sDN[q][a][j];
+                const double dn = sDN[q * SQ + a * 3 + j];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) J[i][j] += X[i] * dn;
                 if constexpr (T != 0) {
-                    const double d2 = sD2[q][a][j];
+                    const double d2 = sD2[q * SQ + a * 3 + j];
 #pragma unroll
                     for (int i = 0; i < 3; ++i) Dx[i][j] += X[i] * d2;
 #pragma unroll
