@@ -236,6 +236,10 @@ def batched_workload(fea, mg, torch):
     from graphs."""
     import tempfile
     meshes = mg.batched(64)
+    for k, m in enumerate(meshes):
+        # displacement field of the subgrid-scale timing (the linear
+        # assembly does not read it)
+        m.u = mg.smooth_field(m, 3, seed=100 + k)
     dms = [fea.DeviceMesh(m) for m in meshes]
     b = fea.Batch(dms, model=fea.ELASTIC)
     n_items_default = b.n_items
@@ -290,6 +294,41 @@ def batched_workload(fea, mg, torch):
                                             "elements_per_s": round(b.n_elems / (gms * 1e-3), 1),
                                             "status_ok": bool((gs.cpu() == -1).all())}
             del gv, gr, gs
+        # the subgrid scale of every mesh (nothing scattered): the batch's
+        # per-family queues feeding persistent workgroups, against one
+        # call (four family launches) per mesh
+        del vals, rhs
+        sub_out, sub_st = b.subscale(stream=side)
+        for _ in range(2):
+            b.subscale(out=sub_out, status=sub_st, stream=side)
+        e0.record(side)
+        for _ in range(10):
+            b.subscale(out=sub_out, status=sub_st, stream=side)
+        e1.record(side)
+        side.synchronize()
+        q_ms = e0.elapsed_time(e1) / 10
+        off = b.gauss_points(stream=side)
+        graphs = [dm.graph(stream=side) for dm in dms]
+        one = [dm.subscale(g, dm.u, stream=side) for dm, g in zip(dms, graphs)]
+        for _ in range(2):
+            for (o, st), dm, g in zip(one, dms, graphs):
+                dm.subscale(g, dm.u, out=o, status=st, stream=side)
+        e0.record(side)
+        for _ in range(10):
+            for (o, st), dm, g in zip(one, dms, graphs):
+                dm.subscale(g, dm.u, out=o, status=st, stream=side)
+        e1.record(side)
+        side.synchronize()
+        m_ms = e0.elapsed_time(e1) / 10
+        same = all(torch.equal(sub_out[int(off[k]):int(off[k + 1])], o) for k, (o, _) in enumerate(one))
+        gather["subscale"] = {"gauss_points": int(off[-1]), "queue_ms": round(q_ms, 4),
+                              "one_call_per_mesh_ms": round(m_ms, 4),
+                              "speedup_queue_vs_per_mesh": round(m_ms / q_ms, 3),
+                              "gauss_points_per_s": round(int(off[-1]) / (q_ms * 1e-3), 1),
+                              "bitwise_equal": bool(same),
+                              "status_ok": bool((sub_st.cpu() == -1).all())
+                              and all(int(st.item()) == -1 for _, st in one)}
+        del one, graphs, sub_out
     return {"workload": "batched64-elasticity (64 meshes, 8^3..48^3 cells, jitter 0.25h)",
             "elements": int(b.n_elems), "items": int(b.n_items), "items_default_tiles": int(n_items_default),
             "precision": "mixed", "variant": "rowsym", "tiles": [int(t) for t in tile],

@@ -334,6 +334,33 @@ int fea_batch_workers(const fea_batch *b, int *workers);
 
 void fea_batch_destroy(fea_batch *b);
 
+/* Gauss-point offsets of a batch's meshes in the concatenated subgrid-scale
+ * output: offsets (HOST array of n_meshes+1, may be NULL) receives the
+ * first Gauss point of every mesh and the total. The first call builds each
+ * mesh's Gauss-point layout on `stream` and blocks. Errors: FEA_EINVAL,
+ * FEA_ENOMEM, FEA_EHIP. */
+int fea_batch_gauss_points(fea_batch *b, int64_t *offsets, hipStream_t stream);
+
+/*
+ * Batched subgrid scale (Section 2.1.2, as fea_subscale, FEA_ELASTIC): work
+ * items of its own (runs of four element groups of one family of one mesh:
+ * 1024 tet4, 128 pyr5, 168 pen6 or 128 hex8 elements; built by the first
+ * call, independent of the assembly's tile sizes) dequeued by persistent
+ * workgroups, one launch and queue per element family, with each mesh's
+ * coordinates, material, source and displacement u (its fea_mesh_desc) as
+ * the field; nothing is assembled. Mesh m's Gauss point
+ * q of element e is row offsets[m] + gp_ptr_m[e] + q of out (device FP64,
+ * 3 values per Gauss point, offsets from fea_batch_gauss_points),
+ * overwritten; the values equal fea_subscale's for that mesh. status
+ * (device int32[n_meshes], required) receives per mesh the smallest element
+ * id with detJ <= 0, or -1. Enqueued on `stream`; the first call, and a
+ * call with other output or status pointers, builds a small argument table
+ * and blocks on `stream` first. Meshes with neo-Hookean
+ * flags, a missing u, nu, source or coordinate array, or a batch of
+ * another model: FEA_EINVAL.
+ */
+int fea_batch_subscale(fea_batch *b, hipStream_t stream, double *out, int32_t *status);
+
 /*
  * Tile autotuner: chooses the elements per work item of each family by
  * timing the batch's persistent kernel (the GPU counterpart of the paper's

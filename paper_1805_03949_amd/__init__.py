@@ -58,6 +58,8 @@ _lib.fea_assemble.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Materia
 _lib.fea_last_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.fea_graph_gauss_points.argtypes = [_P, ctypes.POINTER(_I64), _P, _P]
 _lib.fea_subscale.argtypes = [_P, _P, _P, _P, ctypes.POINTER(Material), _P, _P, _P, _P, _P]
+_lib.fea_batch_gauss_points.argtypes = [_P, _P, _P]
+_lib.fea_batch_subscale.argtypes = [_P, _P, _P, _P]
 _lib.fea_last_class_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.fea_last_error.restype = ctypes.c_char_p
 _lib.fea_version.restype = ctypes.c_char_p
@@ -111,7 +113,8 @@ N_FEATURES, N_PARAMS = 12, 5057
 
 # every exported symbol declared in include/fea.h
 EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_sym_sizes", "fea_graph_export", "fea_graph_destroy",
-           "fea_assemble", "fea_last_timing", "fea_graph_gauss_points", "fea_subscale", "fea_last_class_timing", "fea_last_error", "fea_version",
+           "fea_assemble", "fea_last_timing", "fea_graph_gauss_points", "fea_subscale",
+           "fea_batch_gauss_points", "fea_batch_subscale", "fea_last_class_timing", "fea_last_error", "fea_version",
            "fea_batch_build", "fea_batch_sizes", "fea_batch_offsets", "fea_batch_items",
            "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_assemble", "fea_batch_capture",
            "fea_batch_replay", "fea_batch_cycles", "fea_batch_last_ms", "fea_batch_workers",
@@ -357,7 +360,7 @@ class Batch:
             descs[i] = MeshDesc(dm.n_nodes, dm.n_elems, _ptr(dm.types), _ptr(dm.conn_ptr), _ptr(dm.conn),
                                 _ptr(dm.x), _ptr(dm.y), _ptr(dm.z), _ptr(dm.young),
                                 _ptr(dm.nu) if model == ELASTIC else None, _ptr(nh),
-                                _ptr(dm.u) if nh is not None else None, _ptr(src))
+                                _ptr(dm.u) if model == ELASTIC else None, _ptr(src))
         h = _P()
         tp = None
         if tile is not None:
@@ -453,6 +456,26 @@ class Batch:
         w = ctypes.c_int()
         _check(_lib.fea_batch_workers(self._h, ctypes.byref(w)))
         return int(w.value)
+
+    def gauss_points(self, stream=None):
+        """Offsets (n_meshes + 1) of every mesh's Gauss points in the
+        concatenated subgrid-scale output."""
+        import numpy as np
+        off = np.zeros(len(self.meshes) + 1, dtype=np.int64)
+        _check(_lib.fea_batch_gauss_points(self._h, off.ctypes.data_as(_P), _stream(stream)))
+        return off
+
+    def subscale(self, out=None, status=None, stream=None):
+        """Batched subgrid scale (linear elasticity, each mesh's u as the
+        field): out[n_points, 3] in mesh order, status[n_meshes]."""
+        if out is None:
+            n = int(self.gauss_points(stream)[-1])
+            out = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        if status is None:
+            status = torch.empty(len(self.meshes), dtype=torch.int32, device=self.device)
+        _dev(out, torch.float64)
+        _check(_lib.fea_batch_subscale(self._h, _stream(stream), _ptr(out), _ptr(status)))
+        return out, status
 
     def destroy(self):
         if getattr(self, "_h", None) is not None:

@@ -269,6 +269,15 @@ struct fea_batch {
     int64_t total_sym_slots = 0, total_nup = 0;
     int32_t *d_sym_ublk = nullptr, *d_sym_lpart = nullptr;
     int64_t *d_sym_ptr = nullptr;
+    // subgrid scale: its own queue heads (one per family) and per-mesh
+    // arguments, kept for the outputs and item list they were built for
+    int32_t *d_sub_head = nullptr;
+    int4 *d_sub_items = nullptr;   // its own work items and family-grouped
+    int32_t *d_sub_order = nullptr;  // order (built once: the meshes are fixed)
+    int64_t sub_foff[5] = {0, 0, 0, 0, 0};
+    void *d_subargs = nullptr;
+    size_t subargs_cap = 0;
+    const void *subargs_key[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -290,7 +299,8 @@ void destroy_batch(fea_batch *b)
         if (g) fea_graph_destroy(g);
     void *bufs[] = {b->d_meshes, b->d_items, b->d_order, b->d_head, b->d_status, b->d_vseg,
                     b->d_rseg, b->d_cycles, b->d_worker, b->d_cu, b->contrib, b->rcontrib,
-                    b->d_part, b->d_sym_ublk, b->d_sym_lpart, b->d_sym_ptr, b->d_itemargs};
+                    b->d_part, b->d_sym_ublk, b->d_sym_lpart, b->d_sym_ptr, b->d_itemargs,
+                    b->d_sub_head, b->d_subargs, b->d_sub_items, b->d_sub_order};
     for (void *p : bufs) dfree(p);
     for (hipEvent_t e : b->ev)
         if (e) (void)hipEventDestroy(e);
@@ -779,6 +789,7 @@ const int kNQ[4] = {1, 8, 6, 8};
 
 int upload_order(fea_batch *b) { return upload_grouped_order(b); }
 
+
 // median duration (ms) of the persistent kernel over `reps` launches
 int time_batch(fea_batch *b, const fea_options *o, int reps, hipStream_t s, void *vals, void *rhs, float *ms)
 {
@@ -1144,4 +1155,26 @@ extern "C" void fea_batch_destroy(fea_batch *b)
         destroy_batch(b);
         (void)hipSetDevice(cur);
     }
+}
+
+int fea::batch_view(fea_batch *b, BatchView *v)
+{
+    int rc;
+    if (!b->d_sub_head && (rc = dalloc((void **)&b->d_sub_head, sizeof(int32_t) * 4))) return rc;
+    v->device = b->device;
+    v->model = b->model;
+    v->n_meshes = b->n_meshes;
+    v->desc = b->desc.data();
+    v->graphs = b->graphs.data();
+    v->items = b->d_sub_items;
+    v->order = b->d_sub_order;
+    for (int t = 0; t < 5; ++t) v->foff[t] = b->sub_foff[t];
+    v->head = b->d_sub_head;
+    v->items_owner = &b->d_sub_items;
+    v->order_owner = &b->d_sub_order;
+    v->foff_owner = b->sub_foff;
+    v->args = &b->d_subargs;
+    v->args_cap = &b->subargs_cap;
+    v->args_key = b->subargs_key;
+    return FEA_OK;
 }

@@ -55,6 +55,29 @@ struct GatherInput {
     const double *u;
 };
 
+// What the subgrid scale needs of a batch (fea_batch is private to the
+// batch code): its meshes and graphs, its own work items and
+// family-grouped order (sized for the subgrid scale's element groups, kept
+// in the batch), queue heads of its own and a cache slot for per-mesh
+// arguments (valid for the key recorded with it).
+struct BatchView {
+    int device, model, n_meshes;
+    const fea_mesh_desc *desc;
+    fea_graph *const *graphs;
+    const int4 *items;
+    const int32_t *order;
+    int64_t foff[5];
+    int32_t *head;
+    // where the subgrid scale's own items live (built on its first call)
+    int4 **items_owner;
+    int32_t **order_owner;
+    int64_t *foff_owner;
+    void **args;
+    size_t *args_cap;
+    const void **args_key;
+};
+int batch_view(fea_batch *b, BatchView *v);
+
 }  // namespace fea
 
 // The graph object behind the opaque fea_graph handle.

@@ -30,6 +30,7 @@
 // derivatives, reads its four nodes directly.) The element volume is
 // summed over the element's Gauss points in ascending order through LDS,
 // and each lane writes its B values at the element's Gauss-point offset.
+#include <algorithm>
 #include <climits>
 #include <mutex>
 
@@ -118,36 +119,55 @@ struct SubArgs {
     int32_t *status;       // smallest element id with detJ <= 0
 };
 
+// LDS of one workgroup. Strides padded to 2 (mod 4) doubles: the 8 Gauss
+// points or elements that a wave reads at once then start in distinct
+// 16-byte bank slots (hex8's 48-double element records aliased every
+// second element).
 template <int T, int MODEL>
-__global__ void __launch_bounds__(256) k_subscale(SubArgs A)
+struct SubSmem {
+    static constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, EPW = 256 / NQ;
+    static constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
+    static constexpr int NV = 3 + B;                                    // node values
+    static constexpr int SQ = NN * 3 + ((2 - (NN * 3) % 4) + 4) % 4;    // per Gauss point of a table
+    static constexpr int SE = NN * NV + ((2 - (NN * NV) % 4) + 4) % 4;  // per element
+    double sDN[NQ * SQ];
+    double sD2[NQ * SQ];
+    double sWq[NQ];
+    double sWd[256];
+    double sNode[(T == 0 ? 1 : EPW) * SE];  // node coordinates and field values
+};
+
+// Reference tables of family T into LDS (the caller synchronises).
+template <int T, int MODEL>
+__device__ inline void sub_tables(SubSmem<T, MODEL> &S)
 {
-    constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, EPW = 256 / NQ;
-    constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
-    // LDS strides padded to 2 (mod 4) doubles: the 8 Gauss points or
-    // elements that a wave reads at once then start in distinct 16-byte
-    // bank slots (hex8's 48-double element records aliased every second
-    // element)
-    constexpr int SQ = NN * 3 + ((2 - (NN * 3) % 4) + 4) % 4;  // per Gauss point of a table
-    __shared__ double sDN[NQ * SQ];
-    __shared__ double sD2[NQ * SQ];
-    __shared__ double sWq[NQ];
-    __shared__ double sWd[256];
-    // node coordinates and field values of the workgroup's elements
-    constexpr int NV = 3 + B;
-    constexpr int SE = NN * NV + ((2 - (NN * NV) % 4) + 4) % 4;  // per element
-    __shared__ double sNode[(T == 0 ? 1 : EPW) * SE];
+    using Sm = SubSmem<T, MODEL>;
+    constexpr int NN = Sm::NN, NQ = Sm::NQ, SQ = Sm::SQ;
     const int tid = threadIdx.x;
     for (int i = tid; i < NQ * NN * 3; i += 256) {
         const int q = i / (NN * 3), a = (i / 3) % NN, j = i % 3;
-        sDN[q * SQ + a * 3 + j] = c_ref.dN[T][q][a][j];
-        sD2[q * SQ + a * 3 + j] = c_sub.d2[T][q][a][j];
+        S.sDN[q * SQ + a * 3 + j] = c_ref.dN[T][q][a][j];
+        S.sD2[q * SQ + a * 3 + j] = c_sub.d2[T][q][a][j];
     }
-    if (tid < NQ) sWq[tid] = c_ref.w[T][tid];
-    __syncthreads();
+    if (tid < NQ) S.sWq[tid] = c_ref.w[T][tid];
+}
 
+// One group of up to EPW consecutive elements of a family, type-sorted
+// positions p0 .. min(p0 + EPW, pend). Every lane of the workgroup calls it;
+// it starts with a barrier (the previous group's readers of S are done)
+// and lanes without an element only take part in the barriers.
+template <int T, int MODEL>
+__device__ void sub_group(const SubArgs &A, int64_t p0, int64_t pend, SubSmem<T, MODEL> &S)
+{
+    using Sm = SubSmem<T, MODEL>;
+    constexpr int NN = Sm::NN, NQ = Sm::NQ, EPW = Sm::EPW, B = Sm::B, NV = Sm::NV, SQ = Sm::SQ, SE = Sm::SE;
+    const double *sDN = S.sDN, *sD2 = S.sD2, *sWq = S.sWq;
+    double *sWd = S.sWd, *sNode = S.sNode;
+    const int tid = threadIdx.x;
+    __syncthreads();
     const int el = tid / NQ, q = tid - el * NQ;
-    const int64_t p = (int64_t)blockIdx.x * EPW + el;
-    const bool act = el < EPW && p < A.n;
+    const int64_t p = p0 + el;
+    const bool act = el < EPW && p < pend;
     const int32_t e = act ? A.perm[p] : 0;
     double wd = 0.0, kmat = 1.0;  // w_q detJ; tau's material constant k
     double r[B];
@@ -273,15 +293,54 @@ __global__ void __launch_bounds__(256) k_subscale(SubArgs A)
     // every lane reaches the barrier, active or not
     sWd[tid] = wd;
     __syncthreads();
-    if (!act) return;
-    double V = 0.0;
+    if (act) {
+        double V = 0.0;
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) V += sWd[el * NQ + k];
-    const double h = cbrt(V);
-    const double tau = h * h / (4.0 * kmat);
-    double *o = A.out + (A.gp_ptr[e] + q) * B;
+        for (int k = 0; k < NQ; ++k) V += sWd[el * NQ + k];
+        const double h = cbrt(V);
+        const double tau = h * h / (4.0 * kmat);
+        double *o = A.out + (A.gp_ptr[e] + q) * B;
 #pragma unroll
-    for (int c = 0; c < B; ++c) o[c] = tau * r[c];
+        for (int c = 0; c < B; ++c) o[c] = tau * r[c];
+    }
+}
+
+template <int T, int MODEL>
+__global__ void __launch_bounds__(256) k_subscale(SubArgs A)
+{
+    __shared__ SubSmem<T, MODEL> S;
+    sub_tables(S);
+    sub_group(A, (int64_t)blockIdx.x * SubSmem<T, MODEL>::EPW, A.n, S);
+}
+
+// Batched form: persistent workgroups of one family dequeue work items
+// (mesh, family, first type-sorted position, count) from the batch's queue
+// of that family and run the item's elements group by group with the
+// arguments of the item's mesh, margs[mesh] (its view of family T). Every
+// workgroup reaches the exit test after each item.
+template <int T, int MODEL>
+__global__ void __launch_bounds__(256) k_subscale_batch(const SubArgs *__restrict__ margs, const int4 *items,
+                                                        const int32_t *order, int32_t n_items, int32_t *head)
+{
+    constexpr int EPW = SubSmem<T, MODEL>::EPW;
+    __shared__ SubSmem<T, MODEL> S;
+    __shared__ int32_t s_item;
+    sub_tables(S);
+    for (;;) {
+        __syncthreads();  // every lane has read the previous item
+        if (threadIdx.x == 0) {
+            const int32_t q = atomicAdd(head, 1);
+            s_item = q < n_items ? order[q] : -1;
+        }
+        __syncthreads();
+        const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it < 0) break;
+        const int4 w = items[it];
+        const int32_t m = __builtin_amdgcn_readfirstlane(w.x);
+        const int64_t first = __builtin_amdgcn_readfirstlane(w.z), count = __builtin_amdgcn_readfirstlane(w.w);
+        const SubArgs &A = margs[m];
+        for (int64_t g0 = 0; g0 < count; g0 += EPW) sub_group(A, first + g0, first + count, S);
+    }
 }
 
 __global__ void k_sub_status_init(int32_t *s) { *s = INT_MAX; }
@@ -423,6 +482,208 @@ extern "C" int fea_subscale(const fea_graph *gc, const double *x, const double *
             run_sub<FEA_ELASTIC>(g, a, stream);
     }
     k_sub_status_final<<<1, 1, 0, stream>>>(st);
+    FEA_HIP(hipGetLastError());
+    return FEA_OK;
+}
+
+// ------------------------------------------------------------------ //
+// Batched subgrid scale: the batch's work items from its device queues. //
+// ------------------------------------------------------------------ //
+namespace fea {
+
+__global__ void k_sub_batch_begin(int32_t *head, int32_t *status, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < 4) head[i] = 0;
+    if (i < n) status[i] = INT_MAX;
+}
+
+__global__ void k_sub_batch_end(int32_t *status, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n && status[i] == INT_MAX) status[i] = -1;
+}
+
+// Resident workgroups of the batched kernel of family T on a device.
+template <int T, int MODEL>
+static int sub_batch_workers(int dev, int64_t *out)
+{
+    static int64_t cache[64] = {0};
+    if (dev < 0 || dev >= 64) return set_error(FEA_EINVAL, "device index %d unsupported", dev);
+    if (!cache[dev]) {
+        int per = 0, cus = 0;
+        FEA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_subscale_batch<T, MODEL>, 256, 0));
+        FEA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        cache[dev] = (int64_t)std::max(per, 1) * std::max(cus, 1);
+    }
+    *out = cache[dev];
+    return FEA_OK;
+}
+
+template <int T>
+static int launch_sub_batch(const BatchView &v, const SubArgs *d_args, hipStream_t s)
+{
+    const int64_t n = v.foff[T + 1] - v.foff[T];
+    if (n == 0) return FEA_OK;
+    int64_t w = 0;
+    int rc = sub_batch_workers<T, FEA_ELASTIC>(v.device, &w);
+    if (rc) return rc;
+    const unsigned grid = (unsigned)std::min<int64_t>(n, w);
+    k_subscale_batch<T, FEA_ELASTIC><<<grid, 256, 0, s>>>(d_args + (size_t)T * v.n_meshes, v.items,
+                                                          v.order + v.foff[T], (int32_t)n, v.head + T);
+    return FEA_OK;
+}
+
+// Gauss-point layouts of every mesh of a batch; off[m] = first Gauss point
+// of mesh m in the concatenated output (off[n_meshes] = total).
+static int batch_gauss_offsets(const BatchView &v, hipStream_t s, std::vector<int64_t> &off)
+{
+    off.assign((size_t)v.n_meshes + 1, 0);
+    for (int m = 0; m < v.n_meshes; ++m) {
+        int rc = gauss_points_prepare(v.graphs[m], s);
+        if (rc) return rc;
+        off[m + 1] = off[m] + v.graphs[m]->n_gp;
+    }
+    return FEA_OK;
+}
+
+}  // namespace fea
+
+namespace fea {
+
+// The subgrid scale's work items: per family, runs of 4 element groups
+// (1024 tet4, 128 pyr5, 168 pen6, 128 hex8 elements) of one mesh, so that
+// only a mesh's last item of a family has a partial group; the order lists
+// them family by family (mesh, then position), as the queues expect.
+static int sub_items_prepare(BatchView &v)
+{
+    if (*v.items_owner) return FEA_OK;
+    const int per[4] = {4 * 256, 4 * 32, 4 * 42, 4 * 32};
+    std::vector<int32_t> items;
+    std::vector<int32_t> order;
+    int64_t foff[5] = {0, 0, 0, 0, 0};
+    for (int t = 0; t < 4; ++t) {
+        foff[t] = (int64_t)order.size();
+        for (int m = 0; m < v.n_meshes; ++m) {
+            const fea_graph *g = v.graphs[m];
+            const int64_t n = g->seg[t + 1] - g->seg[t];
+            for (int64_t s0 = 0; s0 < n; s0 += per[t]) {
+                order.push_back((int32_t)(items.size() / 4));
+                items.push_back(m);
+                items.push_back(t);
+                items.push_back((int32_t)s0);
+                items.push_back((int32_t)std::min<int64_t>(per[t], n - s0));
+            }
+        }
+    }
+    foff[4] = (int64_t)order.size();
+    const size_t ni = order.size();
+    int rc;
+    int4 *d_items = nullptr;
+    int32_t *d_order = nullptr;
+    if ((rc = dalloc((void **)&d_items, sizeof(int4) * std::max<size_t>(ni, 1)))) return rc;
+    if ((rc = dalloc((void **)&d_order, sizeof(int32_t) * std::max<size_t>(ni, 1)))) {
+        dfree(d_items);
+        return rc;
+    }
+    if (ni) {
+        hipError_t e1 = hipMemcpy(d_items, items.data(), sizeof(int4) * ni, hipMemcpyHostToDevice);
+        hipError_t e2 = hipMemcpy(d_order, order.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            dfree(d_items);
+            dfree(d_order);
+            return set_error(FEA_EHIP, "uploading the subgrid-scale items failed");
+        }
+    }
+    *v.items_owner = d_items;
+    *v.order_owner = d_order;
+    for (int t = 0; t < 5; ++t) v.foff_owner[t] = foff[t];
+    v.items = d_items;
+    v.order = d_order;
+    for (int t = 0; t < 5; ++t) v.foff[t] = foff[t];
+    return FEA_OK;
+}
+
+}  // namespace fea
+
+extern "C" int fea_batch_gauss_points(fea_batch *b, int64_t *offsets, hipStream_t stream)
+{
+    clear_error();
+    if (!b) return set_error(FEA_EINVAL, "batch is required");
+    BatchView v;
+    int rc = batch_view(b, &v);
+    if (rc) return rc;
+    std::vector<int64_t> off;
+    if ((rc = batch_gauss_offsets(v, stream, off))) return rc;
+    if (offsets) std::copy(off.begin(), off.end(), offsets);
+    return FEA_OK;
+}
+
+extern "C" int fea_batch_subscale(fea_batch *b, hipStream_t stream, double *out, int32_t *status)
+{
+    clear_error();
+    if (!b) return set_error(FEA_EINVAL, "batch is required");
+    BatchView v;
+    int rc = batch_view(b, &v);
+    if (rc) return rc;
+    if (v.model != FEA_ELASTIC) return set_error(FEA_EINVAL, "the batched subgrid scale is built for FEA_ELASTIC");
+    if (!status) return set_error(FEA_EINVAL, "status (one int32 per mesh) is required");
+    for (int m = 0; m < v.n_meshes; ++m) {
+        const fea_mesh_desc &d = v.desc[m];
+        if (d.nh_flag) return set_error(FEA_EINVAL, "mesh %d: the subgrid scale is defined for linear elasticity only", m);
+        if (d.n_elems > 0 && (!d.u || !d.nu || !d.source || !d.x || !d.y || !d.z))
+            return set_error(FEA_EINVAL, "mesh %d: u, nu, source and coordinates are required", m);
+    }
+    int dev = 0;
+    FEA_HIP(hipGetDevice(&dev));
+    if (dev != v.device) return set_error(FEA_EINVAL, "batch lives on device %d, current is %d", v.device, dev);
+    if ((rc = ensure_tables()) || (rc = ensure_sub_tables())) return rc;
+    std::vector<int64_t> off;
+    if ((rc = batch_gauss_offsets(v, stream, off))) return rc;
+    if (off.back() > 0 && !out) return set_error(FEA_EINVAL, "NULL output");
+    if ((rc = sub_items_prepare(v))) return rc;
+    // per-(family, mesh) arguments, rebuilt when the outputs change
+    const size_t na = (size_t)4 * std::max(v.n_meshes, 1);
+    if (!(v.args_key[0] == out && v.args_key[1] == status && *v.args)) {
+        std::vector<SubArgs> h(na);
+        for (int t = 0; t < 4; ++t)
+            for (int m = 0; m < v.n_meshes; ++m) {
+                const fea_mesh_desc &d = v.desc[m];
+                const fea_graph *g = v.graphs[m];
+                SubArgs a = {};
+                a.x = d.x; a.y = d.y; a.z = d.z;
+                a.u = d.u;
+                a.young = d.young;
+                a.nu = d.nu;
+                a.source = d.source;
+                a.perm = g->perm + g->seg[t];
+                a.pnodes = g->pnodes + g->node_base[t];
+                a.gp_ptr = g->gp_ptr;
+                a.n = g->seg[t + 1] - g->seg[t];
+                a.out = out + off[m] * 3;
+                a.status = status + m;
+                h[(size_t)t * v.n_meshes + m] = a;
+            }
+        // a kernel still in flight may read the previous table
+        FEA_HIP(hipStreamSynchronize(stream));
+        if (*v.args_cap < na) {
+            dfree(*v.args);
+            *v.args = nullptr;
+            *v.args_cap = 0;
+            if ((rc = dalloc(v.args, sizeof(SubArgs) * na))) return rc;
+            *v.args_cap = na;
+        }
+        FEA_HIP(hipMemcpy(*v.args, h.data(), sizeof(SubArgs) * na, hipMemcpyHostToDevice));
+        v.args_key[0] = out;
+        v.args_key[1] = status;
+    }
+    const SubArgs *d_args = (const SubArgs *)*v.args;
+    const int nb = (int)grid_for(std::max(v.n_meshes, 4), 256);
+    k_sub_batch_begin<<<nb, 256, 0, stream>>>(v.head, status, v.n_meshes);
+    if ((rc = launch_sub_batch<1>(v, d_args, stream)) || (rc = launch_sub_batch<3>(v, d_args, stream)) ||
+        (rc = launch_sub_batch<2>(v, d_args, stream)) || (rc = launch_sub_batch<0>(v, d_args, stream)))
+        return rc;
+    k_sub_batch_end<<<nb, 256, 0, stream>>>(status, v.n_meshes);
     FEA_HIP(hipGetLastError());
     return FEA_OK;
 }

@@ -171,3 +171,46 @@ def test_subscale_rejects_neo_hookean_and_bad_model():
                                    ctypes.byref(mat), P(u.data_ptr()), P(dm.source.data_ptr()),
                                    fea._stream(None), P(out.data_ptr()), None)
         assert rc == fea.FEA_EINVAL
+
+
+def test_batched_subscale_equals_one_mesh_bitwise():
+    """The batched form (persistent workgroups fed by per-family queues of
+    its own items) computes each element exactly as the one-mesh form:
+    outputs are equal bit for bit, mesh by mesh, and stay so when the
+    assembly's tile sizes change."""
+    meshes = mg.batched(n_meshes=5, seed=31, n_range=(3, 7), jitter=0.2, first_seed=900)
+    dms = []
+    for k, m in enumerate(meshes):
+        m.u = mg.smooth_field(m, 3, seed=40 + k, noise=0.3)
+        dms.append(fea.DeviceMesh(m))
+    b = fea.Batch(dms, model=fea.ELASTIC)
+    off = b.gauss_points()
+    refs = []
+    for dm in dms:
+        g = dm.graph()
+        out, st = dm.subscale(g, dm.u)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -1
+        refs.append(out.cpu().numpy())
+    assert int(off[-1]) == sum(r.shape[0] for r in refs)
+    for tiles in (None, [25, 17, 12, 7]):
+        if tiles is not None:
+            b.set_tiles(tiles)
+        out, st = b.subscale()
+        torch.cuda.synchronize()
+        assert (st.cpu().numpy() == -1).all()
+        got = out.cpu().numpy()
+        for k, r in enumerate(refs):
+            assert np.array_equal(got[off[k]:off[k + 1]], r), (tiles, k)
+    # oracle agreement of one mesh of the batch
+    _, oref = oracle.subscale(meshes[2], meshes[2].u, model=oracle.ELASTIC)
+    np.testing.assert_allclose(got[off[2]:off[3]], oref, rtol=1e-11, atol=1e-11 * np.abs(oref).max())
+
+
+def test_batched_subscale_rejects_neo_hookean_batches():
+    m = mg.heterogeneous(8, seed=6, brick=2, jitter=0.1)
+    dm = fea.DeviceMesh(m)
+    b = fea.Batch([dm], model=fea.ELASTIC, use_nh=True)
+    with pytest.raises(fea.FeaError) as ei:
+        b.subscale()
+    assert ei.value.code == fea.FEA_EINVAL
