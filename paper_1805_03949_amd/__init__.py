@@ -468,11 +468,13 @@ class Batch:
     def subscale(self, out=None, status=None, stream=None):
         """Batched subgrid scale (linear elasticity, each mesh's u as the
         field): out[n_points, 3] in mesh order, status[n_meshes]."""
+        n = int(self.gauss_points(stream)[-1])
         if out is None:
-            n = int(self.gauss_points(stream)[-1])
             out = torch.empty((n, 3), dtype=torch.float64, device=self.device)
         if status is None:
             status = torch.empty(len(self.meshes), dtype=torch.int32, device=self.device)
+        if out.numel() != 3 * n or status.numel() != len(self.meshes):
+            raise ValueError(f"out needs {3 * n} values and status {len(self.meshes)}")
         _dev(out, torch.float64)
         _check(_lib.fea_batch_subscale(self._h, _stream(stream), _ptr(out), _ptr(status)))
         return out, status
