@@ -420,6 +420,24 @@ def large_workload(fea, mg, torch, np, cells=256):
                                        "elements_per_s": round(mesh.n_elems / (float(np.median(tot)) * 1e-3), 1),
                                        "status_ok": ok}
             del vals, rhs, st
+    # the element-wise subgrid scale of the whole mesh at a smooth field
+    u = torch.from_numpy(mg.smooth_field(mesh, 3, seed=12)).to(dm.x.device)
+    so, ss = dm.subscale(g, u)
+    dm.subscale(g, u, out=so, status=ss)
+    ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dm.subscale(g, u, out=so, status=ss)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    sms = float(np.median(ts))
+    out["subscale_fp64"] = {"ms": round(sms, 3), "gauss_points": int(so.shape[0]),
+                            "gauss_points_per_s": round(int(so.shape[0]) / (sms * 1e-3), 1),
+                            "elements_per_s": round(mesh.n_elems / (sms * 1e-3), 1),
+                            "status_ok": int(ss.item()) == -1}
+    del so, ss, u
     g.destroy()
     return out
 

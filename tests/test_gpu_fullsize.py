@@ -137,43 +137,53 @@ def test_hybrid256_batched_sampled_rows():
             worst = check_rows(mesh, rows, row_ptr, col, v, r, 3, fp32_L=L)
             assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (variant, prec, worst)
             del v, r
+    # the subgrid scale of the whole mesh at the bench's field, sampled
+    print("[case] hybrid256 subscale", flush=True)
+    worst = _subscale_sampled(mesh, dm, g, mg.smooth_field(mesh, 3, seed=12), seed=13, k=1000)
+    assert worst <= 1.0, worst
 
 
-def test_hybrid96_subscale_sampled_elements():
-    """The subgrid scale of the benchmark workload (hybrid96 elasticity, the
-    bench's smooth field), checked on sampled elements of every family that
-    the oracle evaluates one by one; the tolerance is the one derived in
-    tests/test_gpu_subscale.py."""
+def _subscale_sampled(mesh, dm, g, u, seed, k):
+    """Worst ratio of |gpu - oracle| to the subgrid-scale tolerance (derived
+    in tests/test_gpu_subscale.py) over k sampled elements and the first and
+    last element of every family, which the oracle evaluates one by one."""
     import oracle
-    mesh = mg.hybrid_bands(96, seed=2)
-    print(f"[case] hybrid96 subscale: {mesh.n_elems} elements", flush=True)
-    dm = fea.DeviceMesh(mesh)
-    g = dm.graph()
-    u = mg.smooth_field(mesh, 3, seed=11)
     out, st = dm.subscale(g, torch.from_numpy(u).cuda())
     torch.cuda.synchronize()
     assert int(st.item()) == -1
     _, gp = g.gauss_points()
     gp = gp.cpu().numpy()
-    rng = np.random.default_rng(12)
-    elems = set(rng.choice(mesh.n_elems, 2000, replace=False).tolist())
-    for t in range(4):  # first and last element of every family
+    rng = np.random.default_rng(seed)
+    elems = set(rng.choice(mesh.n_elems, k, replace=False).tolist())
+    for t in range(4):
         ids = np.flatnonzero(mesh.types == t)
-        elems.update([int(ids[0]), int(ids[-1])])
+        if ids.size:
+            elems.update([int(ids[0]), int(ids[-1])])
     X = np.stack([mesh.x, mesh.y, mesh.z], axis=1)
     U = u.reshape(-1, 3)
-    got_all = out.cpu().numpy()
     worst = 0.0
     for e in sorted(elems):
         nodes = mesh.conn[mesh.conn_ptr[e]:mesh.conn_ptr[e + 1]]
         E, nu = float(mesh.young[e]), float(mesh.nu[e])
         ref = oracle.element_subscale(int(mesh.types[e]), X[nodes], U[nodes], model=oracle.ELASTIC,
                                       young=E, nu=nu, f=mesh.source[e])
-        got = got_all[gp[e]:gp[e + 1]]
+        got = out[int(gp[e]):int(gp[e + 1])].cpu().numpy()
         assert got.shape == ref.shape
         lam, mu = E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
         scale = (lam + 2 * mu) / (4 * mu) * np.abs(U[nodes]).max()
         worst = max(worst, float((np.abs(got - ref) / (1e-11 * (np.abs(ref) + scale))).max()))
+    del out, st
+    return worst
+
+
+def test_hybrid96_subscale_sampled_elements():
+    """The subgrid scale of the benchmark workload (hybrid96 elasticity, the
+    bench's smooth field) on sampled elements of every family."""
+    mesh = mg.hybrid_bands(96, seed=2)
+    print(f"[case] hybrid96 subscale: {mesh.n_elems} elements", flush=True)
+    dm = fea.DeviceMesh(mesh)
+    g = dm.graph()
+    worst = _subscale_sampled(mesh, dm, g, mg.smooth_field(mesh, 3, seed=11), seed=12, k=2000)
     assert worst <= 1.0, worst
 
 
