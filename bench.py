@@ -523,7 +523,7 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
 
     # static split of the whole mesh into 8 contiguous parts (the sharding
     # of a mesh over 8 GPUs): cut the type-sorted items where the running
-    # weight crosses k/8 of the total, then judge each split by the
+    # weight crosses k/8 of the total, then rate each split by the
     # measured cycles of its parts (load balance = mean / max part cost)
     cyc = np.exp(t)
 
@@ -621,9 +621,9 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 8}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(assembly shards across GPUs without communication; see the design notes).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(assembly would shard by element slabs or whole meshes, with no communication "
+              "between GPUs).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
