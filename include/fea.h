@@ -352,7 +352,8 @@ int fea_batch_gauss_points(fea_batch *b, int64_t *offsets, hipStream_t stream);
  * q of element e is row offsets[m] + gp_ptr_m[e] + q of out (device FP64,
  * 3 values per Gauss point, offsets from fea_batch_gauss_points),
  * overwritten; the values equal fea_subscale's for that mesh. status
- * (device int32[n_meshes], required) receives per mesh the smallest element
+ * (device int32[n_meshes], required unless the batch has no mesh) receives
+ * per mesh the smallest element
  * id with detJ <= 0, or -1. Enqueued on `stream`; the first call, and a
  * call with other output or status pointers, builds a small argument table
  * and blocks on `stream` first. Meshes with neo-Hookean

@@ -627,7 +627,7 @@ extern "C" int fea_batch_subscale(fea_batch *b, hipStream_t stream, double *out,
     int rc = batch_view(b, &v);
     if (rc) return rc;
     if (v.model != FEA_ELASTIC) return set_error(FEA_EINVAL, "the batched subgrid scale is built for FEA_ELASTIC");
-    if (!status) return set_error(FEA_EINVAL, "status (one int32 per mesh) is required");
+    if (!status && v.n_meshes > 0) return set_error(FEA_EINVAL, "status (one int32 per mesh) is required");
     for (int m = 0; m < v.n_meshes; ++m) {
         const fea_mesh_desc &d = v.desc[m];
         if (d.nh_flag) return set_error(FEA_EINVAL, "mesh %d: the subgrid scale is defined for linear elasticity only", m);

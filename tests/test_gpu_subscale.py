@@ -214,3 +214,11 @@ def test_batched_subscale_rejects_neo_hookean_batches():
     with pytest.raises(fea.FeaError) as ei:
         b.subscale()
     assert ei.value.code == fea.FEA_EINVAL
+
+
+def test_batched_subscale_of_an_empty_batch():
+    b = fea.Batch([], model=fea.ELASTIC)
+    assert b.gauss_points().tolist() == [0]
+    out, st = b.subscale()
+    torch.cuda.synchronize()
+    assert out.shape == (0, 3) and st.numel() == 0
