@@ -64,3 +64,26 @@ def test_sym_tile_blocks_match_brute_force():
 def test_sym_reduce_bytes_definition():
     b = bench.sym_reduce_bytes(100, 10, 15, 3, 4, 8)
     assert b == 100 * 9 * 4 + 11 * 8 + 10 * 8 + 15 * 9 * 8
+
+
+def test_subscale_work_counts_every_element_and_node_once():
+    """The subgrid scale's algorithmic bytes and flops: per element its id,
+    node ids, material, source, Gauss-point offset and outputs, per node its
+    coordinates and field once; flops per Gauss point by family. A brute
+    force over the elements must give the same sums."""
+    m = mg.hybrid_bands(6, seed=2)
+    byts, flops = bench.subscale_work(m, 3, np)
+    nn = {0: 4, 1: 5, 2: 6, 3: 8}
+    nq = {0: 1, 1: 8, 2: 6, 3: 8}
+    b2 = m.n_nodes * (24 + 24)
+    f2 = 0
+    for t in m.types:
+        t = int(t)
+        b2 += 4 + 4 * nn[t] + 16 + 24 + 8 + 24 * nq[t]
+        f2 += nq[t] * bench.subscale_flops_per_point(t, 3)
+    assert byts == b2 and flops == f2
+    # per Gauss point, by hand: tet4 reads J only (18 per node); the others
+    # add 54 per node for the second derivatives and 282 after the node loop
+    assert bench.subscale_flops_per_point(0, 3) == 4 * 18 + 43 + 1 + 3
+    assert bench.subscale_flops_per_point(3, 3) == 8 * 72 + 43 + 282 + 1 + 3
+    assert bench.subscale_flops_per_point(1, 1) == 5 * (18 + 18 + 12) + 43 + 56 + 1 + 1
