@@ -206,7 +206,7 @@ int fea_last_class_timing(const fea_graph *g, float *ms);
 int fea_graph_gauss_points(const fea_graph *g, int64_t *n_points, int64_t *gp_ptr, hipStream_t stream);
 
 /*
- * Subgrid scale (Section 2.1.2: the subscale is obtained element by element
+ * Subgrid scale (Section 2.1.3: the subscale is obtained element by element
  * from the strong residual at the Gauss points and a diagonal stabilisation
  * matrix, in a loop over the elements that forms no system). For the linear
  * models, at every Gauss point q of every element e, in FP64:
@@ -258,7 +258,7 @@ typedef struct fea_batch fea_batch;
  * the item sizes, each rounded up to a multiple of the family's
  * upper-triangle tile (25, 17, 12, 7 elements), so that items start on
  * tile boundaries in every form.
- * The paper's dynamic schedule with a chunk size (Section 5.1, chunk study)
+ * The paper's dynamic schedule with a chunk size (Section 5.2, chunk study)
  * is the analogue: items are chunks handed out by a device work queue.
  * The queue order starts type-sorted (family, mesh, first element).
  * Outputs of all meshes are concatenated: mesh m's values start at
@@ -342,7 +342,7 @@ void fea_batch_destroy(fea_batch *b);
 int fea_batch_gauss_points(fea_batch *b, int64_t *offsets, hipStream_t stream);
 
 /*
- * Batched subgrid scale (Section 2.1.2, as fea_subscale, FEA_ELASTIC): work
+ * Batched subgrid scale (Section 2.1.3, as fea_subscale, FEA_ELASTIC): work
  * items of its own (runs of four element groups of one family of one mesh:
  * 1024 tet4, 128 pyr5, 168 pen6 or 128 hex8 elements; built by the first
  * call, independent of the assembly's tile sizes) dequeued by persistent
@@ -365,7 +365,7 @@ int fea_batch_subscale(fea_batch *b, hipStream_t stream, double *out, int32_t *s
 /*
  * Tile autotuner: chooses the elements per work item of each family by
  * timing the batch's persistent kernel (the GPU counterpart of the paper's
- * chunk-size study, Section 5.1). Coordinate descent: for each family in
+ * chunk-size study, Section 5.2). Coordinate descent: for each family in
  * turn the candidates EPB*{1,2,4,8,16,32} are tried with the other tiles
  * fixed (EPB = the upper-triangle tile: 25 tet4, 17 pyr5, 12 pen6, 7 hex8),
  * two sweeps, each candidate timed as the median of `reps`

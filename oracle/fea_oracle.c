@@ -29,7 +29,7 @@
  *       AA_iJjL = mu d_ij d_JL + (mu - lam ln J) Finv_Jj Finv_Li + lam Finv_Ji Finv_Lj,
  *       K_(a,i)(b,j) = sum_q w detJ sum_JL dN_a/dX_J AA_iJjL dN_b/dX_L.
  * It also evaluates, element by element with nothing assembled, the
- * subgrid scale of Section 2.1.2 read for these problems (the strong
+ * subgrid scale of Section 2.1.3 read for these problems (the strong
  * residual f + L(u_h) at every Gauss point scaled by an element constant;
  * or_element_subscale states the reading).
  * Alongside the values it assembles T, the same sums taken over the
@@ -471,7 +471,7 @@ int or_shape2(int type, const double *xi, double *D2)
 }
 
 /*
- * Subgrid scale of one element (Section 2.1.2: the subgrid scale comes from
+ * Subgrid scale of one element (Section 2.1.3: the subgrid scale comes from
  * an element-wise equation, utilde = tau^-1 (R u + b) with a diagonal tau
  * and a rectangular R, in a plain loop over elements, no system formed).
  * Read for the problems assembled here: at Gauss point q,

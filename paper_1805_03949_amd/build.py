@@ -6,6 +6,7 @@ shared library next to this file.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -33,16 +34,18 @@ def _run(cmd):
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(build_dir, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
+    objs = [os.path.join(build_dir, src.replace(".hip", ".o")) for src in SOURCES]
+    cmds = [[HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj] for src, obj in zip(SOURCES, objs)]
+    if verbose:
+        for cmd in cmds:
             print(" ".join(cmd), flush=True)
-        _run(cmd)
-        objs.append(obj)
+    # one hipcc per source, at most 16 at a time (the sources are independent)
+    jobs = max(1, min(len(cmds), os.cpu_count() or 1, 16))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as pool:
+        for f in [pool.submit(_run, cmd) for cmd in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp, *objs]
     _run(cmd)

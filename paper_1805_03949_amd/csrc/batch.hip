@@ -2,7 +2,7 @@
 //
 // The paper distributes the element loop over threads with a dynamic
 // schedule and a chunk size (Section 3.2, Algorithms 4 and 5; chunk study
-// in Section 5.1) and over ranks with weighted partitions (Section 4.1).
+// in Section 5.2) and over ranks with weighted partitions (Section 4.1).
 // Here the chunks are work items -- `count` consecutive elements of one
 // family of one mesh -- handed out by a device queue (an atomic head over an
 // order array) to persistent workgroups. Each workgroup records the shader

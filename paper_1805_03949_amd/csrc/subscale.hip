@@ -1,4 +1,4 @@
-// Element-wise subgrid scale (Section 2.1.2): the subscale comes from an
+// Element-wise subgrid scale (Section 2.1.3): the subscale comes from an
 // equation posed element by element -- the strong residual at the Gauss
 // points times a diagonal stabilisation matrix -- evaluated in a plain loop
 // over the elements with no system formed and nothing scattered. Read for

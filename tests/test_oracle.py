@@ -479,6 +479,126 @@ def test_term_sums_bound_values():
     np.testing.assert_allclose(tvp[diag], vp[diag], rtol=1e-14)
 
 
+def _lame(young, nu):
+    return young * nu / ((1 + nu) * (1 - 2 * nu)), young / (2 * (1 + nu))
+
+
+def _tet_term_closed_form(G, V, lam, mu, c, s):
+    """|term| sums of a one-point tet4 element with gradient rows G (barycentric,
+    from a linear solve) and volume V, for the tangent lam_eff |G_ai G_bj| +
+    |c| |G_aj G_bi| + mu d_ij sum_k |G_ak G_bk|, where the deformation
+    F = s I scales every pushed gradient by 1/s (s = 1, c = mu: linear)."""
+    A = np.abs(G)
+    T = np.zeros((12, 12))
+    for a in range(4):
+        for b in range(4):
+            dot = (A[a] * A[b]).sum()
+            for i in range(3):
+                for j in range(3):
+                    T[3 * a + i, 3 * b + j] = V * (lam * A[a, i] * A[b, j] / s ** 2
+                                                   + abs(c) * A[a, j] * A[b, i] / s ** 2
+                                                   + (mu * dot if i == j else 0.0))
+    return T
+
+
+def test_term_sums_tet4_closed_form_from_above():
+    """T pinned from above on a perturbed tet4 (one Gauss point, weight 1/6,
+    det J = 6V): Poisson V sum_k |G_ak G_bk|, elasticity V (lam |G_ai G_bj| +
+    mu |G_aj G_bi| + d_ij mu sum_k |G_ak G_bk|), right-hand side V/4 |f_i|.
+    A T too large by any factor fails here, not only one too small."""
+    rng = np.random.default_rng(41)
+    young, nu = 1.3, 0.31
+    lam, mu = _lame(young, nu)
+    for _ in range(4):
+        X = REF_NODES[TET4] + rng.uniform(-0.2, 0.2, (4, 3))
+        G, V = _barycentric_gradients(X)
+        _, _, Tp, Tfp = oracle.element(TET4, X, model=oracle.POISSON, with_terms=True)
+        np.testing.assert_allclose(Tp, V * np.abs(G) @ np.abs(G).T, rtol=1e-13)
+        np.testing.assert_allclose(Tfp, np.full(4, V / 4), rtol=1e-13)
+        f = np.array([0.3, -2.0, 0.7])
+        _, _, T, Tf = oracle.element(TET4, X, young=young, nu=nu, f=f, with_terms=True)
+        np.testing.assert_allclose(T, _tet_term_closed_form(G, V, lam, mu, mu, 1.0), rtol=1e-13)
+        np.testing.assert_allclose(Tf.reshape(4, 3), np.tile(V / 4 * np.abs(f), (4, 1)), rtol=1e-13)
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.1, -0.12, 0.35])
+def test_term_sums_neo_hookean_tet4_dilation(eps):
+    """Neo-Hookean T, its three tangent parts summed in absolute value, on a
+    tet4 under the uniform dilation u = eps X: F = (1 + eps) I, so
+    F^-1 = I / (1 + eps) and ln det F = 3 ln(1 + eps), and T is the linear
+    closed form with lam and |mu - lam ln J| scaled by (1 + eps)^-2. eps = 0
+    is the identity (T equals the linear T); eps = 0.35 makes
+    mu - lam ln J negative, which only its absolute value survives."""
+    rng = np.random.default_rng(42)
+    young, nu = 1.0, 0.3
+    lam, mu = _lame(young, nu)
+    X = REF_NODES[TET4] + rng.uniform(-0.15, 0.15, (4, 3))
+    G, V = _barycentric_gradients(X)
+    s = 1.0 + eps
+    c = mu - lam * 3 * np.log(s)
+    if eps == 0.35:
+        assert c < 0
+    _, _, T, _ = oracle.element(TET4, X, young=young, nu=nu, nh=True, u=eps * X, with_terms=True)
+    np.testing.assert_allclose(T, _tet_term_closed_form(G, V, lam, mu, c, s), rtol=1e-12)
+    if eps == 0.0:
+        _, _, Tl, _ = oracle.element(TET4, X, young=young, nu=nu, with_terms=True)
+        np.testing.assert_allclose(T, Tl, rtol=1e-14)
+
+
+@pytest.mark.parametrize("t", [PYR5, PEN6, HEX8])
+def test_term_sums_neo_hookean_equal_linear_at_rest(t):
+    """At u = 0 every neo-Hookean tangent part reduces to its linear
+    counterpart (F = I, ln det F = 0), so the two T agree for every family."""
+    rng = np.random.default_rng(50 + t)
+    X = REF_NODES[t] * 0.2 + rng.uniform(-0.02, 0.02, REF_NODES[t].shape)
+    _, _, Tl, _ = oracle.element(t, X, young=1.0, nu=0.3, with_terms=True)
+    _, _, Tn, _ = oracle.element(t, X, young=1.0, nu=0.3, nh=True, u=np.zeros_like(X), with_terms=True)
+    np.testing.assert_allclose(Tn, Tl, rtol=1e-13)
+
+
+def test_term_sums_hex8_box_closed_form():
+    """Eight Gauss points: on an axis-aligned box every product term
+    dN_a/dx_i dN_b/dx_j keeps one sign inside the element, so its sum of
+    absolute values over the exact rule is the absolute value of its
+    integral, a product of 1D stiffness, mass and coupling matrices:
+    T = lam |I_ij| + mu |I_ji| + d_ij mu sum_k |I_kk| (Poisson: sum_k |I_kk|)."""
+    hx, hy, hz = 0.6, 1.1, 0.45
+    young, nu = 1.7, 0.29
+    lam, mu = _lame(young, nu)
+    X = _box_hex(hx, hy, hz)
+    bits = ((REF_NODES[HEX8] + 1) / 2).astype(int)
+    h = (hx, hy, hz)
+
+    def integ(a, b, i, j):
+        v = 1.0
+        for d in range(3):
+            A, B = bits[a, d], bits[b, d]
+            if d == i and d == j:
+                v *= _k1(h[d])[A, B]
+            elif d == i:
+                v *= C1D[A, B]
+            elif d == j:
+                v *= C1D[B, A]
+            else:
+                v *= _m1(h[d])[A, B]
+        return v
+
+    Tx = np.zeros((24, 24))
+    Tpx = np.zeros((8, 8))
+    for a in range(8):
+        for b in range(8):
+            adot = sum(abs(integ(a, b, k, k)) for k in range(3))
+            Tpx[a, b] = adot
+            for i in range(3):
+                for j in range(3):
+                    Tx[3 * a + i, 3 * b + j] = (lam * abs(integ(a, b, i, j)) + mu * abs(integ(a, b, j, i))
+                                                + (mu * adot if i == j else 0.0))
+    _, _, T, _ = oracle.element(HEX8, X, young=young, nu=nu, with_terms=True)
+    np.testing.assert_allclose(T, Tx, rtol=1e-13, atol=1e-15)
+    _, _, Tp, _ = oracle.element(HEX8, X, model=oracle.POISSON, with_terms=True)
+    np.testing.assert_allclose(Tp, Tpx, rtol=1e-13, atol=1e-15)
+
+
 # ---------------------------------------------------------------- paper fixture
 
 def test_table2_load_balance_golden():
@@ -545,7 +665,7 @@ def test_residual_internal_forces_sum_to_zero():
 
 
 # ---------------------------------------------------------------- subgrid scale
-# The element-wise subgrid scale (Section 2.1.2), read for Poisson and linear
+# The element-wise subgrid scale (Section 2.1.3), read for Poisson and linear
 # elasticity: tau_e (f + L(u_h)) at every Gauss point, tau_e = V_e^(2/3)/(4k).
 
 # physical volume of the element whose nodes sit at REF_NODES[t]
