@@ -66,9 +66,11 @@ enum fea_precision { FEA_FP64 = 0, FEA_MIXED = 1 };
  *             n(n+1)/2 blocks a <= b and stores each one, or its transpose,
  *             as the contribution to an upper block (i <= j); a lower block
  *             (j, i) is written as the transpose of the ordered sum of block
- *             (i, j). About 40% less element work and workspace traffic;
- *             deterministic, and A is exactly symmetric. Single-mesh
- *             assembly only;
+ *             (i, j), and each element's diagonal blocks are made
+ *             symmetric by copying their upper entries before they are
+ *             summed. About 40% less element work and workspace traffic;
+ *             deterministic, and A equals its transpose bitwise. Also
+ *             runs batched (fea_batch_assemble);
  *   TILECOLOUR the GPU counterpart of commutative multidependences
  *             (Algorithm 7): the ROWSYM element tiles, greedily coloured so
  *             that no two tiles of a colour share a node (built by the

@@ -288,7 +288,12 @@ struct ElemSmem {
     static constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM || VAR == V_TILECOL;
 
     static constexpr bool SYM = VAR == V_ROWSYM || VAR == V_TILECOL;  // tile sums
+    static constexpr bool TCOL = VAR == V_TILECOL;
     static_assert(!SYM || EPB == sym_epb(T), "tile size of the upper-triangle layout");
+    // a tile holds one entry per lane (the graph rejects an element that
+    // repeats a node, and the layout builder checks the count), and so at
+    // most as many tile-blocks
+    static constexpr int MAXENT = EPB * PW;
     double sX[EPB][NN][3];
     double sU[EU][NN][3];
     static constexpr int NC = NHK ? 4 : 1;
@@ -296,8 +301,8 @@ struct ElemSmem {
     double sLM[ELAS ? EPB : 1][2];  // lam, mu of every element (elasticity)
     int32_t sE[EPB];
     int sNH[EPB];
-    int64_t sM[EPB];         // first slot of each element
-    int64_t sCP[EPB];        // first conn position of each element
+    int64_t sM[RO ? 1 : EPB];   // first slot of each element
+    int64_t sCP[RO ? 1 : EPB];  // first conn position of each element
     // Row-owner stores staged in LDS so that BB consecutive threads write one
     // block's BB contiguous values. Measured per family on MI355X: a gain
     // everywhere except FP64 pyramids of the neo-Hookean kernel, where the
@@ -305,9 +310,7 @@ struct ElemSmem {
     // always stages (its tile sums read the staged blocks).
     static constexpr bool STAGE = RO && (SYM || sizeof(CT) == 4 || T != 1 || !NHK);
     // physical gradients sG[EPB][NQ][NN][3], neo-Hookean gradients pushed
-    // through F^-T sH[EU][NQ][NN][3], staged blocks sK[EPB * PW * BB]; in the
-    // upper-triangle form the blocks overwrite the gradients once every lane
-    // has read them
+    // through F^-T sH[EU][NQ][NN][3], staged blocks sK[EPB * PW * BB].
     // Per-element gradient records are padded by one value where their size
     // is a multiple of the 64 LDS banks (hex8: 192 values): the lanes of a
     // wave span two elements, whose same-position reads would otherwise
@@ -315,139 +318,61 @@ struct ElemSmem {
     using GradRec = GradRecT<CT, NQ, NN, (NQ * NN * 3 * (int)sizeof(CT) / 4) % 64 == 0>;
     static constexpr int NG = EPB * (int)(sizeof(GradRec) / sizeof(CT)), NHG = EU * (int)(sizeof(GradRec) / sizeof(CT)),
                          NK = STAGE ? EPB * PW * BB : 1;
-    static constexpr int NBUF = SYM ? (NG + NHG > NK ? NG + NHG : NK) : NG + NHG + NK;
+    // Upper-triangle form: the staged blocks overwrite the gradients (one
+    // barrier more, after every lane has read them) where the gradient
+    // records are large enough for the shared space to decide occupancy;
+    // tet4's are small, and its blocks get a space of their own.
+    static constexpr bool ALIAS = SYM && (NG + NHG) * (int)sizeof(CT) > 4096;
+    static constexpr int NBUF = ALIAS ? (NG + NHG > NK ? NG + NHG : NK) : NG + NHG + NK;
+    static constexpr int KOFF = ALIAS ? 0 : NG + NHG;  // where sK starts in buf
     CT buf[NBUF];
     int32_t sD[STAGE && !SYM ? EPB * PW : 1];
-    uint16_t sEnt[SYM ? 2 * EPB * PW : 1];   // the tile's entries
-    uint16_t sEend[SYM ? 2 * EPB * PW : 1];  // and tile-block ends
+    uint16_t sEnt[SYM ? MAXENT : 1];   // the tile's entries
+    uint16_t sEend[SYM ? MAXENT : 1];  // and tile-block ends
+    int32_t sSlot[SYM ? MAXENT : 1];   // workspace slot (tile-coloured: block) of every tile-block
+    int32_t sLp[TCOL ? MAXENT : 1];    // tile-coloured: lower partner of every tile-block's block
+    double sSrc[SYM ? EPB : 1][B];     // source of every element
     double sDN[NQ][NN][3];   // reference gradients of this family
     double sNr[NQ][NN];      // reference shape functions
-
 };
 
-// Processes the EPB elements A.elems[first .. first + EPB) (ids beyond A.n
-// are skipped) with the calling workgroup's 256 threads and LDS S.
+// Reference shape functions and gradients of family T into LDS.
 template <int T, int MODEL, int VAR, typename CT>
-__device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, VAR, CT> &S,
-                          const int tid = threadIdx.x)
+__device__ inline void elem_ref_tables(ElemSmem<T, MODEL, VAR, CT> &S, const int tid)
 {
-    constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
-    constexpr int PW = ElemSmem<T, MODEL, VAR, CT>::PW;
-    constexpr int EPB = ElemSmem<T, MODEL, VAR, CT>::EPB;
-    constexpr bool ELAS = MODEL != FEA_POISSON;
-    constexpr bool NHK = MODEL == M_ELASTIC_NH || MODEL == M_ELASTIC_RES;
-    constexpr bool RES = MODEL == M_ELASTIC_RES && sizeof(CT) == 8;
-    constexpr int B = ELAS ? 3 : 1;
-    constexpr int BB = B * B;
-    constexpr int EU = NHK ? EPB : 1;
-    constexpr bool RO = VAR == V_ROWOWNER || VAR == V_ROWSYM || VAR == V_TILECOL;
-    constexpr bool SYM = VAR == V_ROWSYM || VAR == V_TILECOL;  // tile sums
-    constexpr bool TCOL = VAR == V_TILECOL;
+    constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ;
+    for (int i = tid; i < NQ * NN; i += 256) {
+        const int q = i / NN, a = i % NN;
+        S.sNr[q][a] = c_ref.N[T][q][a];
+        S.sDN[q][a][0] = c_ref.dN[T][q][a][0];
+        S.sDN[q][a][1] = c_ref.dN[T][q][a][1];
+        S.sDN[q][a][2] = c_ref.dN[T][q][a][2];
+    }
+}
 
+// Lame parameters of element e into LDS (elasticity).
+__device__ inline void elem_lame(const ElemArgs &A, int32_t e, double lm[2])
+{
+    const double E = (e >= 0 && A.young) ? A.young[e] : 1.0, nu = e >= 0 ? A.nu[e] : 0.25;
+    lm[0] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    lm[1] = E / (2.0 * (1.0 + nu));
+}
+
+// Geometry: one thread per (element, Gauss point), in FP64. Reads sX, sU,
+// sE, sNH, sLM and the reference tables; writes the physical gradients (and
+// the neo-Hookean pushed gradients) and the Gauss-point coefficients.
+template <int T, int MODEL, int VAR, typename CT>
+__device__ inline void elem_geometry(const ElemArgs &A, ElemSmem<T, MODEL, VAR, CT> &S, const int tid)
+{
     using Smem = ElemSmem<T, MODEL, VAR, CT>;
-    auto &sX = S.sX;
-    auto &sU = S.sU;
+    constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, EPB = Smem::EPB;
+    constexpr bool NHK = Smem::NHK;
     using GradRec = typename Smem::GradRec;
     GradRec *sG = reinterpret_cast<GradRec *>(S.buf);
     GradRec *sH = reinterpret_cast<GradRec *>(S.buf + Smem::NG);
-    CT *sK = S.buf + (SYM ? 0 : Smem::NG + Smem::NHG);
-    auto &sC = S.sC;
-    auto &sLM = S.sLM;
-    auto &sE = S.sE;
-    auto &sNH = S.sNH;
-    auto &sM = S.sM;
-    auto &sCP = S.sCP;
-    auto &sD = S.sD;
-    constexpr bool STAGE = ElemSmem<T, MODEL, VAR, CT>::STAGE;
-    auto &sDN = S.sDN;
-    auto &sNr = S.sNr;
-    __syncthreads();  // the previous tile's readers of S are done
-    // upper-triangle form: slot (tile-coloured form: block) of the first
-    // tile-sum item of this thread
-    constexpr int KPRE = 1;  // deeper prefetch measured slower (registers)
-    int32_t spre[KPRE];
-#pragma unroll
-    for (int k = 0; k < KPRE; ++k) spre[k] = 0;
-
-    for (int i = tid; i < NQ * NN; i += 256) {
-        const int q = i / NN, a = i % NN;
-        sNr[q][a] = c_ref.N[T][q][a];
-        sDN[q][a][0] = c_ref.dN[T][q][a][0];
-        sDN[q][a][1] = c_ref.dN[T][q][a][1];
-        sDN[q][a][2] = c_ref.dN[T][q][a][2];
-    }
-
-    // element data (threads below EPB) and, for the row-owner layout, node
-    // data (the next EPB*NN threads) are fetched in the same phase
-    if (tid < EPB) {
-        int64_t i = first + tid;
-        int32_t e = i < A.n ? A.elems[i] : -1;
-        sE[tid] = e;
-        if constexpr (!RO) {
-            sM[tid] = e >= 0 ? A.map_ptr[e] : 0;
-            sCP[tid] = e >= 0 ? A.conn_ptr[e] : 0;
-        }
-        sNH[tid] = (ELAS && e >= 0 && A.nh_flag) ? (int)A.nh_flag[e] : 0;
-        if constexpr (ELAS) {
-            double E = (e >= 0 && A.young) ? A.young[e] : 1.0, nu = e >= 0 ? A.nu[e] : 0.25;
-            sLM[tid][0] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-            sLM[tid][1] = E / (2.0 * (1.0 + nu));
-        }
-    }
-    if constexpr (RO) {
-        if (tid >= EPB && tid < EPB + EPB * NN) {
-            const int k = tid - EPB, el = k / NN, a = k % NN;
-            const int64_t i = first + el;
-            if (i < A.n) {
-                const int32_t v = A.pnodes[i * NN + a];
-                sX[el][a][0] = A.x[v];
-                sX[el][a][1] = A.y[v];
-                sX[el][a][2] = A.z[v];
-                if constexpr (NHK) {
-                    for (int c = 0; c < 3; ++c) sU[el][a][c] = A.u[3 * (int64_t)v + c];
-                }
-            }
-        }
-        if constexpr (SYM) {
-            // the tile's entries and tile-block ends (at most two entries per
-            // lane), and the slots (blocks) of this thread's first tile sums,
-            // fetched with the other loads rather than after the contraction
-            const int64_t tl = first / EPB;
-            const int64_t e0 = A.tent_ptr[tl], d0 = A.ttb_ptr[tl];
-            const int ne = (int)(A.tent_ptr[tl + 1] - e0), nd = (int)(A.ttb_ptr[tl + 1] - d0);
-            for (int i = tid; i < ne; i += 256) S.sEnt[i] = A.tent[e0 + i];
-            for (int i = tid; i < nd; i += 256) S.sEend[i] = A.tb_eend[d0 + i];
-            const int32_t *tbv = TCOL ? A.tb_blk : A.tb_slot;
-#pragma unroll
-            for (int k = 0; k < KPRE; ++k) {
-                const int idx = tid + k * 256;
-                spre[k] = idx < nd * BB ? tbv[d0 + idx / BB] : 0;
-            }
-        }
-        __syncthreads();
-    } else {
-        __syncthreads();
-        if (tid < EPB * NN) {
-            int el = tid / NN, a = tid % NN;
-            int32_t e = sE[el];
-            if (e >= 0) {
-                int32_t v = A.conn[sCP[el] + a];
-                sX[el][a][0] = A.x[v];
-                sX[el][a][1] = A.y[v];
-                sX[el][a][2] = A.z[v];
-                if constexpr (NHK) {
-                    bool nh = sNH[el] != 0 || MODEL == M_ELASTIC_RES;
-                    for (int c = 0; c < 3; ++c) sU[el][a][c] = nh ? A.u[3 * (int64_t)v + c] : 0.0;
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    // geometry: one thread per (element, Gauss point), in FP64
     if (tid < EPB * NQ) {
         int el = tid / NQ, q = tid % NQ;
-        int32_t e = sE[el];
+        int32_t e = S.sE[el];
         if (e >= 0) {
             double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
@@ -455,7 +380,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) J[i][j] += sX[el][a][i] * sDN[q][a][j];
+                    for (int j = 0; j < 3; ++j) J[i][j] += S.sX[el][a][i] * S.sDN[q][a][j];
             double d = det3(J);
             if (!(d > 0.0)) atomicMin(A.status, e);
             double Ji[3][3];
@@ -465,14 +390,14 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
             for (int a = 0; a < NN; ++a)
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    G[a][i] = Ji[0][i] * sDN[q][a][0] + Ji[1][i] * sDN[q][a][1] + Ji[2][i] * sDN[q][a][2];
+                    G[a][i] = Ji[0][i] * S.sDN[q][a][0] + Ji[1][i] * S.sDN[q][a][1] + Ji[2][i] * S.sDN[q][a][2];
                     sG[el].v[q][a][i] = (CT)G[a][i];
                 }
             double wd = c_ref.w[T][q] * d;
-            sC[el][q][0] = (CT)wd;
+            S.sC[el][q][0] = (CT)wd;
             if constexpr (NHK) {
-                if (sNH[el]) {
-                    const double lam = sLM[el][0], mu = sLM[el][1];
+                if (S.sNH[el]) {
+                    const double lam = S.sLM[el][0], mu = S.sLM[el][1];
                     double F[3][3];
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
@@ -480,7 +405,7 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                         for (int j = 0; j < 3; ++j) {
                             double acc = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-                            for (int a = 0; a < NN; ++a) acc += sU[el][a][i] * G[a][j];
+                            for (int a = 0; a < NN; ++a) acc += S.sU[el][a][i] * G[a][j];
                             F[i][j] = acc;
                         }
                     double jf = det3(F);
@@ -493,117 +418,235 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
                         for (int j = 0; j < 3; ++j)
                             sH[el].v[q][a][j] =
                                 (CT)(G[a][0] * Fi[0][j] + G[a][1] * Fi[1][j] + G[a][2] * Fi[2][j]);
-                    sC[el][q][1] = (CT)(wd * lam);
-                    sC[el][q][2] = (CT)(wd * (mu - lam * log(jf)));
-                    sC[el][q][3] = (CT)(wd * mu);
+                    S.sC[el][q][1] = (CT)(wd * lam);
+                    S.sC[el][q][2] = (CT)(wd * (mu - lam * log(jf)));
+                    S.sC[el][q][3] = (CT)(wd * mu);
                 }
             }
         }
     }
+}
+
+// Block (a, b) of element el of the tile, from the gradients in LDS.
+template <int T, int MODEL, int VAR, typename CT>
+__device__ inline void elem_block(const ElemSmem<T, MODEL, VAR, CT> &S, const int el, const int a, const int b,
+                                  CT *K)
+{
+    using Smem = ElemSmem<T, MODEL, VAR, CT>;
+    constexpr int NQ = Fam<T>::NQ;
+    constexpr bool ELAS = Smem::ELAS, NHK = Smem::NHK;
+    using GradRec = typename Smem::GradRec;
+    const GradRec *sG = reinterpret_cast<const GradRec *>(S.buf);
+    const GradRec *sH = reinterpret_cast<const GradRec *>(S.buf + Smem::NG);
+    if constexpr (!ELAS) {
+        CT acc = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            CT dot = sG[el].v[q][a][0] * sG[el].v[q][b][0] + sG[el].v[q][a][1] * sG[el].v[q][b][1] +
+                     sG[el].v[q][a][2] * sG[el].v[q][b][2];
+            acc += S.sC[el][q][0] * dot;
+        }
+        K[0] = acc;
+    } else if (!NHK || !S.sNH[el]) {
+        // linear: K = lam S + mu S^T + mu tr(S) I, S = sum_q wd G_a (x) G_b
+        CT Sm[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Sm[c] = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            CT w = S.sC[el][q][0];
+            CT ga[3] = {w * sG[el].v[q][a][0], w * sG[el].v[q][a][1], w * sG[el].v[q][a][2]};
+            CT gb[3] = {sG[el].v[q][b][0], sG[el].v[q][b][1], sG[el].v[q][b][2]};
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) Sm[i * 3 + j] += ga[i] * gb[j];
+        }
+        const CT lam = (CT)S.sLM[el][0], mu = (CT)S.sLM[el][1];
+        const CT tr = Sm[0] + Sm[4] + Sm[8];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                CT v = lam * Sm[i * 3 + j] + mu * Sm[j * 3 + i];
+                if (i == j) v += mu * tr;
+                K[i * 3 + j] = v;
+            }
+    } else if constexpr (NHK) {
+        // neo-Hookean: K_ij = sum_q c1 h_a,i h_b,j + c2 h_a,j h_b,i + c0 d_ij G_a.G_b
+        CT T1[9], T2[9], dsum = 0;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) T1[c] = T2[c] = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            CT c1 = S.sC[el][q][1], c2 = S.sC[el][q][2], c0 = S.sC[el][q][3];
+            CT ha[3] = {sH[el].v[q][a][0], sH[el].v[q][a][1], sH[el].v[q][a][2]};
+            CT hb[3] = {sH[el].v[q][b][0], sH[el].v[q][b][1], sH[el].v[q][b][2]};
+            CT dot = sG[el].v[q][a][0] * sG[el].v[q][b][0] + sG[el].v[q][a][1] * sG[el].v[q][b][1] +
+                     sG[el].v[q][a][2] * sG[el].v[q][b][2];
+            dsum += c0 * dot;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    CT hh = ha[i] * hb[j];
+                    T1[i * 3 + j] += c1 * hh;
+                    T2[i * 3 + j] += c2 * hh;
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                CT v = T1[i * 3 + j] + T2[j * 3 + i];
+                if (i == j) v += dsum;
+                K[i * 3 + j] = v;
+            }
+    }
+}
+
+// Right-hand side of node a of element el: the body force (src, B values),
+// minus, for the Newton residual, the internal force.
+template <int T, int MODEL, int VAR, typename CT>
+__device__ inline void elem_rhs(const ElemSmem<T, MODEL, VAR, CT> &S, const int el, const int a, const double *src,
+                                CT *f)
+{
+    using Smem = ElemSmem<T, MODEL, VAR, CT>;
+    constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, B = Smem::B;
+    constexpr bool RES = MODEL == M_ELASTIC_RES && sizeof(CT) == 8;
+    using GradRec = typename Smem::GradRec;
+    const GradRec *sG = reinterpret_cast<const GradRec *>(S.buf);
+    const GradRec *sH = reinterpret_cast<const GradRec *>(S.buf + Smem::NG);
+#pragma unroll
+    for (int i = 0; i < B; ++i) f[i] = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        CT wn = S.sC[el][q][0] * (CT)S.sNr[q][a];
+#pragma unroll
+        for (int i = 0; i < B; ++i) f[i] += wn * (CT)src[i];
+    }
+    if constexpr (RES) {
+        // f -= f_int_a = sum_q w detJ P grad N_a. Neo-Hookean:
+        // P grad N_a = mu F grad N_a + (lam ln J - mu) F^-T grad N_a,
+        // with F grad N_a = grad N_a + sum_b u_b (grad N_b . grad N_a)
+        // and h_a = F^-T grad N_a from the tangent's records.
+        // Linear: sigma = lam tr(H) I + mu (H + H^T), H = sum_b u_b (x) grad N_b.
+        const bool nh = S.sNH[el] != 0;
+        const double lam = S.sLM[el][0], mu = S.sLM[el][1];
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) {
+            const double ga[3] = {sG[el].v[q][a][0], sG[el].v[q][a][1], sG[el].v[q][a][2]};
+            double uh[3] = {0.0, 0.0, 0.0};  // sum_b u_b (G_b . G_a)
+            double hu[3] = {0.0, 0.0, 0.0};  // sum_b (u_b . G_a) G_b
+            double trh = 0.0;                // sum_b u_b . G_b
+            // both loops rolled: unrolled, every node's gradient and
+            // displacement is hoisted into registers for the whole kernel
+            // (residual instances at 133-188 VGPRs)
+#pragma unroll 1
+            for (int b = 0; b < NN; ++b) {
+                const double gb[3] = {sG[el].v[q][b][0], sG[el].v[q][b][1], sG[el].v[q][b][2]};
+                const double ub[3] = {S.sU[el][b][0], S.sU[el][b][1], S.sU[el][b][2]};
+                const double gg = gb[0] * ga[0] + gb[1] * ga[1] + gb[2] * ga[2];
+                const double ug = ub[0] * ga[0] + ub[1] * ga[1] + ub[2] * ga[2];
+                trh += ub[0] * gb[0] + ub[1] * gb[1] + ub[2] * gb[2];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    uh[i] += ub[i] * gg;
+                    hu[i] += ug * gb[i];
+                }
+            }
+            if (nh) {
+                const double c0 = S.sC[el][q][3], c2 = S.sC[el][q][2];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) f[i] -= c0 * (ga[i] + uh[i]) - c2 * (double)sH[el].v[q][a][i];
+            } else {
+                const double wd = S.sC[el][q][0];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) f[i] -= wd * (lam * trh * ga[i] + mu * (uh[i] + hu[i]));
+            }
+        }
+    }
+}
+
+// Row-owner, atomic and colour forms: the EPB elements A.elems[first ..
+// first + EPB) (ids beyond A.n are skipped) with the calling workgroup's 256
+// threads and LDS S; one thread per block (a, b) of every element.
+template <int T, int MODEL, int VAR, typename CT>
+__device__ void elem_tile_full(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, VAR, CT> &S, const int tid)
+{
+    using Smem = ElemSmem<T, MODEL, VAR, CT>;
+    constexpr int NN = Fam<T>::NN, P = NN * NN;
+    constexpr int PW = Smem::PW, EPB = Smem::EPB, B = Smem::B, BB = Smem::BB;
+    constexpr bool ELAS = Smem::ELAS, NHK = Smem::NHK, RO = Smem::RO, STAGE = Smem::STAGE;
+    CT *sK = S.buf + Smem::NG + Smem::NHG;
+    __syncthreads();  // the previous tile's readers of S are done
+    elem_ref_tables(S, tid);
+
+    // element data (threads below EPB) and, for the row-owner layout, node
+    // data (the next EPB*NN threads) are fetched in the same phase
+    if (tid < EPB) {
+        int64_t i = first + tid;
+        int32_t e = i < A.n ? A.elems[i] : -1;
+        S.sE[tid] = e;
+        if constexpr (!RO) {
+            S.sM[tid] = e >= 0 ? A.map_ptr[e] : 0;
+            S.sCP[tid] = e >= 0 ? A.conn_ptr[e] : 0;
+        }
+        S.sNH[tid] = (ELAS && e >= 0 && A.nh_flag) ? (int)A.nh_flag[e] : 0;
+        if constexpr (ELAS) elem_lame(A, e, S.sLM[tid]);
+    }
+    if constexpr (RO) {
+        if (tid >= EPB && tid < EPB + EPB * NN) {
+            const int k = tid - EPB, el = k / NN, a = k % NN;
+            const int64_t i = first + el;
+            if (i < A.n) {
+                const int32_t v = A.pnodes[i * NN + a];
+                S.sX[el][a][0] = A.x[v];
+                S.sX[el][a][1] = A.y[v];
+                S.sX[el][a][2] = A.z[v];
+                if constexpr (NHK) {
+                    for (int c = 0; c < 3; ++c) S.sU[el][a][c] = A.u[3 * (int64_t)v + c];
+                }
+            }
+        }
+        __syncthreads();
+    } else {
+        __syncthreads();
+        if (tid < EPB * NN) {
+            int el = tid / NN, a = tid % NN;
+            int32_t e = S.sE[el];
+            if (e >= 0) {
+                int32_t v = A.conn[S.sCP[el] + a];
+                S.sX[el][a][0] = A.x[v];
+                S.sX[el][a][1] = A.y[v];
+                S.sX[el][a][2] = A.z[v];
+                if constexpr (NHK) {
+                    bool nh = S.sNH[el] != 0 || MODEL == M_ELASTIC_RES;
+                    for (int c = 0; c < 3; ++c) S.sU[el][a][c] = nh ? A.u[3 * (int64_t)v + c] : 0.0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    elem_geometry(A, S, tid);
     __syncthreads();
 
-    // element matrix: one thread per (element, block a-b), or per pair a <= b
-    CT Ks[SYM ? BB : 1];  // the upper-triangle form's block, staged after the barrier below
-#pragma unroll
-    for (int c = 0; c < (SYM ? BB : 1); ++c) Ks[c] = 0;
+    // element matrix: one thread per (element, block a-b)
     if (tid < EPB * PW) {
         const int el = tid / PW, w = tid % PW;
-        int a, b;
-        if constexpr (SYM) {
-            // w-th pair of the row-major upper triangle
-            a = 0;
-            int r = w;
-#pragma unroll
-            for (int k = 0; k < NN - 1; ++k) {
-                const bool step = r >= NN - a;
-                r -= step ? NN - a : 0;
-                a += step ? 1 : 0;
-            }
-            b = a + r;
-        } else {
-            a = w / NN;
-            b = w % NN;
-        }
+        const int a = w / NN, b = w % NN;
         const int p = a * NN + b;
-        int32_t e = sE[el];
-        // destination of this block, fetched before the contraction (the
-        // upper-triangle form's destinations are its tile-blocks)
+        int32_t e = S.sE[el];
+        // destination of this block, fetched before the contraction
         const int64_t dest = e < 0 ? -1
-                             : SYM ? 0
                              : RO  ? (int64_t)A.pdest[(first + el) * P + p]
-                                   : (int64_t)A.e2nnz[sM[el] + p];
+                                   : (int64_t)A.e2nnz[S.sM[el] + p];
         if (dest >= 0) {
             CT K[BB];
-            if constexpr (!ELAS) {
-                CT acc = 0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    CT dot = sG[el].v[q][a][0] * sG[el].v[q][b][0] + sG[el].v[q][a][1] * sG[el].v[q][b][1] +
-                             sG[el].v[q][a][2] * sG[el].v[q][b][2];
-                    acc += sC[el][q][0] * dot;
-                }
-                K[0] = acc;
-            } else if (!NHK || !sNH[el]) {
-                // linear: K = lam S + mu S^T + mu tr(S) I, S = sum_q wd G_a (x) G_b
-                CT S[9];
-#pragma unroll
-                for (int c = 0; c < 9; ++c) S[c] = 0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    CT w = sC[el][q][0];
-                    CT ga[3] = {w * sG[el].v[q][a][0], w * sG[el].v[q][a][1], w * sG[el].v[q][a][2]};
-                    CT gb[3] = {sG[el].v[q][b][0], sG[el].v[q][b][1], sG[el].v[q][b][2]};
-#pragma unroll
-                    for (int i = 0; i < 3; ++i)
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) S[i * 3 + j] += ga[i] * gb[j];
-                }
-                const CT lam = (CT)sLM[el][0], mu = (CT)sLM[el][1];
-                const CT tr = S[0] + S[4] + S[8];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        CT v = lam * S[i * 3 + j] + mu * S[j * 3 + i];
-                        if (i == j) v += mu * tr;
-                        K[i * 3 + j] = v;
-                    }
-            } else if constexpr (NHK) {
-                // neo-Hookean: K_ij = sum_q c1 h_a,i h_b,j + c2 h_a,j h_b,i + c0 d_ij G_a.G_b
-                CT T1[9], T2[9], dsum = 0;
-#pragma unroll
-                for (int c = 0; c < 9; ++c) T1[c] = T2[c] = 0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    CT c1 = sC[el][q][1], c2 = sC[el][q][2], c0 = sC[el][q][3];
-                    CT ha[3] = {sH[el].v[q][a][0], sH[el].v[q][a][1], sH[el].v[q][a][2]};
-                    CT hb[3] = {sH[el].v[q][b][0], sH[el].v[q][b][1], sH[el].v[q][b][2]};
-                    CT dot = sG[el].v[q][a][0] * sG[el].v[q][b][0] + sG[el].v[q][a][1] * sG[el].v[q][b][1] +
-                             sG[el].v[q][a][2] * sG[el].v[q][b][2];
-                    dsum += c0 * dot;
-#pragma unroll
-                    for (int i = 0; i < 3; ++i)
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) {
-                            CT hh = ha[i] * hb[j];
-                            T1[i * 3 + j] += c1 * hh;
-                            T2[i * 3 + j] += c2 * hh;
-                        }
-                }
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        CT v = T1[i * 3 + j] + T2[j * 3 + i];
-                        if (i == j) v += dsum;
-                        K[i * 3 + j] = v;
-                    }
-            }
-            if constexpr (SYM) {
-#pragma unroll
-                for (int c = 0; c < BB; ++c) Ks[c] = K[c];
-            } else if constexpr (STAGE) {
-                sD[el * P + p] = (int32_t)dest;
+            elem_block(S, el, a, b, K);
+            if constexpr (STAGE) {
+                S.sD[el * P + p] = (int32_t)dest;
 #pragma unroll
                 for (int c = 0; c < BB; ++c) sK[(el * P + p) * BB + c] = K[c];
             } else if constexpr (RO) {
@@ -627,67 +670,19 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
     // right-hand side: one thread per (element, node)
     if (tid < EPB * NN) {
         int el = tid / NN, a = tid % NN;
-        int32_t e = sE[el];
+        int32_t e = S.sE[el];
         if (e >= 0) {
+            double src[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) src[i] = A.source[(int64_t)e * B + i];
             CT f[B];
-#pragma unroll
-            for (int i = 0; i < B; ++i) f[i] = 0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                CT wn = sC[el][q][0] * (CT)sNr[q][a];
-#pragma unroll
-                for (int i = 0; i < B; ++i) f[i] += wn * (CT)A.source[(int64_t)e * B + i];
-            }
-            if constexpr (RES) {
-                {
-                    // f -= f_int_a = sum_q w detJ P grad N_a. Neo-Hookean:
-                    // P grad N_a = mu F grad N_a + (lam ln J - mu) F^-T grad N_a,
-                    // with F grad N_a = grad N_a + sum_b u_b (grad N_b . grad N_a)
-                    // and h_a = F^-T grad N_a from the tangent's records.
-                    // Linear: sigma = lam tr(H) I + mu (H + H^T), H = sum_b u_b (x) grad N_b.
-                    const bool nh = sNH[el] != 0;
-                    const double lam = sLM[el][0], mu = sLM[el][1];
-#pragma unroll 1
-                    for (int q = 0; q < NQ; ++q) {
-                        const double ga[3] = {sG[el].v[q][a][0], sG[el].v[q][a][1], sG[el].v[q][a][2]};
-                        double uh[3] = {0.0, 0.0, 0.0};  // sum_b u_b (G_b . G_a)
-                        double hu[3] = {0.0, 0.0, 0.0};  // sum_b (u_b . G_a) G_b
-                        double trh = 0.0;                // sum_b u_b . G_b
-                        // both loops rolled: unrolled, every node's gradient
-                        // and displacement is hoisted into registers for the
-                        // whole kernel (residual instances at 133-188 VGPRs)
-#pragma unroll 1
-                        for (int b = 0; b < NN; ++b) {
-                            const double gb[3] = {sG[el].v[q][b][0], sG[el].v[q][b][1], sG[el].v[q][b][2]};
-                            const double ub[3] = {sU[el][b][0], sU[el][b][1], sU[el][b][2]};
-                            const double gg = gb[0] * ga[0] + gb[1] * ga[1] + gb[2] * ga[2];
-                            const double ug = ub[0] * ga[0] + ub[1] * ga[1] + ub[2] * ga[2];
-                            trh += ub[0] * gb[0] + ub[1] * gb[1] + ub[2] * gb[2];
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) {
-                                uh[i] += ub[i] * gg;
-                                hu[i] += ug * gb[i];
-                            }
-                        }
-                        if (nh) {
-                            const double c0 = sC[el][q][3], c2 = sC[el][q][2];
-#pragma unroll
-                            for (int i = 0; i < 3; ++i)
-                                f[i] -= c0 * (ga[i] + uh[i]) - c2 * (double)sH[el].v[q][a][i];
-                        } else {
-                            const double wd = sC[el][q][0];
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) f[i] -= wd * (lam * trh * ga[i] + mu * (uh[i] + hu[i]));
-                        }
-                    }
-                }
-            }
+            elem_rhs(S, el, a, src, f);
             if constexpr (RO) {
                 CT *dst = (CT *)A.rcontrib + (int64_t)A.prdest[(first + el) * NN + a] * B;
 #pragma unroll
                 for (int i = 0; i < B; ++i) dst[i] = f[i];
             } else {
-                int64_t v = A.conn[sCP[el] + a];
+                int64_t v = A.conn[S.sCP[el] + a];
                 double *dst = A.rhs + v * B;
 #pragma unroll
                 for (int i = 0; i < B; ++i) {
@@ -700,53 +695,161 @@ __device__ void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, V
         }
     }
 
+    if constexpr (STAGE) {
+        __syncthreads();
+        CT *out = (CT *)A.contrib;
+        for (int idx = tid; idx < EPB * PW * BB; idx += 256) {
+            const int blk = idx / BB;
+            if (first + blk / PW < A.n) out[(int64_t)S.sD[blk] * BB + (idx - blk * BB)] = sK[idx];
+        }
+    }
+}
 
-    if constexpr (SYM) {
+// Upper-triangle form (V_ROWSYM) and its tile-coloured variant (V_TILECOL):
+// tile first / EPB, one thread per local pair a <= b of every element.
+// Every global load of the tile -- node ids, coordinates, right-hand-side
+// destinations, element data and source, the tile's entries, tile-block
+// ends and slots (tile-coloured: blocks and their lower partners) -- is
+// issued in the first phase, so that a tile waits for two dependent load
+// latencies (range -> entries, node id -> coordinates) before its
+// arithmetic, and none after it.
+template <int T, int MODEL, int VAR, typename CT>
+__device__ void elem_tile_sym(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, VAR, CT> &S, const int tid)
+{
+    using Smem = ElemSmem<T, MODEL, VAR, CT>;
+    constexpr int NN = Fam<T>::NN;
+    constexpr int PW = Smem::PW, EPB = Smem::EPB, B = Smem::B, BB = Smem::BB;
+    constexpr bool ELAS = Smem::ELAS, NHK = Smem::NHK, TCOL = Smem::TCOL, ALIAS = Smem::ALIAS;
+    CT *sK = S.buf + Smem::KOFF;
+    __syncthreads();  // the previous tile's readers of S are done
+    elem_ref_tables(S, tid);
+    const int64_t tl = first / EPB;
+    const int64_t e0 = A.tent_ptr[tl], d0 = A.ttb_ptr[tl];
+    const int ne = (int)(A.tent_ptr[tl + 1] - e0), nd = (int)(A.ttb_ptr[tl + 1] - d0);
+    int32_t rdest = 0;  // right-hand-side destination of (element, node) tid
+    if (tid < EPB * NN) {
+        const int el = tid / NN, a = tid % NN;
+        const int64_t i = first + el;
+        if (i < A.n) {
+            const int32_t v = A.pnodes[i * NN + a];
+            rdest = A.prdest[i * NN + a];
+            S.sX[el][a][0] = A.x[v];
+            S.sX[el][a][1] = A.y[v];
+            S.sX[el][a][2] = A.z[v];
+            if constexpr (NHK) {
+                for (int c = 0; c < 3; ++c) S.sU[el][a][c] = A.u[3 * (int64_t)v + c];
+            }
+        }
+    } else if (tid < EPB * NN + EPB) {
+        const int el = tid - EPB * NN;
+        const int64_t i = first + el;
+        const int32_t e = i < A.n ? A.elems[i] : -1;
+        S.sE[el] = e;
+        S.sNH[el] = (ELAS && e >= 0 && A.nh_flag) ? (int)A.nh_flag[e] : 0;
+        if constexpr (ELAS) elem_lame(A, e, S.sLM[el]);
+#pragma unroll
+        for (int c = 0; c < B; ++c) S.sSrc[el][c] = e >= 0 ? A.source[(int64_t)e * B + c] : 0.0;
+    }
+    for (int i = tid; i < ne; i += 256) S.sEnt[i] = A.tent[e0 + i];
+    for (int i = tid; i < nd; i += 256) {
+        S.sEend[i] = A.tb_eend[d0 + i];
+        if constexpr (TCOL) {
+            const int32_t k = A.tb_blk[d0 + i];
+            S.sSlot[i] = k;
+            S.sLp[i] = A.lpart[k];
+        } else {
+            S.sSlot[i] = A.tb_slot[d0 + i];
+        }
+    }
+    __syncthreads();
+
+    elem_geometry(A, S, tid);
+    __syncthreads();
+
+    // blocks: one thread per (element, pair a <= b); right-hand side: one
+    // thread per (element, node)
+    CT Ks[BB];
+#pragma unroll
+    for (int c = 0; c < BB; ++c) Ks[c] = 0;
+    if (tid < EPB * PW) {
+        const int el = tid / PW, w = tid % PW;
+        // w-th pair of the row-major upper triangle
+        int a = 0, r = w;
+#pragma unroll
+        for (int k = 0; k < NN - 1; ++k) {
+            const bool step = r >= NN - a;
+            r -= step ? NN - a : 0;
+            a += step ? 1 : 0;
+        }
+        const int b = a + r;
+        if (S.sE[el] >= 0) {
+            elem_block(S, el, a, b, Ks);
+            if (a == b) {
+                // a diagonal block is symmetric; copying its upper entries
+                // makes it so bitwise (the products G_i (w G_j) and
+                // G_j (w G_i) round differently), and with it A
+#pragma unroll
+                for (int i = 0; i < B; ++i)
+#pragma unroll
+                    for (int j = i + 1; j < B; ++j) Ks[j * B + i] = Ks[i * B + j];
+            }
+        }
+        if constexpr (!ALIAS) {
+#pragma unroll
+            for (int c = 0; c < BB; ++c) sK[tid * BB + c] = Ks[c];
+        }
+    }
+    if (tid < EPB * NN) {
+        const int el = tid / NN, a = tid % NN;
+        if (S.sE[el] >= 0) {
+            CT f[B];
+            elem_rhs(S, el, a, S.sSrc[el], f);
+            CT *dst = (CT *)A.rcontrib + (int64_t)rdest * B;
+#pragma unroll
+            for (int i = 0; i < B; ++i) dst[i] = f[i];
+        }
+    }
+    if constexpr (ALIAS) {
         __syncthreads();  // every lane has read the gradients that sK overwrites
         if (tid < EPB * PW) {
 #pragma unroll
             for (int c = 0; c < BB; ++c) sK[tid * BB + c] = Ks[c];
         }
-        __syncthreads();
-        // tile sums: one thread per (tile-block, component), the block's
-        // entries added in ascending lane (element) order, in FP64
-        const int64_t tl = first / EPB;
-        const int64_t d0 = A.ttb_ptr[tl];
-        const int nd = (int)(A.ttb_ptr[tl + 1] - d0);
-        CT *out = (CT *)A.contrib;
-        const int32_t *tbv = TCOL ? A.tb_blk : A.tb_slot;
-        auto tile_sum = [&](int idx, int64_t v) {
-            const int d = idx / BB, c = idx - d * BB, ct = (c % B) * B + c / B;
-            double acc = 0.0;
-            for (int q = d ? S.sEend[d - 1] : 0; q < S.sEend[d]; ++q) {
-                const int u = S.sEnt[q];
-                acc += (double)sK[(u >> 1) * BB + ((u & 1) ? ct : c)];
-            }
-            if constexpr (TCOL) {
-                // v is the block; no other tile of this colour touches it or
-                // its partner
-                const int64_t l = A.lpart[v];
-                A.vals[v * BB + c] += acc;
-                if (l >= 0) A.vals[l * BB + ct] += acc;
-            } else {
-                out[v * BB + c] = (CT)acc;
-            }
-        };
-#pragma unroll
-        for (int k = 0; k < KPRE; ++k) {
-            const int idx = tid + k * 256;
-            if (idx < nd * BB) tile_sum(idx, spre[k]);
+    }
+    __syncthreads();
+
+    // tile sums: one thread per (tile-block, component), the block's entries
+    // added in ascending lane (element) order, in FP64
+    CT *out = (CT *)A.contrib;
+    for (int idx = tid; idx < nd * BB; idx += 256) {
+        const int d = idx / BB, c = idx - d * BB, ct = (c % B) * B + c / B;
+        double acc = 0.0;
+        for (int q = d ? S.sEend[d - 1] : 0; q < S.sEend[d]; ++q) {
+            const int u = S.sEnt[q];
+            acc += (double)sK[(u >> 1) * BB + ((u & 1) ? ct : c)];
         }
-        for (int idx = tid + KPRE * 256; idx < nd * BB; idx += 256) tile_sum(idx, tbv[d0 + idx / BB]);
-    } else if constexpr (STAGE) {
-        __syncthreads();
-        CT *out = (CT *)A.contrib;
-        for (int idx = tid; idx < EPB * PW * BB; idx += 256) {
-            const int blk = idx / BB;
-            if (first + blk / PW < A.n) out[(int64_t)sD[blk] * BB + (idx - blk * BB)] = sK[idx];
+        const int64_t v = S.sSlot[d];
+        if constexpr (TCOL) {
+            // v is the block; no other tile of this colour touches it or
+            // its partner
+            const int64_t l = S.sLp[d];
+            A.vals[v * BB + c] += acc;
+            if (l >= 0) A.vals[l * BB + ct] += acc;
+        } else {
+            out[v * BB + c] = (CT)acc;
         }
     }
 }
 
+// One tile of elements in the form VAR.
+template <int T, int MODEL, int VAR, typename CT>
+__device__ inline void elem_tile(const ElemArgs &A, int64_t first, ElemSmem<T, MODEL, VAR, CT> &S,
+                                 const int tid = threadIdx.x)
+{
+    if constexpr (ElemSmem<T, MODEL, VAR, CT>::SYM)
+        elem_tile_sym(A, first, S, tid);
+    else
+        elem_tile_full(A, first, S, tid);
+}
 
 }  // namespace fea

@@ -481,6 +481,14 @@ int sym_prepare(fea_graph *g, hipStream_t s)
     }
     FEA_HIP(hipStreamSynchronize(s));
     if (ntb > INT32_MAX) return set_error(FEA_ERANGE, "%lld tile-blocks exceed the int32 slot range", (long long)ntb);
+    // one entry per (element, pair a <= b): the element kernels size their
+    // tile buffers by it (an element repeating a node would add entries, and
+    // the graph build rejects such elements)
+    int64_t lanes = 0;
+    for (int t = 0; t < 4; ++t) lanes += (g->seg[t + 1] - g->seg[t]) * (nodes_of(t) * (nodes_of(t) + 1) / 2);
+    if (nent != lanes)
+        return set_error(FEA_EMESH, "upper-triangle layout: %lld entries for %lld element pairs", (long long)nent,
+                         (long long)lanes);
     if ((rc = dalloc((void **)&g->tent, sizeof(uint16_t) * std::max<int64_t>(nent, 1)))) return rc;
     if ((rc = dalloc((void **)&g->tb_eend, sizeof(uint16_t) * std::max<int64_t>(ntb, 1)))) return rc;
     if ((rc = dalloc((void **)&g->tb_blk, sizeof(int32_t) * std::max<int64_t>(ntb, 1)))) return rc;
