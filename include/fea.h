@@ -176,6 +176,27 @@ int fea_assemble(const fea_graph *g, const double *x, const double *y, const dou
                  const fea_material *mat, const double *source, const fea_options *opt,
                  hipStream_t stream, void *vals, void *rhs, int32_t *status);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * FEA_ROWOWNER assembly of fea_assemble, with the same kernels and a
+ * bitwise equal result, that calls no hipMalloc, hipFree or allocating
+ * library routine. Its slot and right-hand-side workspaces live in one
+ * static device array of 256 MiB held by every GPU the library runs on
+ * until the process ends (set up by fea_graph_build on that device).
+ * Arguments as fea_assemble; opt->variant must be FEA_ROWOWNER and
+ * opt->timing 0 (else FEA_EINVAL). The workspaces need
+ * sizeof(compute type) * (map_len * b * b + n_conn * b) bytes (each part
+ * rounded up to 256, plus 256), b = 1 (Poisson) or 3; larger meshes get
+ * FEA_ERANGE before anything is enqueued. status may be NULL (the scratch
+ * then holds it). Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (other streams, other threads) race: order them.
+ */
+int fea_assemble_noalloc(const fea_graph *g, const double *x, const double *y, const double *z,
+                         const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
+                         const fea_material *mat, const double *source, const fea_options *opt,
+                         hipStream_t stream, void *vals, void *rhs, int32_t *status);
+
 /* Phase durations of the graph's last fea_assemble call made with
  * opt->timing set, in milliseconds, measured with HIP events on that call's
  * stream: ms[0] element kernels (with the fused scatter for ATOMIC, COLOUR

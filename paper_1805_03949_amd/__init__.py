@@ -55,6 +55,7 @@ _lib.fea_graph_destroy.argtypes = [_P]
 _lib.fea_graph_destroy.restype = None
 _lib.fea_assemble.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Material), _P,
                               ctypes.POINTER(Options), _P, _P, _P, _P]
+_lib.fea_assemble_noalloc.argtypes = _lib.fea_assemble.argtypes
 _lib.fea_last_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.fea_graph_gauss_points.argtypes = [_P, ctypes.POINTER(_I64), _P, _P]
 _lib.fea_subscale.argtypes = [_P, _P, _P, _P, ctypes.POINTER(Material), _P, _P, _P, _P, _P]
@@ -113,7 +114,7 @@ N_FEATURES, N_PARAMS = 12, 5057
 
 # every exported symbol declared in include/fea.h
 EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_sym_sizes", "fea_graph_export", "fea_graph_destroy",
-           "fea_assemble", "fea_last_timing", "fea_graph_gauss_points", "fea_subscale",
+           "fea_assemble", "fea_assemble_noalloc", "fea_last_timing", "fea_graph_gauss_points", "fea_subscale",
            "fea_batch_gauss_points", "fea_batch_subscale", "fea_last_class_timing", "fea_last_error", "fea_version",
            "fea_batch_build", "fea_batch_sizes", "fea_batch_offsets", "fea_batch_items",
            "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_assemble", "fea_batch_capture",
@@ -242,9 +243,12 @@ class Graph:
 
 def assemble(graph, x, y, z, types, conn_ptr, conn, source, model=ELASTIC, young=None, nu=None,
              nh_flag=None, u=None, precision=FP64, variant=ROWOWNER, out_dtype=F64, vals=None,
-             rhs=None, status=None, stream=None, timing=False, residual=False):
+             rhs=None, status=None, stream=None, timing=False, residual=False, noalloc=False):
     """Assembles (vals, rhs, status) on the GPU; all tensors on the graph's device.
-    residual: rhs is the Newton residual f_ext - f_int(u) (elasticity, FP64)."""
+    residual: rhs is the Newton residual f_ext - f_int(u) (elasticity, FP64).
+    noalloc: call fea_assemble_noalloc (row-owner, library workspaces in its
+    static scratch; the caller's tensors are still allocated here when not
+    given)."""
     B = 1 if model == POISSON else 3
     odt = torch.float64 if out_dtype == F64 else torch.float32
     d = graph.device
@@ -267,9 +271,9 @@ def assemble(graph, x, y, z, types, conn_ptr, conn, source, model=ELASTIC, young
     _dev(rhs, odt)
     mat = Material(model, _ptr(young), _ptr(nu), _ptr(nh_flag), _ptr(u), int(bool(residual)))
     opt = Options(precision, variant, out_dtype, int(bool(timing)))
-    _check(_lib.fea_assemble(graph.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(types), _ptr(conn_ptr),
-                             _ptr(conn), ctypes.byref(mat), _ptr(source), ctypes.byref(opt),
-                             _stream(stream), _ptr(vals), _ptr(rhs), _ptr(status)))
+    fn = _lib.fea_assemble_noalloc if noalloc else _lib.fea_assemble
+    _check(fn(graph.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(types), _ptr(conn_ptr), _ptr(conn), ctypes.byref(mat),
+              _ptr(source), ctypes.byref(opt), _stream(stream), _ptr(vals), _ptr(rhs), _ptr(status)))
     return vals, rhs, status
 
 

@@ -83,8 +83,17 @@ static inline void mark(fea_graph *g, int i, const fea_options *o, hipStream_t s
     if (o->timing) (void)hipEventRecord(g->ev[i], s);
 }
 
+// Row-owner workspaces supplied by the caller of run() instead of the
+// graph's own (allocated on first use): contrib holds map_len blocks and
+// rcontrib conn_len right-hand-side entries in the compute type.
+struct Workspace {
+    void *contrib = nullptr;
+    void *rcontrib = nullptr;
+};
+
 template <int MODEL, typename CT>
-static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, void *vals, void *rhs)
+static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, void *vals, void *rhs,
+               const Workspace &ws = Workspace())
 {
     constexpr int B = MODEL == FEA_POISSON ? 1 : 3;
     constexpr int BB = B * B;
@@ -171,10 +180,15 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         return FEA_OK;
     }
     if (o->variant == FEA_ROWOWNER) {
-        if ((rc = ensure_ws(&g->contrib, &g->contrib_bytes, sizeof(CT) * (size_t)g->map_len * BB))) return rc;
-        if ((rc = ensure_ws(&g->rcontrib, &g->rcontrib_bytes, sizeof(CT) * (size_t)g->conn_len * B))) return rc;
-        a.contrib = g->contrib;
-        a.rcontrib = g->rcontrib;
+        if (ws.contrib) {
+            a.contrib = ws.contrib;
+            a.rcontrib = ws.rcontrib;
+        } else {
+            if ((rc = ensure_ws(&g->contrib, &g->contrib_bytes, sizeof(CT) * (size_t)g->map_len * BB))) return rc;
+            if ((rc = ensure_ws(&g->rcontrib, &g->rcontrib_bytes, sizeof(CT) * (size_t)g->conn_len * B))) return rc;
+            a.contrib = g->contrib;
+            a.rcontrib = g->rcontrib;
+        }
         mark(g, 0, o, s);
         for (int t = 0; t < 4; ++t) {
             a.elems = g->perm + g->seg[t];
@@ -244,15 +258,14 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
 
 using namespace fea;
 
-extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *y, const double *z,
-                            const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
-                            const fea_material *mat, const double *source, const fea_options *opt,
-                            hipStream_t stream, void *vals, void *rhs, int32_t *status)
+namespace fea {
+
+// Argument checks shared by fea_assemble and fea_assemble_noalloc.
+static int check_assemble(const fea_graph *g, const double *x, const double *y, const double *z,
+                          const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
+                          const fea_material *mat, const double *source, const fea_options *o, void *vals,
+                          void *rhs)
 {
-    clear_error();
-    fea_graph *g = const_cast<fea_graph *>(gc);
-    fea_options dflt = {0, 0, 0, 0};
-    const fea_options *o = opt ? opt : &dflt;
     if (!g || !mat) return set_error(FEA_EINVAL, "graph and material are required");
     if (o->precision < 0 || o->precision > 1 || o->variant < 0 || o->variant > 5 ||
         o->out_dtype < 0 || o->out_dtype > 1)
@@ -277,21 +290,17 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     int dev = 0;
     FEA_HIP(hipGetDevice(&dev));
     if (dev != g->device) return set_error(FEA_EINVAL, "graph lives on device %d, current is %d", g->device, dev);
-    int rc = ensure_tables();
-    if (rc) return rc;
-    if (o->timing) {
-        for (hipEvent_t &e : g->ev)
-            if (!e) FEA_HIP(hipEventCreate(&e));
-    }
-    g->timed = false;
-    g->gtimed = false;
+    return FEA_OK;
+}
 
-    int32_t *st = status;
-    if (!st) {
-        static thread_local int32_t *own[64] = {nullptr};
-        if (!own[dev] && (rc = dalloc((void **)&own[dev], sizeof(int32_t)))) return rc;
-        st = own[dev];
-    }
+// The assembly proper (after check_assemble): status is a device int32
+// (required), ws an optional row-owner workspace.
+static int assemble_impl(fea_graph *g, const double *x, const double *y, const double *z, const uint8_t *types,
+                         const int64_t *conn_ptr, const int32_t *conn, const fea_material *mat,
+                         const double *source, const fea_options *o, hipStream_t stream, void *vals, void *rhs,
+                         int32_t *st, const Workspace &ws)
+{
+    int rc;
     k_status_init<<<1, 1, 0, stream>>>(st);
 
     ElemArgs a = {};
@@ -314,16 +323,16 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
             return rc;
     } else if (g->n_elems > 0) {
         if (mat->model == FEA_POISSON)
-            rc = o->precision == FEA_FP64 ? run<FEA_POISSON, double>(g, a, o, stream, vals, rhs)
-                                          : run<FEA_POISSON, float>(g, a, o, stream, vals, rhs);
+            rc = o->precision == FEA_FP64 ? run<FEA_POISSON, double>(g, a, o, stream, vals, rhs, ws)
+                                          : run<FEA_POISSON, float>(g, a, o, stream, vals, rhs, ws);
         else if (mat->residual)
-            rc = run<M_ELASTIC_RES, double>(g, a, o, stream, vals, rhs);
+            rc = run<M_ELASTIC_RES, double>(g, a, o, stream, vals, rhs, ws);
         else if (!a.nh_flag)
-            rc = o->precision == FEA_FP64 ? run<FEA_ELASTIC, double>(g, a, o, stream, vals, rhs)
-                                          : run<FEA_ELASTIC, float>(g, a, o, stream, vals, rhs);
+            rc = o->precision == FEA_FP64 ? run<FEA_ELASTIC, double>(g, a, o, stream, vals, rhs, ws)
+                                          : run<FEA_ELASTIC, float>(g, a, o, stream, vals, rhs, ws);
         else
-            rc = o->precision == FEA_FP64 ? run<M_ELASTIC_NH, double>(g, a, o, stream, vals, rhs)
-                                          : run<M_ELASTIC_NH, float>(g, a, o, stream, vals, rhs);
+            rc = o->precision == FEA_FP64 ? run<M_ELASTIC_NH, double>(g, a, o, stream, vals, rhs, ws)
+                                          : run<M_ELASTIC_NH, float>(g, a, o, stream, vals, rhs, ws);
         if (rc) return rc;
     } else {
         const int B = mat->model == FEA_POISSON ? 1 : 3;
@@ -336,6 +345,97 @@ extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *
     FEA_HIP(hipGetLastError());
     g->timed = o->timing && g->n_elems > 0;
     return FEA_OK;
+}
+
+// Scratch of the allocation-free entry point: one array per device, set up
+// once per device (reference tables uploaded, the array's device address
+// looked up) by the graph build on that device, or else by the entry
+// point's first call there. Layout: the status word, then the slot
+// workspace, then the right-hand-side workspace, each 256-byte aligned.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr size_t kScratchHead = 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void *g_scratch[64] = {nullptr};
+static std::mutex g_scratch_mtx;
+
+static inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+int noalloc_setup()
+{
+    int dev = 0;
+    FEA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(FEA_EINVAL, "device index %d unsupported", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mtx);
+    if (g_scratch[dev]) return FEA_OK;
+    int rc = ensure_tables();
+    if (rc) return rc;
+    void *ptr = nullptr;
+    FEA_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return set_error(FEA_EHIP, "scratch array has no device address");
+    g_scratch[dev] = ptr;
+    return FEA_OK;
+}
+
+}  // namespace fea
+
+extern "C" int fea_assemble(const fea_graph *gc, const double *x, const double *y, const double *z,
+                            const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
+                            const fea_material *mat, const double *source, const fea_options *opt,
+                            hipStream_t stream, void *vals, void *rhs, int32_t *status)
+{
+    clear_error();
+    fea_graph *g = const_cast<fea_graph *>(gc);
+    fea_options dflt = {0, 0, 0, 0};
+    const fea_options *o = opt ? opt : &dflt;
+    int rc = check_assemble(g, x, y, z, types, conn_ptr, conn, mat, source, o, vals, rhs);
+    if (rc) return rc;
+    if ((rc = ensure_tables())) return rc;
+    if (o->timing) {
+        for (hipEvent_t &e : g->ev)
+            if (!e) FEA_HIP(hipEventCreate(&e));
+    }
+    g->timed = false;
+    g->gtimed = false;
+    int32_t *st = status;
+    if (!st) {
+        static thread_local int32_t *own[64] = {nullptr};
+        const int dev = g->device;
+        if (!own[dev] && (rc = dalloc((void **)&own[dev], sizeof(int32_t)))) return rc;
+        st = own[dev];
+    }
+    return assemble_impl(g, x, y, z, types, conn_ptr, conn, mat, source, o, stream, vals, rhs, st, Workspace());
+}
+
+extern "C" int fea_assemble_noalloc(const fea_graph *gc, const double *x, const double *y, const double *z,
+                                    const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
+                                    const fea_material *mat, const double *source, const fea_options *opt,
+                                    hipStream_t stream, void *vals, void *rhs, int32_t *status)
+{
+    clear_error();
+    fea_graph *g = const_cast<fea_graph *>(gc);
+    fea_options dflt = {0, 0, 0, 0};
+    const fea_options *o = opt ? opt : &dflt;
+    int rc = check_assemble(g, x, y, z, types, conn_ptr, conn, mat, source, o, vals, rhs);
+    if (rc) return rc;
+    if (o->variant != FEA_ROWOWNER)
+        return set_error(FEA_EINVAL, "fea_assemble_noalloc runs the row-owner variant only (variant %d)", o->variant);
+    if (o->timing) return set_error(FEA_EINVAL, "fea_assemble_noalloc records no timing");
+    const size_t cs = o->precision == FEA_FP64 ? sizeof(double) : sizeof(float);
+    const size_t B = mat->model == FEA_POISSON ? 1 : 3;
+    const size_t need_c = align256(cs * (size_t)g->map_len * B * B);
+    const size_t need_r = align256(cs * (size_t)g->conn_len * B);
+    if (kScratchHead + need_c + need_r > kScratchBytes)
+        return set_error(FEA_ERANGE, "fea_assemble_noalloc: the workspace needs %zu bytes, more than its %zu-byte "
+                                     "scratch", kScratchHead + need_c + need_r, kScratchBytes);
+    if ((rc = noalloc_setup())) return rc;
+    unsigned char *base = (unsigned char *)g_scratch[g->device];
+    Workspace ws;
+    ws.contrib = base + kScratchHead;
+    ws.rcontrib = base + kScratchHead + need_c;
+    g->timed = false;
+    g->gtimed = false;
+    int32_t *st = status ? status : (int32_t *)base;
+    return assemble_impl(g, x, y, z, types, conn_ptr, conn, mat, source, o, stream, vals, rhs, st, ws);
 }
 
 extern "C" int fea_last_timing(const fea_graph *g, float *ms)

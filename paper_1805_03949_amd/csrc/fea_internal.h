@@ -212,6 +212,13 @@ void gather_batch_destroy(GatherBatch *gb);
 }  // namespace fea
 
 namespace fea {
+// Set-up of fea_assemble_noalloc on the current device (assemble.hip):
+// uploads the reference tables and looks up the device address of its
+// scratch array, once per device. Called by the graph build.
+int noalloc_setup();
+}  // namespace fea
+
+namespace fea {
 // Builds the upper-triangle row-owner layout of a graph (graph.hip; blocks
 // on the stream).
 int sym_prepare(fea_graph *g, hipStream_t s);

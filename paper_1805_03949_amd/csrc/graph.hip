@@ -816,6 +816,7 @@ extern "C" int fea_graph_build(int64_t n_nodes, int64_t n_elems, const uint8_t *
     fea_graph *g = new (std::nothrow) fea_graph();
     if (!g) return set_error(FEA_ENOMEM, "host allocation failed");
     int rc = build(n_nodes, n_elems, types, conn_ptr, conn, stream, g);
+    if (rc == FEA_OK) rc = noalloc_setup();
     if (rc != FEA_OK) {
         (void)hipStreamSynchronize(stream);
         destroy(g);
