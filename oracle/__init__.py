@@ -31,10 +31,11 @@ POISSON, ELASTIC = 0, 1
 
 
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (-O2, no fast-math, no contraction)."""
+    """Compile the C oracle with gcc (-O3, OpenMP for the parallel timing
+    variants, no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O3", "-std=c99", "-fPIC", "-shared", "-fopenmp",
                                "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -63,6 +64,10 @@ def lib():
         L.or_assemble.argtypes = [i64, i64, P, P, P, P, P, P, ctypes.c_int, P, P, P, P, P,
                                   P, P, P, P, P, P, P]
         L.or_assemble.restype = i64
+        L.or_assemble_omp.argtypes = [ctypes.c_int, i64, i64, P, P, P, P, P, P, ctypes.c_int, P, P, P, P, P,
+                                      P, P, P, P, P, ctypes.c_int, P, P]
+        L.or_assemble_omp.restype = i64
+        L.or_threads.restype = ctypes.c_int
         L.or_residual.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P, P, P]
         L.or_residual.restype = i64
         L.or_shape2.argtypes = [ctypes.c_int, P, P]
@@ -208,6 +213,49 @@ def assemble(mesh, g, model=ELASTIC, with_terms=False, use_nh=True):
         raise MeshError(-rc - 1)
     if with_terms:
         return vals, rhs, tv, tr
+    return vals, rhs
+
+
+def threads():
+    """OpenMP threads the parallel variants use (OMP_NUM_THREADS, else all cores)."""
+    return int(lib().or_threads())
+
+
+def colour_buckets(colour, n_colours):
+    """Element ids grouped by colour (ascending within a colour) and the
+    bucket offsets cptr[n_colours + 1]."""
+    celems = np.argsort(colour, kind="stable").astype(np.int32)
+    cptr = np.zeros(n_colours + 1, dtype=np.int64)
+    cptr[1:] = np.cumsum(np.bincount(colour.astype(np.int64), minlength=n_colours))
+    return cptr, celems
+
+
+def assemble_parallel(mesh, g, variant, model=ELASTIC, use_nh=True, buckets=None):
+    """Algorithm 1 with the element loop on OpenMP threads (timing variants):
+    variant "atomic" (Algorithm 4) or "colour" (Algorithm 5; buckets from
+    colour_buckets, computed here when not given). Returns (vals, rhs),
+    equal to assemble()'s up to rounding."""
+    B = 1 if model == POISSON else 3
+    vals = np.zeros(g.nnz * B * B)
+    rhs = np.zeros(mesh.n_nodes * B)
+    src = np.ascontiguousarray(mesh.source[:, :B], dtype=np.float64)
+    nh = np.ascontiguousarray(mesh.nh_flag, dtype=np.uint8) if use_nh else None
+    if variant == "colour":
+        if buckets is None:
+            colour, nc = colour_greedy(mesh.n_nodes, mesh.conn_ptr, mesh.conn)
+            buckets = colour_buckets(colour, nc)
+        cptr, celems = buckets
+        v = 2
+    elif variant == "atomic":
+        cptr, celems, v = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int32), 1
+    else:
+        raise ValueError(variant)
+    rc = lib().or_assemble_omp(v, mesh.n_nodes, mesh.n_elems, _p(mesh.types), _p(mesh.conn_ptr), _p(mesh.conn),
+                               _p(mesh.x), _p(mesh.y), _p(mesh.z), model, _p(mesh.young), _p(mesh.nu), _p(nh),
+                               _p(mesh.u), _p(src), _p(g.row_ptr), _p(g.map_ptr), _p(g.e2nnz), _p(cptr),
+                               _p(celems), int(cptr.shape[0] - 1), _p(vals), _p(rhs))
+    if rc != 0:
+        raise MeshError(-rc - 1)
     return vals, rhs
 
 

@@ -44,6 +44,9 @@
  * each block, the slots that land in it, in ascending element order.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -813,4 +816,123 @@ int64_t or_assemble(int64_t n_nodes, int64_t n_elems, const uint8_t *types,
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------ *
+ * Parallel timing variants of Algorithm 1 (the CPU baseline).         *
+ * ------------------------------------------------------------------ */
+
+/* Threads the OpenMP variants use (1 without OpenMP). */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* A^e and b^e of element e and their scatter, in a thread's own buffers:
+ * atomic != 0 adds with atomic updates. Returns 0 or -(1 + e). */
+static int64_t omp_element(int64_t e, const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
+                           const double *x, const double *y, const double *z, int model, const double *young,
+                           const double *nu, const uint8_t *nh_flag, const double *u, const double *source,
+                           const int64_t *map_ptr, const int32_t *e2nnz, double *vals, double *rhs, int atomic)
+{
+    double X[24], U[24], Ke[64 * 9], fe[24];
+    int B = (model == OR_POISSON) ? 1 : 3;
+    int nn = or_nodes(types[e]), a, b, i, j;
+    int nh = (model != OR_POISSON && nh_flag && nh_flag[e]) ? 1 : 0;
+    for (a = 0; a < nn; ++a) {
+        int32_t v = conn[conn_ptr[e] + a];
+        X[3 * a + 0] = x[v]; X[3 * a + 1] = y[v]; X[3 * a + 2] = z[v];
+        if (nh)
+            for (i = 0; i < 3; ++i) U[3 * a + i] = u[3 * (int64_t)v + i];
+    }
+    if (or_element(types[e], model, nh, X, young ? young[e] : 1.0, nu ? nu[e] : 0.0, U, &source[e * B], Ke, fe,
+                   NULL, NULL))
+        return -(1 + e);
+    for (a = 0; a < nn; ++a) {
+        int32_t r = conn[conn_ptr[e] + a];
+        for (b = 0; b < nn; ++b) {
+            int64_t blk = e2nnz[map_ptr[e] + a * nn + b];
+            for (i = 0; i < B; ++i)
+                for (j = 0; j < B; ++j) {
+                    double *d = &vals[blk * B * B + i * B + j];
+                    double v = Ke[((int64_t)(a * nn + b) * B + i) * B + j];
+                    if (atomic) {
+#ifdef _OPENMP
+#pragma omp atomic update
+#endif
+                        *d += v;
+                    } else {
+                        *d += v;
+                    }
+                }
+        }
+        for (i = 0; i < B; ++i) {
+            double *d = &rhs[(int64_t)r * B + i];
+            if (atomic) {
+#ifdef _OPENMP
+#pragma omp atomic update
+#endif
+                *d += fe[a * B + i];
+            } else {
+                *d += fe[a * B + i];
+            }
+        }
+    }
+    return 0;
+}
+
+/*
+ * Algorithm 1 with the element loop shared by OpenMP threads, for timing
+ * (same arguments as or_assemble, no |term| sums):
+ *   variant 1: every element in parallel, A^e and b^e added with atomic
+ *              updates (the paper's Algorithm 4);
+ *   variant 2: colour by colour, the elements of one colour in parallel
+ *              with plain updates (Algorithm 5): colour c's elements are
+ *              celems[cptr[c] .. cptr[c+1]), and no two of them share a node.
+ * Sums are taken in a thread-dependent order, so the result equals
+ * or_assemble's up to rounding. Returns 0, or -(1 + e) for a rejected
+ * element (the smallest such e among those that were run).
+ */
+int64_t or_assemble_omp(int variant, int64_t n_nodes, int64_t n_elems, const uint8_t *types,
+                        const int64_t *conn_ptr, const int32_t *conn, const double *x, const double *y,
+                        const double *z, int model, const double *young, const double *nu,
+                        const uint8_t *nh_flag, const double *u, const double *source, const int64_t *row_ptr,
+                        const int64_t *map_ptr, const int32_t *e2nnz, const int64_t *cptr,
+                        const int32_t *celems, int n_colours, double *vals, double *rhs)
+{
+    int B = (model == OR_POISSON) ? 1 : 3;
+    int64_t nnz = row_ptr[n_nodes], bad = 0;
+    memset(vals, 0, sizeof(double) * (size_t)(nnz * B * B));
+    memset(rhs, 0, sizeof(double) * (size_t)(n_nodes * B));
+    if (variant == 1) {
+        int64_t e;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256) reduction(min : bad)
+#endif
+        for (e = 0; e < n_elems; ++e) {
+            int64_t rc = omp_element(e, types, conn_ptr, conn, x, y, z, model, young, nu, nh_flag, u, source,
+                                     map_ptr, e2nnz, vals, rhs, 1);
+            if (rc < bad) bad = rc;
+        }
+    } else if (variant == 2) {
+        int c;
+        for (c = 0; c < n_colours; ++c) {
+            int64_t k;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256) reduction(min : bad)
+#endif
+            for (k = cptr[c]; k < cptr[c + 1]; ++k) {
+                int64_t rc = omp_element(celems[k], types, conn_ptr, conn, x, y, z, model, young, nu, nh_flag,
+                                         u, source, map_ptr, e2nnz, vals, rhs, 0);
+                if (rc < bad) bad = rc;
+            }
+        }
+    } else {
+        return -(1 + n_elems);
+    }
+    return bad;
 }

@@ -122,13 +122,13 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         // the right-hand side first, while its workspace (just written) is
         // still in the caches; then the block values
         if (f32) {
-            if (nr) launch_segsum<B, CT, float, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
+            if (nr) launch_segsum<B, CT, float>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
             mark(g, 1, o, s);
-            if (g->nup) launch_segsum<BB, CT, float, true>(g->nup, g->ublk, g->lpart, g->ts_ptr, (const CT *)g->contrib, (float *)vals, s);
+            if (g->nup) launch_segsum_sym<BB, CT, float>(g->nup, g->ublk, g->ulp, g->uptr, (const CT *)g->contrib, (float *)vals, s);
         } else {
-            if (nr) launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
+            if (nr) launch_segsum<B, CT, double>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
             mark(g, 1, o, s);
-            if (g->nup) launch_segsum<BB, CT, double, true>(g->nup, g->ublk, g->lpart, g->ts_ptr, (const CT *)g->contrib, (double *)vals, s);
+            if (g->nup) launch_segsum_sym<BB, CT, double>(g->nup, g->ublk, g->ulp, g->uptr, (const CT *)g->contrib, (double *)vals, s);
         }
         mark(g, 2, o, s);
         mark(g, 3, o, s);
@@ -171,9 +171,9 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         mark(g, 2, o, s);
         if (nr) {
             if (f32)
-                launch_segsum<B, CT, float, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
+                launch_segsum<B, CT, float>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
             else
-                launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
+                launch_segsum<B, CT, double>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
         }
         mark(g, 3, o, s);
         FEA_HIP(hipGetLastError());
@@ -200,13 +200,13 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
         }
         // the right-hand side first (its workspace is still cached)
         if (f32) {
-            if (nr) launch_segsum<B, CT, float, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
+            if (nr) launch_segsum<B, CT, float>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
             mark(g, 1, o, s);
-            if (nv) launch_segsum<BB, CT, float, false>(g->nnz, nullptr, nullptr, g->inv_ptr, (const CT *)g->contrib, (float *)vals, s);
+            if (nv) launch_segsum<BB, CT, float>(g->nnz, g->inv_ptr, (const CT *)g->contrib, (float *)vals, s);
         } else {
-            if (nr) launch_segsum<B, CT, double, false>(g->n_nodes, nullptr, nullptr, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
+            if (nr) launch_segsum<B, CT, double>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
             mark(g, 1, o, s);
-            if (nv) launch_segsum<BB, CT, double, false>(g->nnz, nullptr, nullptr, g->inv_ptr, (const CT *)g->contrib, (double *)vals, s);
+            if (nv) launch_segsum<BB, CT, double>(g->nnz, g->inv_ptr, (const CT *)g->contrib, (double *)vals, s);
         }
         mark(g, 2, o, s);
         mark(g, 3, o, s);

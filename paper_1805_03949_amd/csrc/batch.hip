@@ -267,7 +267,7 @@ struct fea_batch {
     int64_t items_version = 0, itemargs_version = -1;
     bool sym_ready = false;
     int64_t total_sym_slots = 0, total_nup = 0;
-    int32_t *d_sym_ublk = nullptr, *d_sym_lpart = nullptr;
+    int32_t *d_sym_ublk = nullptr, *d_sym_lp = nullptr;
     int64_t *d_sym_ptr = nullptr;
     // subgrid scale: its own queue heads (one per family) and per-mesh
     // arguments, kept for the outputs and item list they were built for
@@ -299,7 +299,7 @@ void destroy_batch(fea_batch *b)
         if (g) fea_graph_destroy(g);
     void *bufs[] = {b->d_meshes, b->d_items, b->d_order, b->d_head, b->d_status, b->d_vseg,
                     b->d_rseg, b->d_cycles, b->d_worker, b->d_cu, b->contrib, b->rcontrib,
-                    b->d_part, b->d_sym_ublk, b->d_sym_lpart, b->d_sym_ptr, b->d_itemargs,
+                    b->d_part, b->d_sym_ublk, b->d_sym_lp, b->d_sym_ptr, b->d_itemargs,
                     b->d_sub_head, b->d_subargs, b->d_sub_items, b->d_sub_order};
     for (void *p : bufs) dfree(p);
     for (hipEvent_t e : b->ev)
@@ -464,22 +464,25 @@ int sym_prepare_batch(fea_batch *b, hipStream_t s)
         M.scoff = soff[m];
     }
     dfree(b->d_sym_ublk);
-    dfree(b->d_sym_lpart);
+    dfree(b->d_sym_lp);
     dfree(b->d_sym_ptr);
-    b->d_sym_ublk = b->d_sym_lpart = nullptr;
+    b->d_sym_ublk = b->d_sym_lp = nullptr;
     b->d_sym_ptr = nullptr;
     if ((rc = dalloc((void **)&b->d_sym_ublk, sizeof(int32_t) * std::max<int64_t>(uoff[n], 1)))) return rc;
-    if ((rc = dalloc((void **)&b->d_sym_lpart, sizeof(int32_t) * std::max<int64_t>(koff[n], 1)))) return rc;
-    if ((rc = dalloc((void **)&b->d_sym_ptr, sizeof(int64_t) * (koff[n] + 1)))) return rc;
+    if ((rc = dalloc((void **)&b->d_sym_lp, sizeof(int32_t) * std::max<int64_t>(uoff[n], 1)))) return rc;
+    if ((rc = dalloc((void **)&b->d_sym_ptr, sizeof(int64_t) * (uoff[n] + 1)))) return rc;
     if (koff[n] > INT32_MAX) return set_error(FEA_ERANGE, "batch has more than 2^31 blocks");
     int64_t zero = 0;
     FEA_HIP(hipMemcpy(b->d_sym_ptr, &zero, sizeof(int64_t), hipMemcpyHostToDevice));
+    // concatenated upper-block lists: block ids and lower partners offset by
+    // the mesh's first block, segment bounds by its first workspace slot
+    // (mesh m's last bound is mesh m+1's first, written twice with one value)
     for (int m = 0; m < n; ++m) {
         const fea_graph *g = b->graphs[m];
-        if (g->nup) k_offset_idx<<<grid_for(g->nup, 256), 256, 0, s>>>(g->ublk, g->nup, koff[m], b->d_sym_ublk + uoff[m]);
-        if (g->nnz) {
-            k_offset_idx<<<grid_for(g->nnz, 256), 256, 0, s>>>(g->lpart, g->nnz, koff[m], b->d_sym_lpart + koff[m]);
-            k_offset_ptr<<<grid_for(g->nnz + 1, 256), 256, 0, s>>>(g->ts_ptr, g->nnz, soff[m], b->d_sym_ptr + koff[m]);
+        if (g->nup) {
+            k_offset_idx<<<grid_for(g->nup, 256), 256, 0, s>>>(g->ublk, g->nup, koff[m], b->d_sym_ublk + uoff[m]);
+            k_offset_idx<<<grid_for(g->nup, 256), 256, 0, s>>>(g->ulp, g->nup, koff[m], b->d_sym_lp + uoff[m]);
+            k_offset_ptr<<<grid_for(g->nup + 1, 256), 256, 0, s>>>(g->uptr, g->nup, soff[m], b->d_sym_ptr + uoff[m]);
         }
     }
     FEA_HIP(hipGetLastError());
@@ -594,13 +597,13 @@ int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, 
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[1], s));
     const int64_t nv = b->total_blocks * BB, nr = b->rhs_off.back();
     // the right-hand side first, while its workspace is still cached
-    if (nr) launch_segsum<B, CT, OT, false>(nr / B, nullptr, nullptr, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs, s);
+    if (nr) launch_segsum<B, CT, OT>(nr / B, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs, s);
     if (SYM) {
         if (b->total_nup)
-            launch_segsum<BB, CT, OT, true>(b->total_nup, b->d_sym_ublk, b->d_sym_lpart, b->d_sym_ptr,
-                                            (const CT *)b->contrib, (OT *)vals, s);
+            launch_segsum_sym<BB, CT, OT>(b->total_nup, b->d_sym_ublk, b->d_sym_lp, b->d_sym_ptr,
+                                          (const CT *)b->contrib, (OT *)vals, s);
     } else if (nv) {
-        launch_segsum<BB, CT, OT, false>(b->total_blocks, nullptr, nullptr, b->d_vseg, (const CT *)b->contrib, (OT *)vals, s);
+        launch_segsum<BB, CT, OT>(b->total_blocks, b->d_vseg, (const CT *)b->contrib, (OT *)vals, s);
     }
     k_batch_end<<<grid_for(std::max(b->n_meshes, 1), 256), 256, 0, s>>>(b->d_status, b->n_meshes, status);
     FEA_HIP(hipGetLastError());

@@ -377,6 +377,21 @@ __global__ void __launch_bounds__(256) k_tile_entries(TileBases tb, const int32_
     }
 }
 
+// Per entry m of the upper-block list: its block's lower partner and the
+// start of its workspace segment (uptr[nup] = the workspace length).
+__global__ void k_sym_compact(int64_t nup, int64_t nnz, const int32_t *ublk, const int32_t *lpart,
+                              const int64_t *ts_ptr, int32_t *ulp, int64_t *uptr)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < nup) {
+        const int32_t k = ublk[m];
+        ulp[m] = lpart[k];
+        uptr[m] = ts_ptr[k];
+    } else if (m == nup) {
+        uptr[m] = ts_ptr[nnz];
+    }
+}
+
 __global__ void k_tb_count(int64_t ntb, const int32_t *tb_blk, int32_t *cnt)
 {
     const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -417,7 +432,7 @@ int sym_prepare(fea_graph *g, hipStream_t s)
     int rc;
     void **bufs[] = {(void **)&g->upart, (void **)&g->ublk,    (void **)&g->lpart,  (void **)&g->tent_ptr,
                      (void **)&g->ttb_ptr, (void **)&g->tent,  (void **)&g->tb_eend, (void **)&g->tb_blk,
-                     (void **)&g->tb_slot, (void **)&g->ts_ptr};
+                     (void **)&g->tb_slot, (void **)&g->ts_ptr, (void **)&g->ulp, (void **)&g->uptr};
     for (void **b : bufs) {
         dfree(*b);
         *b = nullptr;
@@ -514,6 +529,10 @@ int sym_prepare(fea_graph *g, hipStream_t s)
     } else {
         FEA_HIP(hipMemsetAsync(g->ts_ptr, 0, sizeof(int64_t), s));
     }
+    const int64_t nup = g->nup;
+    if ((rc = dalloc((void **)&g->ulp, sizeof(int32_t) * std::max<int64_t>(nup, 1)))) return rc;
+    if ((rc = dalloc((void **)&g->uptr, sizeof(int64_t) * (nup + 1)))) return rc;
+    k_sym_compact<<<grid_for(nup + 1, BS), BS, 0, s>>>(nup, nnz, g->ublk, g->lpart, g->ts_ptr, g->ulp, g->uptr);
     FEA_HIP(hipGetLastError());
     FEA_HIP(hipStreamSynchronize(s));
     g->ulen = ntb;
@@ -652,7 +671,7 @@ static void destroy(fea_graph *g)
     void *bufs[] = {g->row_ptr, g->col, g->map_ptr, g->e2nnz, g->inv_ptr, g->inv, g->pnodes, g->pdest, g->prdest,
                     g->n2e_ptr, g->n2e, g->n2a, g->perm, g->colour, g->cperm,
                     g->contrib, g->rcontrib, g->acc64, g->gtile, g->gnodes, g->gdesc, g->upart, g->ublk, g->lpart, g->tent_ptr, g->ttb_ptr,
-                    g->tent, g->tb_eend, g->tb_blk, g->tb_slot, g->ts_ptr, g->ctile, g->gp_ptr};
+                    g->tent, g->tb_eend, g->tb_blk, g->tb_slot, g->ts_ptr, g->ctile, g->gp_ptr, g->ulp, g->uptr};
     for (void *b : bufs) dfree(b);
     for (hipEvent_t e : g->ev)
         if (e) (void)hipEventDestroy(e);

@@ -846,3 +846,28 @@ def test_subscale_mesh_volumes_and_scalar_field():
     for e in range(m.n_elems):
         tau = vol[int(m.types[e])] ** (2 / 3) / 4
         np.testing.assert_allclose(got[gp_ptr[e]:gp_ptr[e + 1], 0], tau * m.source[e, 0], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- parallel timing variants
+
+@pytest.mark.parametrize("variant", ["atomic", "colour"])
+def test_parallel_variants_equal_sequential_up_to_rounding(variant):
+    """The OpenMP timing variants (Algorithm 4 atomics, Algorithm 5 colour
+    sweeps) compute Algorithm 1's sums in another order: equal up to
+    rounding, for linear elasticity, the neo-Hookean tangent and Poisson."""
+    m = mg.heterogeneous(8, seed=71, brick=2, jitter=0.15)
+    g = oracle.mesh_graph(m)
+    for model, nh in ((oracle.ELASTIC, False), (oracle.ELASTIC, True), (oracle.POISSON, False)):
+        v0, r0 = oracle.assemble(m, g, model=model, use_nh=nh)
+        v1, r1 = oracle.assemble_parallel(m, g, variant, model=model, use_nh=nh)
+        assert np.abs(v1 - v0).max() <= 1e-13 * np.abs(v0).max()
+        assert np.abs(r1 - r0).max() <= 1e-13 * np.abs(r0).max()
+    if variant == "colour":
+        # the buckets hold every element once, and a colour's elements share no node
+        colour, nc = oracle.colour_greedy(m.n_nodes, m.conn_ptr, m.conn)
+        cptr, celems = oracle.colour_buckets(colour, nc)
+        assert np.array_equal(np.sort(celems), np.arange(m.n_elems))
+        for c in range(nc):
+            es = celems[cptr[c]:cptr[c + 1]]
+            nodes = np.concatenate([m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]] for e in es])
+            assert np.unique(nodes).size == nodes.size
