@@ -5,13 +5,18 @@ for every element plus the race-free scatter into the 3x3 block matrix and
 the right-hand side), with the mesh, graph and outputs resident in HBM.
 The graph build is timed once and reported separately.
 
-Workload (default): linear elasticity on a 96^3-cell hybrid mesh, four
-z-bands of 24 cell layers (hex8 / pen6 / tet4 / pyr5), E = 1, nu per element
-U[0.2, 0.35], body force (0, 0, -1); 3,317,760 elements, 1,133,857 nodes.
+Workload (default, the largest single-GPU configuration): linear elasticity
+on a 256^3-cell hybrid mesh, z-bands of 102 / 77 / 51 / 26 cell layers
+(hex8 / tet4 / pen6 / pyr5), E = 1, nu per element U[0.2, 0.35], body force
+(0, 0, -1); 53,870,592 elements, 18,678,529 nodes, FP64 upper-triangle
+form. Companion workloads (extra keys): the 96^3-cell hybrid mesh with every
+scatter form, the subgrid scale, the batched and heterogeneous-cost
+workloads and the persistent form of the large mesh.
 
 Prints one JSON line. Usage:
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--variant rowsym]
-                  [--precision fp64|mixed] [--no-cpu] [--no-variants]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hybrid256|hybrid96]
+                  [--variant rowsym] [--precision fp64|mixed] [--no-cpu] [--no-variants]
+                  [--no-small] [--no-extras]
 """
 from __future__ import annotations
 
@@ -183,7 +188,7 @@ def subscale_work(mesh, B, np):
     return byts, flops
 
 
-def subscale_workload(fea, mg, torch, np, mesh, dm, g, reps=20):
+def subscale_workload(fea, mg, torch, np, mesh, dm, g, reps=20, name="hybrid96"):
     """The element-wise subgrid scale of linear elasticity on the headline
     mesh at a smooth displacement field: four family launches, nothing
     assembled."""
@@ -215,7 +220,7 @@ def subscale_workload(fea, mg, torch, np, mesh, dm, g, reps=20):
                  "algorithmic_bytes": int(byts), "algorithmic_flops": int(flops),
                  "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
                  "fp64_TFLOPs": round(tfs, 2), "fp64_frac": round(tfs / PEAK_FP64_TFLOPS, 4)})
-    res = {"workload": "hybrid96 elasticity, smooth displacement field, FP64", "ms": round(ms, 4),
+    res = {"workload": f"{name} elasticity, smooth displacement field, FP64", "ms": round(ms, 4),
            "elements_per_s": round(mesh.n_elems / (ms * 1e-3), 1),
            "gauss_points_per_s": round(n_pts / (ms * 1e-3), 1), "gauss_points": n_pts,
            "roofline": roof, "status_ok": int(st.item()) == -1}
@@ -356,12 +361,13 @@ def copy_bandwidth(torch):
     return round(2 * a.numel() * 8 / (ms * 1e-3) / 1e9, 1)
 
 
-def large_workload(fea, mg, torch, np, cells=256):
+def large_workload(fea, mg, torch, np, cells=256, mesh=None):
     """53.9M-element hybrid mesh (40/30/20/10 hex/tet/pen/pyr layers) through
     the persistent path in the upper-triangle form (plain FP64 against mixed
     precision with the learned schedule; row-owner FP64 for reference), then
-    one-mesh assemblies in the row-gather and upper-triangle forms."""
-    mesh = mg.hybrid_split(cells, seed=5)
+    one-mesh assemblies in the row-gather form and the subgrid scale."""
+    if mesh is None:
+        mesh = mg.hybrid_split(cells, seed=5)
     dm = fea.DeviceMesh(mesh)
     b = fea.Batch([dm], model=fea.ELASTIC)
     out = {"workload": f"hybrid{cells}-elasticity (40/30/20/10 hex/tet/pen/pyr layers)",
@@ -407,7 +413,7 @@ def large_workload(fea, mg, torch, np, cells=256):
     # the same mesh through the fused row-gather form (no workspace) and the
     # upper-triangle row-owner form
     g = dm.graph()
-    for vname in ("rowgather", "rowsym"):
+    for vname in ("rowgather",):
         for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
             var = fea.VARIANTS[vname]
             vals, rhs, st = dm.assemble(g, variant=var, precision=p, out_dtype=o)
@@ -442,16 +448,7 @@ def large_workload(fea, mg, torch, np, cells=256):
     return out
 
 
-def heterogeneous_workload(fea, mg, torch, np, cells=128):
-    """Hybrid split mesh (40/30/20/10 hex/tet/pen/pyr layers) where 30% of
-    8^3-cell bricks use the neo-Hookean tangent: the cost model is trained
-    on the recorded cycles and orders the queue; compared with the
-    type-sorted order and the Gauss-point-weight order, and the learned
-    mixed-precision form with the plain FP64 form."""
-    mesh = mg.heterogeneous(cells, seed=4)
-    dm = fea.DeviceMesh(mesh)
-    b = fea.Batch([dm], model=fea.ELASTIC, use_nh=True)
-
+def _batch_runner(fea, torch, np, b):
     def run(precision, reps=9, variant=fea.ROWSYM):
         outd = fea.F64 if precision == fea.FP64 else fea.F32
         vals, rhs, st = b.outputs(outd)
@@ -484,8 +481,37 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
             held += busy.size * busy.max()
         return {"kernel_ms": round(float(np.median(kern)), 4), "total_ms": round(float(np.median(tot)), 4),
                 "load_balance": round(float(busy_sum / held), 4)}, vals, st
+    return run
 
+
+def _measured_log_cycles(fea, torch, b, runs=5):
+    """Per-item log-cycles averaged over `runs` type-sorted mixed runs (one
+    run is noisy: concurrent workgroups share caches and memory channels)."""
+    vals, rhs, st = b.outputs(fea.F32)
+    logs = []
+    for _ in range(runs):
+        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs, status=st, variant=fea.ROWSYM)
+        c, _, _ = b.cycles()
+        logs.append(fea.CostModel.log_cycles(c))
+    return torch.stack(logs).mean(dim=0).contiguous()
+
+
+def heterogeneous_workload(fea, mg, torch, np, cells=128):
+    """Hybrid split meshes (40/30/20/10 hex/tet/pen/pyr layers) where 30% of
+    8^3-cell bricks use the neo-Hookean tangent. The cost model is trained
+    on the cycles recorded on one mesh (seed 4) and judged on another
+    (seed 6: other bricks, other displacement field) that it never saw:
+    prediction quality against measured cycles, the load balance of a
+    static 8-way split of the whole mesh (the sharding over 8 GPUs, judged
+    by measured cycles), and the queue orders and static partitions of the
+    persistent kernels, against the type-sorted order and the Gauss-point
+    weights of the paper's Section 4.1."""
+    mesh = mg.heterogeneous(cells, seed=4)
+    dm = fea.DeviceMesh(mesh)
+    b = fea.Batch([dm], model=fea.ELASTIC, use_nh=True)
+    run = _batch_runner(fea, torch, np, b)
     out = {"workload": f"hetero{cells}-elasticity (30% neo-Hookean bricks, 40/30/20/10 hex/tet/pen/pyr)",
+           "train_mesh_seed": 4, "heldout_mesh_seed": 6,
            "elements": int(mesh.n_elems), "items": int(b.n_items), "workers": 0,
            "variant": "rowsym (persistent kernel)"}
     out["fp64_type_sorted_rowowner"], _, _ = run(fea.FP64, variant=fea.ROWOWNER)
@@ -493,17 +519,7 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
     out["fp64_type_sorted"] = fp64_ts
     mix_ts, vmx, stm = run(fea.MIXED)
     out["mixed_type_sorted"] = mix_ts
-    # training data: log-cycles of every item, averaged over five
-    # type-sorted mixed runs (single runs are noisy: concurrent workgroups
-    # share the caches and memory channels)
-    vals, rhs, st = b.outputs(fea.F32)
-    logs = []
-    for _ in range(5):
-        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs, status=st, variant=fea.ROWSYM)
-        c, _, _ = b.cycles()
-        logs.append(fea.CostModel.log_cycles(c))
-    target = torch.stack(logs).mean(dim=0).contiguous()
-    del vals, rhs, st
+    target = _measured_log_cycles(fea, torch, b)
     feats = b.features(fp64_geometry=False)
     cm = fea.CostModel(seed=7)
     cm.fit_norm(feats)
@@ -512,62 +528,79 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     pred = cm.predict(feats)
-    t = target.cpu().numpy().astype(np.float64)
-    p = pred.cpu().numpy().astype(np.float64)
-    gp = np.log(b.items[:, 3] * np.array([1, 8, 6, 8])[b.items[:, 1]])
 
     def r2(x, y):
         x = x - x.mean()
         y = y - y.mean()
         return float((x @ y) ** 2 / ((x @ x) * (y @ y)))
 
-    # static split of the whole mesh into 8 contiguous parts (the sharding
-    # of a mesh over 8 GPUs): cut the type-sorted items where the running
-    # weight crosses k/8 of the total, then rate each split by the
-    # measured cycles of its parts (load balance = mean / max part cost)
-    cyc = np.exp(t)
-
-    def split_lb(wts, parts=8):
+    def split_lb(cyc, wts, parts=8):
+        # cut the type-sorted items where the running weight crosses k/8 of
+        # the total, then rate the split by the measured cycles of its parts
         cs = np.cumsum(wts)
         cut = np.searchsorted(cs - 0.5 * wts, cs[-1] * np.arange(1, parts) / parts)
         sums = np.array([c.sum() for c in np.split(cyc, cut)])
         return round(float(sums.mean() / sums.max()), 4)
 
-    out["static_split_8_load_balance"] = {
-        "elements": split_lb(b.items[:, 3].astype(np.float64)),
-        "gauss_points": split_lb(np.exp(gp)),
-        "learned": split_lb(np.exp(p)),
-        "measured_cycles": split_lb(cyc)}
+    def judge(bb, tgt, prd):
+        t = tgt.cpu().numpy().astype(np.float64)
+        p = prd.cpu().numpy().astype(np.float64)
+        gp = np.log(bb.items[:, 3] * np.array([1, 8, 6, 8])[bb.items[:, 1]])
+        cyc = np.exp(t)
+        return {"r2_learned_vs_measured": round(r2(p, t), 4),
+                "r2_gauss_point_weight_vs_measured": round(r2(gp, t), 4),
+                "static_split_8_load_balance": {"elements": split_lb(cyc, bb.items[:, 3].astype(np.float64)),
+                                                "gauss_points": split_lb(cyc, np.exp(gp)),
+                                                "learned": split_lb(cyc, np.exp(p)),
+                                                "measured_cycles": split_lb(cyc, cyc)}}
+
     out["cost_model"] = {"train_steps": 600, "train_s": round(train_s, 3),
                          "loss_first": round(float(hist[0].item()), 5), "loss_last": round(float(hist[-1].item()), 5),
-                         "r2_learned_vs_measured": round(r2(p, t), 4),
-                         "r2_gauss_point_weight_vs_measured": round(r2(gp, t), 4)}
-    # dynamic queue, largest predicted cost first
-    b.order(fea.GP_WEIGHT)
-    out["mixed_queue_gp_weight_lpt"], _, _ = run(fea.MIXED)
-    b.order(fea.LEARNED, pred)
-    out["mixed_queue_learned_lpt"], _, _ = run(fea.MIXED)
-    # static partitions of the type-sorted items, one range per workgroup
-    b.partition(fea.TYPE_SORTED)
-    out["mixed_static_by_elements"], _, _ = run(fea.MIXED)
-    b.partition(fea.GP_WEIGHT)
-    out["mixed_static_by_gauss_points"], _, _ = run(fea.MIXED)
-    b.partition(fea.LEARNED, pred)
-    out["mixed_static_learned"], vl, stl = run(fea.MIXED)
-    b.partition(fea.LEARNED, pred)
-    out["fp64_static_learned"], _, _ = run(fea.FP64)
-    b.order(fea.TYPE_SORTED)
-    out["workers"] = b.workers()
-    best_learned = min(out["mixed_queue_learned_lpt"]["total_ms"], out["mixed_static_learned"]["total_ms"])
-    out["speedup_learned_mixed_vs_fp64_type_sorted"] = round(fp64_ts["total_ms"] / best_learned, 4)
-    out["speedup_learned_static_vs_gauss_point_static"] = round(
-        out["mixed_static_by_gauss_points"]["total_ms"] / out["mixed_static_learned"]["total_ms"], 4)
-    out["speedup_learned_vs_type_sorted_queue_mixed"] = round(mix_ts["total_ms"] / best_learned, 4)
-    d = (vl.double() - v64).norm() / v64.norm()
-    out["mixed_vs_fp64_rel_frobenius"] = float(d.item())
-    out["status_ok"] = bool((st64.cpu() == -1).all()) and bool((stl.cpu() == -1).all())
-    # the same mesh (neo-Hookean bricks included) in the row-gather and
-    # upper-triangle row-owner forms
+                         "in_sample": judge(b, target, pred)}
+    del vmx, stm
+    # the held-out mesh: the trained model predicts, measured cycles judge
+    hmesh = mg.heterogeneous(cells, seed=6)
+    hdm = fea.DeviceMesh(hmesh)
+    hb = fea.Batch([hdm], model=fea.ELASTIC, use_nh=True)
+    hrun = _batch_runner(fea, torch, np, hb)
+    hfeats = hb.features(fp64_geometry=False)
+    hpred = cm.predict(hfeats)
+    htarget = _measured_log_cycles(fea, torch, hb)
+    out["cost_model"]["held_out"] = judge(hb, htarget, hpred)
+    ho = {"elements": int(hmesh.n_elems), "items": int(hb.n_items)}
+    ho["fp64_type_sorted"], hv64, hst64 = hrun(fea.FP64)
+    ho["mixed_type_sorted"], _, _ = hrun(fea.MIXED)
+    hb.order(fea.GP_WEIGHT)
+    ho["mixed_queue_gp_weight_lpt"], _, _ = hrun(fea.MIXED)
+    hb.order(fea.LEARNED, hpred)
+    ho["mixed_queue_learned_lpt"], _, _ = hrun(fea.MIXED)
+    hb.partition(fea.TYPE_SORTED)
+    ho["mixed_static_by_elements"], _, _ = hrun(fea.MIXED)
+    hb.partition(fea.GP_WEIGHT)
+    ho["mixed_static_by_gauss_points"], _, _ = hrun(fea.MIXED)
+    hb.partition(fea.LEARNED, hpred)
+    ho["mixed_static_learned"], hvl, hstl = hrun(fea.MIXED)
+    hb.order(fea.TYPE_SORTED)
+    best = min(ho["mixed_queue_learned_lpt"]["total_ms"], ho["mixed_static_learned"]["total_ms"])
+    ho["speedup_learned_mixed_vs_fp64_type_sorted"] = round(ho["fp64_type_sorted"]["total_ms"] / best, 4)
+    ho["speedup_learned_vs_type_sorted_queue_mixed"] = round(ho["mixed_type_sorted"]["total_ms"] / best, 4)
+    ho["speedup_learned_static_vs_gauss_point_static"] = round(
+        ho["mixed_static_by_gauss_points"]["total_ms"] / ho["mixed_static_learned"]["total_ms"], 4)
+    # the most any queue order can gain on this GPU: the dynamic queue's
+    # measured load balance already bounds the idle share of the launches
+    ho["max_gain_any_order"] = round(1.0 / ho["mixed_type_sorted"]["load_balance"], 4)
+    ho["mixed_vs_fp64_rel_frobenius"] = float(((hvl.double() - hv64).norm() / hv64.norm()).item())
+    ho["status_ok"] = bool((hst64.cpu() == -1).all()) and bool((hstl.cpu() == -1).all())
+    out["held_out"] = ho
+    out["workers"] = hb.workers()
+    del hv64, hvl
+    hb.destroy()
+    del hb, hdm
+    torch.cuda.empty_cache()
+    out["status_ok"] = bool((st64.cpu() == -1).all())
+    del v64
+    # the training mesh (neo-Hookean bricks included) in the row-gather and
+    # upper-triangle row-owner forms, one mesh per call
     g = dm.graph()
     for vname in ("rowgather", "rowsym"):
         var = fea.VARIANTS[vname]
@@ -592,6 +625,266 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
                                           "status_ok": int(gs.item()) == -1}
     del gv, gr, gs
     g.destroy()
+    b.destroy()
+    return out
+
+
+def workload_mesh(mg, name):
+    """The seeded synthetic meshes: hybrid256 (256^3 cells, 40/30/20/10
+    hex8/tet4/pen6/pyr5 layers, seed 5) and hybrid96 (96^3 cells, four equal
+    bands hex8/pen6/tet4/pyr5, seed 2)."""
+    if name == "hybrid256":
+        return mg.hybrid_split(256, seed=5)
+    if name == "hybrid96":
+        return mg.hybrid_bands(96, seed=2)
+    raise ValueError(name)
+
+
+WORKLOAD_DESC = {
+    "hybrid256": "hybrid256-elasticity (256^3 cells, 40/30/20/10 hex8/tet4/pen6/pyr5 z-bands, 3x3 BSR)",
+    "hybrid96": "hybrid96-elasticity (96^3 cells, hex8/pen6/tet4/pyr5 z-bands, 3x3 BSR)",
+}
+PRECISIONS = {"fp64": (0, 0), "mixed": (1, 1)}  # (fea precision, fea out dtype)
+
+
+def timed_steps(torch, step, steps, warmup):
+    """ms per step over `steps` calls after `warmup`, bracketed by
+    synchronisations (torch events on the current stream, where the library
+    enqueues)."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def phase_medians(np, g, step, reps):
+    """Median (element phase, block-value kernel, whole call) in ms from the
+    HIP events the library records on its stream."""
+    ph = []
+    for _ in range(reps):
+        step(True)
+        ph.append(g.last_timing())
+    return [float(x) for x in np.median(np.array(ph), axis=0)]
+
+
+def sym_roofline(g, sym, B, s_c, s_v, k_ms, copy_gbps, key):
+    kb = sym_reduce_bytes(sym["tile_blocks"], sym["upper_blocks"], g.nnz, B, s_c, s_v)
+    achieved = kb / (k_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "kernel": "k_segsum_sym<9>" + ("" if s_c == 8 else ",mixed"),
+           "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(key, "segsum.h"),
+           "algorithmic_bytes": int(kb), "kernel_ms": round(k_ms, 4)}
+    if copy_gbps:
+        out.update({"copy_GBps": copy_gbps, "frac_of_copy": round(achieved / copy_gbps, 4)})
+    return out
+
+
+def one_mesh_workload(fea, torch, np, mesh, name, args, variant_names, copy_gbps):
+    """One fea_assemble per step over the whole mesh: the headline form
+    (args.variant, args.precision) timed over args.steps, its phases, and
+    the other forms of variant_names in both precisions (five timed calls
+    each). Returns (result dict, device mesh, graph)."""
+    B = 3
+    dm = fea.DeviceMesh(mesh, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = dm.graph()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3
+    prec, outd = PRECISIONS[args.precision]
+    var = fea.VARIANTS[args.variant]
+    s_c, s_v = (8, 8) if prec == fea.FP64 else (4, 4)
+    conn_len = int(mesh.conn_ptr[-1])
+    # the first call builds the layout of its form (upper-triangle tiles)
+    t0 = time.perf_counter()
+    vals, rhs, st = dm.assemble(g, variant=var, precision=prec, out_dtype=outd)
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+
+    def step(timing=False):
+        dm.assemble(g, variant=var, precision=prec, out_dtype=outd, vals=vals, rhs=rhs, status=st, timing=timing)
+
+    ms = timed_steps(torch, step, args.steps, args.warmup)
+    assert int(st.item()) == -1, "an element was rejected"
+    print(f"[bench] {name}: {args.steps} steps, {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    ph = phase_medians(np, g, step, max(5, min(args.steps, 20)))
+    dm.assemble(g, variant=fea.ROWSYM)  # builds the upper-triangle layout if the headline form did not
+    sym = g.sym_sizes()
+    eb = element_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes, mesh.n_elems, args.variant, sym)
+    out = {"workload": WORKLOAD_DESC[name], "elements": int(mesh.n_elems), "nodes": int(mesh.n_nodes),
+           "nnz_blocks": int(g.nnz), "variant": args.variant, "precision": args.precision,
+           "ms_per_step": round(ms, 4), "elements_per_s": round(mesh.n_elems / (ms * 1e-3), 1),
+           "phases_ms": {"element": round(ph[0], 4), "block_value_kernel": round(ph[1], 4),
+                         "total": round(ph[2], 4)},
+           "element_phase": {"algorithmic_bytes": int(eb), "ms": round(ph[0], 4),
+                             "effective_GBps": round(eb / (ph[0] * 1e-3) / 1e9, 1),
+                             "frac_of_peak": round(eb / (ph[0] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+           "graph_build_ms": round(graph_ms, 2), "first_call_ms": round(first_ms, 2),
+           "upper_triangle_layout": sym}
+    if args.variant == "rowsym":
+        out["roofline"] = sym_roofline(g, sym, B, s_c, s_v, ph[1], copy_gbps,
+                                       f"k_segsum_sym<9>{'' if s_c == 8 else ',mixed'}@{name}")
+    elif args.variant == "rowowner":
+        kb = reduce_bytes(g, B, s_c, s_v)
+        a = kb / (ph[1] * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": "k_segsum<9>", "achieved": round(a, 1), "peak": PEAK_HBM_GBS,
+                           "unit": "GB/s", "frac": round(a / PEAK_HBM_GBS, 4),
+                           "traffic": traffic_from_profile(f"k_segsum<9>@{name}", "segsum.h"),
+                           "algorithmic_bytes": int(kb), "kernel_ms": round(ph[1], 4)}
+    del vals, rhs
+    variants = {}
+    for vname in variant_names:
+        for pname, (p, o) in PRECISIONS.items():
+            vv, rr, ss = dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o)
+            dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o, vals=vv, rhs=rr, status=ss)
+            med = phase_medians(np, g, lambda t: dm.assemble(g, variant=fea.VARIANTS[vname], precision=p,
+                                                             out_dtype=o, vals=vv, rhs=rr, status=ss,
+                                                             timing=t), 5)
+            sc = 8 if p == fea.FP64 else 4
+            rec = {"total_ms": round(med[2], 4), "element_ms": round(med[0], 4),
+                   "block_value_kernel_ms": round(med[1], 4),
+                   "elements_per_s": round(mesh.n_elems / (med[2] * 1e-3), 1),
+                   "status_ok": int(ss.item()) == -1}
+            key = f"{vname}_{pname}"
+            if vname == "rowsym":
+                rec["roofline"] = sym_roofline(g, sym, B, sc, sc, med[1], copy_gbps,
+                                               f"k_segsum_sym<9>{'' if sc == 8 else ',mixed'}@{name}")
+            elif vname == "rowowner":
+                kb = reduce_bytes(g, B, sc, sc)
+                a = kb / (med[1] * 1e-3) / 1e9
+                rec["roofline"] = {"bound": "hbm", "kernel": "k_segsum<9>" + ("" if sc == 8 else ",mixed"),
+                                   "achieved": round(a, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   "frac": round(a / PEAK_HBM_GBS, 4),
+                                   "traffic": traffic_from_profile(
+                                       f"k_segsum<9>{'' if sc == 8 else ',mixed'}@{name}", "segsum.h"),
+                                   "algorithmic_bytes": int(kb)}
+            elif vname in ("colour", "atomic"):
+                # fused element kernels: the whole scatter happens in them
+                eb2 = element_bytes(g, B, sc, 8, conn_len, mesh.n_nodes, mesh.n_elems, vname)
+                a = eb2 / (med[0] * 1e-3) / 1e9
+                tr = traffic_from_profile(f"{vname}_{pname}@{name}", "elem.h")
+                rec["scatter"] = {"kernels": f"k_element<family, elasticity, {vname}>", "algorithmic_bytes": int(eb2),
+                                  "effective_GBps": round(a, 1), "frac_of_peak": round(a / PEAK_HBM_GBS, 4),
+                                  "counter_bytes": tr,
+                                  "counter_GBps": round(tr / (med[0] * 1e-3) / 1e9, 1) if tr else None}
+            variants[key] = rec
+            del vv, rr, ss
+    if variants:
+        out["variants"] = variants
+    torch.cuda.synchronize()
+    return out, dm, g
+
+
+def cpu_baseline_leg(fea, torch, np, mesh, name):
+    """The only part of this benchmark that runs the oracle. (1) CPU
+    baseline: the C oracle (FP64, -O3) on a bounded sample of the workload,
+    ten z-layers of cells taken from the middle of its bands in its
+    40/30/20/10 hex8/tet4/pen6/pyr5 proportion, timed as sequential
+    Algorithm 1 and as its OpenMP atomic (Algorithm 4) and colour (Algorithm
+    5) analogues on every host thread, median of five runs each; the best
+    is reported, extrapolated to the whole mesh by its elements/s (same
+    per-element work mix). (2) Accuracy: the GPU's FP64 and mixed
+    upper-triangle assemblies of a four-layer sample (one layer per band)
+    against the oracle, and the mixed error against its bound gamma_L T."""
+    import oracle
+    import meshgen as mg
+    n = mesh.n_cells
+    bands = mg.split_bands(n)
+    starts = np.concatenate([[0], np.cumsum([l for _, l in bands])])
+    take = (4, 3, 2, 1)
+
+    def mid_layers(k, cnt):
+        lo, hi = int(starts[k]), int(starts[k + 1])
+        m0 = (lo + hi) // 2 - cnt // 2
+        return list(range(m0, m0 + cnt))
+
+    layers = sum((mid_layers(k, c) for k, c in enumerate(take)), [])
+    sample = mg.layer_sample(mesh, layers)
+    og = oracle.mesh_graph(sample)
+    colour, nc = oracle.colour_greedy(sample.n_nodes, sample.conn_ptr, sample.conn)
+    buckets = oracle.colour_buckets(colour, nc)
+    runs = {}
+    for kind in ("sequential", "atomic", "colour"):
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            if kind == "sequential":
+                oracle.assemble(sample, og, model=oracle.ELASTIC)
+            else:
+                oracle.assemble_parallel(sample, og, kind, buckets=buckets if kind == "colour" else None)
+            ts.append(time.perf_counter() - t0)
+        runs[kind] = float(np.median(ts))
+        print(f"[bench] cpu {kind}: {runs[kind]:.2f} s", file=sys.stderr, flush=True)
+    best = min(runs, key=runs.get)
+    rate = sample.n_elems / runs[best]
+    threads = oracle.threads()
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    cpu = {"value": round(rate, 1), "unit": "elements/s", "cores": threads if best != "sequential" else 1,
+           "kind": "oracle",
+           "sample": (f"{sample.n_elems} elements of {name}: cell layers {layers} (4/3/2/1 layers from the middle "
+                      f"of the hex8/tet4/pen6/pyr5 bands, the workload's family mix); FP64 C oracle at -O3, graph "
+                      f"excluded, median of 5 runs per variant, best variant '{best}'; whole-mesh time "
+                      f"extrapolated at this rate: {mesh.n_elems / rate:.1f} s"),
+           "variants_s": {k: round(v, 3) for k, v in runs.items()},
+           "variants_elements_per_s": {k: round(sample.n_elems / v, 1) for k, v in runs.items()},
+           "omp_threads": threads, "nproc": os.cpu_count(), "cpu_model": model,
+           "omp_proc_bind": os.environ.get("OMP_PROC_BIND", "")}
+    # accuracy of the GPU forms against the oracle on a smaller sample
+    acc_layers = sum((mid_layers(k, 1) for k in range(4)), [])
+    am = mg.layer_sample(mesh, acc_layers)
+    ag = oracle.mesh_graph(am)
+    ov, orhs, tv, tr = oracle.assemble(am, ag, model=oracle.ELASTIC, with_terms=True)
+    dma = fea.DeviceMesh(am, device="cuda:0")
+    ga = dma.graph()
+    scale = np.repeat(_row_max(np, ov, ag.row_ptr), 9)
+    L = max({0: 1, 1: 8, 2: 6, 3: 8}[int(t)] for t in np.unique(am.types)) + 12
+    gam = L * 2.0 ** -24 / (1 - L * 2.0 ** -24)
+    accuracy = {"sample": f"{am.n_elems} elements of {name}: cell layers {acc_layers} (one per band)",
+                "fp32_bound": f"|v32 - v64| <= gamma_L T + 1e-12 rowscale, L = {L}"}
+    for pname, (p, o) in PRECISIONS.items():
+        v, r, s = dma.assemble(ga, variant=fea.ROWSYM, precision=p, out_dtype=o)
+        torch.cuda.synchronize()
+        v = v.cpu().numpy().astype(np.float64)
+        r = r.cpu().numpy().astype(np.float64)
+        err = np.abs(v - ov)
+        rec = {"status_ok": int(s.item()) == -1,
+               "max_row_scaled": float((err / scale).max()),
+               "median_row_scaled": float(np.median(err / scale)),
+               "rhs_max_rel": float(np.abs(r - orhs).max() / np.abs(orhs).max())}
+        if pname == "mixed":
+            bound = gam * tv + 1e-12 * scale
+            ratio = err / bound
+            rec.update({"max_err_over_bound": float(ratio.max()), "median_err_over_bound": float(np.median(ratio)),
+                        "max_abs_err": float(err.max()), "median_abs_err": float(np.median(err))})
+        accuracy[pname] = rec
+    ga.destroy()
+    del dma
+    torch.cuda.empty_cache()
+    return cpu, accuracy
+
+
+def _row_max(np, vals, row_ptr):
+    """max_j |A(i, j)| of every block row i, broadcast to its blocks."""
+    a = np.abs(vals.reshape(-1, 9)).max(axis=1)
+    nr = np.diff(row_ptr)
+    rm = np.zeros(row_ptr.size - 1)
+    nz = nr > 0
+    rm[nz] = np.maximum.reduceat(a, row_ptr[:-1][nz])
+    out = np.repeat(rm, nr)
+    out[out == 0] = 1.0
     return out
 
 
@@ -600,14 +893,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cells", type=int, default=96)
+    ap.add_argument("--workload", default="hybrid256", choices=["hybrid256", "hybrid96"])
     ap.add_argument("--variant", default="rowsym")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 workload")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other scatter forms")
+    ap.add_argument("--no-small", action="store_true", help="skip the hybrid96 companion workload")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched and heterogeneous-cost workloads")
+                    help="skip the subgrid-scale, batched, heterogeneous-cost and persistent workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -633,217 +926,81 @@ def main():
     import paper_1805_03949_amd as fea
 
     t0 = time.time()
-    mesh = mg.hybrid_bands(args.cells, seed=2)
-    print(f"[bench] mesh {mesh.n_elems} elements in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    dm = fea.DeviceMesh(mesh, device="cuda:0")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g = dm.graph()
-    torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - t0) * 1e3
-
-    prec = fea.FP64 if args.precision == "fp64" else fea.MIXED
-    outd = fea.F64 if prec == fea.FP64 else fea.F32
-    var = fea.VARIANTS[args.variant]
-    B = 3
-    s_c = 8 if prec == fea.FP64 else 4
-    s_v = 8 if outd == fea.F64 else 4
-    conn_len = int(mesh.conn_ptr[-1])
-
-    vals, rhs, st = dm.assemble(g, variant=var, precision=prec, out_dtype=outd)
-
-    def step(timing=False):
-        dm.assemble(g, variant=var, precision=prec, out_dtype=outd, vals=vals, rhs=rhs, status=st,
-                    timing=timing)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    assert int(st.item()) == -1, "an element was rejected"
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    print(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
-
-    # phase durations from HIP events recorded by the library on its stream
-    phases, classes = [], []
-    for _ in range(max(5, min(args.steps, 20))):
-        step(timing=True)
-        phases.append(g.last_timing())
-        if args.variant == "rowgather":
-            classes.append(g.last_class_timing())
-    ph = np.median(np.array(phases), axis=0)
-    elem_ms, second_ms = float(ph[0]), float(ph[1])
-    # sizes of the upper-triangle layout (built by its first assembly)
-    vs, rs, ss = dm.assemble(g, variant=fea.ROWSYM)
-    del vs, rs, ss
-    sym = g.sym_sizes()
-    ulen, nup = sym["tile_blocks"], sym["upper_blocks"]
-    eb = element_bytes(g, B, s_c, s_v, conn_len, mesh.n_nodes, mesh.n_elems, args.variant, sym)
+    mesh = workload_mesh(mg, args.workload)
+    print(f"[bench] {args.workload}: {mesh.n_elems} elements in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     copy_gbps = copy_bandwidth(torch)
-    class_ms = None
-    if args.variant == "rowgather":
-        # dominant kernel: the row-tile class kernel that takes longest; its
-        # bound is FP64 (vector ALU) arithmetic, not HBM
-        cm = np.median(np.array(classes), axis=0)
-        class_ms = {n: round(float(v), 4) for n, v in zip(GATHER_FAMILIES, cm)}
-        flops, executed = gather_class_flops(mesh, np)
-        c = int(np.argmax(cm))
-        kernel, k_ms, k_work = f"k_gather<{GATHER_FAMILIES[c]}>", float(cm[c]), flops[c]
-        achieved = k_work / (k_ms * 1e-3) / 1e12
-        peak = PEAK_FP64_TFLOPS if prec == fea.FP64 else PEAK_FP32_TFLOPS
-        roofline = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 2), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                    "traffic": traffic_from_profile(kernel, "gather.hip"),
-                    "algorithmic_flops": int(k_work), "kernel_ms": round(k_ms, 4),
-                    "executed_flops": int(executed[c]),
-                    "executed_TFLOPs": round(executed[c] / (k_ms * 1e-3) / 1e12, 2),
-                    "note": "algorithmic: per-element element-matrix flops exploiting the sparsity of B, "
-                            "1/n of an element per (row, element) pair; executed: the kernel's own "
-                            "operations, geometry recomputed per pair"}
-    elif args.variant in ("rowowner", "rowsym"):
-        if args.variant == "rowowner":
-            kernel, k_bytes = "k_segsum<9>", reduce_bytes(g, B, s_c, s_v)
-        else:
-            kernel, k_bytes = "k_segsum<9,sym>", sym_reduce_bytes(ulen, nup, g.nnz, B, s_c, s_v)
-        k_ms = second_ms
-        achieved = k_bytes / (k_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
-                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                    "traffic": traffic_from_profile(kernel + ("" if prec == fea.FP64 else ",mixed"), "segsum.h"),
-                    "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4),
-                    "copy_GBps": copy_gbps, "frac_of_copy": round(achieved / copy_gbps, 4)}
-    else:
-        kernel, k_ms, k_bytes = f"{args.variant} element phase", elem_ms, eb
-        achieved = k_bytes / (k_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
-                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                    "traffic": None, "algorithmic_bytes": int(k_bytes), "kernel_ms": round(k_ms, 4)}
-
-    variants = {}
-    if not args.no_variants:
-        for vname in ("rowgather", "rowsym", "tilecolour", "rowowner", "atomic", "colour"):
-            for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
-                vv, rr, ss = dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o)
-                dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o, vals=vv, rhs=rr, status=ss)
-                ts = []
-                for _ in range(5):
-                    dm.assemble(g, variant=fea.VARIANTS[vname], precision=p, out_dtype=o, vals=vv, rhs=rr,
-                                status=ss, timing=True)
-                    ts.append(g.last_timing())
-                med = np.median(np.array(ts), axis=0)
-                variants[f"{vname}_{pname}"] = {"total_ms": round(float(med[2]), 4),
-                                                "element_ms": round(float(med[0]), 4),
-                                                "block_value_kernel_ms": round(float(med[1]), 4),
-                                                "elements_per_s": round(mesh.n_elems / (float(med[2]) * 1e-3), 1)}
-                del vv, rr, ss
-        torch.cuda.synchronize()
-        # HBM rooflines of the block-value kernels of the two-phase forms
-        for vkey, kname, sc in (("rowowner_fp64", "k_segsum<9>", 8), ("rowowner_mixed", "k_segsum<9>,mixed", 4),
-                                ("rowsym_fp64", "k_segsum<9,sym>", 8), ("rowsym_mixed", "k_segsum<9,sym>,mixed", 4)):
-            ro = variants[vkey]
-            rb = (reduce_bytes(g, B, sc, sc) if vkey.startswith("rowowner")
-                  else sym_reduce_bytes(ulen, nup, g.nnz, B, sc, sc))
-            ra = rb / (ro["block_value_kernel_ms"] * 1e-3) / 1e9
-            variants[vkey]["roofline"] = {
-                "bound": "hbm", "kernel": kname, "achieved": round(ra, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(ra / PEAK_HBM_GBS, 4),
-                "traffic": traffic_from_profile(kname, "segsum.h"),
-                "algorithmic_bytes": int(rb), "copy_GBps": copy_gbps, "frac_of_copy": round(ra / copy_gbps, 4)}
-
-    print("[bench] subgrid scale", file=sys.stderr, flush=True)
-    sub, sub_u = subscale_workload(fea, mg, torch, np, mesh, dm, g)
+    head_variants = [] if args.no_variants else (["rowsym"] if args.workload == "hybrid256" else
+                                                 ["rowsym", "rowowner", "rowgather", "tilecolour", "atomic",
+                                                  "colour"])
+    head, dm, g = one_mesh_workload(fea, torch, np, mesh, args.workload, args, head_variants, copy_gbps)
 
     extras = {}
-    if not args.no_extras:
-        del vals, rhs
+    print("[bench] subgrid scale", file=sys.stderr, flush=True)
+    sub, _ = subscale_workload(fea, mg, torch, np, mesh, dm, g, name=args.workload)
+    g.destroy()
+    del dm, g
+    torch.cuda.empty_cache()
+
+    if args.workload == "hybrid256" and not args.no_small:
+        print("[bench] hybrid96", file=sys.stderr, flush=True)
+        small = workload_mesh(mg, "hybrid96")
+        sargs = argparse.Namespace(**{**vars(args), "steps": 20, "warmup": 3})
+        sv = [] if args.no_variants else ["rowsym", "rowowner", "rowgather", "tilecolour", "atomic", "colour"]
+        extras["hybrid96"], sdm, sg = one_mesh_workload(fea, torch, np, small, "hybrid96", sargs, sv, copy_gbps)
+        sg.destroy()
+        del sdm, sg
         torch.cuda.empty_cache()
+
+    if not args.no_extras:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         extras["batched"] = batched_workload(fea, mg, torch)
         torch.cuda.empty_cache()
         print("[bench] heterogeneous workload", file=sys.stderr, flush=True)
         extras["heterogeneous"] = heterogeneous_workload(fea, mg, torch, np)
         torch.cuda.empty_cache()
-        if not args.no_large:
-            print("[bench] large workload", file=sys.stderr, flush=True)
-            extras["large"] = large_workload(fea, mg, torch, np)
+        if args.workload == "hybrid256":
+            print("[bench] persistent form of the large workload", file=sys.stderr, flush=True)
+            extras["large_persistent"] = large_workload(fea, mg, torch, np, mesh=mesh)
             torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        import oracle
-        og = oracle.mesh_graph(mesh)
-        t0 = time.perf_counter()
-        oracle.assemble(mesh, og, model=oracle.ELASTIC)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": round(mesh.n_elems / cpu_s, 1), "unit": "elements/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"the whole workload ({mesh.n_elems} elements), FP64 C oracle, sequential "
-                         f"Algorithm 1 order, graph build excluded; {cpu_s:.1f} s"}
-        t0 = time.perf_counter()
-        oracle.subscale(mesh, sub_u.cpu().numpy(), model=oracle.ELASTIC)
-        sub_s = time.perf_counter() - t0
-        sub["cpu_baseline"] = {"value": round(mesh.n_elems / sub_s, 1), "unit": "elements/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"the whole subgrid-scale workload, FP64 C oracle; {sub_s:.1f} s"}
+        if args.workload == "hybrid256":
+            cpu, extras["accuracy"] = cpu_baseline_leg(fea, torch, np, mesh, args.workload)
+        else:
+            import oracle
+            og = oracle.mesh_graph(mesh)
+            t0 = time.perf_counter()
+            oracle.assemble(mesh, og, model=oracle.ELASTIC)
+            cpu_s = time.perf_counter() - t0
+            cpu = {"value": round(mesh.n_elems / cpu_s, 1), "unit": "elements/s", "cores": 1, "kind": "oracle",
+                   "sample": f"the whole workload ({mesh.n_elems} elements), FP64 C oracle, sequential "
+                             f"Algorithm 1 order, graph build excluded; {cpu_s:.1f} s"}
 
-    # scatter HBM rate of the two-phase (row-owner) form: its block-value
-    # kernel (the right-hand-side reduction runs before it, inside the
-    # element phase of the timing)
-    scatter = {"kernel": "k_segsum<9>", "copy_GBps": copy_gbps,
-               "note": "row-owner form, block-value kernel (workspace sorted by destination block)"}
-    if args.variant == "rowowner":
-        t2 = second_ms
-    elif "rowowner_" + args.precision in variants:
-        t2 = variants["rowowner_" + args.precision]["block_value_kernel_ms"]
-    else:
-        t2 = None
-    if t2:
-        rb = reduce_bytes(g, B, s_c, s_v)
-        eff = rb / (t2 * 1e-3) / 1e9
-        scatter.update({"algorithmic_bytes": int(rb), "effective_GBps": round(eff, 1),
-                        "frac_of_peak": round(eff / PEAK_HBM_GBS, 4), "frac_of_copy": round(eff / copy_gbps, 4),
-                        "ms": round(t2, 4)})
-    tr = traffic_from_profile("k_segsum<9>" + ("" if prec == fea.FP64 else ",mixed"), "segsum.h")
-    if tr and t2:
-        scatter["counter_GBps"] = round(tr / (t2 * 1e-3) / 1e9, 1)
-
-    value = mesh.n_elems / (ms_per_step * 1e-3)
+    value = head["elements_per_s"]
     out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": value,
         "unit": "elements/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == fea.FP64 else "f32+f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"hybrid{args.cells}-elasticity (hex8/pen6/tet4/pyr5 z-bands, 3x3 BSR)",
-                   "elements": mesh.n_elems, "nodes": mesh.n_nodes, "nnz_blocks": g.nnz,
-                   "variant": args.variant, "precision": args.precision,
-                   "out_dtype": "f64" if outd == fea.F64 else "f32"},
-        "roofline": roofline,
-        "scatter": scatter,
-        "gather_class_ms": class_ms,
-        "element_phase": {"algorithmic_bytes": int(eb), "ms": round(elem_ms, 4),
-                          "effective_GBps": round(eb / (elem_ms * 1e-3) / 1e9, 1)},
-        "phases_ms": {"element": round(elem_ms, 4), "block_value_kernel": round(second_ms, 4),
-                      "total": round(float(ph[2]), 4)},
-        "graph_build_ms": round(graph_ms, 2),
-        "variants": variants,
-        "subscale": sub,
-        **extras,
+        "config": {"workload": head["workload"], "elements": head["elements"], "nodes": head["nodes"],
+                   "nnz_blocks": head["nnz_blocks"], "variant": args.variant, "precision": args.precision,
+                   "out_dtype": "f64" if args.precision == "fp64" else "f32"},
+        "roofline": head.get("roofline"),
         "cpu_baseline": cpu,
+        "headline": head,
+        "subscale": sub,
+        "copy_GBps": copy_gbps,
+        **extras,
     }
     print(json.dumps(out), flush=True)
 

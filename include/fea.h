@@ -72,13 +72,15 @@ enum fea_precision { FEA_FP64 = 0, FEA_MIXED = 1 };
  *             deterministic, and A equals its transpose bitwise. Also
  *             runs batched (fea_batch_assemble);
  *   TILECOLOUR the GPU counterpart of commutative multidependences
- *             (Algorithm 7): the ROWSYM element tiles, greedily coloured so
- *             that no two tiles of a colour share a node (built by the
- *             first such call, on the host); one launch per (colour,
- *             family), each tile adding its LDS tile sums and their
- *             transposes straight into FP64 block values (no block
- *             workspace, no atomics); right-hand side as ROWOWNER;
- *             deterministic. Single-mesh assembly only. */
+ *             (Algorithm 7): the ROWSYM element tiles, greedily coloured in
+ *             descending neighbour count so that no two tiles of a colour
+ *             share a node (built by the first such call, on the host;
+ *             fea_graph_tile_colouring exports it); one launch per
+ *             (colour, family), its tiles in descending neighbour count,
+ *             each tile adding its LDS tile sums and their transposes
+ *             straight into FP64 block values (no block workspace, no
+ *             atomics); right-hand side as ROWOWNER; deterministic.
+ *             Single-mesh assembly only. */
 enum fea_variant { FEA_ROWOWNER = 0, FEA_ATOMIC = 1, FEA_COLOUR = 2, FEA_ROWGATHER = 3, FEA_ROWSYM = 4,
                    FEA_TILECOLOUR = 5 };
 enum fea_dtype { FEA_F64 = 0, FEA_F32 = 1 };
@@ -142,6 +144,22 @@ int fea_graph_sizes(const fea_graph *g, int64_t *n_nodes, int64_t *n_elems,
  * layout has not been built yet. */
 int fea_graph_sym_sizes(const fea_graph *g, int64_t *tiles, int64_t *entries, int64_t *tile_blocks,
                         int64_t *upper_blocks);
+
+/* The tile colouring of FEA_TILECOLOUR (built by the first such call; the
+ * counterpart of Algorithm 7's commutative multidependences with priority
+ * by neighbour count, Section 3.2): tiles sharing a node are neighbours,
+ * nneig is a tile's neighbour count, tiles are coloured greedily (first fit)
+ * in descending nneig, ties by tile index. *n_colours = C; bucket_ptr (HOST
+ * int64[4 * (C + 1)]): family t's colour-c tiles are
+ * tiles[bucket_ptr[t*(C+1)+c] .. bucket_ptr[t*(C+1)+c+1]) (the end of
+ * family t's last colour is the start of family t+1's first); tiles (DEVICE
+ * int32[n_tiles], enqueued on `stream`): family-local tile indices in launch
+ * order, descending nneig within a bucket; nneig (HOST int32[n_tiles]):
+ * the neighbour count of every tile, families in order (tile
+ * fea_graph_sym_sizes order). Any output may be NULL. FEA_EINVAL if the
+ * colouring has not been built. */
+int fea_graph_tile_colouring(const fea_graph *g, int *n_colours, int64_t *bucket_ptr, int32_t *tiles,
+                             int32_t *nneig, hipStream_t stream);
 
 /* Copies graph arrays into caller-owned DEVICE buffers (any may be NULL):
  * row_ptr[n_nodes+1], col[nnz], map_ptr[n_elems+1], e2nnz[map_len],
@@ -311,6 +329,11 @@ int fea_batch_set_tiles(fea_batch *b, const int32_t *tile);
  * persistent launch and queue, in family order). Returns to the dynamic
  * queue and drops a captured graph. FEA_EINVAL if not a permutation. */
 int fea_batch_set_order(fea_batch *b, const int32_t *order);
+
+/* The current queue order (HOST int32[n_items]): the permutation set by
+ * fea_batch_set_order or fea_batch_order (identity after fea_batch_build,
+ * fea_batch_set_tiles and fea_batch_partition). */
+int fea_batch_get_order(const fea_batch *b, int32_t *order);
 
 /*
  * One batched assembly on `stream`: reset the queue heads, one persistent

@@ -51,6 +51,7 @@ _lib.fea_graph_sizes.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                  ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int)]
 _lib.fea_graph_sym_sizes.argtypes = [_P] + [ctypes.POINTER(_I64)] * 4
 _lib.fea_graph_export.argtypes = [_P] * 9 + [ctypes.POINTER(_I64), _P]
+_lib.fea_graph_tile_colouring.argtypes = [_P, ctypes.POINTER(ctypes.c_int), _P, _P, _P, _P]
 _lib.fea_graph_destroy.argtypes = [_P]
 _lib.fea_graph_destroy.restype = None
 _lib.fea_assemble.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Material), _P,
@@ -81,6 +82,7 @@ _lib.fea_batch_offsets.argtypes = [_P, _I64P, _I64P]
 _lib.fea_batch_items.argtypes = [_P, _I32P]
 _lib.fea_batch_set_tiles.argtypes = [_P, _I32P]
 _lib.fea_batch_set_order.argtypes = [_P, _I32P]
+_lib.fea_batch_get_order.argtypes = [_P, _I32P]
 _lib.fea_batch_assemble.argtypes = [_P, ctypes.POINTER(Options), _P, _P, _P, _P]
 _lib.fea_batch_capture.argtypes = [_P, ctypes.POINTER(Options), _P, _P, _P, _P]
 _lib.fea_batch_replay.argtypes = [_P, ctypes.c_int, _P]
@@ -114,10 +116,11 @@ N_FEATURES, N_PARAMS = 12, 5057
 
 # every exported symbol declared in include/fea.h
 EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_sym_sizes", "fea_graph_export", "fea_graph_destroy",
+           "fea_graph_tile_colouring",
            "fea_assemble", "fea_assemble_noalloc", "fea_last_timing", "fea_graph_gauss_points", "fea_subscale",
            "fea_batch_gauss_points", "fea_batch_subscale", "fea_last_class_timing", "fea_last_error", "fea_version",
            "fea_batch_build", "fea_batch_sizes", "fea_batch_offsets", "fea_batch_items",
-           "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_assemble", "fea_batch_capture",
+           "fea_batch_set_tiles", "fea_batch_set_order", "fea_batch_get_order", "fea_batch_assemble", "fea_batch_capture",
            "fea_batch_replay", "fea_batch_cycles", "fea_batch_last_ms", "fea_batch_workers",
            "fea_batch_destroy", "fea_batch_autotune", "fea_tile_table_load", "fea_batch_order",
            "fea_batch_partition",
@@ -207,6 +210,20 @@ class Graph:
         v = [_I64() for _ in range(4)]
         _check(_lib.fea_graph_sym_sizes(self.handle, *[ctypes.byref(x) for x in v]))
         return dict(zip(("tiles", "entries", "tile_blocks", "upper_blocks"), (x.value for x in v)))
+
+    def tile_colouring(self, stream=None):
+        """(n_colours, bucket_ptr[4 * (C + 1)], tiles (device int32), nneig)
+        of the tile-coloured form (after its first assembly)."""
+        nc = ctypes.c_int()
+        _check(_lib.fea_graph_tile_colouring(self.handle, ctypes.byref(nc), None, None, None, _stream(stream)))
+        import numpy as np
+        sz = self.sym_sizes()
+        bp = np.zeros(4 * (nc.value + 1), dtype=np.int64)
+        nneig = np.zeros(max(sz["tiles"], 1), dtype=np.int32)
+        tiles = torch.empty(max(sz["tiles"], 1), dtype=torch.int32, device=self.device)
+        _check(_lib.fea_graph_tile_colouring(self.handle, ctypes.byref(nc), bp.ctypes.data_as(_P),
+                                             _ptr(tiles), nneig.ctypes.data_as(_P), _stream(stream)))
+        return nc.value, bp, tiles[:sz["tiles"]], nneig[:sz["tiles"]]
 
     def gauss_points(self, stream=None):
         """(n_points, gp_ptr): total Gauss points and the device offsets of
@@ -398,6 +415,12 @@ class Batch:
         arr, p = _np_i32(order)
         _check(_lib.fea_batch_set_order(self._h, p))
 
+    def get_order(self):
+        import numpy as np
+        out = np.zeros(max(1, self.n_items), dtype=np.int32)
+        _check(_lib.fea_batch_get_order(self._h, out.ctypes.data_as(_I32P)))
+        return out[: self.n_items]
+
     def outputs(self, out_dtype=F64):
         odt = torch.float64 if out_dtype == F64 else torch.float32
         return (torch.empty(self.vals_len, dtype=odt, device=self.device),
@@ -460,6 +483,20 @@ class Batch:
         w = ctypes.c_int()
         _check(_lib.fea_batch_workers(self._h, ctypes.byref(w)))
         return int(w.value)
+
+    def tile_colouring(self, stream=None):
+        """(n_colours, bucket_ptr[4 * (C + 1)], tiles (device int32), nneig)
+        of the tile-coloured form (after its first assembly)."""
+        nc = ctypes.c_int()
+        _check(_lib.fea_graph_tile_colouring(self.handle, ctypes.byref(nc), None, None, None, _stream(stream)))
+        import numpy as np
+        sz = self.sym_sizes()
+        bp = np.zeros(4 * (nc.value + 1), dtype=np.int64)
+        nneig = np.zeros(max(sz["tiles"], 1), dtype=np.int32)
+        tiles = torch.empty(max(sz["tiles"], 1), dtype=torch.int32, device=self.device)
+        _check(_lib.fea_graph_tile_colouring(self.handle, ctypes.byref(nc), bp.ctypes.data_as(_P),
+                                             _ptr(tiles), nneig.ctypes.data_as(_P), _stream(stream)))
+        return nc.value, bp, tiles[:sz["tiles"]], nneig[:sz["tiles"]]
 
     def gauss_points(self, stream=None):
         """Offsets (n_meshes + 1) of every mesh's Gauss points in the

@@ -1044,6 +1044,14 @@ extern "C" int fea_batch_set_tiles(fea_batch *b, const int32_t *tile)
     return build_items(b);
 }
 
+extern "C" int fea_batch_get_order(const fea_batch *b, int32_t *order)
+{
+    clear_error();
+    if (!b || !order) return set_error(FEA_EINVAL, "batch and order are required");
+    std::copy(b->order.begin(), b->order.end(), order);
+    return FEA_OK;
+}
+
 extern "C" int fea_batch_set_order(fea_batch *b, const int32_t *order)
 {
     clear_error();

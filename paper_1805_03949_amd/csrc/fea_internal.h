@@ -166,12 +166,14 @@ struct fea_graph {
     int64_t *ts_ptr = nullptr;
     int64_t ulen = 0, nent = 0;
     // Tile colouring (built by the first FEA_TILECOLOUR assembly): greedy
-    // first-fit over the tiles in tile order, no two tiles of a colour
-    // sharing a node; bucket (t, c) = family t's tiles of colour c,
-    // ctile[tcseg[t*(tc_colours+1)+c] .. tcseg[t*(tc_colours+1)+c+1])
-    // (family-local tile indices, ascending; tcseg is a host copy).
+    // first-fit over the tiles in descending neighbour count, no two tiles
+    // of a colour sharing a node; bucket (t, c) = family t's tiles of
+    // colour c, ctile[tcseg[t*(tc_colours+1)+c] .. tcseg[t*(tc_colours+1)+c+1])
+    // (family-local tile indices in descending neighbour count, ties by
+    // index; tcseg is a host copy).
     int32_t *ctile = nullptr;
     std::vector<int64_t> tcseg;
+    std::vector<int32_t> tc_nneig;  // neighbour count of every tile (global tile index)
     int tc_colours = 0;
     bool tcready = false;
     bool sready = false;

@@ -11,6 +11,7 @@
 #include <cstring>
 
 #include "fea_internal.h"
+#include "host_graph.h"
 
 namespace fea {
 
@@ -541,66 +542,51 @@ int sym_prepare(fea_graph *g, hipStream_t s)
     return FEA_OK;
 }
 
-// Greedy first-fit colouring of the upper-triangle tiles in tile order (a
-// tile's nodes are its elements' nodes); the tiles of one colour share no
-// node, so no block either. Sequential by definition: on the host.
+// Colouring of the upper-triangle tiles, the GPU counterpart of the
+// commutative multidependences of Algorithm 7: a tile's nodes are its
+// elements' nodes, tiles sharing a node are neighbours, and a tile's
+// priority is its neighbour count (nneig). Tiles are coloured greedily
+// (first fit) in descending priority, so that the tiles of one colour
+// share no node and no block, and each (family, colour) launch lists its
+// tiles in descending priority too, so that the most connected tiles are
+// dispatched first. Sequential by definition: on the host.
 int tile_colour_prepare(fea_graph *g, hipStream_t s)
 {
     const int64_t N = g->n_nodes, C = g->conn_len;
     std::vector<int32_t> pn(std::max<int64_t>(C, 1));
     if (C) FEA_HIP(hipMemcpyAsync(pn.data(), g->pnodes, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
     FEA_HIP(hipStreamSynchronize(s));
-    constexpr int kWords = 4;  // up to 256 colours
-    std::vector<uint64_t> used((size_t)N * kWords, 0);
     const int64_t nt = g->tile_base[4];
-    std::vector<int16_t> colour(std::max<int64_t>(nt, 1));
-    int ncol = 0;
+    // node ranges of the tiles in pnodes (families and tiles are contiguous)
+    std::vector<int64_t> ptr((size_t)nt + 1, 0);
+    std::vector<uint8_t> fam((size_t)std::max<int64_t>(nt, 1), 0);
     for (int t = 0; t < 4; ++t) {
         const int n = nodes_of(t), epb = sym_epb(t);
         const int64_t ne = g->seg[t + 1] - g->seg[t];
         for (int64_t i = 0; i < g->tile_base[t + 1] - g->tile_base[t]; ++i) {
-            const int64_t e0 = i * epb, e1 = std::min<int64_t>(ne, e0 + epb);
-            const int32_t *p0 = pn.data() + g->node_base[t] + e0 * n, *p1 = pn.data() + g->node_base[t] + e1 * n;
-            uint64_t m[kWords] = {0, 0, 0, 0};
-            for (const int32_t *p = p0; p < p1; ++p)
-                for (int w = 0; w < kWords; ++w) m[w] |= used[(size_t)*p * kWords + w];
-            int c = -1;
-            for (int w = 0; w < kWords && c < 0; ++w)
-                if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
-            if (c < 0) return set_error(FEA_ERANGE, "tile %lld needs more than 256 colours", (long long)i);
-            colour[g->tile_base[t] + i] = (int16_t)c;
-            ncol = std::max(ncol, c + 1);
-            for (const int32_t *p = p0; p < p1; ++p) used[(size_t)*p * kWords + c / 64] |= 1ull << (c % 64);
+            ptr[(size_t)(g->tile_base[t] + i + 1)] = g->node_base[t] + std::min<int64_t>(ne, (i + 1) * epb) * n;
+            fam[(size_t)(g->tile_base[t] + i)] = (uint8_t)t;
         }
     }
-    // stable buckets by (family, colour) of family-local tile indices
-    std::vector<int64_t> seg((size_t)4 * (ncol + 1), 0);
-    for (int t = 0; t < 4; ++t)
-        for (int64_t i = g->tile_base[t]; i < g->tile_base[t + 1]; ++i) seg[(size_t)t * (ncol + 1) + colour[i] + 1]++;
-    int64_t run = 0;
-    for (int t = 0; t < 4; ++t)
-        for (int c = 0; c <= ncol; ++c) {
-            int64_t &v = seg[(size_t)t * (ncol + 1) + c];
-            if (c == 0) {
-                v = run;
-                continue;
-            }
-            run += v;
-            v = run;
-        }
-    std::vector<int64_t> cur(seg);
-    std::vector<int32_t> ctile(std::max<int64_t>(nt, 1));
-    for (int t = 0; t < 4; ++t)
-        for (int64_t i = g->tile_base[t]; i < g->tile_base[t + 1]; ++i)
-            ctile[cur[(size_t)t * (ncol + 1) + colour[i]]++] = (int32_t)(i - g->tile_base[t]);
+    std::vector<int32_t> nneig((size_t)std::max<int64_t>(nt, 1), 0);
+    host::neighbour_counts(N, nt, ptr.data(), pn.data(), nneig.data());
+    const std::vector<int64_t> order = host::priority_order(nt, nneig.data());
+    std::vector<int16_t> colour((size_t)std::max<int64_t>(nt, 1), 0);
+    const int64_t ncol = host::greedy_first_fit(N, nt, ptr.data(), pn.data(), order.data(), colour.data());
+    if (ncol < 0)
+        return set_error(FEA_ERANGE, "tile %lld needs more than %d colours", (long long)(-ncol - 1), host::kMaxColours);
+    std::vector<int64_t> seg;
+    std::vector<int32_t> ctile;
+    host::buckets(nt, 4, fam.data(), colour.data(), (int)ncol, order.data(), g->tile_base, seg, ctile);
     dfree(g->ctile);
     g->ctile = nullptr;
     int rc;
     if ((rc = dalloc((void **)&g->ctile, sizeof(int32_t) * std::max<int64_t>(nt, 1)))) return rc;
     if (nt) FEA_HIP(hipMemcpyAsync(g->ctile, ctile.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, s));
     FEA_HIP(hipStreamSynchronize(s));
-    g->tc_colours = ncol;
+    g->tc_colours = (int)ncol;
     g->tcseg = std::move(seg);
+    g->tc_nneig = std::move(nneig);
     g->tcready = true;
     return FEA_OK;
 }
@@ -621,37 +607,15 @@ static int colour_host(fea_graph *g, const int64_t *conn_ptr_d, const int32_t *c
         FEA_HIP(hipMemcpyAsync(cn.data(), conn_d, sizeof(int32_t) * g->conn_len, hipMemcpyDeviceToHost, s));
     if (E) FEA_HIP(hipMemcpyAsync(ty.data(), types_d, E, hipMemcpyDeviceToHost, s));
     FEA_HIP(hipStreamSynchronize(s));
-    constexpr int kWords = 4;  // up to 256 colours
-    std::vector<uint64_t> used((size_t)N * kWords, 0);
-    std::vector<int16_t> colour(E);
-    int ncol = 0;
-    for (int64_t e = 0; e < E; ++e) {
-        uint64_t m[kWords] = {0, 0, 0, 0};
-        for (int64_t p = cp[e]; p < cp[e + 1]; ++p)
-            for (int w = 0; w < kWords; ++w) m[w] |= used[(size_t)cn[p] * kWords + w];
-        int c = -1;
-        for (int w = 0; w < kWords && c < 0; ++w)
-            if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
-        if (c < 0) return set_error(FEA_ERANGE, "element %lld needs more than 256 colours", (long long)e);
-        colour[e] = (int16_t)c;
-        ncol = std::max(ncol, c + 1);
-        for (int64_t p = cp[e]; p < cp[e + 1]; ++p)
-            used[(size_t)cn[p] * kWords + c / 64] |= 1ull << (c % 64);
-    }
-    // stable buckets by (family, colour)
-    std::vector<int64_t> cseg((size_t)4 * (ncol + 1), 0);
-    for (int64_t e = 0; e < E; ++e) cseg[(size_t)ty[e] * (ncol + 1) + colour[e] + 1]++;
-    int64_t run = 0;
-    for (int t = 0; t < 4; ++t)
-        for (int c = 0; c <= ncol; ++c) {
-            int64_t &v = cseg[(size_t)t * (ncol + 1) + c];
-            if (c == 0) { v = run; continue; }
-            run += v;
-            v = run;
-        }
-    std::vector<int64_t> cur(cseg);
-    std::vector<int32_t> cperm(E);
-    for (int64_t e = 0; e < E; ++e) cperm[cur[(size_t)ty[e] * (ncol + 1) + colour[e]]++] = (int32_t)e;
+    std::vector<int16_t> colour((size_t)std::max<int64_t>(E, 1), 0);
+    const int64_t ncol = host::greedy_first_fit(N, E, cp.data(), cn.data(), nullptr, colour.data());
+    if (ncol < 0)
+        return set_error(FEA_ERANGE, "element %lld needs more than %d colours", (long long)(-ncol - 1),
+                         host::kMaxColours);
+    // stable buckets by (family, colour) of element ids
+    std::vector<int64_t> cseg;
+    std::vector<int32_t> cperm;
+    host::buckets(E, 4, ty.data(), colour.data(), (int)ncol, nullptr, nullptr, cseg, cperm);
     int rc;
     if ((rc = dalloc((void **)&g->colour, sizeof(int16_t) * std::max<int64_t>(E, 1)))) return rc;
     if ((rc = dalloc((void **)&g->cperm, sizeof(int32_t) * std::max<int64_t>(E, 1)))) return rc;
@@ -660,7 +624,7 @@ static int colour_host(fea_graph *g, const int64_t *conn_ptr_d, const int32_t *c
         FEA_HIP(hipMemcpyAsync(g->cperm, cperm.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice, s));
     }
     FEA_HIP(hipStreamSynchronize(s));
-    g->n_colours = ncol;
+    g->n_colours = (int)ncol;
     g->cseg = std::move(cseg);
     return FEA_OK;
 }
@@ -842,6 +806,21 @@ extern "C" int fea_graph_build(int64_t n_nodes, int64_t n_elems, const uint8_t *
         return rc;
     }
     *out = g;
+    return FEA_OK;
+}
+
+extern "C" int fea_graph_tile_colouring(const fea_graph *g, int *n_colours, int64_t *bucket_ptr, int32_t *tiles,
+                                        int32_t *nneig, hipStream_t stream)
+{
+    clear_error();
+    if (!g) return set_error(FEA_EINVAL, "graph is NULL");
+    if (!g->tcready) return set_error(FEA_EINVAL, "the tile colouring has not been built (no FEA_TILECOLOUR call yet)");
+    if (n_colours) *n_colours = g->tc_colours;
+    if (bucket_ptr) std::copy(g->tcseg.begin(), g->tcseg.end(), bucket_ptr);
+    const int64_t nt = g->tile_base[4];
+    if (nneig && nt) std::copy(g->tc_nneig.begin(), g->tc_nneig.begin() + nt, nneig);
+    if (tiles && nt)
+        FEA_HIP(hipMemcpyAsync(tiles, g->ctile, sizeof(int32_t) * nt, hipMemcpyDeviceToDevice, stream));
     return FEA_OK;
 }
 

@@ -1,0 +1,120 @@
+// Host-side graph steps that are sequential by definition: greedy
+// first-fit colouring of items (elements, or element tiles) over the
+// node-sharing graph, the neighbour count of every item, and the
+// (family, colour) buckets the colour-by-colour launches walk. Plain C++
+// (no HIP), so that it also builds and runs under the host sanitizers.
+//
+// An item is a list of node ids: item i holds nodes[ptr[i] .. ptr[i+1]).
+// Two items are neighbours when they share a node.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+namespace fea {
+namespace host {
+
+constexpr int kMaxColours = 256;
+
+// Greedy first fit (Algorithm 5's colouring): items are visited in `order`
+// (all n_items of them; nullptr = ascending), and each takes the smallest
+// colour that no neighbour visited before it holds. Returns the number of
+// colours, or -(1 + i) when item i would need more than kMaxColours.
+inline int64_t greedy_first_fit(int64_t n_nodes, int64_t n_items, const int64_t *ptr, const int32_t *nodes,
+                                const int64_t *order, int16_t *colour)
+{
+    constexpr int kWords = kMaxColours / 64;
+    std::vector<uint64_t> used((size_t)std::max<int64_t>(n_nodes, 1) * kWords, 0);
+    int ncol = 0;
+    for (int64_t k = 0; k < n_items; ++k) {
+        const int64_t i = order ? order[k] : k;
+        uint64_t m[kWords] = {0, 0, 0, 0};
+        for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p)
+            for (int w = 0; w < kWords; ++w) m[w] |= used[(size_t)nodes[p] * kWords + w];
+        int c = -1;
+        for (int w = 0; w < kWords && c < 0; ++w)
+            if (~m[w]) c = w * 64 + __builtin_ctzll(~m[w]);
+        if (c < 0) return -(1 + i);
+        colour[i] = (int16_t)c;
+        ncol = std::max(ncol, c + 1);
+        for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) used[(size_t)nodes[p] * kWords + c / 64] |= 1ull << (c % 64);
+    }
+    return ncol;
+}
+
+// nneig[i] = number of other items sharing at least one node with item i
+// (the neighbour count that sets a chunk's priority in Algorithm 7).
+inline void neighbour_counts(int64_t n_nodes, int64_t n_items, const int64_t *ptr, const int32_t *nodes,
+                             int32_t *nneig)
+{
+    // node -> items incidence
+    std::vector<int64_t> nptr((size_t)n_nodes + 1, 0);
+    for (int64_t i = 0; i < n_items; ++i)
+        for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) ++nptr[(size_t)nodes[p] + 1];
+    for (int64_t v = 0; v < n_nodes; ++v) nptr[(size_t)v + 1] += nptr[(size_t)v];
+    std::vector<int64_t> fill(nptr.begin(), nptr.end() - 1);
+    std::vector<int64_t> inc((size_t)std::max<int64_t>(nptr[(size_t)n_nodes], 1));
+    for (int64_t i = 0; i < n_items; ++i)
+        for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) inc[(size_t)fill[(size_t)nodes[p]]++] = i;
+    std::vector<int64_t> stamp((size_t)std::max<int64_t>(n_items, 1), -1);
+    for (int64_t i = 0; i < n_items; ++i) {
+        int32_t cnt = 0;
+        stamp[(size_t)i] = i;
+        for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+            const int32_t v = nodes[p];
+            for (int64_t q = nptr[(size_t)v]; q < nptr[(size_t)v + 1]; ++q) {
+                const int64_t j = inc[(size_t)q];
+                if (stamp[(size_t)j] != i) {
+                    stamp[(size_t)j] = i;
+                    ++cnt;
+                }
+            }
+        }
+        nneig[i] = cnt;
+    }
+}
+
+// Visit order by descending neighbour count, ties by ascending index.
+inline std::vector<int64_t> priority_order(int64_t n_items, const int32_t *nneig)
+{
+    std::vector<int64_t> order((size_t)n_items);
+    for (int64_t i = 0; i < n_items; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return nneig[a] > nneig[b]; });
+    return order;
+}
+
+// Buckets by (group, colour): group[i] in [0, n_groups), colour[i] in
+// [0, ncol). seg (n_groups * (ncol + 1) entries) receives, for group g, the
+// start of bucket (g, c) at seg[g * (ncol + 1) + c] and the end of its last
+// bucket at seg[g * (ncol + 1) + ncol] (= the start of group g + 1's first);
+// list receives the items bucket by bucket, each bucket in `order`
+// (nullptr = ascending), as item - first[group] (group-local indices).
+inline void buckets(int64_t n_items, int n_groups, const uint8_t *group, const int16_t *colour, int ncol,
+                    const int64_t *order, const int64_t *first, std::vector<int64_t> &seg,
+                    std::vector<int32_t> &list)
+{
+    seg.assign((size_t)n_groups * (ncol + 1), 0);
+    for (int64_t i = 0; i < n_items; ++i) seg[(size_t)group[i] * (ncol + 1) + colour[i] + 1]++;
+    int64_t run = 0;
+    for (int g = 0; g < n_groups; ++g)
+        for (int c = 0; c <= ncol; ++c) {
+            int64_t &v = seg[(size_t)g * (ncol + 1) + c];
+            if (c == 0) {
+                v = run;
+                continue;
+            }
+            run += v;
+            v = run;
+        }
+    std::vector<int64_t> cur(seg);
+    list.assign((size_t)std::max<int64_t>(n_items, 1), 0);
+    for (int64_t k = 0; k < n_items; ++k) {
+        const int64_t i = order ? order[k] : k;
+        const int g = group[i];
+        list[(size_t)cur[(size_t)g * (ncol + 1) + colour[i]]++] = (int32_t)(i - (first ? first[g] : 0));
+    }
+}
+
+}  // namespace host
+}  // namespace fea

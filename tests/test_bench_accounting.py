@@ -87,3 +87,33 @@ def test_subscale_work_counts_every_element_and_node_once():
     assert bench.subscale_flops_per_point(0, 3) == 4 * 18 + 43 + 1 + 3
     assert bench.subscale_flops_per_point(3, 3) == 8 * 72 + 43 + 282 + 1 + 3
     assert bench.subscale_flops_per_point(1, 1) == 5 * (18 + 18 + 12) + 43 + 56 + 1 + 1
+
+
+def test_layer_sample_keeps_the_elements_of_its_layers():
+    """The CPU baseline's sample: the elements of the chosen cell layers,
+    with their own coordinates, materials and node order."""
+    m = mg.hybrid_split(12, seed=5)
+    layers = [1, 6, 9, 11]
+    s = mg.layer_sample(m, layers)
+    epl = {t: 144 * n for t, n in enumerate((6, 6, 2, 1))}   # elements per layer by family
+    # layer offsets from the band definition
+    bands = mg.split_bands(12)
+    lt = np.concatenate([np.full(l, t) for t, l in bands])
+    start = np.concatenate([[0], np.cumsum([epl[int(t)] for t in lt])])
+    elems = np.concatenate([np.arange(start[L], start[L + 1]) for L in layers])
+    assert s.n_elems == elems.size
+    assert np.array_equal(s.types, m.types[elems])
+    for k in range(0, elems.size, 97):
+        e = elems[k]
+        on = m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]]
+        sn = s.conn[s.conn_ptr[k]:s.conn_ptr[k + 1]]
+        assert np.array_equal(m.x[on], s.x[sn]) and np.array_equal(m.z[on], s.z[sn])
+        assert s.nu[k] == m.nu[e]
+    assert np.unique(s.conn).size == s.n_nodes
+
+
+def test_row_max_by_hand():
+    vals = np.arange(27, dtype=np.float64) - 13.0     # 3 blocks
+    row_ptr = np.array([0, 2, 2, 3])
+    rm = bench._row_max(np, vals, row_ptr)
+    assert list(rm) == [13.0, 13.0, 13.0]

@@ -437,3 +437,64 @@ def test_residual_rejects_mixed_precision_and_row_gather():
         with pytest.raises(fea.FeaError) as ei:
             dm.assemble(g, model=fea.ELASTIC, use_nh=True, residual=True, **kw)
         assert ei.value.code == fea.FEA_EINVAL
+
+
+def _tile_node_sets(m):
+    """Node sets of the upper-triangle tiles on the host: per family the
+    stably type-sorted elements in tiles of 256 // (n(n+1)/2)."""
+    order = np.argsort(m.types, kind="stable")
+    tiles, fam = [], []
+    for t in range(4):
+        idx = order[m.types[order] == t]
+        n = (4, 5, 6, 8)[t]
+        epb = 256 // (n * (n + 1) // 2)
+        for i in range(0, idx.size, epb):
+            tiles.append(set(int(v) for e in idx[i:i + epb] for v in m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]]))
+            fam.append(t)
+    return tiles, np.array(fam, dtype=np.int64)
+
+
+@pytest.mark.parametrize("name", ["bands8_jitter", "mix6_jitter", "tet_ragged"])
+def test_tile_colouring_is_valid_and_prioritised(name):
+    """The exported tile colouring (Algorithm 7's commutative
+    multidependences with priority by neighbour count), checked by brute
+    force on the host: every tile in exactly one (family, colour) bucket,
+    the tiles of a bucket pairwise node-disjoint, neighbour counts exact,
+    buckets in descending neighbour count (ties by index), and each tile's
+    colour the first fit among its neighbours visited before it in that
+    priority order."""
+    m, og, dm, g = case(name)
+    dm.assemble(g, variant=fea.TILECOLOUR)
+    torch.cuda.synchronize()
+    nc, bp, tiles_d, nneig = g.tile_colouring()
+    tiles = tiles_d.cpu().numpy()
+    sets, fam = _tile_node_sets(m)
+    nt = len(sets)
+    assert tiles.size == nt and nneig.size == nt
+    first = np.concatenate([[0], np.cumsum(np.bincount(fam, minlength=4))])
+    node_tiles = {}
+    for i, s in enumerate(sets):
+        for v in s:
+            node_tiles.setdefault(v, set()).add(i)
+    nb = [set().union(*(node_tiles[v] for v in s)) - {i} for i, s in enumerate(sets)]
+    assert [len(x) for x in nb] == nneig.tolist()
+    colour = np.full(nt, -1)
+    for t in range(4):
+        for c in range(nc):
+            b, e = int(bp[t * (nc + 1) + c]), int(bp[t * (nc + 1) + c + 1])
+            members = [int(first[t] + x) for x in tiles[b:e]]
+            seen = set()
+            for k, i in enumerate(members):
+                assert fam[i] == t and colour[i] == -1
+                colour[i] = c
+                assert not (sets[i] & seen), (t, c, i)
+                seen |= sets[i]
+                if k:
+                    p = members[k - 1]
+                    assert (nneig[p], -p) > (nneig[i], -i)
+    assert (colour >= 0).all()
+    rank = np.empty(nt, dtype=np.int64)
+    rank[sorted(range(nt), key=lambda i: (-int(nneig[i]), i))] = np.arange(nt)
+    for i in range(nt):
+        earlier = {int(colour[j]) for j in nb[i] if rank[j] < rank[i]}
+        assert int(colour[i]) == min(set(range(nc + 1)) - earlier)

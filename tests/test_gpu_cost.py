@@ -162,10 +162,19 @@ def test_schedules_order_items_and_keep_results():
     cm.train(feats, target, steps=200, lr=3e-3)
     pred = cm.predict(feats)
     b.order(fea.LEARNED, pred)
+    # the queue order is the oracle's longest-predicted-first order (ties by index)
+    from oracle import sched
+    assert np.array_equal(b.get_order(), sched.lpt_order(pred.cpu().numpy()))
+    gpw = b.items[:, 3] * np.array([1, 8, 6, 8])[b.items[:, 1]]
+    b.order(fea.GP_WEIGHT)
+    assert np.array_equal(b.get_order(), sched.lpt_order(gpw))
+    b.order(fea.LEARNED, pred)
     v, r, _ = b.assemble()
     assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
     with pytest.raises(fea.FeaError):
         b.order(fea.LEARNED, None)
+    b.order(fea.TYPE_SORTED)
+    assert np.array_equal(b.get_order(), np.arange(b.n_items))
 
 
 def test_static_partitions_keep_results_and_ranges():
@@ -195,3 +204,69 @@ def test_static_partitions_keep_results_and_ranges():
     b.order(fea.TYPE_SORTED)
     v, r, _ = b.assemble()
     assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
+
+
+def _log_cycles(b, runs=3):
+    v, r, s = b.outputs(fea.F32)
+    logs = []
+    for _ in range(runs):
+        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=v, rhs=r, status=s, variant=fea.ROWSYM)
+        c, _, _ = b.cycles()
+        logs.append(fea.CostModel.log_cycles(c))
+    return torch.stack(logs).mean(dim=0).contiguous()
+
+
+def test_learned_cost_model_on_a_held_out_mesh():
+    """The paper's premise (abstract; Section 4.1): element cost is not known
+    a priori and Gauss-point weights balance poorly. Trained on the measured
+    cycles of one heterogeneous mesh, the model is judged on another (other
+    neo-Hookean bricks, other displacement field): its predictions explain
+    the held-out measured cycles better than Gauss-point weights, and an
+    8-way static split of the held-out mesh by its predictions is better
+    balanced (by measured cycles) than one by Gauss points. The persistent
+    kernel's times under each queue order are reported."""
+    from oracle import sched
+    train = mg.heterogeneous(48, seed=51, brick=8)
+    test = mg.heterogeneous(48, seed=52, brick=8)
+    print(f"[case] hetero48 train/held-out: {train.n_elems} elements", flush=True)
+    bt = fea.Batch([fea.DeviceMesh(train)], model=fea.ELASTIC, use_nh=True)
+    cm = fea.CostModel(seed=9)
+    ft = bt.features(fp64_geometry=False)
+    cm.fit_norm(ft)
+    cm.train(ft, _log_cycles(bt), steps=300, lr=3e-3)
+    bh = fea.Batch([fea.DeviceMesh(test)], model=fea.ELASTIC, use_nh=True)
+    pred = cm.predict(bh.features(fp64_geometry=False)).cpu().numpy().astype(np.float64)
+    meas = _log_cycles(bh).cpu().numpy().astype(np.float64)
+    gp = np.log(bh.items[:, 3] * np.array([1, 8, 6, 8])[bh.items[:, 1]])
+
+    def r2(x, y):
+        x, y = x - x.mean(), y - y.mean()
+        return float((x @ y) ** 2 / ((x @ x) * (y @ y)))
+
+    cyc = np.exp(meas)
+
+    def split_lb(w, parts=8):
+        cs = np.cumsum(w)
+        cut = np.searchsorted(cs - 0.5 * w, cs[-1] * np.arange(1, parts) / parts)
+        return sched.load_balance([c.sum() for c in np.split(cyc, cut)])
+
+    r2l, r2g = r2(pred, meas), r2(gp, meas)
+    lbl, lbg = split_lb(np.exp(pred)), split_lb(np.exp(gp))
+    times = {}
+    v, r, s = bh.outputs(fea.F32)
+    for name, setup in (("type_sorted", lambda: bh.order(fea.TYPE_SORTED)),
+                        ("gp_weight_lpt", lambda: bh.order(fea.GP_WEIGHT)),
+                        ("learned_lpt", lambda: bh.order(fea.LEARNED, torch.from_numpy(pred.astype(np.float32)).cuda())),
+                        ("learned_static", lambda: bh.partition(fea.LEARNED,
+                                                                torch.from_numpy(pred.astype(np.float32)).cuda()))):
+        setup()
+        ts = []
+        for _ in range(5):
+            bh.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=v, rhs=r, status=s, variant=fea.ROWSYM,
+                        timing=True)
+            ts.append(bh.last_ms())
+        times[name] = float(np.median(ts))
+    print(f"[held-out] r2 learned {r2l:.3f} gp {r2g:.3f}; 8-way split LB learned {lbl:.3f} gp {lbg:.3f}; "
+          f"persistent kernel ms {times}", flush=True)
+    assert r2l > r2g + 0.1, (r2l, r2g)
+    assert lbl > lbg and lbl >= 0.85, (lbl, lbg)

@@ -217,3 +217,24 @@ def test_hetero128_newton_residual_sampled_rows():
         rg = r[3 * i:3 * i + 3].cpu().numpy()
         worst_b = max(worst_b, float(np.max(np.abs(rg - r_ref)) / r_scale.max()))
     assert worst_a <= 1e-12 and worst_b <= 1e-12, (worst_a, worst_b)
+
+
+def test_hybrid96_bitwise_repeatable_ten_assemblies():
+    """The deterministic forms at the benchmark size: ten FP64 assemblies
+    of the hybrid96 mesh in the row-owner and upper-triangle forms give the
+    same bits (compared on the device)."""
+    mesh = mg.hybrid_bands(96, seed=2)
+    print(f"[case] hybrid96 repeatability: {mesh.n_elems} elements", flush=True)
+    dm = fea.DeviceMesh(mesh)
+    g = dm.graph()
+    for variant in (fea.ROWOWNER, fea.ROWSYM):
+        v0, r0, st = dm.assemble(g, variant=variant)
+        v, r = torch.empty_like(v0), torch.empty_like(r0)
+        for k in range(9):
+            dm.assemble(g, variant=variant, vals=v, rhs=r, status=st)
+            torch.cuda.synchronize()
+            assert int(st.item()) == -1
+            assert torch.equal(v.view(torch.int64), v0.view(torch.int64)), (variant, k)
+            assert torch.equal(r.view(torch.int64), r0.view(torch.int64)), (variant, k)
+        del v0, r0, v, r
+    g.destroy()
