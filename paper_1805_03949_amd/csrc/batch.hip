@@ -54,8 +54,15 @@ __device__ inline void run_item(const ElemArgs &A, int32_t count, ElemSmem<T, MO
 // read-only table (itemargs) as a one-tile kernel reads its kernel
 // arguments: arguments assembled in the loop stayed live across the
 // element code (98-134 VGPRs instead of 64-82, 4 waves per SIMD).
+// The register budget of the linear-elastic upper-triangle instances is
+// bounded by the occupancy their LDS allows: inside the item loop the
+// scheduler otherwise keeps several Gauss points' gradient products of the
+// block contraction live at once (pyr5 and hex8: 131-133 VGPRs and 3 waves
+// per SIMD, against 74-90 for the same code in the one-tile kernel).
 template <int T, int MODEL, typename CT, int VAR>
-__global__ void __launch_bounds__(256) k_batch(const ElemArgs *__restrict__ itemargs, const int4 *items,
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
+                               amdgpu_waves_per_eu(persistent_min_waves<T, MODEL, VAR, CT>())))
+k_batch(const ElemArgs *__restrict__ itemargs, const int4 *items,
                                                const int32_t *order, int32_t n_items,
                                                int32_t *head, const int32_t *part, uint64_t *cycles,
                                                int32_t *worker, int32_t *cu)

@@ -336,6 +336,28 @@ struct ElemSmem {
     double sNr[NQ][NN];      // reference shape functions
 };
 
+// Waves per SIMD that the LDS of one 256-thread workgroup (one wave per
+// SIMD) and the extra bytes of a kernel leave room for on a 160 KB CU, at
+// most 8: the occupancy a kernel's register budget should not undercut.
+template <typename Smem>
+constexpr int lds_waves(int extra = 0)
+{
+    const int w = (160 * 1024) / (int)(sizeof(Smem) + extra);
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+// Minimum waves per SIMD asked of the persistent element kernels: the
+// linear-elastic upper-triangle instances at their LDS occupancy, at most
+// six (80 VGPRs: their one-tile code needs 52-90); the others unbounded (a
+// bound there spills, neo-Hookean instances included: measured with the
+// compiler's resource report).
+template <int T, int MODEL, int VAR, typename CT>
+constexpr int persistent_min_waves()
+{
+    using S = ElemSmem<T, MODEL, VAR, CT>;
+    return (MODEL == FEA_ELASTIC && S::SYM) ? (lds_waves<S>(16) < 6 ? lds_waves<S>(16) : 6) : 1;
+}
+
 // Reference shape functions and gradients of family T into LDS.
 template <int T, int MODEL, int VAR, typename CT>
 __device__ inline void elem_ref_tables(ElemSmem<T, MODEL, VAR, CT> &S, const int tid)
@@ -452,7 +474,7 @@ __device__ inline void elem_block(const ElemSmem<T, MODEL, VAR, CT> &S, const in
         CT Sm[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) Sm[c] = 0;
-#pragma unroll
+#pragma unroll 2
         for (int q = 0; q < NQ; ++q) {
             CT w = S.sC[el][q][0];
             CT ga[3] = {w * sG[el].v[q][a][0], w * sG[el].v[q][a][1], w * sG[el].v[q][a][2]};
