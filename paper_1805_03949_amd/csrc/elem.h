@@ -347,15 +347,15 @@ constexpr int lds_waves(int extra = 0)
 }
 
 // Minimum waves per SIMD asked of the persistent element kernels: the
-// linear-elastic upper-triangle instances at their LDS occupancy, at most
-// six (80 VGPRs: their one-tile code needs 52-90); the others unbounded (a
-// bound there spills, neo-Hookean instances included: measured with the
-// compiler's resource report).
+// FP64 linear-elastic upper-triangle instances at their LDS occupancy, at
+// most six (80 VGPRs: their one-tile code needs 56-90); the others
+// unbounded (a bound there spills, the FP32 hex8 and the neo-Hookean
+// instances included: measured with the compiler's resource report).
 template <int T, int MODEL, int VAR, typename CT>
 constexpr int persistent_min_waves()
 {
     using S = ElemSmem<T, MODEL, VAR, CT>;
-    return (MODEL == FEA_ELASTIC && S::SYM) ? (lds_waves<S>(16) < 6 ? lds_waves<S>(16) : 6) : 1;
+    return (MODEL == FEA_ELASTIC && S::SYM && sizeof(CT) == 8) ? (lds_waves<S>(16) < 6 ? lds_waves<S>(16) : 6) : 1;
 }
 
 // Reference shape functions and gradients of family T into LDS.
@@ -840,25 +840,41 @@ __device__ void elem_tile_sym(const ElemArgs &A, int64_t first, ElemSmem<T, MODE
     }
     __syncthreads();
 
-    // tile sums: one thread per (tile-block, component), the block's entries
-    // added in ascending lane (element) order, in FP64
+    // tile sums: one thread per tile-block, all BB components, the block's
+    // entries added in ascending lane (element) order, in FP64. (One thread
+    // per (tile-block, component) walks the same entry list BB times over a
+    // chain of dependent LDS reads: 0.69 of the 1.78 ms FP64 element phase
+    // of the 96^3 mesh.)
     CT *out = (CT *)A.contrib;
-    for (int idx = tid; idx < nd * BB; idx += 256) {
-        const int d = idx / BB, c = idx - d * BB, ct = (c % B) * B + c / B;
-        double acc = 0.0;
-        for (int q = d ? S.sEend[d - 1] : 0; q < S.sEend[d]; ++q) {
+    for (int d = tid; d < nd; d += 256) {
+        double acc[BB];
+#pragma unroll
+        for (int c = 0; c < BB; ++c) acc[c] = 0.0;
+        const int q1 = S.sEend[d];
+        for (int q = d ? S.sEend[d - 1] : 0; q < q1; ++q) {
             const int u = S.sEnt[q];
-            acc += (double)sK[(u >> 1) * BB + ((u & 1) ? ct : c)];
+            const CT *k = sK + (u >> 1) * BB;
+            CT v[BB];
+#pragma unroll
+            for (int c = 0; c < BB; ++c) v[c] = k[c];
+            const bool tr = (u & 1) != 0;
+#pragma unroll
+            for (int c = 0; c < BB; ++c) acc[c] += (double)(tr ? v[(c % B) * B + c / B] : v[c]);
         }
-        const int64_t v = S.sSlot[d];
+        const int64_t blk = S.sSlot[d];
         if constexpr (TCOL) {
-            // v is the block; no other tile of this colour touches it or
+            // blk is the block; no other tile of this colour touches it or
             // its partner
             const int64_t l = S.sLp[d];
-            A.vals[v * BB + c] += acc;
-            if (l >= 0) A.vals[l * BB + ct] += acc;
+#pragma unroll
+            for (int c = 0; c < BB; ++c) A.vals[blk * BB + c] += acc[c];
+            if (l >= 0) {
+#pragma unroll
+                for (int c = 0; c < BB; ++c) A.vals[l * BB + (c % B) * B + c / B] += acc[c];
+            }
         } else {
-            out[v * BB + c] = (CT)acc;
+#pragma unroll
+            for (int c = 0; c < BB; ++c) out[blk * BB + c] = (CT)acc[c];
         }
     }
 }
