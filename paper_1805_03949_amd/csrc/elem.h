@@ -840,41 +840,66 @@ __device__ void elem_tile_sym(const ElemArgs &A, int64_t first, ElemSmem<T, MODE
     }
     __syncthreads();
 
-    // tile sums: one thread per tile-block, all BB components, the block's
-    // entries added in ascending lane (element) order, in FP64. (One thread
-    // per (tile-block, component) walks the same entry list BB times over a
-    // chain of dependent LDS reads: 0.69 of the 1.78 ms FP64 element phase
-    // of the 96^3 mesh.)
+    // tile sums, the block's entries added in ascending lane (element)
+    // order, in FP64: either one thread per tile-block adding all BB
+    // components, or one thread per (tile-block, component), which walks
+    // the block's entry list BB times but spreads a tile's sums over more
+    // threads. Measured on MI355X over the 256^3 mesh, FP64, ms per family
+    // per block / per component: tet4 7.63 / 7.13, pyr5 4.34 / 4.22, pen6
+    // 4.55 / 4.74, hex8 9.88 / 10.11 (element phase 27.2 ms with one thread
+    // per block everywhere, 26.65 with this choice); FP32 staged blocks:
+    // per block in every family (per component for tet4 and pyr5 was
+    // slightly slower). Both give bitwise the same sums.
     CT *out = (CT *)A.contrib;
-    for (int d = tid; d < nd; d += 256) {
-        double acc[BB];
+    constexpr bool PER_BLOCK = T >= 2 || sizeof(CT) == 4;
+    if constexpr (PER_BLOCK) {
+        for (int d = tid; d < nd; d += 256) {
+            double acc[BB];
 #pragma unroll
-        for (int c = 0; c < BB; ++c) acc[c] = 0.0;
-        const int q1 = S.sEend[d];
-        for (int q = d ? S.sEend[d - 1] : 0; q < q1; ++q) {
-            const int u = S.sEnt[q];
-            const CT *k = sK + (u >> 1) * BB;
-            CT v[BB];
+            for (int c = 0; c < BB; ++c) acc[c] = 0.0;
+            const int q1 = S.sEend[d];
+            for (int q = d ? S.sEend[d - 1] : 0; q < q1; ++q) {
+                const int u = S.sEnt[q];
+                const CT *k = sK + (u >> 1) * BB;
+                CT v[BB];
 #pragma unroll
-            for (int c = 0; c < BB; ++c) v[c] = k[c];
-            const bool tr = (u & 1) != 0;
+                for (int c = 0; c < BB; ++c) v[c] = k[c];
+                const bool tr = (u & 1) != 0;
 #pragma unroll
-            for (int c = 0; c < BB; ++c) acc[c] += (double)(tr ? v[(c % B) * B + c / B] : v[c]);
-        }
-        const int64_t blk = S.sSlot[d];
-        if constexpr (TCOL) {
-            // blk is the block; no other tile of this colour touches it or
-            // its partner
-            const int64_t l = S.sLp[d];
-#pragma unroll
-            for (int c = 0; c < BB; ++c) A.vals[blk * BB + c] += acc[c];
-            if (l >= 0) {
-#pragma unroll
-                for (int c = 0; c < BB; ++c) A.vals[l * BB + (c % B) * B + c / B] += acc[c];
+                for (int c = 0; c < BB; ++c) acc[c] += (double)(tr ? v[(c % B) * B + c / B] : v[c]);
             }
-        } else {
+            const int64_t blk = S.sSlot[d];
+            if constexpr (TCOL) {
+                // blk is the block; no other tile of this colour touches it
+                // or its partner
+                const int64_t l = S.sLp[d];
 #pragma unroll
-            for (int c = 0; c < BB; ++c) out[blk * BB + c] = (CT)acc[c];
+                for (int c = 0; c < BB; ++c) A.vals[blk * BB + c] += acc[c];
+                if (l >= 0) {
+#pragma unroll
+                    for (int c = 0; c < BB; ++c) A.vals[l * BB + (c % B) * B + c / B] += acc[c];
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < BB; ++c) out[blk * BB + c] = (CT)acc[c];
+            }
+        }
+    } else {
+        for (int idx = tid; idx < nd * BB; idx += 256) {
+            const int d = idx / BB, c = idx - d * BB, ct = (c % B) * B + c / B;
+            double acc = 0.0;
+            for (int q = d ? S.sEend[d - 1] : 0; q < S.sEend[d]; ++q) {
+                const int u = S.sEnt[q];
+                acc += (double)sK[(u >> 1) * BB + ((u & 1) ? ct : c)];
+            }
+            const int64_t blk = S.sSlot[d];
+            if constexpr (TCOL) {
+                const int64_t l = S.sLp[d];
+                A.vals[blk * BB + c] += acc;
+                if (l >= 0) A.vals[l * BB + ct] += acc;
+            } else {
+                out[blk * BB + c] = (CT)acc;
+            }
         }
     }
 }
