@@ -392,6 +392,45 @@ __device__ inline void elem_geometry(const ElemArgs &A, ElemSmem<T, MODEL, VAR, 
     using GradRec = typename Smem::GradRec;
     GradRec *sG = reinterpret_cast<GradRec *>(S.buf);
     GradRec *sH = reinterpret_cast<GradRec *>(S.buf + Smem::NG);
+    if constexpr (!NHK && EPB * NQ <= 4 * 21) {
+        // Three lanes per (element, Gauss point), 21 such groups per wave
+        // (lane 63 idle, so that a group never spans two waves): lane r of a
+        // group forms row r of J, the rows are exchanged across the group's
+        // lanes, each lane inverts J and writes the gradients of nodes
+        // r, r + 3, ... Same operations per value as one lane per point,
+        // spread over up to four waves instead of one or two.
+        const int lane = tid & 63, r = lane % 3;
+        const int grp = (tid >> 6) * 21 + lane / 3;
+        if (lane < 63 && grp < EPB * NQ) {
+            const int el = grp / NQ, q = grp % NQ;
+            const int32_t e = S.sE[el];
+            if (e >= 0) {
+                double Jr[3] = {0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < NN; ++a)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Jr[j] += S.sX[el][a][r] * S.sDN[q][a][j];
+                const int g0 = lane - r;
+                double J[3][3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) J[i][j] = __shfl(Jr[j], g0 + i);
+                const double d = det3(J);
+                if (r == 0 && !(d > 0.0)) atomicMin(A.status, e);
+                double Ji[3][3];
+                inv3(J, d, Ji);
+#pragma unroll
+                for (int a = r; a < NN; a += 3)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        sG[el].v[q][a][i] =
+                            (CT)(Ji[0][i] * S.sDN[q][a][0] + Ji[1][i] * S.sDN[q][a][1] + Ji[2][i] * S.sDN[q][a][2]);
+                if (r == 0) S.sC[el][q][0] = (CT)(c_ref.w[T][q] * d);
+            }
+        }
+        return;
+    }
     if (tid < EPB * NQ) {
         int el = tid / NQ, q = tid % NQ;
         int32_t e = S.sE[el];
