@@ -274,8 +274,9 @@ struct GradRecT<CT, NQ, NN, true> {
     CT pad;
 };
 
-template <int T, int MODEL, int VAR, typename CT>
-struct ElemSmem {
+template <int T, int MODEL, int VAR, typename CT_>
+struct ElemDims {
+    using CT = CT_;
     static constexpr int NN = Fam<T>::NN, NQ = Fam<T>::NQ, P = NN * NN;
     // threads per element: all n*n blocks, or the n(n+1)/2 pairs a <= b
     static constexpr int PW = (VAR == V_ROWSYM || VAR == V_TILECOL) ? NN * (NN + 1) / 2 : P;
@@ -294,15 +295,7 @@ struct ElemSmem {
     // repeats a node, and the layout builder checks the count), and so at
     // most as many tile-blocks
     static constexpr int MAXENT = EPB * PW;
-    double sX[EPB][NN][3];
-    double sU[EU][NN][3];
     static constexpr int NC = NHK ? 4 : 1;
-    CT sC[EPB][NQ][NC];      // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
-    double sLM[ELAS ? EPB : 1][2];  // lam, mu of every element (elasticity)
-    int32_t sE[EPB];
-    int sNH[EPB];
-    int64_t sM[RO ? 1 : EPB];   // first slot of each element
-    int64_t sCP[RO ? 1 : EPB];  // first conn position of each element
     // Row-owner stores staged in LDS so that BB consecutive threads write one
     // block's BB contiguous values. Measured per family on MI355X: a gain
     // everywhere except FP64 pyramids of the neo-Hookean kernel, where the
@@ -320,20 +313,60 @@ struct ElemSmem {
                          NK = STAGE ? EPB * PW * BB : 1;
     // Upper-triangle form: the staged blocks overwrite the gradients (one
     // barrier more, after every lane has read them) where the gradient
-    // records are large enough for the shared space to decide occupancy;
-    // tet4's are small, and its blocks get a space of their own.
-    static constexpr bool ALIAS = SYM && (NG + NHG) * (int)sizeof(CT) > 4096;
+    // records are large enough for the shared space to decide occupancy,
+    // and always in FP64; FP32 tet4 blocks get a space of their own.
+    static constexpr bool ALIAS = SYM && ((NG + NHG) * (int)sizeof(CT) > 4096 || sizeof(CT) == 8);
     static constexpr int NBUF = ALIAS ? (NG + NHG > NK ? NG + NHG : NK) : NG + NHG + NK;
     static constexpr int KOFF = ALIAS ? 0 : NG + NHG;  // where sK starts in buf
-    CT buf[NBUF];
-    int32_t sD[STAGE && !SYM ? EPB * PW : 1];
-    uint16_t sEnt[SYM ? MAXENT : 1];   // the tile's entries
-    uint16_t sEend[SYM ? MAXENT : 1];  // and tile-block ends
-    int32_t sSlot[SYM ? MAXENT : 1];   // workspace slot (tile-coloured: block) of every tile-block
-    int32_t sLp[TCOL ? MAXENT : 1];    // tile-coloured: lower partner of every tile-block's block
-    double sSrc[SYM ? EPB : 1][B];     // source of every element
-    double sDN[NQ][NN][3];   // reference gradients of this family
-    double sNr[NQ][NN];      // reference shape functions
+    // FP64 upper-triangle form: the coordinates, Gauss-point coefficients
+    // and reference tables are dead once the blocks are staged, and share
+    // the staged blocks' space beyond the gradients where they fit
+    static constexpr int PRE_BYTES = (EPB * NN * 3 + NQ * NN * 3 + NQ * NN) * 8 + EPB * NQ * NC * (int)sizeof(CT);
+    static constexpr bool PRE_ALIAS =
+        ALIAS && sizeof(CT) == 8 && (NG + NHG) * (int)sizeof(CT) + PRE_BYTES <= NBUF * (int)sizeof(CT);
+};
+
+// The LDS arrays that the upper-triangle form may overlay on the staged
+// blocks, apart or overlaid.
+template <typename D, bool OVERLAY = D::PRE_ALIAS>
+struct ElemPre {
+    using CT = typename D::CT;
+    double sX[D::EPB][D::NN][3];
+    CT sC[D::EPB][D::NQ][D::NC];  // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
+    alignas(16) CT buf[D::NBUF];
+    double sDN[D::NQ][D::NN][3];  // reference gradients of this family
+    double sNr[D::NQ][D::NN];     // reference shape functions
+};
+template <typename D>
+struct ElemPre<D, true> {
+    using CT = typename D::CT;
+    union {
+        alignas(16) CT buf[D::NBUF];
+        struct {
+            CT pre_gradients_[D::NG + D::NHG];
+            double sX[D::EPB][D::NN][3];
+            CT sC[D::EPB][D::NQ][D::NC];
+            double sDN[D::NQ][D::NN][3];
+            double sNr[D::NQ][D::NN];
+        };
+    };
+};
+
+template <int T, int MODEL, int VAR, typename CT>
+struct ElemSmem : ElemDims<T, MODEL, VAR, CT>, ElemPre<ElemDims<T, MODEL, VAR, CT>> {
+    using D = ElemDims<T, MODEL, VAR, CT>;
+    double sU[D::EU][D::NN][3];
+    double sLM[D::ELAS ? D::EPB : 1][2];  // lam, mu of every element (elasticity)
+    int32_t sE[D::EPB];
+    int sNH[D::EPB];
+    int64_t sM[D::RO ? 1 : D::EPB];   // first slot of each element
+    int64_t sCP[D::RO ? 1 : D::EPB];  // first conn position of each element
+    int32_t sD[D::STAGE && !D::SYM ? D::EPB * D::PW : 1];
+    uint16_t sEnt[D::SYM ? D::MAXENT : 1];   // the tile's entries
+    uint16_t sEend[D::SYM ? D::MAXENT : 1];  // and tile-block ends
+    int32_t sSlot[D::SYM ? D::MAXENT : 1];   // workspace slot (tile-coloured: block) of every tile-block
+    int32_t sLp[D::TCOL ? D::MAXENT : 1];    // tile-coloured: lower partner of every tile-block's block
+    double sSrc[D::SYM ? D::EPB : 1][D::B];  // source of every element
 };
 
 // Waves per SIMD that the LDS of one 256-thread workgroup (one wave per
