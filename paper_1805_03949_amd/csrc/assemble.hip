@@ -11,7 +11,8 @@
 namespace fea {
 
 template <int T, int MODEL, int VAR, typename CT>
-__global__ void __launch_bounds__(256) k_element(ElemArgs A)
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
+                               amdgpu_waves_per_eu(one_tile_min_waves<T, MODEL, VAR, CT>()))) k_element(ElemArgs A)
 {
     __shared__ ElemSmem<T, MODEL, VAR, CT> S;
     constexpr int EPB = ElemSmem<T, MODEL, VAR, CT>::EPB;

@@ -318,24 +318,36 @@ struct ElemDims {
     static constexpr bool ALIAS = SYM && ((NG + NHG) * (int)sizeof(CT) > 4096 || sizeof(CT) == 8);
     static constexpr int NBUF = ALIAS ? (NG + NHG > NK ? NG + NHG : NK) : NG + NHG + NK;
     static constexpr int KOFF = ALIAS ? 0 : NG + NHG;  // where sK starts in buf
-    // FP64 upper-triangle form: the coordinates, Gauss-point coefficients
-    // and reference tables are dead once the blocks are staged, and share
-    // the staged blocks' space beyond the gradients where they fit
-    static constexpr int PRE_BYTES = (EPB * NN * 3 + NQ * NN * 3 + NQ * NN) * 8 + EPB * NQ * NC * (int)sizeof(CT);
+    // FP64 upper-triangle form: the per-element inputs, Gauss-point
+    // coefficients and reference tables are dead once the blocks are
+    // staged, and share the staged blocks' space beyond the gradients where
+    // they fit
+    static constexpr int SRC = SYM ? EPB : 1, NLM = ELAS ? EPB : 1;
+    static constexpr int PRE_BYTES =
+        (EPB * NN * 3 + EU * NN * 3 + NLM * 2 + SRC * B + NQ * NN * 3 + NQ * NN) * 8 +
+        EPB * NQ * NC * (int)sizeof(CT) + 2 * EPB * 4;
     static constexpr bool PRE_ALIAS =
         ALIAS && sizeof(CT) == 8 && (NG + NHG) * (int)sizeof(CT) + PRE_BYTES <= NBUF * (int)sizeof(CT);
 };
 
 // The LDS arrays that the upper-triangle form may overlay on the staged
 // blocks, apart or overlaid.
-template <typename D, bool OVERLAY = D::PRE_ALIAS>
-struct ElemPre {
+template <typename D>
+struct ElemPreArrays {
     using CT = typename D::CT;
     double sX[D::EPB][D::NN][3];
-    CT sC[D::EPB][D::NQ][D::NC];  // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
-    alignas(16) CT buf[D::NBUF];
+    double sU[D::EU][D::NN][3];
+    double sLM[D::NLM][2];        // lam, mu of every element (elasticity)
+    double sSrc[D::SRC][D::B];    // source of every element (upper-triangle form)
     double sDN[D::NQ][D::NN][3];  // reference gradients of this family
     double sNr[D::NQ][D::NN];     // reference shape functions
+    CT sC[D::EPB][D::NQ][D::NC];  // wd, and for neo-Hookean wd*lam, wd*c2, wd*mu
+    int32_t sE[D::EPB];
+    int sNH[D::EPB];
+};
+template <typename D, bool OVERLAY = D::PRE_ALIAS>
+struct ElemPre : ElemPreArrays<D> {
+    alignas(16) typename D::CT buf[D::NBUF];
 };
 template <typename D>
 struct ElemPre<D, true> {
@@ -345,9 +357,14 @@ struct ElemPre<D, true> {
         struct {
             CT pre_gradients_[D::NG + D::NHG];
             double sX[D::EPB][D::NN][3];
-            CT sC[D::EPB][D::NQ][D::NC];
+            double sU[D::EU][D::NN][3];
+            double sLM[D::NLM][2];
+            double sSrc[D::SRC][D::B];
             double sDN[D::NQ][D::NN][3];
             double sNr[D::NQ][D::NN];
+            CT sC[D::EPB][D::NQ][D::NC];
+            int32_t sE[D::EPB];
+            int sNH[D::EPB];
         };
     };
 };
@@ -355,10 +372,6 @@ struct ElemPre<D, true> {
 template <int T, int MODEL, int VAR, typename CT>
 struct ElemSmem : ElemDims<T, MODEL, VAR, CT>, ElemPre<ElemDims<T, MODEL, VAR, CT>> {
     using D = ElemDims<T, MODEL, VAR, CT>;
-    double sU[D::EU][D::NN][3];
-    double sLM[D::ELAS ? D::EPB : 1][2];  // lam, mu of every element (elasticity)
-    int32_t sE[D::EPB];
-    int sNH[D::EPB];
     int64_t sM[D::RO ? 1 : D::EPB];   // first slot of each element
     int64_t sCP[D::RO ? 1 : D::EPB];  // first conn position of each element
     int32_t sD[D::STAGE && !D::SYM ? D::EPB * D::PW : 1];
@@ -366,7 +379,6 @@ struct ElemSmem : ElemDims<T, MODEL, VAR, CT>, ElemPre<ElemDims<T, MODEL, VAR, C
     uint16_t sEend[D::SYM ? D::MAXENT : 1];  // and tile-block ends
     int32_t sSlot[D::SYM ? D::MAXENT : 1];   // workspace slot (tile-coloured: block) of every tile-block
     int32_t sLp[D::TCOL ? D::MAXENT : 1];    // tile-coloured: lower partner of every tile-block's block
-    double sSrc[D::SYM ? D::EPB : 1][D::B];  // source of every element
 };
 
 // Waves per SIMD that the LDS of one 256-thread workgroup (one wave per
@@ -379,16 +391,25 @@ constexpr int lds_waves(int extra = 0)
     return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-// Minimum waves per SIMD asked of the persistent element kernels: the
-// FP64 linear-elastic upper-triangle instances at their LDS occupancy, at
-// most six (80 VGPRs: their one-tile code needs 56-90); the others
+// Minimum waves per SIMD asked of the element kernels: the FP64
+// linear-elastic upper-triangle instances at their LDS occupancy (tet4,
+// pen6 and hex8 eight waves: 64 VGPRs, which their one-tile code fits
+// without spills, and their persistent code too; pyr5 six); the others
 // unbounded (a bound there spills, the FP32 hex8 and the neo-Hookean
-// instances included: measured with the compiler's resource report).
+// instances included, and a seven-wave bound on the persistent pen6 and
+// hex8 code as well: measured with the compiler's resource report).
 template <int T, int MODEL, int VAR, typename CT>
 constexpr int persistent_min_waves()
 {
     using S = ElemSmem<T, MODEL, VAR, CT>;
-    return (MODEL == FEA_ELASTIC && S::SYM && sizeof(CT) == 8) ? (lds_waves<S>(16) < 6 ? lds_waves<S>(16) : 6) : 1;
+    return (MODEL == FEA_ELASTIC && S::SYM && sizeof(CT) == 8) ? lds_waves<S>(16) : 1;
+}
+
+template <int T, int MODEL, int VAR, typename CT>
+constexpr int one_tile_min_waves()
+{
+    using S = ElemSmem<T, MODEL, VAR, CT>;
+    return (MODEL == FEA_ELASTIC && S::SYM && sizeof(CT) == 8) ? lds_waves<S>() : 1;
 }
 
 // Reference shape functions and gradients of family T into LDS.
