@@ -388,12 +388,13 @@ def tiny_mesh(cell_types_grid, jitter=0.0, seed=0, dofs=3):
     return cube_mesh(n, ct.reshape(-1), jitter=jitter, seed=seed, dofs=dofs)
 
 
-def layer_sample(mesh, layers):
+def layer_sample(mesh, layers, return_nodes=False):
     """The elements of the given z-layers of cells of a band mesh (every cell
     of a layer has one family), as a mesh of their own: nodes renumbered in
     ascending order of their ids in `mesh`, coordinates, materials, sources
     and flags copied. Used to time work on a bounded part of a large mesh
-    with its family mix."""
+    with its family mix, and to check whole rows of it. return_nodes: also
+    return the ids in `mesh` of the sample's nodes (ascending)."""
     n = mesh.n_cells
     lay = n * n
     # element offset of every layer: a layer holds n^2 cells of one family
@@ -410,8 +411,9 @@ def layer_sample(mesh, layers):
     conn_ptr = np.zeros(elems.size + 1, dtype=np.int64)
     np.cumsum(lens, out=conn_ptr[1:])
     u = mesh.u.reshape(-1, 3)[nodes].reshape(-1).copy()
-    return Mesh(n_cells=n, x=mesh.x[nodes].copy(), y=mesh.y[nodes].copy(), z=mesh.z[nodes].copy(),
-                types=mesh.types[elems].copy(), conn_ptr=conn_ptr, conn=conn.astype(np.int32),
-                young=mesh.young[elems].copy(), nu=mesh.nu[elems].copy(), source=mesh.source[elems].copy(),
-                nh_flag=mesh.nh_flag[elems].copy(), u=u, boundary=mesh.boundary[nodes].copy(),
-                redraws=0)
+    sample = Mesh(n_cells=n, x=mesh.x[nodes].copy(), y=mesh.y[nodes].copy(), z=mesh.z[nodes].copy(),
+                  types=mesh.types[elems].copy(), conn_ptr=conn_ptr, conn=conn.astype(np.int32),
+                  young=mesh.young[elems].copy(), nu=mesh.nu[elems].copy(), source=mesh.source[elems].copy(),
+                  nh_flag=mesh.nh_flag[elems].copy(), u=u, boundary=mesh.boundary[nodes].copy(),
+                  redraws=0)
+    return (sample, nodes) if return_nodes else sample

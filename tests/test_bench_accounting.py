@@ -110,6 +110,14 @@ def test_layer_sample_keeps_the_elements_of_its_layers():
         assert np.array_equal(m.x[on], s.x[sn]) and np.array_equal(m.z[on], s.z[sn])
         assert s.nu[k] == m.nu[e]
     assert np.unique(s.conn).size == s.n_nodes
+    s2, nodes = mg.layer_sample(m, layers, return_nodes=True)
+    assert np.array_equal(s2.conn, s.conn)
+    assert np.all(np.diff(nodes) > 0) and nodes.size == s.n_nodes
+    assert np.array_equal(m.x[nodes], s.x) and np.array_equal(m.z[nodes], s.z)
+    # the sample's connectivity is the mesh's, renumbered
+    k = elems[::131]
+    for e, kk in zip(k, np.searchsorted(elems, k)):
+        assert np.array_equal(nodes[s.conn[s.conn_ptr[kk]:s.conn_ptr[kk + 1]]], m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]])
 
 
 def test_row_max_by_hand():

@@ -238,3 +238,80 @@ def test_hybrid96_bitwise_repeatable_ten_assemblies():
             assert torch.equal(r.view(torch.int64), r0.view(torch.int64)), (variant, k)
         del v0, r0, v, r
     g.destroy()
+
+
+def _plane_oracle(mesh, L):
+    """The oracle's assembly (with its |term| sums) of the two cell layers
+    around the node plane z = L, which hold every element of that plane's
+    rows, and the sample's node ids in the mesh."""
+    import oracle
+    sample, snodes = mg.layer_sample(mesh, [L - 1, L], return_nodes=True)
+    og = oracle.mesh_graph(sample)
+    return (snodes, np.asarray(og.row_ptr), np.asarray(og.col)) + tuple(oracle.assemble(sample, og, with_terms=True))
+
+
+def _plane_rows(mesh, L, orc, vals, rhs, row_ptr, col, fp32_L=None):
+    """Whole rows of the node plane z = L (every node of that plane) of a
+    full-mesh assembly against the oracle's assembly `orc` of the two cell
+    layers around it (_plane_oracle): the pattern bit-exact, values
+    row-scaled (FP64) or against the FP32 bound. Returns (rows, worst)."""
+    from tests.helpers import gamma
+    snodes, orp, ocol, v_o, r_o, t_o, tr_o = orc
+    m = mesh.n_cells + 1
+    p0, p1 = L * m * m, (L + 1) * m * m
+    s0, s1 = np.searchsorted(snodes, [p0, p1])
+    assert s1 - s0 == p1 - p0 and snodes[s0] == p0 and snodes[s1 - 1] == p1 - 1
+    k0, k1 = int(row_ptr[p0]), int(row_ptr[p1])
+    o0, o1 = int(orp[s0]), int(orp[s1])
+    # the pattern of the plane's rows, mapped back to the mesh's node ids
+    assert k1 - k0 == o1 - o0
+    assert np.array_equal(np.diff(row_ptr[p0:p1 + 1]), np.diff(orp[s0:s1 + 1]))
+    assert np.array_equal(col[k0:k1], snodes[ocol[o0:o1]])
+    ref = v_o[o0 * 9:o1 * 9].reshape(-1, 3, 3)
+    terms = t_o[o0 * 9:o1 * 9].reshape(-1, 3, 3)
+    got = vals[k0 * 9:k1 * 9].cpu().numpy().astype(np.float64).reshape(-1, 3, 3)
+    starts = (orp[s0:s1] - o0).astype(np.int64)
+    counts = np.diff(orp[s0:s1 + 1])
+    scale = np.maximum.reduceat(np.abs(ref).max(axis=2), starts, axis=0)   # per scalar row
+    sb = np.repeat(scale, counts, axis=0)[:, :, None]
+    rg = rhs[p0 * 3:p1 * 3].cpu().numpy().astype(np.float64).reshape(-1, 3)
+    rr = r_o[s0 * 3:s1 * 3].reshape(-1, 3)
+    rt = tr_o[s0 * 3:s1 * 3].reshape(-1, 3)
+    rs = np.abs(rr).max(axis=1)[:, None]
+    if fp32_L is None:
+        worst = max(float(np.max(np.abs(got - ref) / sb)), float(np.max(np.abs(rg - rr) / rs)))
+    else:
+        worst = max(float(np.max(np.abs(got - ref) / (gamma(fp32_L) * terms + 1e-12 * sb))),
+                    float(np.max(np.abs(rg - rr) / (gamma(fp32_L) * rt + 1e-12 * rs))))
+    return p1 - p0, worst
+
+
+def test_hybrid256_interface_planes_whole_rows():
+    """Every row of the three family-interface node planes of the 256^3
+    mesh (hex8/tet4, tet4/pen6, pen6/pyr5: 3 x 66,049 rows) from the
+    benchmark's headline launch (one-mesh upper-triangle form), FP64 and
+    mixed, against the oracle on the two cell layers around each plane."""
+    mesh = mg.hybrid_split(256, seed=5)
+    bands = mg.split_bands(256)
+    planes = [int(L) for L in np.cumsum([l for _, l in bands])[:-1]]
+    print(f"[case] hybrid256 planes {planes}", flush=True)
+    orc = {L: _plane_oracle(mesh, L) for L in planes}
+    dm = fea.DeviceMesh(mesh)
+    g = dm.graph()
+    ex = g.export()
+    row_ptr, col = ex["row_ptr"].cpu().numpy(), ex["col"].cpu().numpy()
+    del ex
+    L32 = fp32_bound_L(mesh.types)
+    for prec in (fea.FP64, fea.MIXED):
+        outd = fea.F64 if prec == fea.FP64 else fea.F32
+        print(f"[case] hybrid256 rowsym precision {prec}", flush=True)
+        v, r, st = dm.assemble(g, variant=fea.ROWSYM, precision=prec, out_dtype=outd)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -1
+        for L in planes:
+            n, worst = _plane_rows(mesh, L, orc[L], v, r, row_ptr, col,
+                                   fp32_L=None if prec == fea.FP64 else L32)
+            print(f"[case] plane {L}: {n} rows, worst {worst:.3g}", flush=True)
+            assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (L, prec, worst)
+        del v, r
+    g.destroy()
