@@ -130,6 +130,25 @@ int fea_graph_build(int64_t n_nodes, int64_t n_elems, const uint8_t *types,
                     const int64_t *conn_ptr, const int32_t *conn, hipStream_t stream,
                     fea_graph **out);
 
+/* Graph cache (a checkpoint of the graph, so that a later run can skip
+ * fea_graph_build): fea_graph_save writes the graph's pattern, maps,
+ * incidence, type segmentation and colouring to `path` (binary: a header
+ * with a magic string, format version, the GPU architecture name, the
+ * sizes and a fingerprint of the mesh's connectivity, then the arrays);
+ * the layouts built on first use by FEA_ROWSYM, FEA_TILECOLOUR and
+ * FEA_ROWGATHER are not saved (the first such call builds them again).
+ * Synchronises the device. fea_graph_load reads such a file for the mesh
+ * given (device arrays as fea_graph_build, which it validates the same
+ * way) on `stream`, into a new graph equal to the one saved, for callers
+ * that assemble the same mesh in several processes. Errors: FEA_EINVAL
+ * (cannot open or write the file, not a graph cache, another format
+ * version, written on another GPU architecture, mesh sizes or connectivity
+ * fingerprint differ from the saved graph's, file truncated), FEA_EMESH
+ * (invalid mesh), FEA_ENOMEM, FEA_EHIP. */
+int fea_graph_save(const fea_graph *g, const char *path);
+int fea_graph_load(const char *path, int64_t n_nodes, int64_t n_elems, const uint8_t *types,
+                   const int64_t *conn_ptr, const int32_t *conn, hipStream_t stream, fea_graph **out);
+
 /* Sizes: nodes (block rows), elements, nonzero blocks, slots (sum n_e^2),
  * colours. Any output pointer may be NULL. */
 int fea_graph_sizes(const fea_graph *g, int64_t *n_nodes, int64_t *n_elems,

@@ -47,6 +47,8 @@ class Material(ctypes.Structure):
 
 _lib.fea_graph_build.argtypes = [_I64, _I64, _P, _P, _P, _P, ctypes.POINTER(_P)]
 _lib.fea_graph_build.restype = ctypes.c_int
+_lib.fea_graph_save.argtypes = [_P, ctypes.c_char_p]
+_lib.fea_graph_load.argtypes = [ctypes.c_char_p, _I64, _I64, _P, _P, _P, _P, ctypes.POINTER(_P)]
 _lib.fea_graph_sizes.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                  ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int)]
 _lib.fea_graph_sym_sizes.argtypes = [_P] + [ctypes.POINTER(_I64)] * 4
@@ -115,7 +117,8 @@ TYPE_SORTED, LEARNED, GP_WEIGHT = 0, 1, 2
 N_FEATURES, N_PARAMS = 12, 5057
 
 # every exported symbol declared in include/fea.h
-EXPORTS = ("fea_graph_build", "fea_graph_sizes", "fea_graph_sym_sizes", "fea_graph_export", "fea_graph_destroy",
+EXPORTS = ("fea_graph_build", "fea_graph_save", "fea_graph_load", "fea_graph_sizes", "fea_graph_sym_sizes",
+           "fea_graph_export", "fea_graph_destroy",
            "fea_graph_tile_colouring",
            "fea_assemble", "fea_assemble_noalloc", "fea_last_timing", "fea_graph_gauss_points", "fea_subscale",
            "fea_batch_gauss_points", "fea_batch_subscale", "fea_last_class_timing", "fea_last_error", "fea_version",
@@ -160,15 +163,20 @@ def _dev(t, dtype):
 
 
 class Graph:
-    """Sparsity graph built on the GPU from device connectivity tensors."""
+    """Sparsity graph built on the GPU from device connectivity tensors, or
+    read from a graph cache file written by save() (cache=path)."""
 
-    def __init__(self, n_nodes, types, conn_ptr, conn, stream=None):
+    def __init__(self, n_nodes, types, conn_ptr, conn, stream=None, cache=None):
         _dev(types, torch.uint8)
         _dev(conn_ptr, torch.int64)
         _dev(conn, torch.int32)
         h = _P()
-        _check(_lib.fea_graph_build(int(n_nodes), int(types.numel()), _ptr(types), _ptr(conn_ptr),
-                                    _ptr(conn), _stream(stream), ctypes.byref(h)))
+        if cache is None:
+            _check(_lib.fea_graph_build(int(n_nodes), int(types.numel()), _ptr(types), _ptr(conn_ptr),
+                                        _ptr(conn), _stream(stream), ctypes.byref(h)))
+        else:
+            _check(_lib.fea_graph_load(str(cache).encode(), int(n_nodes), int(types.numel()), _ptr(types),
+                                       _ptr(conn_ptr), _ptr(conn), _stream(stream), ctypes.byref(h)))
         self._h = h
         self.device = types.device
         n, e, nnz, ml = _I64(), _I64(), _I64(), _I64()
@@ -183,6 +191,10 @@ class Graph:
         if self._h is None:
             raise ValueError("graph destroyed")
         return self._h
+
+    def save(self, path):
+        """Writes the graph cache file (fea_graph_save)."""
+        _check(_lib.fea_graph_save(self.handle, str(path).encode()))
 
     def export(self, stream=None):
         d = self.device
@@ -333,8 +345,8 @@ class DeviceMesh:
         src = mesh.source[:, :dofs]
         self.source = torch.from_numpy(src.copy()).to(dev).contiguous()
 
-    def graph(self, stream=None):
-        return Graph(self.n_nodes, self.types, self.conn_ptr, self.conn, stream=stream)
+    def graph(self, stream=None, cache=None):
+        return Graph(self.n_nodes, self.types, self.conn_ptr, self.conn, stream=stream, cache=cache)
 
     def assemble(self, graph, model=ELASTIC, use_nh=False, residual=False, **kw):
         src = self.source

@@ -84,6 +84,7 @@ int batch_view(fea_batch *b, BatchView *v);
 struct fea_graph {
     int device = 0;
     int64_t n_nodes = 0, n_elems = 0, nnz = 0, map_len = 0, conn_len = 0;
+    uint64_t mesh_fp = 0;  // connectivity fingerprint of the mesh it was built for
     int n_colours = 0;
     // block pattern, element-to-nonzero map and its inverse
     int64_t *row_ptr = nullptr;

@@ -8,7 +8,9 @@
 // elements of one colour share no node.
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "fea_internal.h"
 #include "host_graph.h"
@@ -34,6 +36,30 @@ __global__ void k_validate(int64_t n_nodes, int64_t n_elems, const uint8_t *type
         }
     }
     if (!ok) atomicMin((unsigned long long *)bad, (unsigned long long)e);
+}
+
+// Fingerprint of a validated mesh's connectivity: the sum over elements,
+// modulo 2^64, of a SplitMix64-style mix of the element id, its family and
+// its node ids in order (integer addition, so the result does not depend on
+// the order the elements are visited in). Graph caches are checked against
+// it.
+__device__ inline uint64_t fp_mix(uint64_t z)
+{
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_mesh_fingerprint(int64_t n_elems, const uint8_t *types, const int64_t *conn_ptr,
+                                   const int32_t *conn, unsigned long long *out)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_elems) return;
+    const int t = types[e];
+    uint64_t h = fp_mix((uint64_t)e ^ ((uint64_t)t << 56));
+    for (int64_t p = conn_ptr[e]; p < conn_ptr[e + 1]; ++p) h = fp_mix(h ^ (uint64_t)(uint32_t)conn[p]);
+    atomicAdd(out, (unsigned long long)h);
 }
 
 __global__ void k_slot_count(int64_t n_elems, const uint8_t *types, int64_t *cnt)
@@ -645,6 +671,41 @@ static void destroy(fea_graph *g)
 }
 
 
+// Validates a mesh (FEA_EMESH names the first bad element) and returns
+// its connectivity fingerprint.
+static int mesh_fingerprint(int64_t E, const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
+                            hipStream_t s, uint64_t *fp)
+{
+    TmpBuf acc;
+    int rc;
+    if ((rc = dalloc(&acc.p, sizeof(unsigned long long)))) return rc;
+    FEA_HIP(hipMemsetAsync(acc.p, 0, sizeof(unsigned long long), s));
+    if (E) k_mesh_fingerprint<<<grid_for(E, 256), 256, 0, s>>>(E, types, conn_ptr, conn, (unsigned long long *)acc.p);
+    FEA_HIP(hipGetLastError());
+    FEA_HIP(hipMemcpyAsync(fp, acc.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    return FEA_OK;
+}
+
+static int validate(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn_ptr, const int32_t *conn,
+                    hipStream_t s)
+{
+    TmpBuf bad;
+    int rc;
+    if ((rc = dalloc(&bad.p, sizeof(int64_t)))) return rc;
+    int64_t big = INT64_MAX;
+    FEA_HIP(hipMemcpyAsync(bad.p, &big, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (E) k_validate<<<grid_for(E, 256), 256, 0, s>>>(N, E, types, conn_ptr, conn, (int64_t *)bad.p);
+    FEA_HIP(hipGetLastError());
+    int64_t first_bad = INT64_MAX;
+    FEA_HIP(hipMemcpyAsync(&first_bad, bad.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    if (first_bad != INT64_MAX)
+        return set_error(FEA_EMESH, "invalid element %lld (unknown type, wrong node count, node id out "
+                         "of range or repeated node)", (long long)first_bad);
+    return FEA_OK;
+}
+
 static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn_ptr,
                  const int32_t *conn, hipStream_t s, fea_graph *g)
 {
@@ -658,18 +719,9 @@ static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn
     FEA_HIP(hipStreamSynchronize(s));
 
     // validation
-    TmpBuf bad, tmp, cnt64, cnt32, flag, fillb;
-    if ((rc = dalloc(&bad.p, sizeof(int64_t)))) return rc;
-    int64_t big = INT64_MAX;
-    FEA_HIP(hipMemcpyAsync(bad.p, &big, sizeof(int64_t), hipMemcpyHostToDevice, s));
-    if (E) k_validate<<<grid_for(E, BS), BS, 0, s>>>(N, E, types, conn_ptr, conn, (int64_t *)bad.p);
-    FEA_HIP(hipGetLastError());
-    int64_t first_bad = INT64_MAX;
-    FEA_HIP(hipMemcpyAsync(&first_bad, bad.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    FEA_HIP(hipStreamSynchronize(s));
-    if (first_bad != INT64_MAX)
-        return set_error(FEA_EMESH, "invalid element %lld (unknown type, wrong node count, node id out "
-                         "of range or repeated node)", (long long)first_bad);
+    TmpBuf tmp, cnt64, cnt32, flag, fillb;
+    if ((rc = validate(N, E, types, conn_ptr, conn, s))) return rc;
+    if ((rc = mesh_fingerprint(E, types, conn_ptr, conn, s, &g->mesh_fp))) return rc;
 
     int64_t scan_n = std::max<int64_t>(std::max<int64_t>(E, N), g->conn_len);
     // slots: map_ptr = prefix sum of n_e^2
@@ -802,6 +854,207 @@ extern "C" int fea_graph_build(int64_t n_nodes, int64_t n_elems, const uint8_t *
     if (rc == FEA_OK) rc = noalloc_setup();
     if (rc != FEA_OK) {
         (void)hipStreamSynchronize(stream);
+        destroy(g);
+        return rc;
+    }
+    *out = g;
+    return FEA_OK;
+}
+
+namespace {
+
+// Graph cache file: header (magic, version, GPU architecture name, sizes,
+// mesh fingerprint, family and colour offsets), then the graph's device
+// arrays in a fixed order, each preceded by its byte count.
+constexpr char kGraphMagic[8] = {'F', 'E', 'A', 'G', 'R', 'A', 'P', 'H'};
+constexpr uint32_t kGraphVersion = 1;
+constexpr size_t kStage = size_t(64) << 20;  // host staging buffer (bytes)
+
+struct GraphHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t n_colours;
+    char arch[64];
+    int64_t n_nodes, n_elems, nnz, map_len, conn_len;
+    uint64_t mesh_fp;
+    int64_t seg[5], node_base[5], slot_base[5];
+    int64_t cseg_len;
+};
+
+struct HostFile {
+    FILE *f = nullptr;
+    ~HostFile()
+    {
+        if (f) fclose(f);
+    }
+};
+
+struct PinnedBuf {
+    void *p = nullptr;
+    ~PinnedBuf()
+    {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+int device_arch(int dev, char *arch)
+{
+    hipDeviceProp_t prop;
+    FEA_HIP(hipGetDeviceProperties(&prop, dev));
+    memset(arch, 0, 64);
+    strncpy(arch, prop.gcnArchName, 63);
+    return FEA_OK;
+}
+
+// The graph's arrays that the cache holds, with their lengths in bytes.
+struct GraphArray {
+    void **p;
+    size_t bytes;
+};
+
+std::vector<GraphArray> graph_arrays(fea_graph *g)
+{
+    const size_t N = (size_t)g->n_nodes, E = (size_t)g->n_elems, nnz = (size_t)g->nnz,
+                 ml = (size_t)g->map_len, cl = (size_t)g->conn_len;
+    auto one = [](size_t n) { return n ? n : 1; };
+    return {{(void **)&g->row_ptr, 8 * (N + 1)},   {(void **)&g->col, 4 * one(nnz)},
+            {(void **)&g->map_ptr, 8 * (E + 1)},   {(void **)&g->e2nnz, 4 * one(ml)},
+            {(void **)&g->inv_ptr, 8 * (nnz + 1)}, {(void **)&g->inv, 4 * one(ml)},
+            {(void **)&g->pnodes, 4 * one(cl)},    {(void **)&g->pdest, 4 * one(ml)},
+            {(void **)&g->prdest, 4 * one(cl)},    {(void **)&g->n2e_ptr, 8 * (N + 1)},
+            {(void **)&g->n2e, 4 * one(cl)},       {(void **)&g->n2a, one(cl)},
+            {(void **)&g->perm, 4 * one(E)},       {(void **)&g->colour, 2 * one(E)},
+            {(void **)&g->cperm, 4 * one(E)}};
+}
+
+}  // namespace
+
+extern "C" int fea_graph_save(const fea_graph *gc, const char *path)
+{
+    clear_error();
+    if (!gc || !path) return set_error(FEA_EINVAL, "graph and path are required");
+    fea_graph *g = const_cast<fea_graph *>(gc);
+    GraphHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, kGraphMagic, 8);
+    h.version = kGraphVersion;
+    h.n_colours = g->n_colours;
+    int rc = device_arch(g->device, h.arch);
+    if (rc) return rc;
+    h.n_nodes = g->n_nodes;
+    h.n_elems = g->n_elems;
+    h.nnz = g->nnz;
+    h.map_len = g->map_len;
+    h.conn_len = g->conn_len;
+    h.mesh_fp = g->mesh_fp;
+    memcpy(h.seg, g->seg, sizeof(h.seg));
+    memcpy(h.node_base, g->node_base, sizeof(h.node_base));
+    memcpy(h.slot_base, g->slot_base, sizeof(h.slot_base));
+    h.cseg_len = (int64_t)g->cseg.size();
+    HostFile f;
+    f.f = fopen(path, "wb");
+    if (!f.f) return set_error(FEA_EINVAL, "cannot write %s", path);
+    bool ok = fwrite(&h, sizeof(h), 1, f.f) == 1 &&
+              (h.cseg_len == 0 || fwrite(g->cseg.data(), 8, (size_t)h.cseg_len, f.f) == (size_t)h.cseg_len);
+    PinnedBuf stage;
+    FEA_HIP(hipHostMalloc(&stage.p, kStage, hipHostMallocDefault));
+    FEA_HIP(hipDeviceSynchronize());
+    for (const GraphArray &a : graph_arrays(g)) {
+        const uint64_t nb = a.bytes;
+        ok = ok && fwrite(&nb, 8, 1, f.f) == 1;
+        for (size_t off = 0; ok && off < a.bytes; off += kStage) {
+            const size_t n = std::min(kStage, a.bytes - off);
+            FEA_HIP(hipMemcpy(stage.p, (char *)*a.p + off, n, hipMemcpyDeviceToHost));
+            ok = fwrite(stage.p, 1, n, f.f) == n;
+        }
+    }
+    if (!ok) return set_error(FEA_EINVAL, "short write to %s", path);
+    return FEA_OK;
+}
+
+extern "C" int fea_graph_load(const char *path, int64_t n_nodes, int64_t n_elems, const uint8_t *types,
+                              const int64_t *conn_ptr, const int32_t *conn, hipStream_t stream, fea_graph **out)
+{
+    clear_error();
+    if (!out || !path) return set_error(FEA_EINVAL, "path and out are required");
+    *out = nullptr;
+    if (n_nodes < 0 || n_elems < 0) return set_error(FEA_EINVAL, "negative size");
+    if (n_elems > 0 && (!types || !conn_ptr || !conn))
+        return set_error(FEA_EINVAL, "types, conn_ptr and conn are required");
+    HostFile f;
+    f.f = fopen(path, "rb");
+    if (!f.f) return set_error(FEA_EINVAL, "cannot read %s", path);
+    GraphHeader h;
+    if (fread(&h, sizeof(h), 1, f.f) != 1 || memcmp(h.magic, kGraphMagic, 8) != 0)
+        return set_error(FEA_EINVAL, "%s is not a graph cache", path);
+    if (h.version != kGraphVersion)
+        return set_error(FEA_EINVAL, "%s: graph cache version %u, this library reads %u", path, h.version,
+                         kGraphVersion);
+    int dev = 0;
+    FEA_HIP(hipGetDevice(&dev));
+    char arch[64];
+    int rc = device_arch(dev, arch);
+    if (rc) return rc;
+    h.arch[63] = 0;
+    if (strcmp(arch, h.arch) != 0)
+        return set_error(FEA_EINVAL, "%s was written on %s, this device is %s", path, h.arch, arch);
+    if (h.n_nodes != n_nodes || h.n_elems != n_elems)
+        return set_error(FEA_EINVAL, "%s holds the graph of a mesh of %lld nodes and %lld elements, not %lld and %lld",
+                         path, (long long)h.n_nodes, (long long)h.n_elems, (long long)n_nodes, (long long)n_elems);
+    if (h.cseg_len < 0 || h.n_colours < 0 || h.nnz < 0 || h.map_len < 0 || h.conn_len < 0 ||
+        h.cseg_len != 4 * ((int64_t)h.n_colours + 1))
+        return set_error(FEA_EINVAL, "%s: inconsistent header", path);
+    // the mesh must be the one the graph was built for
+    if ((rc = validate(n_nodes, n_elems, types, conn_ptr, conn, stream))) return rc;
+    uint64_t fp = 0;
+    if ((rc = mesh_fingerprint(n_elems, types, conn_ptr, conn, stream, &fp))) return rc;
+    if (fp != h.mesh_fp) return set_error(FEA_EINVAL, "%s was built for another mesh (connectivity differs)", path);
+    fea_graph *g = new (std::nothrow) fea_graph();
+    if (!g) return set_error(FEA_ENOMEM, "host allocation failed");
+    FEA_HIP(hipGetDevice(&g->device));
+    g->n_nodes = h.n_nodes;
+    g->n_elems = h.n_elems;
+    g->nnz = h.nnz;
+    g->map_len = h.map_len;
+    g->conn_len = h.conn_len;
+    g->n_colours = h.n_colours;
+    g->mesh_fp = h.mesh_fp;
+    memcpy(g->seg, h.seg, sizeof(h.seg));
+    memcpy(g->node_base, h.node_base, sizeof(h.node_base));
+    memcpy(g->slot_base, h.slot_base, sizeof(h.slot_base));
+    g->cseg.resize((size_t)h.cseg_len);
+    bool ok = h.cseg_len == 0 || fread(g->cseg.data(), 8, (size_t)h.cseg_len, f.f) == (size_t)h.cseg_len;
+    PinnedBuf stage;
+    if (ok) {
+        hipError_t e = hipHostMalloc(&stage.p, kStage, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            destroy(g);
+            return set_error(FEA_ENOMEM, "pinned staging buffer: %s", hipGetErrorString(e));
+        }
+    }
+    for (const GraphArray &a : graph_arrays(g)) {
+        if (!ok) break;
+        uint64_t nb = 0;
+        ok = fread(&nb, 8, 1, f.f) == 1 && nb == a.bytes;
+        if (!ok) break;
+        if ((rc = dalloc(a.p, a.bytes))) {
+            destroy(g);
+            return rc;
+        }
+        for (size_t off = 0; ok && off < a.bytes; off += kStage) {
+            const size_t n = std::min(kStage, a.bytes - off);
+            ok = fread(stage.p, 1, n, f.f) == n;
+            if (ok && hipMemcpy((char *)*a.p + off, stage.p, n, hipMemcpyHostToDevice) != hipSuccess) {
+                destroy(g);
+                return set_error(FEA_EHIP, "copy of %s to the device failed", path);
+            }
+        }
+    }
+    if (!ok) {
+        destroy(g);
+        return set_error(FEA_EINVAL, "%s is truncated or does not match its header", path);
+    }
+    if ((rc = noalloc_setup())) {
         destroy(g);
         return rc;
     }
