@@ -430,11 +430,13 @@ int fea_batch_subscale(fea_batch *b, hipStream_t stream, double *out, int32_t *s
 /*
  * Tile autotuner: chooses the elements per work item of each family by
  * timing the batch's persistent kernel (the GPU counterpart of the paper's
- * chunk-size study, Section 5.2). Coordinate descent: for each family in
- * turn the candidates EPB*{1,2,4,8,16,32} are tried with the other tiles
- * fixed (EPB = the upper-triangle tile: 25 tet4, 17 pyr5, 12 pen6, 7 hex8),
- * two sweeps, each candidate timed as the median of `reps`
- * launches of opt->variant (FEA_ROWOWNER or FEA_ROWSYM). The best tiles
+ * chunk-size study, Section 5.2). Coordinate descent from the batch's
+ * current tiles: for each family in turn the candidates
+ * EPB*{1,2,3,4,6,8,12,16,24,32} are tried with the other tiles fixed (EPB =
+ * the upper-triangle tile: 25 tet4, 17 pyr5, 12 pen6, 7 hex8), two sweeps,
+ * each candidate timed as the median of `reps` launches of opt->variant
+ * (FEA_ROWOWNER or FEA_ROWSYM) and taken only if at least 1% faster than
+ * the best so far (smaller gains are within run-to-run noise). The best tiles
  * are applied to the batch, returned in tile_out
  * (HOST int32[4]) and, if table_path is not NULL, stored in that text file
  * under the key (gfx950, model, precision). Allocates temporary outputs.

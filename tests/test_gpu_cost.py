@@ -136,7 +136,7 @@ def test_autotune_picks_candidates_and_persists():
         tile = b.autotune(precision=fea.MIXED, out_dtype=fea.F32, reps=3, table_path=path)
         epb = (25, 17, 12, 7)
         for t in range(4):
-            assert tile[t] % epb[t] == 0 and tile[t] // epb[t] in (1, 2, 4, 8, 16, 32)
+            assert tile[t] % epb[t] == 0 and tile[t] // epb[t] in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32)
         assert list(fea.tile_table_load(path, fea.ELASTIC, fea.MIXED)) == list(tile)
         with pytest.raises(fea.FeaError):
             fea.tile_table_load(path, fea.POISSON, fea.FP64)
