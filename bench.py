@@ -162,15 +162,20 @@ SUB_NQ = (1, 8, 6, 8)   # Gauss points per family
 
 def subscale_flops_per_point(t, B):
     """Algorithmic flops of the subgrid scale at one Gauss point of family t
-    (FMA = 2): per node J (9 FMA) and, unless the family is affine (tet4),
-    the mixed second derivatives of x (9) and grad / mixed second
-    derivatives of u (3B + 3B); then J^-1 with its determinant and w detJ
-    (43), the second-derivative transform and the operator (282 for
+    (FMA = 2). tet4: per node J (9 FMA). The others, per field (the three
+    coordinates and the B field components): the lane's polynomial
+    coefficient of it from the node values (hex8 and the pyramid: eight
+    signed additions and a scaling by 1/8; pen6: at most five operations)
+    and its first and mixed second reference derivatives at the point
+    (hex8, pyramid: 9 FMA; pen6: 4 FMA). Then J^-1 with its determinant and
+    w detJ (43), the second-derivative transform and the operator (282 for
     elasticity, 56 for Poisson; tet4: none), the volume sum (1) and tau r
     (B)."""
-    per_node = 18 + (0 if t == 0 else 18 + 12 * B)
-    post = 0 if t == 0 else (282 if B == 3 else 56)
-    return SUB_NN[t] * per_node + 43 + post + 1 + B
+    if t == 0:
+        return SUB_NN[0] * 18 + 43 + 1 + B
+    per_field = 27 if t in (1, 3) else 13
+    post = 282 if B == 3 else 56
+    return (3 + B) * per_field + 43 + post + 1 + B
 
 
 def subscale_work(mesh, B, np):

@@ -83,10 +83,14 @@ def test_subscale_work_counts_every_element_and_node_once():
         f2 += nq[t] * bench.subscale_flops_per_point(t, 3)
     assert byts == b2 and flops == f2
     # per Gauss point, by hand: tet4 reads J only (18 per node); the others
-    # add 54 per node for the second derivatives and 282 after the node loop
+    # form one polynomial coefficient per field (hex8 / pyramid: 8 additions
+    # and a scaling; pen6: at most 5 operations) and evaluate its first and
+    # mixed second derivatives (hex8 / pyramid 9 FMA, pen6 4 FMA), then 282
+    # (elasticity) or 56 (Poisson) after them
     assert bench.subscale_flops_per_point(0, 3) == 4 * 18 + 43 + 1 + 3
-    assert bench.subscale_flops_per_point(3, 3) == 8 * 72 + 43 + 282 + 1 + 3
-    assert bench.subscale_flops_per_point(1, 1) == 5 * (18 + 18 + 12) + 43 + 56 + 1 + 1
+    assert bench.subscale_flops_per_point(3, 3) == 6 * (9 + 18) + 43 + 282 + 1 + 3
+    assert bench.subscale_flops_per_point(2, 3) == 6 * (5 + 8) + 43 + 282 + 1 + 3
+    assert bench.subscale_flops_per_point(1, 1) == 4 * (9 + 18) + 43 + 56 + 1 + 1
 
 
 def test_layer_sample_keeps_the_elements_of_its_layers():
