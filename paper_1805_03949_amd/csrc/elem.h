@@ -937,14 +937,13 @@ __device__ void elem_tile_sym(const ElemArgs &A, int64_t first, ElemSmem<T, MODE
     // order, in FP64: either one thread per tile-block adding all BB
     // components, or one thread per (tile-block, component), which walks
     // the block's entry list BB times but spreads a tile's sums over more
-    // threads. Measured on MI355X over the 256^3 mesh, FP64, ms per family
-    // per block / per component: tet4 7.63 / 7.13, pyr5 4.34 / 4.22, pen6
-    // 4.55 / 4.74, hex8 9.88 / 10.11 (element phase 27.2 ms with one thread
-    // per block everywhere, 26.65 with this choice); FP32 staged blocks:
-    // per block in every family (per component for tet4 and pyr5 was
-    // slightly slower). Both give bitwise the same sums.
+    // threads. Measured on MI355X (element phase, ms, FP64, hybrid256 /
+    // hybrid96): per component everywhere 24.56 / 1.62, per block for pen6
+    // and hex8 24.70 / 1.67, per block everywhere 26.2 / 1.71; FP32 staged
+    // blocks: per block in every family (per component for tet4 and pyr5
+    // was slightly slower). Both give bitwise the same sums.
     CT *out = (CT *)A.contrib;
-    constexpr bool PER_BLOCK = T >= 2 || sizeof(CT) == 4;
+    constexpr bool PER_BLOCK = sizeof(CT) == 4;
     if constexpr (PER_BLOCK) {
         for (int d = tid; d < nd; d += 256) {
             double acc[BB];
