@@ -87,7 +87,7 @@ k_batch(const ElemArgs *__restrict__ itemargs, const int4 *items,
         if (it < 0) break;
         const uint64_t t0 = clock64();
         const int32_t count = __builtin_amdgcn_readfirstlane(items[it].w);
-        const ElemArgs &A = itemargs[it];
+        const ElemArgs A = from_global(reinterpret_cast<const ElemArgsGlobal *>(itemargs)[it]);
         run_item<T, MODEL, CT, VAR>(A, count, S);
         __syncthreads();
         if (threadIdx.x == 0) {

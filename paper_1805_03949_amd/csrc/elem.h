@@ -21,6 +21,7 @@
 // points; the right-hand side one thread per (element, node).
 #pragma once
 #include <climits>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 
@@ -197,6 +198,92 @@ struct ElemArgs {
     const int32_t *tb_blk;
     const int32_t *lpart;
 };
+
+// The element arguments as the persistent kernels read them from their
+// argument table: the same layout as ElemArgs, with every pointer typed as
+// addressing global memory. Pointers loaded as plain (generic) pointers are
+// accessed with flat instructions, which also count against the LDS wait
+// counter, so that every wait for LDS data would wait for outstanding
+// global loads and stores too; pointers typed global keep global
+// instructions, as kernel arguments do.
+#define FEA_G(T) T __attribute__((address_space(1))) *
+struct ElemArgsGlobal {
+    FEA_G(const double) x;
+    FEA_G(const double) y;
+    FEA_G(const double) z;
+    FEA_G(const int64_t) conn_ptr;
+    FEA_G(const int32_t) conn;
+    FEA_G(const int32_t) elems;
+    int64_t n;
+    FEA_G(const int64_t) map_ptr;
+    FEA_G(const int32_t) e2nnz;
+    FEA_G(const int32_t) pnodes;
+    FEA_G(const int32_t) pdest;
+    FEA_G(const int32_t) prdest;
+    FEA_G(const double) young;
+    FEA_G(const double) nu;
+    FEA_G(const uint8_t) nh_flag;
+    FEA_G(const double) u;
+    FEA_G(const double) source;
+    FEA_G(double) vals;
+    FEA_G(double) rhs;
+    FEA_G(void) contrib;
+    FEA_G(void) rcontrib;
+    FEA_G(int32_t) status;
+    FEA_G(const int64_t) tent_ptr;
+    FEA_G(const int64_t) ttb_ptr;
+    FEA_G(const uint16_t) tent;
+    FEA_G(const uint16_t) tb_eend;
+    FEA_G(const int32_t) tb_slot;
+    FEA_G(const int32_t) tiles;
+    int64_t ntiles;
+    FEA_G(const int32_t) tb_blk;
+    FEA_G(const int32_t) lpart;
+};
+#undef FEA_G
+static_assert(sizeof(ElemArgsGlobal) == sizeof(ElemArgs), "ElemArgsGlobal mirrors ElemArgs");
+static_assert(offsetof(ElemArgsGlobal, lpart) == offsetof(ElemArgs, lpart), "ElemArgsGlobal mirrors ElemArgs");
+static_assert(offsetof(ElemArgsGlobal, ntiles) == offsetof(ElemArgs, ntiles), "ElemArgsGlobal mirrors ElemArgs");
+static_assert(offsetof(ElemArgsGlobal, n) == offsetof(ElemArgs, n), "ElemArgsGlobal mirrors ElemArgs");
+
+// ElemArgs from an argument-table entry (its pointers converted from the
+// global address space, so that the compiler keeps global accesses).
+__device__ __forceinline__ ElemArgs from_global(const ElemArgsGlobal &g)
+{
+    ElemArgs a;
+    a.x = (const double *)g.x;
+    a.y = (const double *)g.y;
+    a.z = (const double *)g.z;
+    a.conn_ptr = (const int64_t *)g.conn_ptr;
+    a.conn = (const int32_t *)g.conn;
+    a.elems = (const int32_t *)g.elems;
+    a.n = g.n;
+    a.map_ptr = (const int64_t *)g.map_ptr;
+    a.e2nnz = (const int32_t *)g.e2nnz;
+    a.pnodes = (const int32_t *)g.pnodes;
+    a.pdest = (const int32_t *)g.pdest;
+    a.prdest = (const int32_t *)g.prdest;
+    a.young = (const double *)g.young;
+    a.nu = (const double *)g.nu;
+    a.nh_flag = (const uint8_t *)g.nh_flag;
+    a.u = (const double *)g.u;
+    a.source = (const double *)g.source;
+    a.vals = (double *)g.vals;
+    a.rhs = (double *)g.rhs;
+    a.contrib = (void *)g.contrib;
+    a.rcontrib = (void *)g.rcontrib;
+    a.status = (int32_t *)g.status;
+    a.tent_ptr = (const int64_t *)g.tent_ptr;
+    a.ttb_ptr = (const int64_t *)g.ttb_ptr;
+    a.tent = (const uint16_t *)g.tent;
+    a.tb_eend = (const uint16_t *)g.tb_eend;
+    a.tb_slot = (const int32_t *)g.tb_slot;
+    a.tiles = (const int32_t *)g.tiles;
+    a.ntiles = g.ntiles;
+    a.tb_blk = (const int32_t *)g.tb_blk;
+    a.lpart = (const int32_t *)g.lpart;
+    return a;
+}
 
 // V_ROWSYM: the row-owner scatter on the upper triangle. A symmetric
 // element matrix has block (b, a) equal to block (a, b) transposed, so one
