@@ -27,6 +27,7 @@
 // class; neo-Hookean kernels add F^-1 and the tangent coefficients to the
 // records.
 #include <algorithm>
+#include <cstddef>
 #include <vector>
 
 #include "elem.h"
@@ -149,6 +150,70 @@ struct GatherArgs {
     void *vals, *rhs;
     int out_f32;
 };
+
+// GatherArgs as the batched kernels read them from the mesh table: every
+// pointer typed as addressing global memory, so that the compiler keeps
+// global instead of flat accesses (flat ones also count against the LDS
+// wait counter).
+#define FEA_G(T) T __attribute__((address_space(1))) *
+struct GatherArgsGlobal {
+    FEA_G(const double) x;
+    FEA_G(const double) y;
+    FEA_G(const double) z;
+    FEA_G(const uint8_t) types;
+    FEA_G(const double) young;
+    FEA_G(const double) nu;
+    FEA_G(const double) source;
+    FEA_G(int32_t) status;
+    FEA_G(const int64_t) n2e_ptr;
+    FEA_G(const int64_t) inv_ptr;
+    FEA_G(const int32_t) n2e;
+    FEA_G(const uint8_t) n2a;
+    FEA_G(const int32_t) gnodes;
+    FEA_G(const uint8_t) desc;
+    FEA_G(const uint8_t) nh_flag;
+    FEA_G(const double) u;
+    int64_t vals_off, rhs_off;
+    int32_t mesh;
+    FEA_G(const int32_t) tiles;
+    FEA_G(void) vals;
+    FEA_G(void) rhs;
+    int out_f32;
+};
+#undef FEA_G
+static_assert(sizeof(GatherArgsGlobal) == sizeof(GatherArgs) &&
+                  offsetof(GatherArgsGlobal, tiles) == offsetof(GatherArgs, tiles) &&
+                  offsetof(GatherArgsGlobal, out_f32) == offsetof(GatherArgs, out_f32),
+              "GatherArgsGlobal mirrors GatherArgs");
+
+__device__ __forceinline__ GatherArgs from_global(const GatherArgsGlobal &g)
+{
+    GatherArgs a;
+    a.x = (const double *)g.x;
+    a.y = (const double *)g.y;
+    a.z = (const double *)g.z;
+    a.types = (const uint8_t *)g.types;
+    a.young = (const double *)g.young;
+    a.nu = (const double *)g.nu;
+    a.source = (const double *)g.source;
+    a.status = (int32_t *)g.status;
+    a.n2e_ptr = (const int64_t *)g.n2e_ptr;
+    a.inv_ptr = (const int64_t *)g.inv_ptr;
+    a.n2e = (const int32_t *)g.n2e;
+    a.n2a = (const uint8_t *)g.n2a;
+    a.gnodes = (const int32_t *)g.gnodes;
+    a.desc = (const uint8_t *)g.desc;
+    a.nh_flag = (const uint8_t *)g.nh_flag;
+    a.u = (const double *)g.u;
+    a.vals_off = g.vals_off;
+    a.rhs_off = g.rhs_off;
+    a.mesh = g.mesh;
+    a.tiles = (const int32_t *)g.tiles;
+    a.vals = (void *)g.vals;
+    a.rhs = (void *)g.rhs;
+    a.out_f32 = g.out_f32;
+    return a;
+}
 
 // J, det J, J^-1 and the row node's gradient at Gauss point q of pair p
 // (coordinates at lanes x0 ..), with the expressions of the element kernels
@@ -529,8 +594,8 @@ k_gather(GatherArgs L, const GatherArgs *meshes, const int32_t *tmesh, int64_t n
     }
     // mesh view of tile t (scalar loads; one mesh when not batched)
     auto mesh_of = [&](int64_t tt) -> int32_t { return BATCHED ? tmesh[tt] : 0; };
-    auto M = [&](int32_t m) -> const GatherArgs & {
-        if constexpr (BATCHED) return meshes[m];
+    auto M = [&](int32_t m) -> GatherArgs {
+        if constexpr (BATCHED) return from_global(reinterpret_cast<const GatherArgsGlobal *>(meshes)[m]);
         else return L;
     };
     TileRec R = load_rec(L.tiles, t);

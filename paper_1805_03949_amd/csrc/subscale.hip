@@ -128,6 +128,48 @@ struct SubArgs {
     int32_t *status;       // smallest element id with detJ <= 0
 };
 
+// SubArgs as the batched kernel reads them from its table: every pointer
+// typed as addressing global memory, so that the compiler keeps global
+// instead of flat accesses (see ElemArgsGlobal).
+#define FEA_G(T) T __attribute__((address_space(1))) *
+struct SubArgsGlobal {
+    FEA_G(const double) x;
+    FEA_G(const double) y;
+    FEA_G(const double) z;
+    FEA_G(const double) u;
+    FEA_G(const double) young;
+    FEA_G(const double) nu;
+    FEA_G(const double) source;
+    FEA_G(const int32_t) perm;
+    FEA_G(const int32_t) pnodes;
+    FEA_G(const int64_t) gp_ptr;
+    int64_t n;
+    FEA_G(double) out;
+    FEA_G(int32_t) status;
+};
+#undef FEA_G
+static_assert(sizeof(SubArgsGlobal) == sizeof(SubArgs) && offsetof(SubArgsGlobal, status) == offsetof(SubArgs, status),
+              "SubArgsGlobal mirrors SubArgs");
+
+__device__ __forceinline__ SubArgs from_global(const SubArgsGlobal &g)
+{
+    SubArgs a;
+    a.x = (const double *)g.x;
+    a.y = (const double *)g.y;
+    a.z = (const double *)g.z;
+    a.u = (const double *)g.u;
+    a.young = (const double *)g.young;
+    a.nu = (const double *)g.nu;
+    a.source = (const double *)g.source;
+    a.perm = (const int32_t *)g.perm;
+    a.pnodes = (const int32_t *)g.pnodes;
+    a.gp_ptr = (const int64_t *)g.gp_ptr;
+    a.n = g.n;
+    a.out = (double *)g.out;
+    a.status = (int32_t *)g.status;
+    return a;
+}
+
 // LDS of one workgroup. Strides padded to 2 (mod 4) doubles: the 8 Gauss
 // points or elements that a wave reads at once then start in distinct
 // 16-byte bank slots (hex8's 48-double element records aliased every
@@ -432,7 +474,7 @@ __global__ void __launch_bounds__(256) k_subscale_batch(const SubArgs *__restric
         const int4 w = items[it];
         const int32_t m = __builtin_amdgcn_readfirstlane(w.x);
         const int64_t first = __builtin_amdgcn_readfirstlane(w.z), count = __builtin_amdgcn_readfirstlane(w.w);
-        const SubArgs &A = margs[m];
+        const SubArgs A = from_global(reinterpret_cast<const SubArgsGlobal *>(margs)[m]);
         for (int64_t g0 = 0; g0 < count; g0 += EPW) sub_group(A, first + g0, first + count, S);
     }
 }
