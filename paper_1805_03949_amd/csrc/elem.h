@@ -481,15 +481,20 @@ constexpr int lds_waves(int extra = 0)
 // Minimum waves per SIMD asked of the element kernels: the FP64
 // linear-elastic upper-triangle instances at their LDS occupancy (tet4,
 // pen6 and hex8 eight waves: 64 VGPRs, which their one-tile code fits
-// without spills, and their persistent code too; pyr5 six); the others
-// unbounded (a bound there spills, the FP32 hex8 and the neo-Hookean
-// instances included, and a seven-wave bound on the persistent pen6 and
-// hex8 code as well: measured with the compiler's resource report).
+// without spills, and their persistent code too; pyr5 six); in the
+// persistent kernels also the FP64 neo-Hookean tet4 instance at five (96
+// VGPRs instead of 102, no spills; hetero128 kernel 5.47 -> 5.27 ms); the
+// others unbounded (a bound there spills, the FP32 hex8 and the other
+// neo-Hookean instances included, and a seven-wave bound on the persistent
+// pen6 and hex8 code as well: measured with the compiler's resource
+// report).
 template <int T, int MODEL, int VAR, typename CT>
 constexpr int persistent_min_waves()
 {
     using S = ElemSmem<T, MODEL, VAR, CT>;
-    return (MODEL == FEA_ELASTIC && S::SYM && sizeof(CT) == 8) ? lds_waves<S>(16) : 1;
+    if (MODEL == FEA_ELASTIC && S::SYM && sizeof(CT) == 8) return lds_waves<S>(16);
+    if (MODEL == M_ELASTIC_NH && S::SYM && T == 0 && sizeof(CT) == 8) return 5;
+    return 1;
 }
 
 template <int T, int MODEL, int VAR, typename CT>
