@@ -38,81 +38,13 @@
 // the element's Gauss-point offset.
 #include <algorithm>
 #include <climits>
-#include <mutex>
 
 #include "elem.h"
 
 namespace fea {
 
-// Mixed second reference derivatives d2 N_a / dxi_j dxi_l for the pairs
-// (j, l) = (0, 1), (0, 2), (1, 2), per family, Gauss point and node.
-struct SubTables {
-    double d2[4][8][8][3];
-};
-static __constant__ SubTables c_sub;
-
 // Gauss coordinate of the two-point rule, as in the reference tables.
 constexpr double kGauss = 0.57735026918962576451;
-
-// Same shape functions as shape_host, differentiated twice (hexahedron
-// factors f = (1 + s xi) / 2 per direction; the pyramid's apex is the sum
-// of the collapsed top nodes).
-static void shape2_host(int t, const double p[3], double d2[8][3])
-{
-    static const int sg[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
-                                 {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
-    for (int a = 0; a < 8; ++a)
-        for (int m = 0; m < 3; ++m) d2[a][m] = 0.0;
-    if (t == 3 || t == 1) {
-        double h[8][3];
-        for (int a = 0; a < 8; ++a) {
-            const double fx = 0.5 * (1 + sg[a][0] * p[0]), fy = 0.5 * (1 + sg[a][1] * p[1]),
-                         fz = 0.5 * (1 + sg[a][2] * p[2]);
-            h[a][0] = 0.25 * sg[a][0] * sg[a][1] * fz;
-            h[a][1] = 0.25 * sg[a][0] * sg[a][2] * fy;
-            h[a][2] = 0.25 * sg[a][1] * sg[a][2] * fx;
-        }
-        const int nb = t == 3 ? 8 : 4;
-        for (int a = 0; a < nb; ++a)
-            for (int m = 0; m < 3; ++m) d2[a][m] = h[a][m];
-        if (t == 1)
-            for (int m = 0; m < 3; ++m) d2[4][m] = h[4][m] + h[5][m] + h[6][m] + h[7][m];
-    } else if (t == 2) {
-        const double dL[3][2] = {{-1, -1}, {1, 0}, {0, 1}};
-        for (int a = 0; a < 6; ++a) {
-            const int k = a % 3;
-            const double s = a < 3 ? -1.0 : 1.0;
-            d2[a][1] = 0.5 * s * dL[k][0];
-            d2[a][2] = 0.5 * s * dL[k][1];
-        }
-    }
-}
-
-static int ensure_sub_tables()
-{
-    static std::mutex mtx;
-    static bool done[64] = {false};
-    int dev = 0;
-    FEA_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return set_error(FEA_EINVAL, "device index %d unsupported", dev);
-    std::lock_guard<std::mutex> lock(mtx);
-    if (done[dev]) return FEA_OK;
-    SubTables S;
-    memset(&S, 0, sizeof(S));
-    for (int t = 0; t < 4; ++t) {
-        double pts[8][3], w[8];
-        const int nq = rule_host(t, pts, w);
-        for (int q = 0; q < nq; ++q) {
-            double d2[8][3];
-            shape2_host(t, pts[q], d2);
-            for (int a = 0; a < 8; ++a)
-                for (int m = 0; m < 3; ++m) S.d2[t][q][a][m] = d2[a][m];
-        }
-    }
-    FEA_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_sub), &S, sizeof(S), 0, hipMemcpyHostToDevice));
-    done[dev] = true;
-    return FEA_OK;
-}
 
 struct SubArgs {
     const double *x, *y, *z;
@@ -593,7 +525,7 @@ extern "C" int fea_subscale(const fea_graph *gc, const double *x, const double *
     FEA_HIP(hipGetDevice(&dev));
     if (dev != g->device) return set_error(FEA_EINVAL, "graph lives on device %d, current is %d", g->device, dev);
     int rc;
-    if ((rc = ensure_tables()) || (rc = ensure_sub_tables()) || (rc = gauss_points_prepare(g, stream))) return rc;
+    if ((rc = ensure_tables()) || (rc = gauss_points_prepare(g, stream))) return rc;
 
     int32_t *st = status;
     if (!st) {
@@ -773,7 +705,7 @@ extern "C" int fea_batch_subscale(fea_batch *b, hipStream_t stream, double *out,
     int dev = 0;
     FEA_HIP(hipGetDevice(&dev));
     if (dev != v.device) return set_error(FEA_EINVAL, "batch lives on device %d, current is %d", v.device, dev);
-    if ((rc = ensure_tables()) || (rc = ensure_sub_tables())) return rc;
+    if ((rc = ensure_tables())) return rc;
     std::vector<int64_t> off;
     if ((rc = batch_gauss_offsets(v, stream, off))) return rc;
     if (off.back() > 0 && !out) return set_error(FEA_EINVAL, "NULL output");
