@@ -388,21 +388,14 @@ def tiny_mesh(cell_types_grid, jitter=0.0, seed=0, dofs=3):
     return cube_mesh(n, ct.reshape(-1), jitter=jitter, seed=seed, dofs=dofs)
 
 
-def layer_sample(mesh, layers, return_nodes=False):
-    """The elements of the given z-layers of cells of a band mesh (every cell
-    of a layer has one family), as a mesh of their own: nodes renumbered in
-    ascending order of their ids in `mesh`, coordinates, materials, sources
-    and flags copied. Used to time work on a bounded part of a large mesh
-    with its family mix, and to check whole rows of it. return_nodes: also
-    return the ids in `mesh` of the sample's nodes (ascending)."""
-    n = mesh.n_cells
-    lay = n * n
-    # element offset of every layer: a layer holds n^2 cells of one family
-    start = np.zeros(n + 1, dtype=np.int64)
-    for L in range(n):
-        start[L + 1] = start[L] + lay * SUBELEMS[int(mesh.types[start[L]])]
-    assert start[-1] == mesh.n_elems, "not a band mesh"
-    elems = np.concatenate([np.arange(start[L], start[L + 1]) for L in sorted(layers)])
+def submesh(mesh, elems, return_nodes=False):
+    """The elements `elems` (ids in `mesh`, kept in the order given) as a
+    mesh of their own: nodes renumbered in ascending order of their ids in
+    `mesh`, coordinates, materials, sources, flags and displacements
+    copied. Used for the parts of a partition of the elements, each
+    assembled on its own. return_nodes: also return the ids in `mesh` of
+    the submesh's nodes (ascending)."""
+    elems = np.asarray(elems, dtype=np.int64)
     lens = mesh.conn_ptr[elems + 1] - mesh.conn_ptr[elems]
     pos = np.repeat(mesh.conn_ptr[elems] - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + \
         np.arange(int(lens.sum()))
@@ -411,9 +404,26 @@ def layer_sample(mesh, layers, return_nodes=False):
     conn_ptr = np.zeros(elems.size + 1, dtype=np.int64)
     np.cumsum(lens, out=conn_ptr[1:])
     u = mesh.u.reshape(-1, 3)[nodes].reshape(-1).copy()
-    sample = Mesh(n_cells=n, x=mesh.x[nodes].copy(), y=mesh.y[nodes].copy(), z=mesh.z[nodes].copy(),
-                  types=mesh.types[elems].copy(), conn_ptr=conn_ptr, conn=conn.astype(np.int32),
-                  young=mesh.young[elems].copy(), nu=mesh.nu[elems].copy(), source=mesh.source[elems].copy(),
-                  nh_flag=mesh.nh_flag[elems].copy(), u=u, boundary=mesh.boundary[nodes].copy(),
-                  redraws=0)
-    return (sample, nodes) if return_nodes else sample
+    sub = Mesh(n_cells=mesh.n_cells, x=mesh.x[nodes].copy(), y=mesh.y[nodes].copy(), z=mesh.z[nodes].copy(),
+               types=mesh.types[elems].copy(), conn_ptr=conn_ptr, conn=conn.reshape(-1).astype(np.int32),
+               young=mesh.young[elems].copy(), nu=mesh.nu[elems].copy(), source=mesh.source[elems].copy(),
+               nh_flag=mesh.nh_flag[elems].copy(), u=u, boundary=mesh.boundary[nodes].copy(),
+               redraws=0)
+    return (sub, nodes) if return_nodes else sub
+
+
+def layer_sample(mesh, layers, return_nodes=False):
+    """The elements of the given z-layers of cells of a band mesh (every cell
+    of a layer has one family), as a mesh of their own (submesh). Used to
+    time work on a bounded part of a large mesh with its family mix, and to
+    check whole rows of it. return_nodes: also return the ids in `mesh` of
+    the sample's nodes (ascending)."""
+    n = mesh.n_cells
+    lay = n * n
+    # element offset of every layer: a layer holds n^2 cells of one family
+    start = np.zeros(n + 1, dtype=np.int64)
+    for L in range(n):
+        start[L + 1] = start[L] + lay * SUBELEMS[int(mesh.types[start[L]])]
+    assert start[-1] == mesh.n_elems, "not a band mesh"
+    elems = np.concatenate([np.arange(start[L], start[L + 1]) for L in sorted(layers)])
+    return submesh(mesh, elems, return_nodes=return_nodes)

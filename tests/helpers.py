@@ -54,3 +54,20 @@ def within_fp32_bound(v, ref, T, L, floor=None):
         bound = bound + floor
     tiny = np.finfo(np.float64).tiny
     return float(np.max(np.abs(v.astype(np.float64) - ref) / np.maximum(bound, tiny))) if v.size else 0.0
+
+
+def scatter_part(row_ptr, col, nodes, part_row_ptr, part_col, part_vals, B, acc, part_rhs=None, acc_rhs=None):
+    """Adds the matrix of a part of a mesh (a mesh of its own, node i of the
+    part being node nodes[i] of the mesh) into the mesh's value array `acc`
+    (pattern row_ptr, col), and its right-hand side into `acc_rhs`. Every
+    block of the part must exist in the mesh's pattern."""
+    N = row_ptr.size - 1
+    keys = np.repeat(np.arange(N, dtype=np.int64), np.diff(row_ptr)) * N + col.astype(np.int64)
+    prow = np.repeat(np.arange(part_row_ptr.size - 1, dtype=np.int64), np.diff(part_row_ptr))
+    pkeys = nodes[prow].astype(np.int64) * N + nodes[part_col].astype(np.int64)
+    pos = np.searchsorted(keys, pkeys)
+    assert np.all(pos < keys.size) and np.array_equal(keys[pos], pkeys)
+    np.add.at(acc.reshape(-1, B * B), pos, np.asarray(part_vals, dtype=np.float64).reshape(-1, B * B))
+    if part_rhs is not None:
+        np.add.at(acc_rhs.reshape(-1, B), nodes, np.asarray(part_rhs, dtype=np.float64).reshape(-1, B))
+    return acc

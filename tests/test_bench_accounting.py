@@ -124,6 +124,28 @@ def test_layer_sample_keeps_the_elements_of_its_layers():
         assert np.array_equal(nodes[s.conn[s.conn_ptr[kk]:s.conn_ptr[kk + 1]]], m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]])
 
 
+def test_submesh_copies_its_elements_and_renumbers_their_nodes():
+    """A part of a partition of the elements as a mesh of its own: its
+    elements in the order given, every per-element and per-node input
+    copied, nodes renumbered in ascending order of their mesh ids."""
+    m = mg.heterogeneous(8, seed=4, brick=4)
+    rng = np.random.default_rng(1)
+    elems = rng.permutation(m.n_elems)[: m.n_elems // 3]
+    s, nodes = mg.submesh(m, elems, return_nodes=True)
+    assert s.n_elems == elems.size and np.all(np.diff(nodes) > 0)
+    assert np.array_equal(s.types, m.types[elems]) and np.array_equal(s.nh_flag, m.nh_flag[elems])
+    assert np.array_equal(s.young, m.young[elems]) and np.array_equal(s.nu, m.nu[elems])
+    assert np.array_equal(s.source, m.source[elems])
+    assert np.array_equal(s.x, m.x[nodes]) and np.array_equal(s.y, m.y[nodes]) and np.array_equal(s.z, m.z[nodes])
+    assert np.array_equal(s.u.reshape(-1, 3), m.u.reshape(-1, 3)[nodes])
+    assert np.array_equal(s.boundary, m.boundary[nodes])
+    # every node of the part is used, and the connectivity maps back
+    assert np.unique(s.conn).size == s.n_nodes == nodes.size
+    for k in range(0, elems.size, 7):
+        e = elems[k]
+        assert np.array_equal(nodes[s.conn[s.conn_ptr[k]:s.conn_ptr[k + 1]]], m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]])
+
+
 def test_row_max_by_hand():
     vals = np.arange(27, dtype=np.float64) - 13.0     # 3 blocks
     row_ptr = np.array([0, 2, 2, 3])

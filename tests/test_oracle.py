@@ -629,6 +629,37 @@ def _with_u(m, seed, amp=0.03):
     return m
 
 
+def test_parts_of_a_partition_sum_to_the_whole():
+    """Assembly is a sum over elements (Algorithm 1), so the matrices and
+    right-hand sides of the parts of any partition of the elements, each
+    assembled as a mesh of its own and mapped back to the mesh's node ids,
+    add up to the whole mesh's: the identity a split of the elements over
+    several GPUs (each summing partial rows) rests on."""
+    from tests.helpers import fp64_errors, scatter_part
+    m = mg.heterogeneous(8, seed=4, brick=4)
+    assert m.nh_flag.any() and not m.nh_flag.all()
+    g = oracle.mesh_graph(m)
+    v, r = oracle.assemble(m, g)
+    part = np.random.default_rng(0).integers(0, 3, m.n_elems)
+    acc, accr = np.zeros_like(v), np.zeros_like(r)
+    for p in range(3):
+        sub, nodes = mg.submesh(m, np.nonzero(part == p)[0], return_nodes=True)
+        sg = oracle.mesh_graph(sub)
+        sv, sr = oracle.assemble(sub, sg)
+        scatter_part(np.asarray(g.row_ptr), np.asarray(g.col), nodes, np.asarray(sg.row_ptr), np.asarray(sg.col),
+                     sv, 3, acc, sr, accr)
+    ev, er = fp64_errors(acc, v, np.asarray(g.row_ptr), 3, accr, r)
+    assert ev < 1e-13 and er < 1e-13, (ev, er)
+    # a part left out is missed
+    acc2 = acc.copy()
+    sub, nodes = mg.submesh(m, np.nonzero(part == 0)[0], return_nodes=True)
+    sg = oracle.mesh_graph(sub)
+    sv, _ = oracle.assemble(sub, sg)
+    scatter_part(np.asarray(g.row_ptr), np.asarray(g.col), nodes, np.asarray(sg.row_ptr), np.asarray(sg.col),
+                 -sv, 3, acc2)
+    assert fp64_errors(acc2, v, np.asarray(g.row_ptr), 3)[0] > 1e-3
+
+
 def test_residual_at_rest_is_the_external_force():
     """f_int(0) = 0 for both materials (P(I) = 0, K u = 0): the residual at
     u = 0 is exactly the assembled right-hand side."""
