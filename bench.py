@@ -547,6 +547,45 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
         sums = np.array([c.sum() for c in np.split(cyc, cut)])
         return round(float(sums.mean() / sums.max()), 4)
 
+    def executed_split(msh, bb, wts, parts=8, reps=5):
+        # the cut of split_lb, each part then assembled as a mesh of its own
+        # (upper-triangle form, FP64, neo-Hookean tangent where flagged) and
+        # timed alone on the GPU: what each of 8 GPUs would run, so the
+        # makespan is the slowest part's time
+        perm = np.argsort(msh.types, kind="stable")
+        seg = np.concatenate([[0], np.cumsum(np.bincount(msh.types, minlength=4))])
+        cs = np.cumsum(wts)
+        cut = np.searchsorted(cs - 0.5 * wts, cs[-1] * np.arange(1, parts) / parts)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms, ne = [], []
+        for sel in np.split(np.arange(bb.items.shape[0]), cut):
+            el = [perm[seg[f] + z: seg[f] + z + c] for _, f, z, c in bb.items[sel]]
+            el = np.concatenate(el) if el else np.zeros(0, np.int64)
+            ne.append(int(el.size))
+            if el.size == 0:
+                ms.append(0.0)
+                continue
+            sdm = fea.DeviceMesh(mg.submesh(msh, el))
+            sg = sdm.graph()
+            kw = dict(use_nh=True, variant=fea.ROWSYM, precision=fea.FP64, out_dtype=fea.F64)
+            v, r, st = sdm.assemble(sg, **kw)
+            ts = []
+            for _ in range(reps + 2):
+                e0.record()
+                sdm.assemble(sg, vals=v, rhs=r, status=st, **kw)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            assert int(st.item()) == -1
+            ms.append(float(np.median(ts[2:])))
+            del v, r, st
+            sg.destroy()
+            del sdm
+        torch.cuda.empty_cache()
+        ms = np.array(ms)
+        return {"part_elements": ne, "part_ms": [round(float(x), 3) for x in ms],
+                "makespan_ms": round(float(ms.max()), 3), "balance": round(float(ms.mean() / ms.max()), 4)}
+
     def judge(bb, tgt, prd):
         t = tgt.cpu().numpy().astype(np.float64)
         p = prd.cpu().numpy().astype(np.float64)
@@ -572,6 +611,16 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
     hpred = cm.predict(hfeats)
     htarget = _measured_log_cycles(fea, torch, hb)
     out["cost_model"]["held_out"] = judge(hb, htarget, hpred)
+    # the 8-part static split executed: each part assembled alone
+    w_el = hb.items[:, 3].astype(np.float64)
+    ex = {"form": "each part a mesh of its own, upper-triangle FP64, timed alone (median of 5)"}
+    for key, w in (("elements", w_el), ("gauss_points", w_el * np.array([1, 8, 6, 8])[hb.items[:, 1]]),
+                   ("learned", np.exp(hpred.cpu().numpy().astype(np.float64))),
+                   ("measured_cycles", np.exp(htarget.cpu().numpy().astype(np.float64)))):
+        ex[key] = executed_split(hmesh, hb, w)
+    for key in ("elements", "gauss_points"):
+        ex[f"makespan_gain_learned_vs_{key}"] = round(ex[key]["makespan_ms"] / ex["learned"]["makespan_ms"], 4)
+    out["cost_model"]["held_out"]["executed_split_8"] = ex
     ho = {"elements": int(hmesh.n_elems), "items": int(hb.n_items)}
     ho["fp64_type_sorted"], hv64, hst64 = hrun(fea.FP64)
     ho["mixed_type_sorted"], _, _ = hrun(fea.MIXED)
