@@ -10,6 +10,7 @@
 #include <climits>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "fea_internal.h"
@@ -620,38 +621,80 @@ int tile_colour_prepare(fea_graph *g, hipStream_t s)
 // ------------------------------------------------------------- colouring
 // Greedy first-fit in element order (the colouring of Algorithm 5; any
 // valid colouring is correct, this one is deterministic). Sequential by
-// definition, so it runs on the host over per-node masks of used colours.
-static int colour_host(fea_graph *g, const int64_t *conn_ptr_d, const int32_t *conn_d,
-                       const uint8_t *types_d, hipStream_t s)
-{
-    const int64_t E = g->n_elems, N = g->n_nodes;
-    std::vector<int64_t> cp(E + 1);
-    std::vector<int32_t> cn(g->conn_len);
-    std::vector<uint8_t> ty(E);
-    FEA_HIP(hipMemcpyAsync(cp.data(), conn_ptr_d, sizeof(int64_t) * (E + 1), hipMemcpyDeviceToHost, s));
-    if (g->conn_len)
-        FEA_HIP(hipMemcpyAsync(cn.data(), conn_d, sizeof(int32_t) * g->conn_len, hipMemcpyDeviceToHost, s));
-    if (E) FEA_HIP(hipMemcpyAsync(ty.data(), types_d, E, hipMemcpyDeviceToHost, s));
-    FEA_HIP(hipStreamSynchronize(s));
-    std::vector<int16_t> colour((size_t)std::max<int64_t>(E, 1), 0);
-    const int64_t ncol = host::greedy_first_fit(N, E, cp.data(), cn.data(), nullptr, colour.data());
-    if (ncol < 0)
-        return set_error(FEA_ERANGE, "element %lld needs more than %d colours", (long long)(-ncol - 1),
-                         host::kMaxColours);
-    // stable buckets by (family, colour) of element ids
+// definition, so it runs on the host over per-node masks of used colours,
+// on a thread of its own that starts once the mesh is validated and works
+// while the device builds the pattern and the maps.
+struct HostColouring {
+    std::vector<int64_t> cp;
+    std::vector<int32_t> cn;
+    std::vector<uint8_t> ty;
+    std::vector<int16_t> colour;
     std::vector<int64_t> cseg;
     std::vector<int32_t> cperm;
-    host::buckets(E, 4, ty.data(), colour.data(), (int)ncol, nullptr, nullptr, cseg, cperm);
+    int64_t ncol = 0;
+    bool nomem = false;
+    std::thread th;
+    ~HostColouring()
+    {
+        if (th.joinable()) th.join();
+    }
+    void run(int64_t N, int64_t E)
+    {
+        try {
+            colour.assign((size_t)std::max<int64_t>(E, 1), 0);
+            ncol = host::greedy_first_fit(N, E, cp.data(), cn.data(), nullptr, colour.data());
+            // stable buckets by (family, colour) of element ids
+            if (ncol >= 0) host::buckets(E, 4, ty.data(), colour.data(), (int)ncol, nullptr, nullptr, cseg, cperm);
+        } catch (...) {
+            nomem = true;
+        }
+    }
+};
+
+// Copies the (validated) connectivity to the host and starts the colouring.
+static int colour_start(fea_graph *g, const int64_t *conn_ptr_d, const int32_t *conn_d, const uint8_t *types_d,
+                        hipStream_t s, HostColouring &hc)
+{
+    const int64_t E = g->n_elems, N = g->n_nodes;
+    try {
+        hc.cp.resize(E + 1);
+        hc.cn.resize(g->conn_len);
+        hc.ty.resize(E);
+    } catch (...) {
+        return set_error(FEA_ENOMEM, "host allocation failed (colouring)");
+    }
+    FEA_HIP(hipMemcpyAsync(hc.cp.data(), conn_ptr_d, sizeof(int64_t) * (E + 1), hipMemcpyDeviceToHost, s));
+    if (g->conn_len)
+        FEA_HIP(hipMemcpyAsync(hc.cn.data(), conn_d, sizeof(int32_t) * g->conn_len, hipMemcpyDeviceToHost, s));
+    if (E) FEA_HIP(hipMemcpyAsync(hc.ty.data(), types_d, E, hipMemcpyDeviceToHost, s));
+    FEA_HIP(hipStreamSynchronize(s));
+    try {
+        hc.th = std::thread([&hc, N, E] { hc.run(N, E); });
+    } catch (...) {
+        hc.run(N, E);  // no thread to be had: colour here
+    }
+    return FEA_OK;
+}
+
+// Waits for the colouring and uploads it.
+static int colour_finish(fea_graph *g, HostColouring &hc, hipStream_t s)
+{
+    const int64_t E = g->n_elems;
+    if (hc.th.joinable()) hc.th.join();
+    if (hc.nomem) return set_error(FEA_ENOMEM, "host allocation failed (colouring)");
+    if (hc.ncol < 0)
+        return set_error(FEA_ERANGE, "element %lld needs more than %d colours", (long long)(-hc.ncol - 1),
+                         host::kMaxColours);
     int rc;
     if ((rc = dalloc((void **)&g->colour, sizeof(int16_t) * std::max<int64_t>(E, 1)))) return rc;
     if ((rc = dalloc((void **)&g->cperm, sizeof(int32_t) * std::max<int64_t>(E, 1)))) return rc;
     if (E) {
-        FEA_HIP(hipMemcpyAsync(g->colour, colour.data(), sizeof(int16_t) * E, hipMemcpyHostToDevice, s));
-        FEA_HIP(hipMemcpyAsync(g->cperm, cperm.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice, s));
+        FEA_HIP(hipMemcpyAsync(g->colour, hc.colour.data(), sizeof(int16_t) * E, hipMemcpyHostToDevice, s));
+        FEA_HIP(hipMemcpyAsync(g->cperm, hc.cperm.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice, s));
     }
     FEA_HIP(hipStreamSynchronize(s));
-    g->n_colours = (int)ncol;
-    g->cseg = std::move(cseg);
+    g->n_colours = (int)hc.ncol;
+    g->cseg = std::move(hc.cseg);
     return FEA_OK;
 }
 
@@ -722,6 +765,8 @@ static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn
     TmpBuf tmp, cnt64, cnt32, flag, fillb;
     if ((rc = validate(N, E, types, conn_ptr, conn, s))) return rc;
     if ((rc = mesh_fingerprint(E, types, conn_ptr, conn, s, &g->mesh_fp))) return rc;
+    HostColouring hc;  // joined on every return
+    if ((rc = colour_start(g, conn_ptr, conn, types, s, hc))) return rc;
 
     int64_t scan_n = std::max<int64_t>(std::max<int64_t>(E, N), g->conn_len);
     // slots: map_ptr = prefix sum of n_e^2
@@ -827,8 +872,7 @@ static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn
         FEA_HIP(hipStreamSynchronize(s));
     }
 
-    if ((rc = colour_host(g, conn_ptr, conn, types, s))) return rc;
-    FEA_HIP(hipStreamSynchronize(s));
+    if ((rc = colour_finish(g, hc, s))) return rc;
     return FEA_OK;
 }
 
