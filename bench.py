@@ -70,8 +70,11 @@ def sym_reduce_bytes(ulen, nup, nnz, B, s_c, s_v):
     """Algorithmic bytes of one launch of the upper-triangle block-value
     kernel: every tile sum (ulen tile-blocks) read once, per upper block its
     segment bound (int64), its block index and its lower partner (int32),
-    every block value (upper and transposed lower) written once."""
-    return ulen * B * B * s_c + (nup + 1) * 8 + nup * 8 + nnz * B * B * s_v
+    every block value (upper and transposed lower) written once, and with
+    3x3 blocks the right-hand side of every row that has a diagonal block
+    (2 nup - nnz rows), which those blocks' tile sums carry."""
+    rows = 2 * nup - nnz if B == 3 else 0
+    return ulen * B * B * s_c + (nup + 1) * 8 + nup * 8 + nnz * B * B * s_v + rows * B * s_v
 
 
 def element_bytes(g, B, s_c, s_v, conn_len, n_nodes, n_elems, variant, sym=None):
@@ -79,14 +82,16 @@ def element_bytes(g, B, s_c, s_v, conn_len, n_nodes, n_elems, variant, sym=None)
     connectivity and per-element data once, and its outputs once (the slot
     contributions for row-owner; for the upper-triangle form the tile sums
     plus its tile entries (2 bytes), tile-block ends and slots (6 bytes) and
-    tile ranges (16 bytes); for row-gather the final values, plus the
-    pair-ordered node lists, lane bytes and segment bounds it reads)."""
+    tile ranges (16 bytes), and with 1x1 blocks the per-element
+    right-hand-side contributions (3x3 blocks carry them in the tile sums);
+    for row-gather the final values, plus the pair-ordered node lists, lane
+    bytes and segment bounds it reads)."""
     inputs = n_nodes * 24 + conn_len * 4 + n_elems * (8 + 4 + 8 + 16 + 8 * B)
     if variant == "rowowner":
         return inputs + g.map_len * B * B * s_c + conn_len * B * s_c
     if variant == "rowsym":
         return (inputs + sym["tile_blocks"] * (B * B * s_c + 6) + sym["entries"] * 2 + sym["tiles"] * 16
-                + conn_len * B * s_c)
+                + (conn_len * B * s_c if B == 1 else 0))
     if variant == "rowgather":
         maps = g.map_len * (4 + 1) + conn_len * 5 + (g.nnz + 1) * 8 + (n_nodes + 1) * 8
         return inputs + maps + g.nnz * B * B * s_v + n_nodes * B * s_v

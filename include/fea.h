@@ -67,10 +67,15 @@ enum fea_precision { FEA_FP64 = 0, FEA_MIXED = 1 };
  *             as the contribution to an upper block (i <= j); a lower block
  *             (j, i) is written as the transpose of the ordered sum of block
  *             (i, j), and each element's diagonal blocks are made
- *             symmetric by copying their upper entries before they are
- *             summed. About 40% less element work and workspace traffic;
- *             deterministic, and A equals its transpose bitwise. Also
- *             runs batched (fea_batch_assemble);
+ *             symmetric by copying their upper entries (with 3x3 blocks,
+ *             when the block values are written: the strictly lower
+ *             entries of an element's diagonal block carry that node's
+ *             right-hand side through the tile sums instead, so b needs no
+ *             workspace or reduction of its own and equals the other
+ *             forms' up to the rounding of that grouping). About 40% less
+ *             element work and workspace traffic; deterministic, and A
+ *             equals its transpose bitwise. Also runs batched
+ *             (fea_batch_assemble);
  *   TILECOLOUR the GPU counterpart of commutative multidependences
  *             (Algorithm 7): the ROWSYM element tiles, greedily coloured in
  *             descending neighbour count so that no two tiles of a colour
@@ -237,10 +242,11 @@ int fea_assemble_noalloc(const fea_graph *g, const double *x, const double *y, c
 /* Phase durations of the graph's last fea_assemble call made with
  * opt->timing set, in milliseconds, measured with HIP events on that call's
  * stream: ms[0] element kernels (with the fused scatter for ATOMIC, COLOUR
- * and TILECOLOUR, and all of ROWGATHER; for ROWOWNER and ROWSYM also the
- * right-hand-side reduction, which runs first), ms[1] the one kernel that
- * forms the matrix values after them (ROWOWNER/ROWSYM: the segmented
- * reduction of the block values; ATOMIC/COLOUR/TILECOLOUR with FP32 output:
+ * and TILECOLOUR, and all of ROWGATHER; for ROWOWNER, and ROWSYM with 1x1
+ * blocks, also the right-hand-side reduction, which runs first), ms[1] the
+ * one kernel that forms the matrix values after them (ROWOWNER/ROWSYM: the
+ * segmented reduction of the block values, for ROWSYM with 3x3 blocks also
+ * of the right-hand side; ATOMIC/COLOUR/TILECOLOUR with FP32 output:
  * the conversion; otherwise empty), ms[2] the whole call including
  * zero-fill and the right-hand side. Waits for the events. FEA_EINVAL if no
  * timed call was made. */

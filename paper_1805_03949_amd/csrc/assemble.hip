@@ -102,11 +102,14 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
     const bool f32 = o->out_dtype == FEA_F32;
     int rc;
     if (o->variant == FEA_ROWSYM) {
+        // 3x3 blocks: the right-hand side rides in the diagonal blocks' tile
+        // sums (no workspace of its own); 1x1: its own workspace and sums
+        constexpr bool RHSD = B == 3;
         if (!g->sready && (rc = sym_prepare(g, s))) return rc;
         if ((rc = ensure_ws(&g->contrib, &g->contrib_bytes, sizeof(CT) * (size_t)std::max<int64_t>(g->ulen, 1) * BB))) return rc;
-        if ((rc = ensure_ws(&g->rcontrib, &g->rcontrib_bytes, sizeof(CT) * (size_t)g->conn_len * B))) return rc;
+        if (!RHSD && (rc = ensure_ws(&g->rcontrib, &g->rcontrib_bytes, sizeof(CT) * (size_t)g->conn_len * B))) return rc;
         a.contrib = g->contrib;
-        a.rcontrib = g->rcontrib;
+        a.rcontrib = RHSD ? nullptr : g->rcontrib;
         a.tent = g->tent;
         a.tb_eend = g->tb_eend;
         a.tb_slot = g->tb_slot;
@@ -120,16 +123,23 @@ static int run(fea_graph *g, ElemArgs a, const fea_options *o, hipStream_t s, vo
             a.ttb_ptr = g->ttb_ptr + g->tile_base[t];
             launch_type<MODEL, V_ROWSYM, CT>(t, a, s);
         }
-        // the right-hand side first, while its workspace (just written) is
-        // still in the caches; then the block values
+        // 1x1: the right-hand side first, while its workspace (just written)
+        // is still in the caches; then the block values (3x3: with the
+        // right-hand side, rows that no element touches set to zero first)
         if (f32) {
-            if (nr) launch_segsum<B, CT, float>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
+            if (RHSD && g->sym_empty_rows && nr) k_zero<float><<<grid_for(nr, 256), 256, 0, s>>>(nr, (float *)rhs);
+            if (!RHSD && nr) launch_segsum<B, CT, float>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (float *)rhs, s);
             mark(g, 1, o, s);
-            if (g->nup) launch_segsum_sym<BB, CT, float>(g->nup, g->ublk, g->ulp, g->uptr, (const CT *)g->contrib, (float *)vals, s);
+            if (g->nup)
+                launch_segsum_sym<BB, CT, float>(g->nup, g->ublk, g->ulp, g->uptr, (const CT *)g->contrib, (float *)vals,
+                                                 (float *)rhs, s);
         } else {
-            if (nr) launch_segsum<B, CT, double>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
+            if (RHSD && g->sym_empty_rows && nr) k_zero<double><<<grid_for(nr, 256), 256, 0, s>>>(nr, (double *)rhs);
+            if (!RHSD && nr) launch_segsum<B, CT, double>(g->n_nodes, g->n2e_ptr, (const CT *)g->rcontrib, (double *)rhs, s);
             mark(g, 1, o, s);
-            if (g->nup) launch_segsum_sym<BB, CT, double>(g->nup, g->ublk, g->ulp, g->uptr, (const CT *)g->contrib, (double *)vals, s);
+            if (g->nup)
+                launch_segsum_sym<BB, CT, double>(g->nup, g->ublk, g->ulp, g->uptr, (const CT *)g->contrib,
+                                                  (double *)vals, (double *)rhs, s);
         }
         mark(g, 2, o, s);
         mark(g, 3, o, s);

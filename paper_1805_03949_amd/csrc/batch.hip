@@ -112,6 +112,14 @@ __global__ void k_offset_idx(const int32_t *in, int64_t n, int64_t off, int32_t 
     if (i < n) out[i] = in[i] < 0 ? -1 : (int32_t)(in[i] + off);
 }
 
+// Lower partners (>= 0) offset by the mesh's first block, diagonal rows
+// (-(v + 1)) by its first node.
+__global__ void k_offset_lp(const int32_t *in, int64_t n, int64_t off, int64_t node_off, int32_t *out)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = in[i] < 0 ? (int32_t)(in[i] - node_off) : (int32_t)(in[i] + off);
+}
+
 __global__ void k_batch_begin(int32_t *head, int32_t *status, int n_meshes)
 {
     int i = blockIdx.x * 256 + threadIdx.x;
@@ -275,6 +283,7 @@ struct fea_batch {
     bool sym_ready = false;
     int64_t total_sym_slots = 0, total_nup = 0;
     int32_t *d_sym_ublk = nullptr, *d_sym_lp = nullptr;
+    int64_t sym_empty_rows = 0;  // rows of all meshes that no element touches
     int64_t *d_sym_ptr = nullptr;
     // subgrid scale: its own queue heads (one per family) and per-mesh
     // arguments, kept for the outputs and item list they were built for
@@ -454,13 +463,16 @@ int sym_prepare_batch(fea_batch *b, hipStream_t s)
     if (b->sym_ready) return FEA_OK;
     int rc;
     const int n = b->n_meshes;
-    std::vector<int64_t> soff(n + 1, 0), uoff(n + 1, 0), koff(n + 1, 0);
+    std::vector<int64_t> soff(n + 1, 0), uoff(n + 1, 0), koff(n + 1, 0), noff(n + 1, 0);
+    b->sym_empty_rows = 0;
     for (int m = 0; m < n; ++m) {
         fea_graph *g = b->graphs[m];
         if (!g->sready && (rc = sym_prepare(g, s))) return rc;
         soff[m + 1] = soff[m] + g->ulen;
         uoff[m + 1] = uoff[m] + g->nup;
         koff[m + 1] = koff[m] + g->nnz;
+        noff[m + 1] = noff[m] + g->n_nodes;
+        b->sym_empty_rows += g->sym_empty_rows;
         BatchMesh &M = b->hmeshes[m];
         M.a.tent_ptr = g->tent_ptr;
         M.a.ttb_ptr = g->ttb_ptr;
@@ -478,7 +490,7 @@ int sym_prepare_batch(fea_batch *b, hipStream_t s)
     if ((rc = dalloc((void **)&b->d_sym_ublk, sizeof(int32_t) * std::max<int64_t>(uoff[n], 1)))) return rc;
     if ((rc = dalloc((void **)&b->d_sym_lp, sizeof(int32_t) * std::max<int64_t>(uoff[n], 1)))) return rc;
     if ((rc = dalloc((void **)&b->d_sym_ptr, sizeof(int64_t) * (uoff[n] + 1)))) return rc;
-    if (koff[n] > INT32_MAX) return set_error(FEA_ERANGE, "batch has more than 2^31 blocks");
+    if (koff[n] > INT32_MAX || noff[n] > INT32_MAX) return set_error(FEA_ERANGE, "batch has more than 2^31 blocks or nodes");
     int64_t zero = 0;
     FEA_HIP(hipMemcpy(b->d_sym_ptr, &zero, sizeof(int64_t), hipMemcpyHostToDevice));
     // concatenated upper-block lists: block ids and lower partners offset by
@@ -488,7 +500,7 @@ int sym_prepare_batch(fea_batch *b, hipStream_t s)
         const fea_graph *g = b->graphs[m];
         if (g->nup) {
             k_offset_idx<<<grid_for(g->nup, 256), 256, 0, s>>>(g->ublk, g->nup, koff[m], b->d_sym_ublk + uoff[m]);
-            k_offset_idx<<<grid_for(g->nup, 256), 256, 0, s>>>(g->ulp, g->nup, koff[m], b->d_sym_lp + uoff[m]);
+            k_offset_lp<<<grid_for(g->nup, 256), 256, 0, s>>>(g->ulp, g->nup, koff[m], noff[m], b->d_sym_lp + uoff[m]);
             k_offset_ptr<<<grid_for(g->nup + 1, 256), 256, 0, s>>>(g->uptr, g->nup, soff[m], b->d_sym_ptr + uoff[m]);
         }
     }
@@ -603,12 +615,16 @@ int launch_batch(fea_batch *b, const fea_options *o, hipStream_t s, void *vals, 
     }
     if (o->timing) FEA_HIP(hipEventRecord(b->ev[1], s));
     const int64_t nv = b->total_blocks * BB, nr = b->rhs_off.back();
-    // the right-hand side first, while its workspace is still cached
-    if (nr) launch_segsum<B, CT, OT>(nr / B, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs, s);
+    // the right-hand side first, while its workspace is still cached (the
+    // upper-triangle form with 3x3 blocks carries it in the diagonal
+    // blocks' tile sums instead, as one-mesh assembly does)
+    constexpr bool RHSD = SYM && B == 3;
+    if (RHSD && b->sym_empty_rows && nr) k_zero<OT><<<grid_for(nr, 256), 256, 0, s>>>(nr, (OT *)rhs);
+    if (!RHSD && nr) launch_segsum<B, CT, OT>(nr / B, b->d_rseg, (const CT *)b->rcontrib, (OT *)rhs, s);
     if (SYM) {
         if (b->total_nup)
             launch_segsum_sym<BB, CT, OT>(b->total_nup, b->d_sym_ublk, b->d_sym_lp, b->d_sym_ptr,
-                                          (const CT *)b->contrib, (OT *)vals, s);
+                                          (const CT *)b->contrib, (OT *)vals, (OT *)rhs, s);
     } else if (nv) {
         launch_segsum<BB, CT, OT>(b->total_blocks, b->d_vseg, (const CT *)b->contrib, (OT *)vals, s);
     }

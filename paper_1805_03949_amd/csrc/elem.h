@@ -927,6 +927,13 @@ __device__ void elem_tile_sym(const ElemArgs &A, int64_t first, ElemSmem<T, MODE
     constexpr int NN = Fam<T>::NN;
     constexpr int PW = Smem::PW, EPB = Smem::EPB, B = Smem::B, BB = Smem::BB;
     constexpr bool ELAS = Smem::ELAS, NHK = Smem::NHK, TCOL = Smem::TCOL, ALIAS = Smem::ALIAS;
+    // 3x3 blocks of the upper-triangle form: the right-hand side of node a
+    // of an element rides in the strictly lower entries (3, 6, 7) of the
+    // element's diagonal block (a, a), which symmetry makes redundant; the
+    // tile sums then add it with the block values, and the block-value
+    // kernel writes it out (no right-hand-side workspace, no reduction of
+    // its own)
+    constexpr bool RHSD = !TCOL && B == 3;
     CT *sK = S.buf + Smem::KOFF;
     __syncthreads();  // the previous tile's readers of S are done
     elem_ref_tables(S, tid);
@@ -939,7 +946,7 @@ __device__ void elem_tile_sym(const ElemArgs &A, int64_t first, ElemSmem<T, MODE
         const int64_t i = first + el;
         if (i < A.n) {
             const int32_t v = A.pnodes[i * NN + a];
-            rdest = A.prdest[i * NN + a];
+            if constexpr (!RHSD) rdest = A.prdest[i * NN + a];
             S.sX[el][a][0] = A.x[v];
             S.sX[el][a][1] = A.y[v];
             S.sX[el][a][2] = A.z[v];
@@ -978,6 +985,14 @@ __device__ void elem_tile_sym(const ElemArgs &A, int64_t first, ElemSmem<T, MODE
     CT Ks[BB];
 #pragma unroll
     for (int c = 0; c < BB; ++c) Ks[c] = 0;
+    bool diag = false;
+    // the block's staged entries; on a diagonal lane with RHSD the
+    // strictly lower ones belong to the right-hand side
+    auto stage = [&] {
+#pragma unroll
+        for (int c = 0; c < BB; ++c)
+            if (!(RHSD && diag && (c == 3 || c == 6 || c == 7))) sK[tid * BB + c] = Ks[c];
+    };
     if (tid < EPB * PW) {
         const int el = tid / PW, w = tid % PW;
         // w-th pair of the row-major upper triangle
@@ -989,38 +1004,46 @@ __device__ void elem_tile_sym(const ElemArgs &A, int64_t first, ElemSmem<T, MODE
             a += step ? 1 : 0;
         }
         const int b = a + r;
+        diag = a == b;
         if (S.sE[el] >= 0) {
             elem_block(S, el, a, b, Ks);
-            if (a == b) {
+            if (!RHSD && diag) {
                 // a diagonal block is symmetric; copying its upper entries
                 // makes it so bitwise (the products G_i (w G_j) and
-                // G_j (w G_i) round differently), and with it A
+                // G_j (w G_i) round differently), and with it A (with
+                // RHSD the block-value kernel writes the copies)
 #pragma unroll
                 for (int i = 0; i < B; ++i)
 #pragma unroll
                     for (int j = i + 1; j < B; ++j) Ks[j * B + i] = Ks[i * B + j];
             }
         }
-        if constexpr (!ALIAS) {
-#pragma unroll
-            for (int c = 0; c < BB; ++c) sK[tid * BB + c] = Ks[c];
-        }
+        if constexpr (!ALIAS) stage();
     }
+    CT f[B];
+    int flane = -1;  // RHSD: the diagonal lane that carries f
     if (tid < EPB * NN) {
         const int el = tid / NN, a = tid % NN;
         if (S.sE[el] >= 0) {
-            CT f[B];
             elem_rhs(S, el, a, S.sSrc[el], f);
-            CT *dst = (CT *)A.rcontrib + (int64_t)rdest * B;
+            if constexpr (RHSD) {
+                flane = el * PW + a * NN - a * (a - 1) / 2;  // pair (a, a)
+            } else {
+                CT *dst = (CT *)A.rcontrib + (int64_t)rdest * B;
 #pragma unroll
-            for (int i = 0; i < B; ++i) dst[i] = f[i];
+                for (int i = 0; i < B; ++i) dst[i] = f[i];
+            }
         }
     }
     if constexpr (ALIAS) {
         __syncthreads();  // every lane has read the gradients that sK overwrites
-        if (tid < EPB * PW) {
-#pragma unroll
-            for (int c = 0; c < BB; ++c) sK[tid * BB + c] = Ks[c];
+        if (tid < EPB * PW) stage();
+    }
+    if constexpr (RHSD) {
+        if (flane >= 0) {
+            sK[flane * BB + 3] = f[0];
+            sK[flane * BB + 6] = f[1];
+            sK[flane * BB + 7] = f[2];
         }
     }
     __syncthreads();

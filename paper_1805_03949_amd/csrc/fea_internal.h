@@ -143,10 +143,11 @@ struct fea_graph {
     int32_t *lpart = nullptr;
     int64_t nup = 0;
     // the same per entry m of the upper-block list: lower partner of ublk[m]
-    // (ulp, -1 for diagonal blocks) and its workspace segment uptr[m] ..
+    // (ulp; -(v + 1) for the diagonal block of row v) and its workspace segment uptr[m] ..
     // uptr[m+1] (segments of consecutive entries are adjacent)
     int32_t *ulp = nullptr;
     int64_t *uptr = nullptr;
+    int64_t sym_empty_rows = 0;  // rows no element touches (no diagonal block)
     // Element tiles: family t's elements in type-sorted order, EPB_t =
     // 256 / (n(n+1)/2) consecutive ones per tile, tiles tile_base[t] ..
     // tile_base[t+1]. Lane l = el * n(n+1)/2 + w of a tile is the w-th local

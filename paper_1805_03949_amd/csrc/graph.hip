@@ -405,15 +405,25 @@ __global__ void __launch_bounds__(256) k_tile_entries(TileBases tb, const int32_
     }
 }
 
-// Per entry m of the upper-block list: its block's lower partner and the
-// start of its workspace segment (uptr[nup] = the workspace length).
-__global__ void k_sym_compact(int64_t nup, int64_t nnz, const int32_t *ublk, const int32_t *lpart,
-                              const int64_t *ts_ptr, int32_t *ulp, int64_t *uptr)
+// Per entry m of the upper-block list: its block's lower partner, or
+// -(v + 1) for the diagonal block of row v, and the start of its workspace
+// segment (uptr[nup] = the workspace length).
+__global__ void k_sym_compact(int64_t nup, int64_t nnz, int64_t n_nodes, const int32_t *ublk, const int32_t *lpart,
+                              const int64_t *ts_ptr, const int64_t *row_ptr, int32_t *ulp, int64_t *uptr)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m < nup) {
         const int32_t k = ublk[m];
-        ulp[m] = lpart[k];
+        int32_t l = lpart[k];
+        if (l < 0) {
+            int64_t lo = 0, hi = n_nodes - 1;  // the row holding block k
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (row_ptr[mid] <= k) lo = mid; else hi = mid - 1;
+            }
+            l = -(int32_t)lo - 1;
+        }
+        ulp[m] = l;
         uptr[m] = ts_ptr[k];
     } else if (m == nup) {
         uptr[m] = ts_ptr[nnz];
@@ -560,11 +570,14 @@ int sym_prepare(fea_graph *g, hipStream_t s)
     const int64_t nup = g->nup;
     if ((rc = dalloc((void **)&g->ulp, sizeof(int32_t) * std::max<int64_t>(nup, 1)))) return rc;
     if ((rc = dalloc((void **)&g->uptr, sizeof(int64_t) * (nup + 1)))) return rc;
-    k_sym_compact<<<grid_for(nup + 1, BS), BS, 0, s>>>(nup, nnz, g->ublk, g->lpart, g->ts_ptr, g->ulp, g->uptr);
+    k_sym_compact<<<grid_for(nup + 1, BS), BS, 0, s>>>(nup, nnz, N, g->ublk, g->lpart, g->ts_ptr, g->row_ptr, g->ulp,
+                                                       g->uptr);
     FEA_HIP(hipGetLastError());
     FEA_HIP(hipStreamSynchronize(s));
     g->ulen = ntb;
     g->nent = nent;
+    // every row an element touches has one diagonal block: nnz = 2 nup - rows
+    g->sym_empty_rows = N - (2 * nup - nnz);
     g->sready = true;
     return FEA_OK;
 }

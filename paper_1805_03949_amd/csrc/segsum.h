@@ -108,7 +108,12 @@ __global__ void __launch_bounds__(256) k_segsum(int64_t n, const int64_t *ptr, c
 // is block blk[m] (an upper or diagonal block), its tile sums are slots
 // uptr[m] .. uptr[m+1] of the workspace (segments of consecutive m are
 // adjacent), and the sum is written to block blk[m] and, transposed, to its
-// lower partner lp[m] when that is >= 0. Every per-output index is read at
+// lower partner lp[m] when that is >= 0; lp[m] = -(v + 1) marks the
+// diagonal block of row v. With RHSD (3x3 blocks) a diagonal block's
+// strictly lower entries (3, 6, 7) carry row v's right-hand side: those
+// sums go to rhs[3v .. 3v+2], and entries 1, 2, 5 are written to their
+// mirror positions too, so that every diagonal block is symmetric
+// bitwise. Every per-output index is read at
 // position m, so a workgroup's index loads are contiguous and independent
 // of each other, and its workspace range (uptr[m0] .. uptr[m0 + BPW]) is
 // known after one load; R rounds of 256 / W outputs per workgroup.
@@ -124,9 +129,9 @@ struct SymSegCfg {
     static constexpr int CHUNK_BYTES = 16384;
 };
 
-template <int W, typename CT, typename OT>
+template <int W, typename CT, typename OT, bool RHSD>
 __global__ void __launch_bounds__(256) k_segsum_sym(int64_t n, const int32_t *blk, const int32_t *lp,
-                                                    const int64_t *uptr, const CT *data, OT *out)
+                                                    const int64_t *uptr, const CT *data, OT *out, OT *rhs)
 {
     constexpr int TPS = 256 / W;                                      // outputs per round
     constexpr int R = SymSegCfg<CT>::ROUNDS;                          // rounds per workgroup
@@ -193,18 +198,35 @@ __global__ void __launch_bounds__(256) k_segsum_sym(int64_t n, const int32_t *bl
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (k[r] < 0) continue;
-        out[k[r] * W + c] = (OT)acc[r];
-        if (l[r] >= 0) out[l[r] * W + ct] = (OT)acc[r];
+        if (l[r] >= 0) {
+            out[k[r] * W + c] = (OT)acc[r];
+            out[l[r] * W + ct] = (OT)acc[r];
+        } else if (RHSD && (c == 3 || c == 6 || c == 7)) {
+            rhs[(-l[r] - 1) * 3 + (c == 3 ? 0 : c == 6 ? 1 : 2)] = (OT)acc[r];
+        } else {
+            out[k[r] * W + c] = (OT)acc[r];
+            if (RHSD && ct != c) out[k[r] * W + ct] = (OT)acc[r];
+        }
     }
 }
 
 template <int W, typename CT, typename OT>
 inline void launch_segsum_sym(int64_t n, const int32_t *blk, const int32_t *lp, const int64_t *uptr,
-                              const CT *data, OT *out, hipStream_t s)
+                              const CT *data, OT *out, OT *rhs, hipStream_t s)
 {
     constexpr int BPW = (256 / W) * SymSegCfg<CT>::ROUNDS;
     const unsigned grid = (unsigned)((n + BPW - 1) / BPW);
-    k_segsum_sym<W, CT, OT><<<grid, 256, 0, s>>>(n, blk, lp, uptr, data, out);
+    k_segsum_sym<W, CT, OT, W == 9><<<grid, 256, 0, s>>>(n, blk, lp, uptr, data, out, rhs);
+}
+
+// out[0 .. n) = 0: the right-hand side of rows that no element touches,
+// which no diagonal block carries (a kernel rather than a memset, so that
+// the sequence can be captured into a graph).
+template <typename OT>
+__global__ void __launch_bounds__(256) k_zero(int64_t n, OT *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = (OT)0;
 }
 
 // Launch over n segments (n > 0).

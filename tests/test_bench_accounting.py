@@ -62,8 +62,11 @@ def test_sym_tile_blocks_match_brute_force():
 
 
 def test_sym_reduce_bytes_definition():
+    # 10 upper blocks, 15 blocks in all: 5 diagonal blocks, so 5 rows whose
+    # right-hand side (3 values) the 3x3 diagonal tile sums carry
     b = bench.sym_reduce_bytes(100, 10, 15, 3, 4, 8)
-    assert b == 100 * 9 * 4 + 11 * 8 + 10 * 8 + 15 * 9 * 8
+    assert b == 100 * 9 * 4 + 11 * 8 + 10 * 8 + 15 * 9 * 8 + 5 * 3 * 8
+    assert bench.sym_reduce_bytes(100, 10, 15, 1, 4, 8) == 100 * 4 + 11 * 8 + 10 * 8 + 15 * 8
 
 
 def test_subscale_work_counts_every_element_and_node_once():
