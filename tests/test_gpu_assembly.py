@@ -231,6 +231,55 @@ def test_rowgather_isolated_nodes_get_zero_rows():
     assert np.abs(v1.cpu().numpy() - v0.cpu().numpy()).max() <= 1e-14 * np.abs(v0.cpu().numpy()).max()
 
 
+def _with_unused_nodes(m, mid, end):
+    """The mesh with `mid` unused nodes inserted in the middle of the
+    numbering and `end` appended: rows that no element touches."""
+    import dataclasses
+    cut = m.n_nodes // 2
+    conn = m.conn.astype(np.int64)
+    conn = np.where(conn >= cut, conn + mid, conn).astype(np.int32)
+    ins = lambda a, v: np.concatenate([a[:cut], np.full(mid, v, a.dtype), a[cut:], np.full(end, v, a.dtype)])
+    u = m.u.reshape(-1, 3)
+    u = np.concatenate([u[:cut], np.zeros((mid, 3)), u[cut:], np.zeros((end, 3))]).reshape(-1)
+    unused = np.r_[cut:cut + mid, m.n_nodes + mid:m.n_nodes + mid + end]
+    return dataclasses.replace(m, x=ins(m.x, 0.5), y=ins(m.y, 0.5), z=ins(m.z, 0.5), conn=conn, u=u,
+                               boundary=ins(m.boundary, False)), unused
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rowsym_rows_no_element_touches(prec):
+    """With 3x3 blocks the upper-triangle form writes b from the diagonal
+    blocks' tile sums; rows that no element touches have none, and get
+    zeros (whatever the buffer held), one mesh and batched."""
+    p, o = (fea.FP64, fea.F64) if prec == "fp64" else (fea.MIXED, fea.F32)
+    m0 = mg.hybrid_bands(4, seed=31, jitter=0.2)
+    m, unused = _with_unused_nodes(m0, 5, 4)
+    dm = fea.DeviceMesh(m, device="cuda:0")
+    g = dm.graph()
+    v0, r0, _ = dm.assemble(g, variant=fea.ROWOWNER, precision=p, out_dtype=o)
+    v1, r1, s1 = dm.assemble(g, variant=fea.ROWSYM, precision=p, out_dtype=o)
+    v1.fill_(-1.0)
+    r1.fill_(-1.0)
+    dm.assemble(g, variant=fea.ROWSYM, precision=p, out_dtype=o, vals=v1, rhs=r1, status=s1)
+    b = fea.Batch([dm], model=fea.ELASTIC)
+    vb, rb, sb = b.outputs(o)
+    rb.fill_(-1.0)
+    b.assemble(precision=p, out_dtype=o, vals=vb, rhs=rb, status=sb, variant=fea.ROWSYM)
+    torch.cuda.synchronize()
+    assert int(s1.item()) == -1 and int(sb[0].item()) == -1
+    tol = 1e-14 if p == fea.FP64 else 1e-6
+    r0 = r0.cpu().numpy().astype(np.float64).reshape(-1, 3)
+    for v, r in ((v1, r1), (vb, rb)):
+        r = r.cpu().numpy().astype(np.float64).reshape(-1, 3)
+        assert np.all(r[unused] == 0.0)
+        assert np.abs(r - r0).max() <= tol * np.abs(r0).max()
+        v = v.cpu().numpy().astype(np.float64)
+        assert np.abs(v - v0.cpu().numpy()).max() <= tol * np.abs(v0.cpu().numpy()).max()
+    assert vb.cpu().numpy().tobytes() == v1.cpu().numpy().tobytes()
+    assert rb.cpu().numpy().tobytes() == r1.cpu().numpy().tobytes()
+    b.destroy()
+
+
 def test_rowgather_rejects_node_in_too_many_elements():
     """A node shared by 70 tetrahedra exceeds the 64 (row, element) pairs a
     row-gather tile holds: the call fails with FEA_ERANGE naming the node,
