@@ -129,12 +129,10 @@ __global__ void k_node_sort(int64_t n_nodes, const int64_t *n2e_ptr, int32_t *n2
 // Row i's columns are the distinct nodes of i's incident elements. They are
 // produced in ascending order by repeatedly taking the smallest candidate
 // above the last one emitted: no per-row buffer, so any row length works.
-__global__ void k_row_pattern(int64_t n_nodes, const int64_t *n2e_ptr, const int32_t *n2e,
-                              const int64_t *conn_ptr, const int32_t *conn,
-                              const int64_t *row_ptr, int32_t *col, int32_t *deg)
+__device__ inline void row_pattern_serial(int64_t i, const int64_t *n2e_ptr, const int32_t *n2e,
+                                          const int64_t *conn_ptr, const int32_t *conn, const int64_t *row_ptr,
+                                          int32_t *col, int32_t *deg)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_nodes) return;
     int64_t b = n2e_ptr[i], e = n2e_ptr[i + 1];
     int32_t last = -1;
     int32_t cnt = 0;
@@ -154,6 +152,66 @@ __global__ void k_row_pattern(int64_t n_nodes, const int64_t *n2e_ptr, const int
         last = best;
     }
     if (deg) deg[i] = cnt;
+}
+
+// One 64-lane wave per row. The row's (element, local node) candidates sit
+// on a fixed stride of 8 per incident element (no family has more nodes), so
+// candidate f = 8 j + a is node a of the row's j-th element; lane l holds
+// candidates l, l + 64, ... in registers (at most 64 elements: 8 each), and
+// the wave emits the columns in ascending order by repeated wave-wide
+// minimum above the last one emitted. A row with more incident elements
+// takes the one-lane loop above.
+__global__ void __launch_bounds__(256) k_row_pattern(int64_t n_nodes, const int64_t *n2e_ptr, const int32_t *n2e,
+                                                     const int64_t *conn_ptr, const int32_t *conn,
+                                                     const int64_t *row_ptr, int32_t *col, int32_t *deg)
+{
+    constexpr int KMAX = 8;  // candidates per lane: 64 elements of up to 8 nodes
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n_nodes) return;  // the whole wave
+    const int64_t b = n2e_ptr[i];
+    const int ne = (int)(n2e_ptr[i + 1] - b);
+    if (ne > 64) {
+        if (lane == 0) row_pattern_serial(i, n2e_ptr, n2e, conn_ptr, conn, row_ptr, col, deg);
+        return;
+    }
+    // lane j < ne: the j-th incident element's first node and node count
+    int64_t s = 0;
+    int c = 0;
+    if (lane < ne) {
+        const int32_t el = n2e[b + lane];
+        s = conn_ptr[el];
+        c = (int)(conn_ptr[el + 1] - s);
+    }
+    const int K = (ne * 8 + 63) / 64;  // uniform over the wave
+    int32_t v[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        v[k] = INT_MAX;
+        if (k < K) {
+            const int f = lane + 64 * k, j = f >> 3, a = f & 7;
+            const int64_t sj = __shfl(s, j);
+            const int cj = __shfl(c, j);
+            if (j < ne && a < cj) v[k] = conn[sj + a];
+        }
+    }
+    int32_t last = -1, cnt = 0;
+    const int64_t out = col ? row_ptr[i] : 0;
+    for (;;) {
+        int32_t m = INT_MAX;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) m = (v[k] > last && v[k] < m) ? v[k] : m;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const int32_t w = __shfl_xor(m, o);
+            m = w < m ? w : m;
+        }
+        if (m == INT_MAX) break;
+        if (col && lane == 0) col[out + cnt] = m;
+        ++cnt;
+        last = m;
+    }
+    if (deg && lane == 0) deg[i] = cnt;
 }
 
 // e2nnz by binary search of conn[e][b] in row conn[e][a].
@@ -828,14 +886,14 @@ static int build(int64_t N, int64_t E, const uint8_t *types, const int64_t *conn
 
     // row pattern: degrees, prefix sum, columns
     if ((rc = dalloc((void **)&g->row_ptr, sizeof(int64_t) * (N + 1)))) return rc;
-    if (N) k_row_pattern<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, conn_ptr, conn, nullptr, nullptr, (int32_t *)cnt32.p);
+    if (N) k_row_pattern<<<grid_for(N, 4), 256, 0, s>>>(N, g->n2e_ptr, g->n2e, conn_ptr, conn, nullptr, nullptr, (int32_t *)cnt32.p);
     if ((rc = scan_to_ptr_i32((int32_t *)cnt32.p, N, g->row_ptr, (int64_t *)tmp.p, s))) return rc;
     FEA_HIP(hipMemcpyAsync(&g->nnz, g->row_ptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     FEA_HIP(hipStreamSynchronize(s));
     if (g->nnz > INT32_MAX)
         return set_error(FEA_ERANGE, "%lld nonzero blocks exceed int32 block indices", (long long)g->nnz);
     if ((rc = dalloc((void **)&g->col, sizeof(int32_t) * std::max<int64_t>(g->nnz, 1)))) return rc;
-    if (N) k_row_pattern<<<grid_for(N, BS), BS, 0, s>>>(N, g->n2e_ptr, g->n2e, conn_ptr, conn, g->row_ptr, g->col, nullptr);
+    if (N) k_row_pattern<<<grid_for(N, 4), 256, 0, s>>>(N, g->n2e_ptr, g->n2e, conn_ptr, conn, g->row_ptr, g->col, nullptr);
     FEA_HIP(hipGetLastError());
 
     // element -> nonzero map

@@ -280,11 +280,9 @@ def test_rowsym_rows_no_element_touches(prec):
     b.destroy()
 
 
-def test_rowgather_rejects_node_in_too_many_elements():
-    """A node shared by 70 tetrahedra exceeds the 64 (row, element) pairs a
-    row-gather tile holds: the call fails with FEA_ERANGE naming the node,
-    and the row-owner variant still assembles the mesh."""
-    k = 70
+def _tet_fan(k):
+    """k positively oriented tetrahedra sharing node 0 (their other nodes
+    their own): node 0's row touches k elements."""
     ang = 2 * np.pi * np.arange(k) / k
     pts = [(0.0, 0.0, 0.0)]
     conn = []
@@ -295,11 +293,37 @@ def test_rowgather_rejects_node_in_too_many_elements():
         conn += [0, base, base + 1, base + 2]
     pts = np.array(pts)
     conn = np.array(conn, dtype=np.int32)
-    # orient every tetrahedron positively
     for e in range(k):
         a, b, c_, d_ = pts[conn[4 * e:4 * e + 4]]
         if np.linalg.det(np.stack([b - a, c_ - a, d_ - a])) < 0:
             conn[4 * e + 1], conn[4 * e + 2] = conn[4 * e + 2], conn[4 * e + 1]
+    return pts, conn
+
+
+@pytest.mark.parametrize("k", [64, 65, 70])
+def test_graph_of_a_node_in_many_elements(k):
+    """The row pattern takes one wave per row with up to 64 incident
+    elements in registers and a one-lane loop beyond: node 0's row (k
+    elements, 3k + 1 columns) and every other row bit-exact against the
+    oracle on both sides of that limit."""
+    pts, conn = _tet_fan(k)
+    types = np.zeros(k, dtype=np.uint8)
+    cp = np.arange(0, 4 * k + 1, 4, dtype=np.int64)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    g = fea.Graph(len(pts), dev(types), dev(cp), dev(conn))
+    ex = g.export()
+    og = oracle.graph(len(pts), types, cp, conn)
+    assert np.array_equal(ex["row_ptr"].cpu().numpy(), np.asarray(og.row_ptr))
+    assert np.array_equal(ex["col"].cpu().numpy(), np.asarray(og.col))
+    assert int(og.row_ptr[1]) == 3 * k + 1
+
+
+def test_rowgather_rejects_node_in_too_many_elements():
+    """A node shared by 70 tetrahedra exceeds the 64 (row, element) pairs a
+    row-gather tile holds: the call fails with FEA_ERANGE naming the node,
+    and the row-owner variant still assembles the mesh."""
+    k = 70
+    pts, conn = _tet_fan(k)
     d = "cuda:0"
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(d)
     types = dev(np.zeros(k, dtype=np.uint8))
