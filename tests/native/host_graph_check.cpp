@@ -2,7 +2,9 @@
 // by the CPU tests with -fsanitize=address,undefined: on seeded random item
 // lists (and one item of size zero), greedy first fit in index and in
 // priority order, neighbour counts and (family, colour) buckets are
-// checked against brute force. Exit status 0 on success.
+// checked against brute force; items sharing one node check the colour
+// count on both sides of one mask word and of kMaxColours. Exit status 0
+// on success.
 #include <cstdio>
 #include <set>
 #include <vector>
@@ -109,8 +111,37 @@ static void run_case(int64_t n_nodes, int64_t n_items, int max_len)
     }
 }
 
+// k items that all hold node 0 need k colours: first fit gives item i
+// colour i, through one mask word up to 64 and the full masks beyond; past
+// kMaxColours the call reports the first item it cannot colour.
+static void run_shared_node(int k)
+{
+    std::vector<int64_t> ptr(k + 1, 0);
+    std::vector<int32_t> nodes;
+    for (int i = 0; i < k; ++i) {
+        nodes.push_back(0);
+        nodes.push_back(1 + i % 3);
+        ptr[i + 1] = (int64_t)nodes.size();
+    }
+    std::vector<int16_t> colour(k, -1), wide(k, -1);
+    const int64_t nc = greedy_first_fit(4, k, ptr.data(), nodes.data(), nullptr, colour.data());
+    if (k > kMaxColours) {
+        CHECK(nc == -(1 + (int64_t)kMaxColours));
+        return;
+    }
+    CHECK(nc == k);
+    for (int i = 0; i < k; ++i) CHECK(colour[i] == i);
+    const int64_t nw = greedy_first_fit_words<kMaxColours / 64>(4, k, ptr.data(), nodes.data(), nullptr, wide.data());
+    CHECK(nw == nc && wide == colour);
+}
+
 int main()
 {
+    run_shared_node(1);
+    run_shared_node(64);
+    run_shared_node(65);
+    run_shared_node(200);
+    run_shared_node(kMaxColours + 1);
     run_case(1, 1, 1);
     run_case(5, 0, 3);
     run_case(40, 30, 4);

@@ -316,6 +316,11 @@ def test_graph_of_a_node_in_many_elements(k):
     assert np.array_equal(ex["row_ptr"].cpu().numpy(), np.asarray(og.row_ptr))
     assert np.array_equal(ex["col"].cpu().numpy(), np.asarray(og.col))
     assert int(og.row_ptr[1]) == 3 * k + 1
+    # all k elements share node 0: k colours, past one 64-bit mask word
+    # for k > 64 (the colouring's fast pass gives way to the full masks)
+    colour, nc = oracle.colour_greedy(len(pts), cp, conn)
+    assert nc == k and g.n_colours == k
+    assert np.array_equal(ex["colour"].cpu().numpy(), colour)
 
 
 def test_rowgather_rejects_node_in_too_many_elements():
