@@ -180,7 +180,7 @@ struct ElemArgs {
     double *vals;    // FP64 target of ATOMIC / COLOUR
     double *rhs;
     void *contrib;   // ROWOWNER slot workspace (compute type)
-    void *rcontrib;  // ROWOWNER right-hand-side workspace
+    void *rcontrib;  // right-hand-side workspace (ROWOWNER, TILECOL; ROWSYM with 1x1 blocks)
     int32_t *status;
     // upper-triangle form, indexed by the launch-local tile index: entry and
     // tile-block ranges, entries (lane << 1 | transposed), tile-block entry
@@ -915,8 +915,9 @@ __device__ void elem_tile_full(const ElemArgs &A, int64_t first, ElemSmem<T, MOD
 // Upper-triangle form (V_ROWSYM) and its tile-coloured variant (V_TILECOL):
 // tile first / EPB, one thread per local pair a <= b of every element.
 // Every global load of the tile -- node ids, coordinates, right-hand-side
-// destinations, element data and source, the tile's entries, tile-block
-// ends and slots (tile-coloured: blocks and their lower partners) -- is
+// destinations (where b has a workspace of its own), element data and
+// source, the tile's entries, tile-block ends and slots (tile-coloured:
+// blocks and their lower partners) -- is
 // issued in the first phase, so that a tile waits for two dependent load
 // latencies (range -> entries, node id -> coordinates) before its
 // arithmetic, and none after it.
