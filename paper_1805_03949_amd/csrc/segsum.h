@@ -117,15 +117,16 @@ __global__ void __launch_bounds__(256) k_segsum(int64_t n, const int64_t *ptr, c
 // position m, so a workgroup's index loads are contiguous and independent
 // of each other, and its workspace range (uptr[m0] .. uptr[m0 + BPW]) is
 // known after one load; R rounds of 256 / W outputs per workgroup.
-// Measured on MI355X over the hybrid96 workspaces (FP64 / FP32 tile sums):
-// 1 round 0.88 / 0.89 ms, 2 rounds 0.85-0.88 / 0.66-0.74, 4 rounds
-// 0.92 / 0.68-0.77; 16-byte FP64 loads, 32 KB chunks with 4-8 rounds
-// (fewer workgroups per CU) and an XCD-contiguous workgroup order were all
-// slower.
+// Measured on MI355X (FP64 / FP32 tile sums, ms): hybrid256 1 round
+// 16.55 / 15.15, 2 rounds 17.24-17.43 / 12.20-12.25, 4 rounds - / 12.53;
+// hybrid96 1 round 0.92-0.94 / 0.88, 2 rounds 0.95 / 0.70, 4 rounds - /
+// 0.71 (with the right-hand side carried in the diagonal tile sums).
+// 16-byte FP64 loads, 32 KB chunks with 4-8 rounds (fewer workgroups per
+// CU) and an XCD-contiguous workgroup order were all slower.
 template <typename CT>
 struct SymSegCfg {
     static constexpr int LOAD_BYTES = sizeof(CT) == 8 ? 8 : 16;
-    static constexpr int ROUNDS = sizeof(CT) == 8 ? 2 : 4;
+    static constexpr int ROUNDS = sizeof(CT) == 8 ? 1 : 2;
     static constexpr int CHUNK_BYTES = 16384;
 };
 
