@@ -33,6 +33,25 @@ def test_reduce_bytes_definition():
     assert b == 84_492_288 * 72 + (22_156_129 + 1) * 8 + 22_156_129 * 72
 
 
+def test_element_bytes_of_the_upper_triangle_form():
+    """Element-phase bytes of the upper-triangle form: the inputs, then per
+    tile-block its b^2 tile sums and 6 bytes of slot and end, 2 bytes per
+    entry and 16 per tile; with 1x1 blocks also one right-hand-side value
+    per element node, with 3x3 blocks none (the diagonal tile sums carry
+    it)."""
+    class G:
+        map_len, nnz = 1000, 400
+    sym = {"tile_blocks": 300, "entries": 500, "tiles": 20}
+    N, E, L = 100, 40, 240
+    for B, s_c in ((3, 8), (3, 4), (1, 8)):
+        inputs = N * 24 + L * 4 + E * (8 + 4 + 8 + 16 + 8 * B)
+        want = inputs + 300 * (B * B * s_c + 6) + 500 * 2 + 20 * 16 + (L * B * s_c if B == 1 else 0)
+        assert bench.element_bytes(G, B, s_c, s_c, L, N, E, "rowsym", sym) == want
+    # the row-owner form writes every slot and every right-hand-side entry
+    assert bench.element_bytes(G, 3, 8, 8, L, N, E, "rowowner") == \
+        N * 24 + L * 4 + E * (8 + 4 + 8 + 16 + 24) + 1000 * 72 + L * 24
+
+
 def _tile_blocks_brute_force(m):
     """Tile entries and distinct (tile, upper block) pairs, element by
     element in type-sorted order with Python sets."""
