@@ -267,6 +267,16 @@ def batched_workload(fea, mg, torch):
         default_ms = _median_ms(lambda: (b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs,
                                                     status=status, timing=True, variant=fea.ROWSYM),
                                          b.last_ms())[1], 5)
+        # the tuner's search starts from the smallest items (one
+        # upper-triangle tile each), timed first, so that what it finds is
+        # measured against where it started as well as against the defaults
+        start = [25, 17, 12, 7]
+        b.set_tiles(start)
+        b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs, status=status, timing=True,
+                   variant=fea.ROWSYM)
+        start_ms = _median_ms(lambda: (b.assemble(precision=fea.MIXED, out_dtype=fea.F32, vals=vals, rhs=rhs,
+                                                  status=status, timing=True, variant=fea.ROWSYM),
+                                       b.last_ms())[1], 5)
         with tempfile.TemporaryDirectory() as d:
             tile = b.autotune(precision=fea.MIXED, out_dtype=fea.F32, reps=3, table_path=f"{d}/tiles.txt",
                               variant=fea.ROWSYM)
@@ -348,7 +358,9 @@ def batched_workload(fea, mg, torch):
             "elements": int(b.n_elems), "items": int(b.n_items), "items_default_tiles": int(n_items_default),
             "precision": "mixed", "variant": "rowsym", "tiles": [int(t) for t in tile],
             "persistent_kernel_ms_default_tiles": round(default_ms, 4),
+            "autotune_start_tiles": start, "persistent_kernel_ms_start_tiles": round(start_ms, 4),
             "persistent_kernel_ms_tuned_tiles": round(tuned_ms, 4),
+            "speedup_tuned_vs_start": round(start_ms / tuned_ms, 4),
             "ms_per_replay": round(ms, 4), "elements_per_s": round(b.n_elems / (ms * 1e-3), 1),
             "replays": 100, "workers": b.workers(), "status_ok": ok, **gather}
 
