@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <thread>
 #include <vector>
 
 namespace fea {
@@ -104,30 +105,64 @@ inline std::vector<int64_t> priority_order(int64_t n_items, const int32_t *nneig
 // bucket at seg[g * (ncol + 1) + ncol] (= the start of group g + 1's first);
 // list receives the items bucket by bucket, each bucket in `order`
 // (nullptr = ascending), as item - first[group] (group-local indices).
+// A stable counting sort over consecutive chunks of the visit order, one
+// thread each: per-chunk bucket counts, then each chunk places its items
+// from its own offsets, so the result is the one-thread result. threads: 0
+// = one per 2^20 items, at most 8; failing to start a thread runs its chunk
+// on the calling thread.
 inline void buckets(int64_t n_items, int n_groups, const uint8_t *group, const int16_t *colour, int ncol,
                     const int64_t *order, const int64_t *first, std::vector<int64_t> &seg,
-                    std::vector<int32_t> &list)
+                    std::vector<int32_t> &list, int threads = 0)
 {
-    seg.assign((size_t)n_groups * (ncol + 1), 0);
-    for (int64_t i = 0; i < n_items; ++i) seg[(size_t)group[i] * (ncol + 1) + colour[i] + 1]++;
-    int64_t run = 0;
-    for (int g = 0; g < n_groups; ++g)
-        for (int c = 0; c <= ncol; ++c) {
-            int64_t &v = seg[(size_t)g * (ncol + 1) + c];
-            if (c == 0) {
-                v = run;
-                continue;
+    const int64_t nb = (int64_t)n_groups * ncol;
+    if (threads <= 0) threads = (int)std::min<int64_t>(8, n_items >> 20);
+    threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, n_items));
+    std::vector<int64_t> cnt((size_t)threads * std::max<int64_t>(nb, 1), 0);
+    auto item = [&](int64_t k) { return order ? order[k] : k; };
+    auto in_chunks = [&](auto &&body) {
+        std::vector<std::thread> pool;
+        for (int p = 1; p < threads; ++p) {
+            try {
+                pool.emplace_back(body, p);
+            } catch (...) {
+                body(p);
             }
-            run += v;
-            v = run;
         }
-    std::vector<int64_t> cur(seg);
-    list.assign((size_t)std::max<int64_t>(n_items, 1), 0);
-    for (int64_t k = 0; k < n_items; ++k) {
-        const int64_t i = order ? order[k] : k;
-        const int g = group[i];
-        list[(size_t)cur[(size_t)g * (ncol + 1) + colour[i]]++] = (int32_t)(i - (first ? first[g] : 0));
+        body(0);
+        for (std::thread &t : pool) t.join();
+    };
+    in_chunks([&](int p) {
+        int64_t *h = cnt.data() + (size_t)p * nb;
+        for (int64_t k = n_items * p / threads, k1 = n_items * (p + 1) / threads; k < k1; ++k) {
+            const int64_t i = item(k);
+            ++h[group[i] * ncol + colour[i]];
+        }
+    });
+    // bucket starts (the one-thread layout), then each chunk's start within
+    // every bucket
+    seg.assign((size_t)n_groups * (ncol + 1), 0);
+    int64_t run = 0;
+    for (int g = 0; g < n_groups; ++g) {
+        for (int c = 0; c < ncol; ++c) {
+            seg[(size_t)g * (ncol + 1) + c] = run;
+            for (int p = 0; p < threads; ++p) {
+                int64_t &h = cnt[(size_t)p * nb + g * ncol + c];
+                const int64_t n = h;
+                h = run;
+                run += n;
+            }
+        }
+        seg[(size_t)g * (ncol + 1) + ncol] = run;
     }
+    list.assign((size_t)std::max<int64_t>(n_items, 1), 0);
+    in_chunks([&](int p) {
+        int64_t *off = cnt.data() + (size_t)p * nb;
+        for (int64_t k = n_items * p / threads, k1 = n_items * (p + 1) / threads; k < k1; ++k) {
+            const int64_t i = item(k);
+            const int g = group[i];
+            list[(size_t)off[g * ncol + colour[i]]++] = (int32_t)(i - (first ? first[g] : 0));
+        }
+    });
 }
 
 }  // namespace host

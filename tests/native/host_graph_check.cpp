@@ -2,7 +2,8 @@
 // by the CPU tests with -fsanitize=address,undefined: on seeded random item
 // lists (and one item of size zero), greedy first fit in index and in
 // priority order, neighbour counts and (family, colour) buckets are
-// checked against brute force; items sharing one node check the colour
+// checked against brute force (the buckets with one and with three
+// threads); items sharing one node check the colour
 // count on both sides of one mask word and of kMaxColours. Exit status 0
 // on success.
 #include <cstdio>
@@ -90,9 +91,12 @@ static void run_case(int64_t n_nodes, int64_t n_items, int max_len)
             first[t] = first[t - 1];
             while (first[t] < n_items && fam[first[t]] < t) ++first[t];
         }
-        std::vector<int64_t> seg;
-        std::vector<int32_t> list;
-        buckets(n_items, 4, fam.data(), colour.data(), (int)nc, ord, first.data(), seg, list);
+        std::vector<int64_t> seg, seg3;
+        std::vector<int32_t> list, list3;
+        buckets(n_items, 4, fam.data(), colour.data(), (int)nc, ord, first.data(), seg, list, 1);
+        // the chunked form (three threads) gives the one-thread result
+        buckets(n_items, 4, fam.data(), colour.data(), (int)nc, ord, first.data(), seg3, list3, 3);
+        CHECK(seg3 == seg && list3 == list);
         std::vector<int> seen(n_items, 0);
         for (int t = 0; t < 4; ++t)
             for (int c = 0; c < nc; ++c) {
