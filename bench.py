@@ -518,6 +518,16 @@ def _measured_log_cycles(fea, torch, b, runs=5):
     return torch.stack(logs).mean(dim=0).contiguous()
 
 
+def static_split_cuts(np, wts, parts):
+    """Cut points of a static split of items (in their order) into `parts`
+    contiguous parts of about equal total weight: part k ends at the first
+    item whose weight midpoint lies past (k+1)/parts of the total, so every
+    part is within one item's weight of an even share."""
+    wts = np.asarray(wts, dtype=np.float64)
+    cs = np.cumsum(wts)
+    return np.searchsorted(cs - 0.5 * wts, cs[-1] * np.arange(1, parts) / parts)
+
+
 def heterogeneous_workload(fea, mg, torch, np, cells=128):
     """Hybrid split meshes (40/30/20/10 hex/tet/pen/pyr layers) where 30% of
     8^3-cell bricks use the neo-Hookean tangent. The cost model is trained
@@ -557,10 +567,9 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
         return float((x @ y) ** 2 / ((x @ x) * (y @ y)))
 
     def split_lb(cyc, wts, parts=8):
-        # cut the type-sorted items where the running weight crosses k/8 of
-        # the total, then rate the split by the measured cycles of its parts
-        cs = np.cumsum(wts)
-        cut = np.searchsorted(cs - 0.5 * wts, cs[-1] * np.arange(1, parts) / parts)
+        # cut the type-sorted items by weight, then rate the split by the
+        # measured cycles of its parts
+        cut = static_split_cuts(np, wts, parts)
         sums = np.array([c.sum() for c in np.split(cyc, cut)])
         return round(float(sums.mean() / sums.max()), 4)
 
@@ -571,8 +580,7 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
         # makespan is the slowest part's time
         perm = np.argsort(msh.types, kind="stable")
         seg = np.concatenate([[0], np.cumsum(np.bincount(msh.types, minlength=4))])
-        cs = np.cumsum(wts)
-        cut = np.searchsorted(cs - 0.5 * wts, cs[-1] * np.arange(1, parts) / parts)
+        cut = static_split_cuts(np, wts, parts)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ms, ne = [], []
         for sel in np.split(np.arange(bb.items.shape[0]), cut):

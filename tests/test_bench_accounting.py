@@ -168,6 +168,24 @@ def test_submesh_copies_its_elements_and_renumbers_their_nodes():
         assert np.array_equal(nodes[s.conn[s.conn_ptr[k]:s.conn_ptr[k + 1]]], m.conn[m.conn_ptr[e]:m.conn_ptr[e + 1]])
 
 
+def test_static_split_cuts():
+    """The 8-part static split of the cost-model study: contiguous parts
+    covering every item, each within one item's weight of an even share."""
+    rng = np.random.default_rng(3)
+    for n, parts in ((1000, 8), (37, 8), (8, 8), (500, 3)):
+        w = rng.lognormal(0.0, 1.0, n)
+        cut = bench.static_split_cuts(np, w, parts)
+        assert cut.size == parts - 1 and np.all(np.diff(cut) >= 0) and cut[0] >= 0 and cut[-1] <= n
+        pieces = np.split(np.arange(n), cut)
+        assert np.array_equal(np.concatenate(pieces), np.arange(n))
+        share = w.sum() / parts
+        for p in pieces:
+            assert abs(w[p].sum() - share) <= w.max() + 1e-9
+    # equal weights: equal parts
+    cut = bench.static_split_cuts(np, np.ones(800), 8)
+    assert np.array_equal(cut, np.arange(100, 800, 100))
+
+
 def test_row_max_by_hand():
     vals = np.arange(27, dtype=np.float64) - 13.0     # 3 blocks
     row_ptr = np.array([0, 2, 2, 3])
