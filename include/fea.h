@@ -90,7 +90,7 @@ enum fea_variant { FEA_ROWOWNER = 0, FEA_ATOMIC = 1, FEA_COLOUR = 2, FEA_ROWGATH
                    FEA_TILECOLOUR = 5 };
 enum fea_dtype { FEA_F64 = 0, FEA_F32 = 1 };
 enum fea_model { FEA_POISSON = 0, FEA_ELASTIC = 1 };
-enum fea_schedule { FEA_TYPE_SORTED = 0, FEA_LEARNED = 1, FEA_GP_WEIGHT = 2 };
+enum fea_schedule { FEA_TYPE_SORTED = 0, FEA_LEARNED = 1, FEA_GP_WEIGHT = 2, FEA_LEARNED_CLASSES = 3 };
 
 /* Options. A zero-initialised struct is FP64, row-owner, f64 output. */
 typedef struct fea_options {
@@ -461,7 +461,16 @@ int fea_tile_table_load(const char *table_path, int model, int precision, int32_
  *   FEA_GP_WEIGHT    largest first by (Gauss points x elements), the paper's
  *                    a-priori element weight (Section 4.1);
  *   FEA_LEARNED      largest first by pred[item] (device float[n_items],
- *                    e.g. fea_cost_predict output), ties by item index.
+ *                    e.g. fea_cost_predict output), ties by item index;
+ *   FEA_LEARNED_CLASSES  largest cost class first, the items of a class in
+ *                    type-sorted order: with pred a predicted log-cost, an
+ *                    item's class is round((pred[item] - med) / ln 2), med
+ *                    the lower median of pred over its family's items (in
+ *                    double precision; round = floor(x + 0.5)). Exact
+ *                    longest-first order scatters items of near-equal cost
+ *                    across the mesh, and with them the nodes and cache
+ *                    lines that neighbouring items share; classes a factor
+ *                    of two wide still start the expensive items first.
  * Drops a captured graph. Waits on `stream` to read pred.
  */
 int fea_batch_order(fea_batch *b, int schedule, const float *pred, hipStream_t stream);

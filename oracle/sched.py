@@ -33,3 +33,23 @@ def lpt_order(pred):
     """Indices by descending prediction; ties keep ascending index."""
     pred = np.asarray(pred)
     return np.lexsort((np.arange(pred.size), -pred))
+
+
+def class_order(pred, family):
+    """Largest cost class first, ascending index within a class.
+
+    pred is a predicted log-cost per item and family its element family. An
+    item's class is round((pred - med) / ln 2) in double precision, med the
+    lower median of pred over the items of its family, round(x) =
+    floor(x + 0.5): items within a factor of two of each other's predicted
+    cost mostly share a class, and a class keeps the given (type-sorted)
+    order.
+    """
+    p = np.asarray(pred).astype(np.float64)
+    family = np.asarray(family)
+    cls = np.zeros(p.size)
+    for t in np.unique(family):
+        sel = family == t
+        med = np.sort(p[sel])[(int(sel.sum()) - 1) // 2]
+        cls[sel] = np.floor((p[sel] - med) / np.log(2.0) + 0.5)
+    return np.lexsort((np.arange(p.size), -cls))

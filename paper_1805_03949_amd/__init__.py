@@ -113,7 +113,7 @@ _lib.fea_cost_log_cycles.argtypes = [_P, _I64, _P, _P]
 _lib.fea_cost_save.argtypes = [_P, ctypes.c_char_p]
 _lib.fea_cost_load.argtypes = [_P, ctypes.c_char_p]
 
-TYPE_SORTED, LEARNED, GP_WEIGHT = 0, 1, 2
+TYPE_SORTED, LEARNED, GP_WEIGHT, LEARNED_CLASSES = 0, 1, 2, 3
 N_FEATURES, N_PARAMS = 12, 5057
 
 # every exported symbol declared in include/fea.h

@@ -949,12 +949,28 @@ extern "C" int fea_batch_order(fea_batch *b, int schedule, const float *pred, hi
         return upload_order(b);
     } else if (schedule == FEA_GP_WEIGHT) {
         for (size_t i = 0; i < ni; ++i) w[i] = (double)b->items[4 * i + 3] * kNQ[b->items[4 * i + 1]];
-    } else if (schedule == FEA_LEARNED) {
+    } else if (schedule == FEA_LEARNED || schedule == FEA_LEARNED_CLASSES) {
         if (!pred && ni) return set_error(FEA_EINVAL, "pred is required for the learned schedule");
         std::vector<float> p(ni);
         if (ni) FEA_HIP(hipMemcpyAsync(p.data(), pred, sizeof(float) * ni, hipMemcpyDeviceToHost, stream));
         FEA_HIP(hipStreamSynchronize(stream));
         for (size_t i = 0; i < ni; ++i) w[i] = p[i];
+        if (schedule == FEA_LEARNED_CLASSES) {
+            // cost classes a factor of two wide, centred on the family's
+            // lower-median prediction: items of near-equal predicted cost
+            // share a class and keep the type-sorted order among themselves
+            for (int t = 0; t < 4; ++t) {
+                std::vector<double> ft;
+                for (size_t i = 0; i < ni; ++i)
+                    if (b->items[4 * i + 1] == t) ft.push_back(w[i]);
+                if (ft.empty()) continue;
+                const size_t mid = (ft.size() - 1) / 2;
+                std::nth_element(ft.begin(), ft.begin() + mid, ft.end());
+                const double med = ft[mid];
+                for (size_t i = 0; i < ni; ++i)
+                    if (b->items[4 * i + 1] == t) w[i] = floor((w[i] - med) / M_LN2 + 0.5);
+            }
+        }
     } else {
         return set_error(FEA_EINVAL, "unknown schedule %d", schedule);
     }

@@ -171,8 +171,15 @@ def test_schedules_order_items_and_keep_results():
     b.order(fea.LEARNED, pred)
     v, r, _ = b.assemble()
     assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
+    # cost classes: the oracle's class order, and the same results
+    b.order(fea.LEARNED_CLASSES, pred)
+    assert np.array_equal(b.get_order(), sched.class_order(pred.cpu().numpy(), b.items[:, 1]))
+    v, r, _ = b.assemble()
+    assert (v.cpu().numpy().tobytes(), r.cpu().numpy().tobytes()) == ref
     with pytest.raises(fea.FeaError):
         b.order(fea.LEARNED, None)
+    with pytest.raises(fea.FeaError):
+        b.order(fea.LEARNED_CLASSES, None)
     b.order(fea.TYPE_SORTED)
     assert np.array_equal(b.get_order(), np.arange(b.n_items))
 

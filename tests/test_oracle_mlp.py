@@ -61,3 +61,23 @@ def test_list_schedule_and_lpt():
     assert list(order) == [4, 0, 1, 2, 3]
     busy = sched.list_schedule(costs[order], 2)
     assert busy.max() == 4 and sched.load_balance(busy) == 1.0
+
+
+def test_class_order_hand_checked():
+    # family 0: lower median 100 -> classes 0, 2, 0, 0; family 1: median 50
+    # -> classes 0, -1, 2
+    fam = np.array([0, 0, 0, 0, 1, 1, 1])
+    pred = np.log(np.array([100.0, 400.0, 110.0, 95.0, 50.0, 25.0, 200.0])).astype(np.float32)
+    assert list(sched.class_order(pred, fam)) == [1, 6, 0, 2, 3, 4, 5]
+    # near-equal costs keep the given order entirely
+    rng = np.random.default_rng(3)
+    p = np.log(1000.0 * (1.0 + 0.3 * rng.random(50)))
+    assert np.array_equal(sched.class_order(p, np.zeros(50, dtype=int)), np.arange(50))
+    # the expensive item first: list scheduling on two workers
+    costs = np.array([1.0, 1, 1, 1, 1, 1, 4])
+    fam0 = np.zeros(7, dtype=int)
+    assert sched.list_schedule(costs, 2).max() == 7
+    assert sched.list_schedule(costs[sched.class_order(np.log(costs), fam0)], 2).max() == 5
+    # a prediction half a class above the median rounds up, just below it down
+    p = np.array([0.0, 0.0, 0.0, 0.5 * np.log(2.0) * (1 + 1e-12), 0.5 * np.log(2.0) * (1 - 1e-12)])
+    assert list(sched.class_order(p, np.zeros(5, dtype=int))) == [3, 0, 1, 2, 4]
