@@ -286,12 +286,17 @@ def _plane_rows(mesh, L, orc, vals, rhs, row_ptr, col, fp32_L=None):
     return p1 - p0, worst
 
 
-def test_hybrid256_interface_planes_whole_rows():
+@pytest.fixture(scope="module")
+def hybrid256():
+    return mg.hybrid_split(256, seed=5)
+
+
+def test_hybrid256_interface_planes_whole_rows(hybrid256):
     """Every row of the three family-interface node planes of the 256^3
     mesh (hex8/tet4, tet4/pen6, pen6/pyr5: 3 x 66,049 rows) from the
     benchmark's headline launch (one-mesh upper-triangle form), FP64 and
     mixed, against the oracle on the two cell layers around each plane."""
-    mesh = mg.hybrid_split(256, seed=5)
+    mesh = hybrid256
     bands = mg.split_bands(256)
     planes = [int(L) for L in np.cumsum([l for _, l in bands])[:-1]]
     print(f"[case] hybrid256 planes {planes}", flush=True)
@@ -314,4 +319,69 @@ def test_hybrid256_interface_planes_whole_rows():
             print(f"[case] plane {L}: {n} rows, worst {worst:.3g}", flush=True)
             assert worst <= (1e-12 if prec == fea.FP64 else 1.0), (L, prec, worst)
         del v, r
+    g.destroy()
+
+
+def test_hybrid256_every_row_rigid_modes_and_symmetry(hybrid256):
+    """Properties that hold at any size, on every row of the 256^3 mesh from
+    the headline launch (one-mesh upper-triangle form). The six rigid-body
+    modes of the free solid are in the kernel of A: every element matrix
+    annihilates them, since a translation or an infinitesimal rotation has
+    no symmetric gradient and the isoparametric map reproduces x exactly, so
+    each row's sum of A_ij r_j cancels to rounding, relative to the sum of
+    |A_ij| |r_j| (FP64: 1e-11, about 300x the rounding of 27 blocks whose
+    entries are themselves sums of up to ten times their size; mixed: 1e-5,
+    the FP32 gradients reproduce x only to a few units of 2^-24 relative,
+    summed over the same terms; measured on MI355X: at most 9.1e-15 and
+    1.2e-7). A wrong or missing term leaves an O(1) residual. In FP64 A
+    also equals its transpose bitwise, block by block."""
+    mesh = hybrid256
+    dm = fea.DeviceMesh(mesh)
+    g = dm.graph()
+    ex = g.export()
+    row_ptr, col = ex["row_ptr"], ex["col"].long()
+    del ex
+    n, nnz = mesh.n_nodes, col.numel()
+    dev = col.device
+    rows = torch.repeat_interleave(torch.arange(n, device=dev), row_ptr[1:] - row_ptr[:-1])
+    X = torch.stack([dm.x, dm.y, dm.z], 1).double()
+    X = X - X.mean(0)
+    eye = torch.eye(3, dtype=torch.float64, device=dev)
+    CH = 1 << 24
+    for prec, tol in ((fea.FP64, 1e-11), (fea.MIXED, 1e-5)):
+        outd = fea.F64 if prec == fea.FP64 else fea.F32
+        print(f"[case] hybrid256 every row, rowsym precision {prec}", flush=True)
+        v, _, st = dm.assemble(g, variant=fea.ROWSYM, precision=prec, out_dtype=outd)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -1
+        A = v.view(nnz, 3, 3)
+        for m in range(6):
+            res = torch.zeros(n, 3, dtype=torch.float64, device=dev)
+            scale = torch.zeros(n, dtype=torch.float64, device=dev)
+            for c0 in range(0, nnz, CH):
+                sl = slice(c0, min(nnz, c0 + CH))
+                a = A[sl].double()
+                if m < 3:
+                    rj = eye[m].expand(a.shape[0], 3)
+                else:
+                    rj = torch.linalg.cross(eye[m - 3].expand(a.shape[0], 3), X[col[sl]])
+                res.index_add_(0, rows[sl], (a * rj.unsqueeze(1)).sum(-1))
+                scale.index_add_(0, rows[sl], (a.abs() * rj.abs().unsqueeze(1)).sum(-1).amax(-1))
+                del a, rj
+            touched = scale > 0
+            ratio = float((res.abs().amax(1)[touched] / scale[touched]).max().item())
+            print(f"[case] mode {m}: worst residual / scale {ratio:.3g}", flush=True)
+            assert ratio <= tol, (prec, m, ratio)
+        if prec == fea.FP64:
+            key = rows * n + col
+            tkey = col * n + rows
+            pos = torch.searchsorted(key, tkey)
+            del tkey
+            assert bool((pos < nnz).all())
+            for c0 in range(0, nnz, CH):
+                sl = slice(c0, min(nnz, c0 + CH))
+                assert torch.equal(key[pos[sl]], col[sl] * n + rows[sl])  # the pattern is symmetric
+                assert torch.equal(A[pos[sl]], A[sl].transpose(1, 2))
+            del key, pos
+        del v, A
     g.destroy()
