@@ -433,6 +433,9 @@ def large_workload(fea, mg, torch, np, cells=256, mesh=None):
     lc = out["mixed_queue_learned_classes"]["total_ms"]
     out["speedup_learned_mixed_vs_fp64"] = round(out["fp64_type_sorted"]["total_ms"] / lc, 4)
     out["speedup_learned_vs_type_sorted_queue_mixed"] = round(out["mixed_type_sorted"]["total_ms"] / lc, 4)
+    # the same ratio with the exact longest-predicted-first queue
+    out["speedup_learned_lpt_mixed_vs_fp64"] = round(
+        out["fp64_type_sorted"]["total_ms"] / out["mixed_queue_learned_lpt"]["total_ms"], 4)
     b.destroy()
     torch.cuda.empty_cache()
 
@@ -672,6 +675,8 @@ def heterogeneous_workload(fea, mg, torch, np, cells=128):
     ho["speedup_learned_vs_type_sorted_queue_mixed"] = round(ho["mixed_type_sorted"]["total_ms"] / lc, 4)
     ho["speedup_learned_lpt_vs_type_sorted_queue_mixed"] = round(
         ho["mixed_type_sorted"]["total_ms"] / ho["mixed_queue_learned_lpt"]["total_ms"], 4)
+    ho["speedup_learned_lpt_mixed_vs_fp64_type_sorted"] = round(
+        ho["fp64_type_sorted"]["total_ms"] / ho["mixed_queue_learned_lpt"]["total_ms"], 4)
     ho["speedup_learned_static_vs_gauss_point_static"] = round(
         ho["mixed_static_by_gauss_points"]["total_ms"] / ho["mixed_static_learned"]["total_ms"], 4)
     # the most any queue order can gain on this GPU: the dynamic queue's
