@@ -266,6 +266,8 @@ def test_learned_cost_model_on_a_held_out_mesh():
     for name, setup in (("type_sorted", lambda: bh.order(fea.TYPE_SORTED)),
                         ("gp_weight_lpt", lambda: bh.order(fea.GP_WEIGHT)),
                         ("learned_lpt", lambda: bh.order(fea.LEARNED, torch.from_numpy(pred.astype(np.float32)).cuda())),
+                        ("learned_classes", lambda: bh.order(fea.LEARNED_CLASSES,
+                                                             torch.from_numpy(pred.astype(np.float32)).cuda())),
                         ("learned_static", lambda: bh.partition(fea.LEARNED,
                                                                 torch.from_numpy(pred.astype(np.float32)).cuda()))):
         setup()
