@@ -471,7 +471,8 @@ int fea_tile_table_load(const char *table_path, int model, int precision, int32_
  *                    across the mesh, and with them the nodes and cache
  *                    lines that neighbouring items share; classes a factor
  *                    of two wide still start the expensive items first.
- * Drops a captured graph. Waits on `stream` to read pred.
+ * Drops a captured graph. Waits on `stream` to read pred. FEA_EINVAL if
+ * pred is NULL or holds a value that is not finite (learned schedules).
  */
 int fea_batch_order(fea_batch *b, int schedule, const float *pred, hipStream_t stream);
 

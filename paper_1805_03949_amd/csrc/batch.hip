@@ -942,9 +942,9 @@ extern "C" int fea_batch_order(fea_batch *b, int schedule, const float *pred, hi
     if (!b) return set_error(FEA_EINVAL, "batch is NULL");
     const size_t ni = b->items.size() / 4;
     std::vector<double> w(ni, 0.0);
-    b->part_for = -1;
-    b->part_w.clear();
     if (schedule == FEA_TYPE_SORTED) {
+        b->part_for = -1;
+        b->part_w.clear();
         for (size_t i = 0; i < ni; ++i) b->order[i] = (int32_t)i;
         return upload_order(b);
     } else if (schedule == FEA_GP_WEIGHT) {
@@ -954,7 +954,10 @@ extern "C" int fea_batch_order(fea_batch *b, int schedule, const float *pred, hi
         std::vector<float> p(ni);
         if (ni) FEA_HIP(hipMemcpyAsync(p.data(), pred, sizeof(float) * ni, hipMemcpyDeviceToHost, stream));
         FEA_HIP(hipStreamSynchronize(stream));
-        for (size_t i = 0; i < ni; ++i) w[i] = p[i];
+        for (size_t i = 0; i < ni; ++i) {
+            if (!std::isfinite(p[i])) return set_error(FEA_EINVAL, "pred[%zu] is not finite", i);
+            w[i] = p[i];
+        }
         if (schedule == FEA_LEARNED_CLASSES) {
             // cost classes a factor of two wide, centred on the family's
             // lower-median prediction: items of near-equal predicted cost
@@ -974,6 +977,9 @@ extern "C" int fea_batch_order(fea_batch *b, int schedule, const float *pred, hi
     } else {
         return set_error(FEA_EINVAL, "unknown schedule %d", schedule);
     }
+    // the arguments are valid: back to the dynamic queue, in the new order
+    b->part_for = -1;
+    b->part_w.clear();
     // longest processing time first; ties keep the item order
     for (size_t i = 0; i < ni; ++i) b->order[i] = (int32_t)i;
     std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t x, int32_t y) { return w[x] > w[y]; });
@@ -996,7 +1002,10 @@ extern "C" int fea_batch_partition(fea_batch *b, int weights, const float *pred,
         std::vector<float> p(ni);
         if (ni) FEA_HIP(hipMemcpyAsync(p.data(), pred, sizeof(float) * ni, hipMemcpyDeviceToHost, stream));
         FEA_HIP(hipStreamSynchronize(stream));
-        for (size_t i = 0; i < ni; ++i) w[i] = exp((double)p[i]);
+        for (size_t i = 0; i < ni; ++i) {
+            if (!std::isfinite(p[i])) return set_error(FEA_EINVAL, "pred[%zu] is not finite", i);
+            w[i] = exp((double)p[i]);
+        }
     } else {
         return set_error(FEA_EINVAL, "unknown weights %d", weights);
     }

@@ -180,6 +180,13 @@ def test_schedules_order_items_and_keep_results():
         b.order(fea.LEARNED, None)
     with pytest.raises(fea.FeaError):
         b.order(fea.LEARNED_CLASSES, None)
+    bad = pred.clone()
+    bad[bad.numel() // 2] = float("nan")
+    for sch in (fea.LEARNED, fea.LEARNED_CLASSES):
+        with pytest.raises(fea.FeaError):
+            b.order(sch, bad)
+    with pytest.raises(fea.FeaError):
+        b.partition(fea.LEARNED, bad)
     b.order(fea.TYPE_SORTED)
     assert np.array_equal(b.get_order(), np.arange(b.n_items))
 
