@@ -139,6 +139,30 @@ class FeaError(RuntimeError):
         self.msg = msg
 
 
+# Library objects released while a HIP graph is being captured on this
+# thread's current stream: freeing device memory then (a garbage-collected
+# Graph, Batch or CostModel) would invalidate the capture, so their
+# destruction waits for the next release outside a capture.
+_deferred = []
+
+
+def _capturing():
+    try:
+        return torch.cuda.is_available() and torch.cuda.is_current_stream_capturing()
+    except Exception:
+        return False
+
+
+def _release(destroy_fn, handle):
+    if _capturing():
+        _deferred.append((destroy_fn, handle))
+        return
+    while _deferred:
+        fn, h = _deferred.pop()
+        fn(h)
+    destroy_fn(handle)
+
+
 def _check(rc):
     if rc != FEA_OK:
         raise FeaError(rc, _lib.fea_last_error().decode())
@@ -260,8 +284,8 @@ class Graph:
 
     def destroy(self):
         if getattr(self, "_h", None) is not None:
-            _lib.fea_graph_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _release(_lib.fea_graph_destroy, h)
 
     def __del__(self):
         try:
@@ -534,8 +558,8 @@ class Batch:
 
     def destroy(self):
         if getattr(self, "_h", None) is not None:
-            _lib.fea_batch_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _release(_lib.fea_batch_destroy, h)
 
     def __del__(self):
         try:
@@ -614,8 +638,8 @@ class CostModel:
 
     def destroy(self):
         if getattr(self, "_h", None) is not None:
-            _lib.fea_cost_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _release(_lib.fea_cost_destroy, h)
 
     def __del__(self):
         try:

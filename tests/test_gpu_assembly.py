@@ -378,6 +378,42 @@ def test_assembly_captured_in_a_graph_replays_eager_result(variant):
         assert rhs.cpu().numpy().tobytes() == ref[1].tobytes()
 
 
+def test_graph_collected_during_a_capture_is_released_after_it():
+    """A library object that Python's garbage collector reaches while a HIP
+    graph is being captured (here a Graph in a reference cycle, collected
+    inside the capture) must not free device memory then, which would
+    invalidate the capture: its release waits until after the capture, and
+    the captured assembly replays the eager result."""
+    import gc
+    m, og, dm, g = case("mix6_jitter")
+    vals, rhs, st = dm.assemble(g, model=fea.ELASTIC, variant=fea.ROWSYM)
+    torch.cuda.synchronize()
+    ref = vals.cpu().numpy().copy()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        dm.assemble(g, model=fea.ELASTIC, variant=fea.ROWSYM, vals=vals, rhs=rhs, status=st)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    gc.collect()
+    doomed = dm.graph()
+    cycle = [doomed]
+    cycle.append(cycle)
+    del doomed, cycle
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dm.assemble(g, model=fea.ELASTIC, variant=fea.ROWSYM, vals=vals, rhs=rhs, status=st)
+        gc.collect()  # reaches the dead Graph inside the capture
+        assert len(fea._deferred) == 1
+    vals.fill_(-1.0)
+    graph.replay()
+    torch.cuda.synchronize()
+    assert vals.cpu().numpy().tobytes() == ref.tobytes()
+    # the next release outside a capture frees the deferred one too
+    dm.graph().destroy()
+    assert not fea._deferred
+
+
 def _same_rhs_up_to_order(ra, rb, B, tol):
     """Right-hand sides of two forms: bitwise equal for 1x1 blocks (both
     add the per-element contributions of a node in element order); with 3x3
