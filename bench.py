@@ -874,6 +874,38 @@ def one_mesh_workload(fea, torch, np, mesh, name, args, variant_names, copy_gbps
     return out, dm, g
 
 
+def persistent_vs_one_mesh(fea, torch, np, dm, g, reps=7):
+    """The one-mesh upper-triangle assembly against the same mesh through
+    the persistent batched kernels (type-sorted queue), FP64 and mixed:
+    median of reps calls each, alternating, timed with events around the
+    whole call."""
+    b = fea.Batch([dm], model=fea.ELASTIC)
+    out = {}
+    for pname, p, o in (("fp64", fea.FP64, fea.F64), ("mixed", fea.MIXED, fea.F32)):
+        v, r, s = b.outputs(o)
+        b.assemble(precision=p, out_dtype=o, vals=v, rhs=r, status=s, variant=fea.ROWSYM)
+        gv, gr, gs = dm.assemble(g, variant=fea.ROWSYM, precision=p, out_dtype=o)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tp, to = [], []
+        for _ in range(reps):
+            e0.record()
+            b.assemble(precision=p, out_dtype=o, vals=v, rhs=r, status=s, variant=fea.ROWSYM)
+            e1.record()
+            torch.cuda.synchronize()
+            tp.append(e0.elapsed_time(e1))
+            e0.record()
+            dm.assemble(g, variant=fea.ROWSYM, precision=p, out_dtype=o, vals=gv, rhs=gr, status=gs)
+            e1.record()
+            torch.cuda.synchronize()
+            to.append(e0.elapsed_time(e1))
+        mp, mo = float(np.median(tp)), float(np.median(to))
+        out[pname] = {"persistent_ms": round(mp, 3), "one_mesh_ms": round(mo, 3), "ratio": round(mp / mo, 3),
+                      "status_ok": bool((s.cpu() == -1).all()) and int(gs.item()) == -1}
+        del v, r, s, gv, gr, gs
+    b.destroy()
+    return out
+
+
 def cpu_baseline_leg(fea, torch, np, mesh, name):
     """The only part of this benchmark that runs the oracle. (1) CPU
     baseline: the C oracle (FP64, -O3) on a bounded sample of the workload,
@@ -1040,6 +1072,8 @@ def main():
         sargs = argparse.Namespace(**{**vars(args), "steps": 20, "warmup": 3})
         sv = [] if args.no_variants else ["rowsym", "rowowner", "rowgather", "tilecolour", "atomic", "colour"]
         extras["hybrid96"], sdm, sg = one_mesh_workload(fea, torch, np, small, "hybrid96", sargs, sv, copy_gbps)
+        if not args.no_extras:
+            extras["hybrid96"]["persistent_vs_one_mesh"] = persistent_vs_one_mesh(fea, torch, np, sdm, sg)
         sg.destroy()
         del sdm, sg
         torch.cuda.empty_cache()
